@@ -1,0 +1,126 @@
+/*
+ * pmace.h -- C ABI of the MI355X PMACE library (libpmace.so).
+ *
+ * PMACE (Projected Multi-Agent Consensus Equilibrium) reconstructs a complex
+ * object x (N1 x N2) from ptychographic intensities z_j (Np x Np, one per
+ * scan position j = 0..J-1) measured through a known complex probe d
+ * (Np x Np), Sec. II eq. (1).  One iteration of the library is one pass of
+ * the loop body of Alg. 1 over all J positions:
+ *     w <- F(v);   z <- G(2w - v);   v <- v + 2 rho (z - w)
+ * with the data agent F_j of eq. (9) and the consensus operator G of
+ * eq. (11) (weights |d|^kappa, normaliser Lambda = sum_j P_j^t |d|^kappa).
+ *
+ * Conventions shared by every entry point:
+ *   - Complex arrays are interleaved (re, im) float32 ("c64"), row-major.
+ *   - Array arguments are DEVICE pointers unless stated otherwise.
+ *   - Calls are stream-ordered on the HIP stream given to pmace_init and
+ *     return as soon as the work is queued; device-side failures (a fault,
+ *     a non-finite state) surface at the next pmace_sync().
+ *   - All persistent state lives in a caller-owned device workspace of
+ *     pmace_footprint() bytes; the library never allocates device memory.
+ *     It keeps a small host-side context (malloc) per reconstruction.
+ *   - No C++ exception crosses this boundary; every call returns a status.
+ *   - A context is not thread-safe; distinct contexts are.
+ */
+#ifndef PMACE_H
+#define PMACE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PMACE_OK = 0,
+  PMACE_EINVAL = 1,        /* bad argument: size, range, NaN/Inf, negative intensity, position */
+  PMACE_EUNSUPPORTED = 2,  /* valid per the paper but not built here (e.g. Np not in {32,64,128,256}) */
+  PMACE_ENOMEM = 3,        /* workspace smaller than pmace_footprint() */
+  PMACE_EDEVICE = 4,       /* a HIP call failed (launch, copy, sync) */
+  PMACE_ESTATE = 5,        /* call out of order (e.g. NULL or destroyed context) */
+  PMACE_EDIVERGED = 6      /* the consensus image became non-finite */
+} pmace_status;
+
+/* Intensities are stored with the zero frequency at the array centre
+ * (fftshift layout); they are reordered once at init. */
+#define PMACE_CENTERED_DC 0x1u
+
+typedef struct {
+  int32_t n1, n2;     /* object grid N1 x N2 (Sec. II); n1, n2 >= np */
+  int32_t np;         /* probe / patch side Np; this build runs 32, 64, 128, 256 */
+  int32_t num_pos;    /* J >= 1 scan positions */
+  float alpha;        /* >= 0: noise-to-signal weight of the agent, eq. (9) */
+  float kappa;        /* >= 0: probe exponent of the consensus weights, eq. (11) */
+  float rho;          /* 0 < rho < 1: Mann averaging parameter, eq. (13) */
+  uint32_t flags;     /* PMACE_CENTERED_DC or 0 */
+  int32_t chunk;      /* Np = 256 only: positions per staging chunk, 0 = library default */
+} pmace_params;
+
+typedef struct pmace_ctx pmace_ctx;      /* one reconstruction */
+typedef struct pmace_batch pmace_batch;  /* several reconstructions stepped together */
+
+/* Bytes of device workspace one reconstruction needs (0 if params are invalid).
+ * Layout: agent states J*Np^2*8, amplitudes J*Np^2*4, images 4*N1*N2*8-ish,
+ * probe tables Np^2*24, positions J*8, and for Np = 256 a staging buffer of
+ * chunk*Np^2*8 bytes; each section 256-byte aligned. */
+size_t pmace_footprint(const pmace_params* params);
+
+/* Alg. 1 initialisation: v_j = P_j x0 for every j.  Also computes
+ * y = sqrt(z) (eq. (2)), the weights |d|^kappa and Lambda^{-1} of eq. (11)
+ * (Lambda^{-1} := 0 where Lambda = 0) and D^{-1} (in FP64 on the host from a
+ * copy of the probe), and the starting reconstruction x0 restricted to the
+ * covered pixels.
+ *   probe_d     np*np c64, the known probe d (Sec. II)
+ *   pos_d       num_pos x 2 int32 (row, col) top-left patch offsets, each in
+ *               [0, n1-np] x [0, n2-np]  (P_j, Sec. II)
+ *   intensity_d num_pos*np*np float32 z_j >= 0, finite; DC at [0,0] unless
+ *               PMACE_CENTERED_DC
+ *   x0_d        n1*n2 c64 initial object, or NULL for 1+0i everywhere
+ *   workspace_d device buffer of ws_bytes >= pmace_footprint(params), owned
+ *               by the caller and kept alive until pmace_destroy
+ *   hip_stream  hipStream_t the context queues all its work on (NULL = the
+ *               null stream)
+ * Inputs are read during this call's stream work; this call synchronises the
+ * stream before returning, so the caller may free them afterwards.
+ * Errors: EINVAL (bad sizes/ranges, non-finite or negative intensity, position
+ * outside the object), EUNSUPPORTED (np), ENOMEM (ws_bytes too small),
+ * EDEVICE.  On error *out is NULL. */
+pmace_status pmace_init(const pmace_params* params, const void* probe_d,
+                        const int32_t* pos_d, const float* intensity_d,
+                        const void* x0_d, void* workspace_d, size_t ws_bytes,
+                        void* hip_stream, pmace_ctx** out);
+
+/* Run n_iter >= 0 iterations of the Alg. 1 loop body (stream-ordered, async).
+ * Each iteration reads and rewrites every agent state once. */
+pmace_status pmace_iterate(pmace_ctx* ctx, int32_t n_iter);
+
+/* Alg. 1 output: xhat = Lambda^{-1} sum_j P_j^t |d|^kappa v_j, written to
+ * xhat_d (n1*n2 c64, device).  Stream-ordered. */
+pmace_status pmace_reconstruct(pmace_ctx* ctx, void* xhat_d);
+
+/* Copy the stacked agent states v (num_pos*np*np c64, device) out / in.
+ * set_state also recomputes the reconstruction as the weighted average of
+ * the new v (checkpoint resume; one-step parity checks). */
+pmace_status pmace_get_state(pmace_ctx* ctx, void* v_d);
+pmace_status pmace_set_state(pmace_ctx* ctx, const void* v_d);
+
+/* Wait for the context's queued work; reports EDEVICE for a failed HIP call
+ * and EDIVERGED if the consensus image became NaN/Inf. */
+pmace_status pmace_sync(pmace_ctx* ctx);
+
+/* Release the host context (not the caller's workspace).  NULL is a no-op. */
+void pmace_destroy(pmace_ctx* ctx);
+
+const char* pmace_status_str(pmace_status s);
+
+/* Batched 2-D orthonormal DFT of `count` np x np c64 arrays (the operator F
+ * of Sec. II, or F^* when inverse != 0), in_d and out_d may alias.
+ * np in {32, 64, 128, 256}.  Stream-ordered on hip_stream. */
+pmace_status pmace_fft2(int32_t np, int32_t count, const void* in_d, void* out_d,
+                        int32_t inverse, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMACE_H */

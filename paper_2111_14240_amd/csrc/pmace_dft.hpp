@@ -1,0 +1,243 @@
+// Register-resident DFT radices and the LDS-exchanged line FFTs used by the
+// PMACE kernels (gfx950, wave64).
+//
+// F in the paper is the 2-D orthonormal DFT (Sec. II).  The kernels compute
+// the *unnormalised* transform  X[k] = sum_n x[n] exp(-2 pi i n k / N)  and its
+// unnormalised inverse; the 1/Np^2 of a forward+inverse pair is folded into
+// the per-pixel probe table, so no pass spends a multiply on scaling.
+//
+// A line (row or column) of N = A*B points is transformed by A threads with
+// one exchange through LDS (Cooley-Tukey, N = A*B):
+//   n = n_a + A*n_b,  k = k_b + B*k_a
+//   X[k_b + B k_a] = sum_{n_a} W_A^{n_a k_a} W_N^{n_a k_b} sum_{n_b} x[n_a + A n_b] W_B^{n_b k_b}
+// Stage 1: thread n_a owns x[n_a + A n_b] (stride A) and does a B-point DFT.
+// Twiddle by W_N^{n_a k_b}.  Exchange.  Stage 2: thread p does the A-point
+// DFTs for k_b = p, p + A, ... (B/A of them) and ends owning X[k_b + B k_a].
+// The inverse runs the same stages backwards, so a forward transform
+// followed by a pointwise step and the inverse needs no extra reordering.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace pmace {
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// multiply by -i (forward) or +i (inverse)
+template <bool INV> __device__ __forceinline__ float2 rotq(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// multiply by W_8^1 (forward (1-i)/sqrt2, inverse (1+i)/sqrt2)
+template <bool INV> __device__ __forceinline__ float2 w8_1(float2 a) {
+  const float s = 0.70710678118654752f;
+  return INV ? make_float2((a.x - a.y) * s, (a.x + a.y) * s)
+             : make_float2((a.x + a.y) * s, (a.y - a.x) * s);
+}
+// multiply by W_8^3 (forward (-1-i)/sqrt2, inverse (-1+i)/sqrt2)
+template <bool INV> __device__ __forceinline__ float2 w8_3(float2 a) {
+  const float s = 0.70710678118654752f;
+  return INV ? make_float2((-a.x - a.y) * s, (a.x - a.y) * s)
+             : make_float2((a.y - a.x) * s, (-a.x - a.y) * s);
+}
+// multiply by W_16^k, k compile-time after unrolling
+template <bool INV> __device__ __forceinline__ float2 w16(int k, float2 a) {
+  const float c1 = 0.92387953251128674f;  // cos(pi/8)
+  const float s1 = 0.38268343236508977f;  // sin(pi/8)
+  const float sg = INV ? 1.f : -1.f;
+  switch (k) {
+    case 0: return a;
+    case 1: return cmul(a, make_float2(c1, sg * s1));
+    case 2: return w8_1<INV>(a);
+    case 3: return cmul(a, make_float2(s1, sg * c1));
+    case 4: return rotq<INV>(a);
+    case 5: return cmul(a, make_float2(-s1, sg * c1));
+    case 6: return w8_3<INV>(a);
+    default: return cmul(a, make_float2(-c1, sg * s1));
+  }
+}
+
+template <bool INV> __device__ __forceinline__ void dft2(float2* a) {
+  float2 t = a[0];
+  a[0] = cadd(t, a[1]);
+  a[1] = csub(t, a[1]);
+}
+
+template <bool INV> __device__ __forceinline__ void dft4r(float2& a0, float2& a1, float2& a2, float2& a3) {
+  float2 t0 = cadd(a0, a2), t1 = csub(a0, a2);
+  float2 t2 = cadd(a1, a3), t3 = rotq<INV>(csub(a1, a3));
+  a0 = cadd(t0, t2);
+  a2 = csub(t0, t2);
+  a1 = cadd(t1, t3);
+  a3 = csub(t1, t3);
+}
+
+template <bool INV> __device__ __forceinline__ void dft4(float2* a) { dft4r<INV>(a[0], a[1], a[2], a[3]); }
+
+// 8 points: two 4-point DFTs on even/odd samples, then W_8 butterflies.
+template <bool INV> __device__ __forceinline__ void dft8(float2* a) {
+  dft4r<INV>(a[0], a[2], a[4], a[6]);
+  dft4r<INV>(a[1], a[3], a[5], a[7]);
+  float2 o0 = a[1], o1 = w8_1<INV>(a[3]), o2 = rotq<INV>(a[5]), o3 = w8_3<INV>(a[7]);
+  float2 e0 = a[0], e1 = a[2], e2 = a[4], e3 = a[6];
+  a[0] = cadd(e0, o0); a[4] = csub(e0, o0);
+  a[1] = cadd(e1, o1); a[5] = csub(e1, o1);
+  a[2] = cadd(e2, o2); a[6] = csub(e2, o2);
+  a[3] = cadd(e3, o3); a[7] = csub(e3, o3);
+}
+
+// 16 points: two 8-point DFTs on even/odd samples, then W_16 butterflies.
+template <bool INV> __device__ __forceinline__ void dft16(float2* a) {
+  float2 e[8], o[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) { e[i] = a[2 * i]; o[i] = a[2 * i + 1]; }
+  dft8<INV>(e);
+  dft8<INV>(o);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    float2 t = w16<INV>(k, o[k]);
+    a[k] = cadd(e[k], t);
+    a[k + 8] = csub(e[k], t);
+  }
+}
+
+template <int R, bool INV> __device__ __forceinline__ void dft(float2* a) {
+  if constexpr (R == 2) dft2<INV>(a);
+  else if constexpr (R == 4) dft4<INV>(a);
+  else if constexpr (R == 8) dft8<INV>(a);
+  else { static_assert(R == 16, "radix"); dft16<INV>(a); }
+}
+
+// Split N = A*B of a line over A threads with B registers each.
+template <int N> struct Geo;
+template <> struct Geo<32>  { static constexpr int A = 4,  B = 8;  };
+template <> struct Geo<64>  { static constexpr int A = 8,  B = 8;  };
+template <> struct Geo<128> { static constexpr int A = 8,  B = 16; };
+template <> struct Geo<256> { static constexpr int A = 16, B = 16; };
+
+// W_N^m = exp(-2 pi i m / N) for m = 0..N-1 into LDS (FP64 sincospi, rounded once).
+template <int N> __device__ __forceinline__ void fill_twiddles(float2* tw, int tid, int nthreads) {
+  for (int m = tid; m < N; m += nthreads) {
+    double s, c;
+    sincospi(-2.0 * (double)m / (double)N, &s, &c);
+    tw[m] = make_float2((float)c, (float)s);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Row-direction line FFT.  Thread (r, p), p in [0, A), owns row r of a tile
+// whose rows start at row_base (float2 units) with the row exchanged through
+// a skewed layout  n_a*(B+1) + k_b  (row capacity N + A float2).
+// ---------------------------------------------------------------------------
+
+// in : x[n_b] = row[p + A n_b]
+// out: x[m*A + k_a] = X[(p + A m) + B k_a]
+template <int N> __device__ __forceinline__ void row_fwd(float2 (&x)[Geo<N>::B], float2* row, int p,
+                                                         const float2* tw) {
+  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A;
+  dft<B, false>(x);
+#pragma unroll
+  for (int kb = 1; kb < B; ++kb) x[kb] = cmul(x[kb], tw[(p * kb) & (N - 1)]);
+  __syncthreads();
+#pragma unroll
+  for (int kb = 0; kb < B; ++kb) row[p * (B + 1) + kb] = x[kb];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int kb = p + A * m;
+    float2 g[A];
+#pragma unroll
+    for (int na = 0; na < A; ++na) g[na] = row[na * (B + 1) + kb];
+    dft<A, false>(g);
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) x[m * A + ka] = g[ka];
+  }
+}
+
+// in : x[m*A + k_a] = X[(p + A m) + B k_a]
+// out: x[n_b] = unnormalised inverse row[p + A n_b]
+template <int N> __device__ __forceinline__ void row_inv(float2 (&x)[Geo<N>::B], float2* row, int p,
+                                                         const float2* tw) {
+  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int kb = p + A * m;
+    dft<A, true>(&x[m * A]);
+#pragma unroll
+    for (int na = 1; na < A; ++na) x[m * A + na] = cmulc(x[m * A + na], tw[(na * kb) & (N - 1)]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int kb = p + A * m;
+#pragma unroll
+    for (int na = 0; na < A; ++na) row[na * (B + 1) + kb] = x[m * A + na];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int kb = 0; kb < B; ++kb) x[kb] = row[p * (B + 1) + kb];
+  dft<B, true>(x);
+}
+
+// ---------------------------------------------------------------------------
+// Column-direction line FFT.  Thread (c, q), q in [0, A), owns column c of a
+// tile with N rows and row stride S (float2); lanes run along c so every LDS
+// access is contiguous across a wave.
+// ---------------------------------------------------------------------------
+
+// in : x[n_b] = col[q + A n_b]
+// out: x[m*A + k_a] = X[(q + A m) + B k_a]
+template <int N> __device__ __forceinline__ void col_fwd(float2 (&x)[Geo<N>::B], float2* tile, int S,
+                                                         int c, int q, const float2* tw) {
+  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A;
+  dft<B, false>(x);
+#pragma unroll
+  for (int kb = 1; kb < B; ++kb) x[kb] = cmul(x[kb], tw[(q * kb) & (N - 1)]);
+  __syncthreads();
+#pragma unroll
+  for (int kb = 0; kb < B; ++kb) tile[(kb * A + q) * S + c] = x[kb];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int kb = q + A * m;
+    float2 g[A];
+#pragma unroll
+    for (int na = 0; na < A; ++na) g[na] = tile[(kb * A + na) * S + c];
+    dft<A, false>(g);
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) x[m * A + ka] = g[ka];
+  }
+}
+
+// in : x[m*A + k_a] = X[(q + A m) + B k_a]
+// out: x[n_b] = unnormalised inverse col[q + A n_b]
+template <int N> __device__ __forceinline__ void col_inv(float2 (&x)[Geo<N>::B], float2* tile, int S,
+                                                         int c, int q, const float2* tw) {
+  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int kb = q + A * m;
+    dft<A, true>(&x[m * A]);
+#pragma unroll
+    for (int na = 1; na < A; ++na) x[m * A + na] = cmulc(x[m * A + na], tw[(na * kb) & (N - 1)]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int kb = q + A * m;
+#pragma unroll
+    for (int na = 0; na < A; ++na) tile[(kb * A + na) * S + c] = x[m * A + na];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int kb = 0; kb < B; ++kb) x[kb] = tile[(kb * A + q) * S + c];
+  dft<B, true>(x);
+}
+
+}  // namespace pmace

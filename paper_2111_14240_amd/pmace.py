@@ -1,0 +1,248 @@
+"""ctypes binding of libpmace.so (include/pmace.h).
+
+Argument marshalling only: every step of the PMACE iteration runs in the HIP
+library.  PyTorch supplies device memory (the caller-owned workspace and the
+input/output tensors) and the current HIP stream.  If the library has not
+been built, every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpmace.so")
+
+PMACE_OK = 0
+PMACE_EINVAL = 1
+PMACE_EUNSUPPORTED = 2
+PMACE_ENOMEM = 3
+PMACE_EDEVICE = 4
+PMACE_ESTATE = 5
+PMACE_EDIVERGED = 6
+PMACE_CENTERED_DC = 0x1
+
+STATUS_NAMES = {
+    0: "PMACE_OK", 1: "PMACE_EINVAL", 2: "PMACE_EUNSUPPORTED", 3: "PMACE_ENOMEM",
+    4: "PMACE_EDEVICE", 5: "PMACE_ESTATE", 6: "PMACE_EDIVERGED",
+}
+
+
+class pmace_params(ctypes.Structure):
+    _fields_ = [
+        ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("np", ctypes.c_int32),
+        ("num_pos", ctypes.c_int32), ("alpha", ctypes.c_float), ("kappa", ctypes.c_float),
+        ("rho", ctypes.c_float), ("flags", ctypes.c_uint32), ("chunk", ctypes.c_int32),
+    ]
+
+
+class PMACEError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} ({_status_str(status)})")
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libpmace.so and declare the C signatures (raises if not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(the PMACE path has no CPU fallback)")
+    L = ctypes.CDLL(path)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    P = ctypes.POINTER(pmace_params)
+    L.pmace_footprint.argtypes = [P]
+    L.pmace_footprint.restype = sz
+    L.pmace_init.argtypes = [P, vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]
+    L.pmace_init.restype = ctypes.c_int
+    for name in ("pmace_reconstruct", "pmace_get_state", "pmace_set_state"):
+        getattr(L, name).argtypes = [vp, vp]
+        getattr(L, name).restype = ctypes.c_int
+    L.pmace_iterate.argtypes = [vp, i32]
+    L.pmace_iterate.restype = ctypes.c_int
+    L.pmace_sync.argtypes = [vp]
+    L.pmace_sync.restype = ctypes.c_int
+    L.pmace_destroy.argtypes = [vp]
+    L.pmace_destroy.restype = None
+    L.pmace_status_str.argtypes = [ctypes.c_int]
+    L.pmace_status_str.restype = ctypes.c_char_p
+    L.pmace_fft2.argtypes = [i32, i32, vp, vp, i32, vp]
+    L.pmace_fft2.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _status_str(s: int) -> str:
+    try:
+        return load_library().pmace_status_str(s).decode()
+    except Exception:
+        return "?"
+
+
+def _check(status: int, where: str):
+    if status != PMACE_OK:
+        raise PMACEError(status, where)
+
+
+def make_params(n1, n2, np_, num_pos, alpha, kappa=1.25, rho=0.5, flags=0, chunk=0) -> pmace_params:
+    return pmace_params(int(n1), int(n2), int(np_), int(num_pos), float(alpha), float(kappa),
+                        float(rho), int(flags), int(chunk))
+
+
+# Thin wrappers with the C names -------------------------------------------
+
+def pmace_footprint(params: pmace_params) -> int:
+    return int(load_library().pmace_footprint(ctypes.byref(params)))
+
+
+def pmace_init(params, probe_ptr, pos_ptr, intensity_ptr, x0_ptr, ws_ptr, ws_bytes, stream_ptr):
+    ctx = ctypes.c_void_p()
+    st = load_library().pmace_init(ctypes.byref(params), probe_ptr, pos_ptr, intensity_ptr,
+                                   x0_ptr, ws_ptr, ws_bytes, stream_ptr, ctypes.byref(ctx))
+    return st, ctx
+
+
+def pmace_iterate(ctx, n_iter: int) -> int:
+    return load_library().pmace_iterate(ctx, int(n_iter))
+
+
+def pmace_reconstruct(ctx, xhat_ptr) -> int:
+    return load_library().pmace_reconstruct(ctx, xhat_ptr)
+
+
+def pmace_get_state(ctx, v_ptr) -> int:
+    return load_library().pmace_get_state(ctx, v_ptr)
+
+
+def pmace_set_state(ctx, v_ptr) -> int:
+    return load_library().pmace_set_state(ctx, v_ptr)
+
+
+def pmace_sync(ctx) -> int:
+    return load_library().pmace_sync(ctx)
+
+
+def pmace_destroy(ctx) -> None:
+    load_library().pmace_destroy(ctx)
+
+
+def pmace_status_str(s: int) -> str:
+    return _status_str(s)
+
+
+def pmace_fft2(np_, count, in_ptr, out_ptr, inverse, stream_ptr) -> int:
+    return load_library().pmace_fft2(int(np_), int(count), in_ptr, out_ptr, int(inverse), stream_ptr)
+
+
+# Torch-facing helpers ------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(int(s.cuda_stream))
+
+
+def to_device_c64(a, device):
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=torch.complex64).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.complex64))).to(device)
+
+
+def fft2(x, inverse: bool = False, stream=None):
+    """Orthonormal 2-D DFT (or its inverse) of a (count, np, np) complex64 CUDA tensor."""
+    torch = _torch()
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    _check(pmace_fft2(x.shape[-1], x.numel() // (x.shape[-1] ** 2), ctypes.c_void_p(x.data_ptr()),
+                      ctypes.c_void_p(out.data_ptr()), 1 if inverse else 0, _stream_ptr(stream)),
+           "pmace_fft2")
+    return out
+
+
+class Reconstruction:
+    """One PMACE reconstruction whose state stays resident on the GPU.
+
+    probe (Np,Np) complex, pos (J,2) int (row, col), z (J,Np,Np) float
+    intensities (numpy or torch); x0 (N1,N2) complex or None for ones."""
+
+    def __init__(self, n1, n2, probe, pos, z, alpha, kappa=1.25, rho=0.5, x0=None,
+                 flags=0, chunk=0, device="cuda", stream=None, workspace=None):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.stream = stream
+        probe_t = to_device_c64(probe, self.device)
+        pos_t = torch.as_tensor(np.asarray(pos, dtype=np.int32) if not isinstance(pos, torch.Tensor) else pos,
+                                dtype=torch.int32).to(self.device).contiguous()
+        z_t = (z if isinstance(z, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(z, dtype=np.float32)))
+        z_t = z_t.to(device=self.device, dtype=torch.float32).contiguous()
+        np_ = probe_t.shape[-1]
+        J = pos_t.shape[0]
+        if z_t.shape != (J, np_, np_):
+            raise ValueError(f"intensities must be ({J},{np_},{np_}), got {tuple(z_t.shape)}")
+        x0_t = None if x0 is None else to_device_c64(x0, self.device)
+        self.params = make_params(n1, n2, np_, J, alpha, kappa, rho, flags, chunk)
+        fp = pmace_footprint(self.params)
+        if fp == 0:
+            raise PMACEError(PMACE_EINVAL, "pmace_footprint")
+        self.footprint = fp
+        if workspace is None:
+            workspace = torch.empty(fp, dtype=torch.uint8, device=self.device)
+        self.workspace = workspace
+        st, ctx = pmace_init(self.params, ctypes.c_void_p(probe_t.data_ptr()),
+                             ctypes.c_void_p(pos_t.data_ptr()), ctypes.c_void_p(z_t.data_ptr()),
+                             ctypes.c_void_p(0 if x0_t is None else x0_t.data_ptr()),
+                             ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                             _stream_ptr(stream))
+        _check(st, "pmace_init")
+        self.ctx = ctx
+        self.n1, self.n2, self.np, self.J = int(n1), int(n2), int(np_), int(J)
+
+    def iterate(self, n: int = 1):
+        _check(pmace_iterate(self.ctx, n), "pmace_iterate")
+
+    def reconstruct(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.n1, self.n2), dtype=torch.complex64, device=self.device)
+        _check(pmace_reconstruct(self.ctx, ctypes.c_void_p(out.data_ptr())), "pmace_reconstruct")
+        return out
+
+    def get_state(self, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty((self.J, self.np, self.np), dtype=torch.complex64, device=self.device)
+        _check(pmace_get_state(self.ctx, ctypes.c_void_p(out.data_ptr())), "pmace_get_state")
+        return out
+
+    def set_state(self, v):
+        v_t = to_device_c64(v, self.device)
+        _check(pmace_set_state(self.ctx, ctypes.c_void_p(v_t.data_ptr())), "pmace_set_state")
+        self.sync()          # keep v_t alive until the copy has run
+
+    def sync(self):
+        _check(pmace_sync(self.ctx), "pmace_sync")
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            pmace_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,82 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/pmace.h declares, and rejects bad arguments before
+touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+from paper_2111_14240_amd import pmace as P
+
+HEADER = os.path.join(ROOT, "include", "pmace.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pmace_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(P.LIB_PATH):
+        pytest.fail("libpmace.so is not built (run __graft_entry__.build())")
+    return P.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert "pmace_init" in names and "pmace_iterate" in names and "pmace_reconstruct" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings(lib):
+    for s in range(7):
+        assert P.pmace_status_str(s) not in ("", "unknown status")
+    assert P.pmace_status_str(99) == "unknown status"
+
+
+def _fp(**kw):
+    base = dict(n1=128, n2=128, np_=32, num_pos=36, alpha=0.5)
+    base.update(kw)
+    return P.pmace_footprint(P.make_params(**base))
+
+
+def test_footprint_formula(lib):
+    J, np_, n = 36, 32, 128
+    fp = _fp()
+    # states 8 B + amplitudes 4 B per patch pixel, four image planes, probe tables
+    lower = J * np_ * np_ * 12 + n * n * 28 + np_ * np_ * 24 + J * 8
+    assert lower <= fp <= lower + 12 * 256 + 256
+    # Np = 256 adds a staging chunk of min(J, chunk) patches
+    a = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=64))
+    b = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=128))
+    assert b - a == 64 * 256 * 256 * 8
+
+
+@pytest.mark.parametrize("kw", [dict(np_=0), dict(num_pos=0), dict(n1=16), dict(alpha=-1.0),
+                                dict(alpha=float("nan")), dict(rho=0.0), dict(rho=1.0),
+                                dict(kappa=-0.5), dict(kappa=float("inf")), dict(flags=8),
+                                dict(chunk=-1), dict(np_=48)])
+def test_invalid_params_rejected(lib, kw):
+    assert _fp(**kw) == 0
+    st, ctx = P.pmace_init(P.make_params(**{**dict(n1=128, n2=128, np_=32, num_pos=36, alpha=0.5), **kw}),
+                           1, 1, 1, None, 1, 1 << 30, None)
+    expect = P.PMACE_EUNSUPPORTED if kw == dict(np_=48) else P.PMACE_EINVAL
+    assert st == expect and not ctx.value
+
+
+def test_init_argument_checks_before_device(lib):
+    prm = P.make_params(128, 128, 32, 36, 0.5)
+    st, _ = P.pmace_init(prm, None, 1, 1, None, 1, 1 << 30, None)
+    assert st == P.PMACE_EINVAL
+    st, _ = P.pmace_init(prm, 1, 1, 1, None, 1, 16, None)
+    assert st == P.PMACE_ENOMEM
+    assert P.pmace_iterate(None, 1) == P.PMACE_ESTATE
+    assert P.pmace_sync(None) == P.PMACE_ESTATE
+    assert P.pmace_fft2(48, 1, 1, 1, 0, None) == P.PMACE_EUNSUPPORTED
+    assert P.pmace_fft2(32, -1, 1, 1, 0, None) == P.PMACE_EINVAL
+    P.pmace_destroy(None)

@@ -1,0 +1,282 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bar: relative L2 error <= 1e-4 per iteration state (FP32 kernels against the
+FP64 oracle), on the whole stacked state v and on the reconstruction xhat.
+The binding check is teacher-forced: the oracle's state at iteration k is set
+on the device, one device iteration is run, and the result is compared with
+the oracle's state at k+1."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pmace_oracle as O
+from paper_2111_14240_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _say(*a):
+    print("[gpu-parity]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2111_14240_amd import pmace
+    pmace.load_library()
+    return pmace
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def as_f32_inputs(prob):
+    """The exact values the device sees, widened to FP64 for the oracle."""
+    d = prob.probe.astype(np.complex64).astype(np.complex128)
+    return d, prob.z.astype(np.float32)
+
+
+def oracle_trajectory(prob, alpha, kappa, rho, n_iter, x0=None):
+    d, z = as_f32_inputs(prob)
+    y = O.amplitudes(z)
+    shape = (prob.n1, prob.n2)
+    x0 = np.ones(shape, complex) if x0 is None else x0
+    st = O.pmace_init(x0, prob.pos, prob.np_)
+    vs, xs = [st.v], [O.reconstruct(st, d, prob.pos, shape, kappa)]
+    for _ in range(n_iter):
+        st = O.pmace_iterate(st, d, y, prob.pos, shape, alpha, kappa, rho, 1)
+        vs.append(st.v)
+        xs.append(O.reconstruct(st, d, prob.pos, shape, kappa))
+    return vs, xs
+
+
+def smooth_start(prob, seed=99):
+    """A non-degenerate start: a smooth random object-like field."""
+    return synth.make_object(prob.n1, prob.n2, np.random.default_rng(seed))
+
+
+def single_precision_step_error(prob, v, alpha, kappa, rho):
+    """Relative error that a plain complex64 evaluation of one loop pass (the
+    oracle's steps with single-precision FFTs) makes against the FP64 oracle.
+    From a flat start the patch spectra F(d v) sit in a few bins and the phase
+    W/|W| of the others is rounding noise in any FP32 evaluation; this sizes
+    the tolerance for that ill-conditioned step."""
+    import scipy.fft as sf
+    d, z = as_f32_inputs(prob)
+    y = O.amplitudes(z)
+    shape = (prob.n1, prob.n2)
+    ref, _, _ = O.pmace_step(v, d, y, prob.pos, shape, alpha, kappa, rho)
+    v32, d32, y32 = v.astype(np.complex64), d.astype(np.complex64), y.astype(np.float32)
+    W = sf.fft2(d32 * v32, norm="ortho")
+    m = np.abs(W)
+    frac = np.where(m > 0, W / np.where(m > 0, m, 1), 0).astype(np.complex64)
+    w = ((alpha * v32 + sf.ifft2(y32 * frac, norm="ortho") / d32) / (1 + alpha)).astype(np.complex64)
+    xbar = O.weighted_average((2 * w - v32).astype(np.complex64), d, prob.pos, shape, kappa)
+    v1 = v32 + 2 * rho * (O.extract(xbar.astype(np.complex64), prob.pos, prob.np_) - w)
+    return rel(v1, ref)
+
+
+def make_recon(P, prob, alpha, kappa=1.25, rho=0.5, chunk=0):
+    return P.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, alpha, kappa, rho,
+                            chunk=chunk)
+
+
+SMALL_CASES = {
+    # name: (n, np, scan, step, peak, seed, chunk)
+    "np32": (128, 32, 6, 16, None, 1, 0),
+    "np64": (200, 64, 5, 30, 1e5, 21, 0),
+    "np128": (320, 128, 4, 56, 1e5, 22, 0),
+    "np256_ragged_chunks": (400, 256, 3, 60, 1e6, 23, 4),
+}
+
+
+@pytest.mark.parametrize("np_", [32, 64, 128, 256])
+@pytest.mark.parametrize("inverse", [False, True])
+def test_fft2_matches_oracle_dft(P, np_, inverse):
+    _say("fft2", np_, "inverse" if inverse else "forward")
+    rng = np.random.default_rng(np_)
+    a = (rng.standard_normal((3, np_, np_)) + 1j * rng.standard_normal((3, np_, np_))).astype(np.complex64)
+    out = P.fft2(torch.from_numpy(a).cuda(), inverse=inverse).cpu().numpy()
+    ref = O.idft2(a) if inverse else O.dft2(a)
+    assert rel(out, ref) < 2e-6
+
+
+@pytest.mark.parametrize("case", sorted(SMALL_CASES))
+def test_init_state_is_patches_of_x0(P, case):
+    n, np_, scan, step, peak, seed, chunk = SMALL_CASES[case]
+    _say("init", case)
+    prob = synth.make_problem(n, np_, scan, step, peak, seed)
+    rng = np.random.default_rng(5)
+    x0 = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))).astype(np.complex64)
+    R = P.Reconstruction(n, n, prob.probe, prob.pos, prob.z, 0.5, x0=x0, chunk=chunk)
+    v = R.get_state().cpu().numpy()
+    assert np.array_equal(v, O.extract(x0.astype(np.complex128), prob.pos, np_).astype(np.complex64))
+    lam = O.weight_image(prob.probe.astype(np.complex64), prob.pos, (n, n), 1.25)
+    xh = R.reconstruct().cpu().numpy()
+    assert np.array_equal(xh[lam > 0], x0[lam > 0]) and np.all(xh[lam == 0] == 0)
+    R.close()
+
+
+@pytest.mark.parametrize("case", sorted(SMALL_CASES))
+@pytest.mark.parametrize("alpha", [0.0, 0.5, 2.0])
+def test_teacher_forced_steps(P, case, alpha):
+    n, np_, scan, step, peak, seed, chunk = SMALL_CASES[case]
+    prob = synth.make_problem(n, np_, scan, step, peak, seed)
+    K = 4
+    vs, xs = oracle_trajectory(prob, alpha, 1.25, 0.5, K, x0=smooth_start(prob))
+    _say("teacher-forced", case, "alpha", alpha, "J", prob.num_pos)
+    R = make_recon(P, prob, alpha, chunk=chunk)
+    for k in range(K):
+        R.set_state(vs[k])
+        xh0 = R.reconstruct().cpu().numpy()
+        assert rel(xh0, xs[k]) < TOL, ("set_state average", k)
+        R.iterate(1)
+        R.sync()
+        v = R.get_state().cpu().numpy()
+        xh = R.reconstruct().cpu().numpy()
+        ev, ex = rel(v, vs[k + 1]), rel(xh, xs[k + 1])
+        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
+        assert ev < TOL and ex < TOL, (k, ev, ex)
+    R.close()
+
+
+@pytest.mark.parametrize("case", sorted(SMALL_CASES))
+def test_flat_start(P, case):
+    """Default start x0 = 1: the first pass is checked against a tolerance sized
+    by a single-precision evaluation of the same pass; later passes at 1e-4."""
+    n, np_, scan, step, peak, seed, chunk = SMALL_CASES[case]
+    prob = synth.make_problem(n, np_, scan, step, peak, seed)
+    alpha = 0.5
+    vs, xs = oracle_trajectory(prob, alpha, 1.25, 0.5, 3)
+    tol0 = max(TOL, 3.0 * single_precision_step_error(prob, vs[0], alpha, 1.25, 0.5))
+    _say("flat start", case, f"tol0={tol0:.2e}")
+    R = make_recon(P, prob, alpha, chunk=chunk)
+    R.iterate(1)
+    e0 = rel(R.get_state().cpu().numpy(), vs[1])
+    _say(f"  k=0 rel(v)={e0:.2e}")
+    assert e0 < tol0
+    for k in (1, 2):
+        R.set_state(vs[k])
+        R.iterate(1)
+        ev = rel(R.get_state().cpu().numpy(), vs[k + 1])
+        ex = rel(R.reconstruct().cpu().numpy(), xs[k + 1])
+        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
+        assert ev < TOL and ex < TOL
+    R.close()
+
+
+def test_c1_every_iteration_teacher_forced_and_free_running(P):
+    prob = synth.make_config_problem("c1")
+    K = synth.CONFIGS["c1"]["iters"]
+    alpha = 0.1
+    vs, xs = oracle_trajectory(prob, alpha, synth.KAPPA, synth.RHO, K)
+    _say("c1 teacher-forced, K", K)
+    R = make_recon(P, prob, alpha)
+    worst = 0.0
+    for k in range(1, K):
+        R.set_state(vs[k])
+        R.iterate(1)
+        v = R.get_state().cpu().numpy()
+        xh = R.reconstruct().cpu().numpy()
+        worst = max(worst, rel(v, vs[k + 1]), rel(xh, xs[k + 1]))
+    _say(f"  worst teacher-forced rel = {worst:.2e}")
+    assert worst < TOL
+    # free-running from the same start: report the drift, bound it loosely
+    R2 = make_recon(P, prob, alpha)
+    drift = []
+    for k in range(K):
+        R2.iterate(1)
+        drift.append(rel(R2.get_state().cpu().numpy(), vs[k + 1]))
+    R2.sync()
+    xh = R2.reconstruct().cpu().numpy()
+    mask = synth.roi_mask(prob.probe, prob.pos, prob.n1, prob.n2)
+    e_gpu, e_ref = O.nrmse(xh, prob.x_true, mask), O.nrmse(xs[-1], prob.x_true, mask)
+    _say(f"  free-running rel(v) at k=1,10,{K}: {drift[0]:.2e} {drift[9]:.2e} {drift[-1]:.2e};"
+         f" NRMSE gpu {e_gpu:.6f} oracle {e_ref:.6f}")
+    assert drift[0] < max(TOL, 3.0 * single_precision_step_error(prob, vs[0], alpha, synth.KAPPA,
+                                                                 synth.RHO))
+    assert abs(e_gpu - e_ref) < 1e-3
+    R.close()
+    R2.close()
+
+
+def test_c2_teacher_forced_steps(P):
+    prob = synth.make_config_problem("c2")
+    alpha = 0.5
+    ks = [1, 2, 5]
+    vs, xs = oracle_trajectory(prob, alpha, synth.KAPPA, synth.RHO, max(ks) + 1)
+    _say("c2 teacher-forced at", ks)
+    R = make_recon(P, prob, alpha)
+    for k in ks:
+        R.set_state(vs[k])
+        R.iterate(1)
+        ev = rel(R.get_state().cpu().numpy(), vs[k + 1])
+        ex = rel(R.reconstruct().cpu().numpy(), xs[k + 1])
+        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
+        assert ev < TOL and ex < TOL
+    R.close()
+
+
+def test_invalid_intensities_rejected(P):
+    prob = synth.make_problem(128, 32, 4, 20, None, 3)
+    for bad in (np.nan, -1.0, np.inf):
+        z = prob.z.copy()
+        z[2, 3, 4] = bad
+        _say("bad intensity", bad)
+        with pytest.raises(P.PMACEError) as ei:
+            P.Reconstruction(128, 128, prob.probe, prob.pos, z, 0.5)
+        assert ei.value.status == P.PMACE_EINVAL
+    pos = prob.pos.copy()
+    pos[0, 1] = 128 - 32 + 1
+    with pytest.raises(P.PMACEError) as ei:
+        P.Reconstruction(128, 128, prob.probe, pos, prob.z, 0.5)
+    assert ei.value.status == P.PMACE_EINVAL
+    with pytest.raises(P.PMACEError) as ei:
+        P.Reconstruction(128, 128, prob.probe, prob.pos, prob.z, 0.5,
+                         workspace=torch.empty(1024, dtype=torch.uint8, device="cuda"))
+    assert ei.value.status == P.PMACE_ENOMEM
+
+
+def test_centered_dc_layout(P):
+    prob = synth.make_problem(160, 64, 4, 30, 1e5, 8)
+    zc = np.fft.fftshift(prob.z, axes=(-2, -1))
+    A = P.Reconstruction(160, 160, prob.probe, prob.pos, prob.z, 0.5)
+    B = P.Reconstruction(160, 160, prob.probe, prob.pos, zc, 0.5, flags=P.PMACE_CENTERED_DC)
+    A.iterate(3)
+    B.iterate(3)
+    assert rel(B.get_state().cpu().numpy(), A.get_state().cpu().numpy()) < 1e-6
+
+
+@pytest.mark.slow
+def test_c3_full_size_steps(P):
+    """The full 1024^2 / Np 256 / 1600-position workload in the launch
+    configuration the benchmark times: the first pass from the default start
+    and a teacher-forced second pass, on every patch."""
+    prob = synth.make_config_problem("c3")
+    alpha = 0.5
+    _say("c3: oracle, 2 passes")
+    vs, xs = oracle_trajectory(prob, alpha, synth.KAPPA, synth.RHO, 2)
+    tol0 = max(TOL, 3.0 * single_precision_step_error(prob, vs[0], alpha, synth.KAPPA, synth.RHO))
+    _say(f"c3: device, tol0={tol0:.2e}")
+    R = make_recon(P, prob, alpha)
+    R.iterate(1)
+    e0 = rel(R.get_state().cpu().numpy(), vs[1])
+    ex0 = rel(R.reconstruct().cpu().numpy(), xs[1])
+    _say(f"  k=0 rel(v)={e0:.2e} rel(xhat)={ex0:.2e}")
+    assert e0 < tol0 and ex0 < tol0
+    R.set_state(vs[1])
+    R.iterate(1)
+    e1 = rel(R.get_state().cpu().numpy(), vs[2])
+    ex1 = rel(R.reconstruct().cpu().numpy(), xs[2])
+    _say(f"  k=1 rel(v)={e1:.2e} rel(xhat)={ex1:.2e}")
+    assert e1 < TOL and ex1 < TOL
+    R.close()
