@@ -57,6 +57,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--chunk", type=int, default=0, help="Np=256 staging chunk (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -74,7 +75,7 @@ def main():
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):
         R = pmace.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, alpha, kappa, rho,
-                                 device=dev, stream=stream)
+                                 device=dev, stream=stream, chunk=args.chunk)
         R.iterate(args.warmup)
         R.sync()
         torch.cuda.synchronize()
@@ -117,7 +118,7 @@ def main():
         "config": {"workload": f"{args.config}: object {prob.n1}x{prob.n2}, probe {np_}x{np_}, "
                                f"{J} positions ({cfg['scan']}x{cfg['scan']} raster, step {cfg['step']} px), "
                                f"Poisson peak {cfg['peak']}",
-                   "alpha": alpha, "kappa": kappa, "rho": rho,
+                   "alpha": alpha, "kappa": kappa, "rho": rho, "chunk": args.chunk,
                    "iteration_graph": "one HIP graph replay per step"},
         "roofline": {"bound": "hbm", "kernel": "one PMACE iteration (agent passes + image update)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -54,16 +54,17 @@ typedef struct {
   float kappa;        /* >= 0: probe exponent of the consensus weights, eq. (11) */
   float rho;          /* 0 < rho < 1: Mann averaging parameter, eq. (13) */
   uint32_t flags;     /* PMACE_CENTERED_DC or 0 */
-  int32_t chunk;      /* Np = 256 only: positions per staging chunk, 0 = library default */
+  int32_t chunk;      /* Np = 256 only: positions per staging chunk (>= 1, capped at J), 0 = 128 */
 } pmace_params;
 
 typedef struct pmace_ctx pmace_ctx;      /* one reconstruction */
 typedef struct pmace_batch pmace_batch;  /* several reconstructions stepped together */
 
 /* Bytes of device workspace one reconstruction needs (0 if params are invalid).
- * Layout: agent states J*Np^2*8, amplitudes J*Np^2*4, images 4*N1*N2*8-ish,
- * probe tables Np^2*24, positions J*8, and for Np = 256 a staging buffer of
- * chunk*Np^2*8 bytes; each section 256-byte aligned. */
+ * Layout: agent states J*Np^2*8, amplitudes J*Np^2*4, object images N1*N2*28,
+ * probe tables Np^2*24, positions J*8, a staging buffer of chunk*Np^2*8
+ * bytes (chunk = J for Np <= 128) and the consensus tile tables; each
+ * section 256-byte aligned. */
 size_t pmace_footprint(const pmace_params* params);
 
 /* Alg. 1 initialisation: v_j = P_j x0 for every j.  Also computes

@@ -5,6 +5,7 @@
 // eq. (11)), and replaying one captured iteration as a HIP graph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <complex>
 #include <cstdlib>
@@ -29,6 +30,7 @@ struct pmace_ctx {
   bool graph_ready;
   bool use_graph;
   pmace_status sticky;  // first asynchronous failure seen
+  std::vector<int4> chunk_info;  // per chunk: (first tile, tiles, first tile row, tiles per row)
 };
 
 namespace {
@@ -39,11 +41,28 @@ inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 bool np_supported(int np) { return np == 32 || np == 64 || np == 128 || np == 256; }
 
-int default_chunk(const pmace_params& p) {
-  if (p.np != 256) return 0;
-  int c = p.chunk > 0 ? p.chunk : 128;
+// Positions per chunk: Np <= 128 runs all positions in one fused launch;
+// Np = 256 stages chunk*Np^2 spectra between its three passes.
+int chunk_of(const pmace_params& p) {
+  int c = p.num_pos;
+  if (p.np == 256 && p.chunk > 0) c = p.chunk;
+  else if (p.np == 256) c = 128;
   if (c > p.num_pos) c = p.num_pos;
   return c;
+}
+
+int num_chunks(const pmace_params& p) {
+  const int c = chunk_of(p);
+  return (p.num_pos + c - 1) / c;
+}
+
+// Upper bounds of the gather tables (depend on sizes only, not on positions).
+size_t max_tiles(const pmace_params& p) {
+  return (size_t)num_chunks(p) * ((p.n1 + pmace::GT_R - 1) / pmace::GT_R) *
+         ((p.n2 + pmace::GT_C - 1) / pmace::GT_C);
+}
+size_t max_list(const pmace_params& p) {
+  return (size_t)p.num_pos * ((p.np - 1) / pmace::GT_R + 2) * ((p.np - 1) / pmace::GT_C + 2);
 }
 
 pmace_status check_params(const pmace_params* p) {
@@ -61,7 +80,7 @@ pmace_status check_params(const pmace_params* p) {
 
 // Section offsets inside the workspace (relative to the aligned base).
 struct Layout {
-  size_t t, ys, pos, d, pc, laminv, num, xbar, xhat, status, stage, total;
+  size_t t, ys, pos, d, pc, laminv, num, xbar, xhat, status, stage, tiles, list, total;
 };
 
 Layout layout_of(const pmace_params& p) {
@@ -80,7 +99,9 @@ Layout layout_of(const pmace_params& p) {
   L.xbar = o;    o = align_up(o + npx * 8);
   L.xhat = o;    o = align_up(o + npx * 8);
   L.status = o;  o = align_up(o + 16);
-  L.stage = o;   o = align_up(o + (size_t)default_chunk(p) * np2 * 8);
+  L.stage = o;   o = align_up(o + (size_t)chunk_of(p) * np2 * 8);
+  L.tiles = o;   o = align_up(o + max_tiles(p) * 8);
+  L.list = o;    o = align_up(o + max_list(p) * 4);
   L.total = o;
   return L;
 }
@@ -98,7 +119,6 @@ pmace_status record(pmace_ctx* c, pmace_status s) {
 
 pmace_status enqueue_iteration(pmace_ctx* c, hipStream_t st) {
   PM_HIP(pmace::launch_agent(c->s, st));
-  PM_HIP(pmace::launch_image_update(c->s, st));
   return PMACE_OK;
 }
 
@@ -224,19 +244,57 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   s.xhat = reinterpret_cast<float2*>(base + L.xhat);
   s.status = reinterpret_cast<unsigned*>(base + L.status);
   s.stage = reinterpret_cast<float2*>(base + L.stage);
+  s.tiles = reinterpret_cast<int2*>(base + L.tiles);
+  s.tile_list = reinterpret_cast<int*>(base + L.list);
   s.n1 = n1;
   s.n2 = n2;
   s.np = np;
   s.J = J;
   s.a = p.alpha / (1.f + p.alpha);
   s.rho = p.rho;
-  s.chunk = default_chunk(p);
+  s.chunk = chunk_of(p);
+  // Gather tables: per chunk, GT_R x GT_C tiles over the rows its patches
+  // cover, each with the chunk's positions overlapping it in ascending order.
+  std::vector<int2> tiles;
+  std::vector<int> list;
+  {
+    const int nch = num_chunks(p);
+    const int tiles_c = (n2 + pmace::GT_C - 1) / pmace::GT_C;
+    c->chunk_info.resize(nch);
+    std::vector<std::vector<int>> per_tile;
+    for (int g = 0; g < nch; ++g) {
+      const int ja = g * s.chunk, jb = std::min(J, ja + s.chunk);
+      int lo = n1, hi = 0;
+      for (int j = ja; j < jb; ++j) {
+        lo = std::min(lo, pos[2 * j]);
+        hi = std::max(hi, pos[2 * j] + np);
+      }
+      const int tiles_r = (hi - lo + pmace::GT_R - 1) / pmace::GT_R;
+      per_tile.assign((size_t)tiles_r * tiles_c, {});
+      for (int j = ja; j < jb; ++j) {
+        const int r = pos[2 * j] - lo, cc = pos[2 * j + 1];
+        for (int tr = r / pmace::GT_R; tr <= (r + np - 1) / pmace::GT_R; ++tr)
+          for (int tc = cc / pmace::GT_C; tc <= (cc + np - 1) / pmace::GT_C; ++tc)
+            per_tile[(size_t)tr * tiles_c + tc].push_back(j);
+      }
+      c->chunk_info[g] = make_int4((int)tiles.size(), (int)per_tile.size(), lo, tiles_c);
+      for (auto& v : per_tile) {
+        tiles.push_back(make_int2((int)list.size(), (int)v.size()));
+        list.insert(list.end(), v.begin(), v.end());
+      }
+    }
+  }
+  if (tiles.size() > max_tiles(p) || list.size() > max_list(p)) { delete c; return PMACE_EDEVICE; }
+  s.chunk_info = c->chunk_info.data();
 
   auto fail = [&](pmace_status e) { delete c; return e; };
   if (hipMemcpyAsync(s.pos, pos.data(), (size_t)J * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(s.d, probe.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(s.pc, pc.data(), np2 * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(s.laminv, laminv.data(), npx * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(s.tiles, tiles.data(), tiles.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      (!list.empty() &&
+       hipMemcpyAsync(s.tile_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess) ||
       hipMemsetAsync(s.status, 0, 16, st) != hipSuccess)
     return fail(PMACE_EDEVICE);
   const float yscale = (float)((double)np / (1.0 + (double)p.alpha));

@@ -37,18 +37,16 @@ __device__ __forceinline__ float2 fourier_prox(float2 W, float ysv, float a) {
   return make_float2(W.x * g, W.y * g);
 }
 
-// Consensus contribution and state update for one pixel (a6-a8).
+// State update and consensus contribution for one pixel (a6-a8): w from the
+// inverse transform z (d^{-1} and the 1/Np^2 folded into pcf.xy; w = v where
+// d == 0), t <- v - 2 rho w, and the weighted reflection |d|^kappa (2w - v).
 __device__ __forceinline__ void finish_pixel(float2 z, float2 v, float4 pcf, float two_rho,
-                                             float2* t_out, float* num_px) {
-  // w = d^{-1} F^* U  (scale folded into pcf.xy), or v where d == 0
+                                             float2* t_out, float2* u_out) {
   float2 w = cmul(make_float2(pcf.x, pcf.y), z);
   w.x = fmaf(pcf.w, v.x, w.x);
   w.y = fmaf(pcf.w, v.y, w.y);
-  float2 tn = make_float2(fmaf(-two_rho, w.x, v.x), fmaf(-two_rho, w.y, v.y));
-  *t_out = tn;
-  const float ux = 2.f * w.x - v.x, uy = 2.f * w.y - v.y;
-  __hip_atomic_fetch_add(num_px, pcf.z * ux, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_fetch_add(num_px + 1, pcf.z * uy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  *t_out = make_float2(fmaf(-two_rho, w.x, v.x), fmaf(-two_rho, w.y, v.y));
+  *u_out = make_float2(pcf.z * (2.f * w.x - v.x), pcf.z * (2.f * w.y - v.y));
 }
 
 struct AgentArgs {
@@ -127,14 +125,14 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused(AgentArgs g) {
     for (int ka = 0; ka < A; ++ka) x[m * A + ka] = row[p + A * m + B * ka];
   row_inv<NP>(x, row, p, tw);
 
-  float* nrow = g.num + 2 * ((size_t)(pj.x + r) * g.n2 + pj.y);
+  float2* urow = g.stage + pb + (size_t)r * NP;
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) {
     const int cc = p + A * nb;
     const float2 tt = trow[cc];
     const float2 xb = xrow[cc];
     const float2 v = make_float2(fmaf(g.two_rho, xb.x, tt.x), fmaf(g.two_rho, xb.y, tt.y));
-    finish_pixel(x[nb], v, g.pc[r * NP + cc], g.two_rho, &trow[cc], nrow + 2 * cc);
+    finish_pixel(x[nb], v, g.pc[r * NP + cc], g.two_rho, &trow[cc], &urow[cc]);
   }
 }
 
@@ -214,22 +212,75 @@ __global__ void __launch_bounds__(RB * 16) agent256_rowsinv(AgentArgs g) {
   const int j = g.j0 + jl;
   const int2 pj = g.pos[j];
   const int rl = tid / A, p = tid % A, r = rb * RB + rl;
-  const float2* in = g.stage + ((size_t)jl * NP + r) * NP;
+  float2* io = g.stage + ((size_t)jl * NP + r) * NP;
   float2 x[16];
 #pragma unroll
-  for (int ka = 0; ka < 16; ++ka) x[ka] = in[p + 16 * ka];
+  for (int ka = 0; ka < 16; ++ka) x[ka] = io[p + 16 * ka];
   __syncthreads();
   row_inv<NP>(x, tile + rl * S, p, tw);
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   float2* trow = g.t + (size_t)j * NP * NP + (size_t)r * NP;
-  float* nrow = g.num + 2 * ((size_t)(pj.x + r) * g.n2 + pj.y);
 #pragma unroll
   for (int nb = 0; nb < 16; ++nb) {
     const int c = p + A * nb;
     const float2 tt = trow[c];
     const float2 xb = xrow[c];
     const float2 v = make_float2(fmaf(g.two_rho, xb.x, tt.x), fmaf(g.two_rho, xb.y, tt.y));
-    finish_pixel(x[nb], v, g.pc[r * NP + c], g.two_rho, &trow[c], nrow + 2 * c);
+    finish_pixel(x[nb], v, g.pc[r * NP + c], g.two_rho, &trow[c], &io[c]);
+  }
+}
+
+// Consensus (eq. (11)) without atomics.  Each thread owns one object pixel
+// of a GT_R x GT_C tile and adds the weighted reflections of the chunk's
+// patches that cover it, walking the tile's position list (built on the host,
+// ascending j).  Chunks run in order on the stream, so every pixel sums its
+// contributions in ascending j and the result is bitwise reproducible.
+// FUSE: a single chunk holds every position, so the sum is complete and a9
+// (xbar, xhat) is finished here.
+struct GatherArgs {
+  const float2* u;
+  const int2* pos;
+  const int2* tiles;
+  const int* list;
+  float2* num;
+  const float* laminv;
+  float2* xbar;
+  float2* xhat;
+  unsigned* status;
+  int tile0, r0, tiles_c, n1, n2, jbase;
+  float rho;
+};
+
+template <int NP, bool FUSE>
+__global__ void __launch_bounds__(GT_R * GT_C) consensus_gather(GatherArgs g) {
+  const int tid = threadIdx.x, bt = blockIdx.x;
+  const int2 ti = g.tiles[g.tile0 + bt];
+  const int R = g.r0 + (bt / g.tiles_c) * GT_R + tid / GT_C;
+  const int C = (bt % g.tiles_c) * GT_C + tid % GT_C;
+  float ax = 0.f, ay = 0.f;
+#pragma unroll 4
+  for (int i = 0; i < ti.y; ++i) {
+    const int j = g.list[ti.x + i];
+    const int2 pj = g.pos[j];
+    const unsigned rr = (unsigned)(R - pj.x), cc = (unsigned)(C - pj.y);
+    const bool in = rr < (unsigned)NP && cc < (unsigned)NP;
+    // lanes outside the patch read its first pixel and discard it
+    const float2 u = g.u[((size_t)(j - g.jbase) * NP + (in ? rr : 0u)) * NP + (in ? cc : 0u)];
+    ax += in ? u.x : 0.f;
+    ay += in ? u.y : 0.f;
+  }
+  if (R >= g.n1 || C >= g.n2) return;
+  const size_t px = (size_t)R * g.n2 + C;
+  if constexpr (FUSE) {
+    const float li = g.laminv[px];
+    const float2 xb = make_float2(ax * li, ay * li);
+    const float2 xh = g.xhat[px];
+    g.xbar[px] = xb;
+    g.xhat[px] = make_float2(fmaf(g.rho, xb.x - xh.x, xh.x), fmaf(g.rho, xb.y - xh.y, xh.y));
+    if (!(isfinite(xb.x) && isfinite(xb.y))) atomicOr(g.status, 1u);
+  } else {
+    const float2 o = g.num[px];
+    g.num[px] = make_float2(o.x + ax, o.y + ay);
   }
 }
 
@@ -317,22 +368,17 @@ __global__ void get_state_k(const float2* t, const float2* xbar, const int2* pos
   v[i] = make_float2(fmaf(two_rho, xb.x, tt.x), fmaf(two_rho, xb.y, tt.y));
 }
 
-// t <- v, and num += P_j^t |d|^kappa v_j
-__global__ void set_state_k(float2* t, const float2* v, const int2* pos, const float4* pc,
-                            float* num, int np, int n2, long long total) {
+// t <- v and u <- |d|^kappa v for positions [j0, j0 + cnt) (u indexed from j0)
+__global__ void set_state_k(float2* t, const float2* v, const float4* pc, float2* u, int np,
+                            int j0, long long cnt_px) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
+  if (i >= cnt_px) return;
   const long long per = (long long)np * np;
-  const int j = (int)(i / per);
-  const int rem = (int)(i - (long long)j * per);
-  const int r = rem / np, c = rem - r * np;
-  const int2 pj = pos[j];
-  const float2 vv = v[i];
-  t[i] = vv;
-  const float om = pc[rem].z;
-  float* px = num + 2 * ((size_t)(pj.x + r) * n2 + pj.y + c);
-  __hip_atomic_fetch_add(px, om * vv.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_fetch_add(px + 1, om * vv.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const long long gi = (long long)j0 * per + i;
+  const float2 vv = v[gi];
+  t[gi] = vv;
+  const float om = pc[i % per].z;
+  u[i] = make_float2(om * vv.x, om * vv.y);
 }
 
 __global__ void zero_c64_k(float2* a, int n) {
@@ -474,37 +520,65 @@ static AgentArgs agent_args(const DevState& s, int j0) {
 
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+static GatherArgs gather_args(const DevState& s, int g, int jbase) {
+  GatherArgs a;
+  const int4 ci = s.chunk_info[g];
+  a.u = s.stage;
+  a.pos = s.pos;
+  a.tiles = s.tiles;
+  a.list = s.tile_list;
+  a.num = reinterpret_cast<float2*>(s.num);
+  a.laminv = s.laminv;
+  a.xbar = s.xbar;
+  a.xhat = s.xhat;
+  a.status = s.status;
+  a.tile0 = ci.x;
+  a.r0 = ci.z;
+  a.tiles_c = ci.w;
+  a.n1 = s.n1;
+  a.n2 = s.n2;
+  a.jbase = jbase;
+  a.rho = s.rho;
+  return a;
+}
+
+template <int NP, bool FUSE>
+static void gather(const DevState& s, int g, int jbase, hipStream_t st) {
+  const int ntiles = s.chunk_info[g].y;
+  if (ntiles > 0)
+    hipLaunchKernelGGL((consensus_gather<NP, FUSE>), dim3(ntiles), dim3(GT_R * GT_C), 0, st,
+                       gather_args(s, g, jbase));
+}
+
 hipError_t launch_agent(const DevState& s, hipStream_t st) {
   const AgentArgs g = agent_args(s, 0);
   switch (s.np) {
-    case 32:
-      hipLaunchKernelGGL(agent_fused<32>, dim3(s.J), dim3(32 * Geo<32>::A), 0, st, g);
-      break;
-    case 64:
-      hipLaunchKernelGGL(agent_fused<64>, dim3(s.J), dim3(64 * Geo<64>::A), 0, st, g);
-      break;
-    case 128:
-      hipLaunchKernelGGL(agent_fused<128>, dim3(s.J), dim3(128 * Geo<128>::A), 0, st, g);
-      break;
-    case 256:
-      for (int j0 = 0; j0 < s.J; j0 += s.chunk) {
+#define PMACE_AGENT_SMALL(N)                                                        \
+  case N:                                                                           \
+    hipLaunchKernelGGL(agent_fused<N>, dim3(s.J), dim3(N * Geo<N>::A), 0, st, g);   \
+    gather<N, true>(s, 0, 0, st);                                                   \
+    break;
+    PMACE_AGENT_SMALL(32)
+    PMACE_AGENT_SMALL(64)
+    PMACE_AGENT_SMALL(128)
+#undef PMACE_AGENT_SMALL
+    case 256: {
+      for (int j0 = 0, gi = 0; j0 < s.J; j0 += s.chunk, ++gi) {
         const int cnt = (s.J - j0 < s.chunk) ? (s.J - j0) : s.chunk;
         const AgentArgs gc = agent_args(s, j0);
         hipLaunchKernelGGL(agent256_rows, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, gc);
         hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, gc);
         hipLaunchKernelGGL(agent256_rowsinv, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, gc);
+        gather<256, false>(s, gi, j0, st);
       }
+      const int npx = s.n1 * s.n2;
+      hipLaunchKernelGGL(image_update, dim3(blocks_for(npx, 256)), dim3(256), 0, st, s.xbar, s.xhat,
+                         reinterpret_cast<float2*>(s.num), s.laminv, npx, s.rho, s.status);
       break;
+    }
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_image_update(const DevState& s, hipStream_t st) {
-  const int npx = s.n1 * s.n2;
-  hipLaunchKernelGGL(image_update, dim3(blocks_for(npx, 256)), dim3(256), 0, st, s.xbar, s.xhat,
-                     reinterpret_cast<float2*>(s.num), s.laminv, npx, s.rho, s.status);
   return hipGetLastError();
 }
 
@@ -534,13 +608,22 @@ hipError_t launch_get_state(const DevState& s, float2* v, hipStream_t st) {
 }
 
 hipError_t launch_set_state(const DevState& s, const float2* v, hipStream_t st) {
-  const long long total = (long long)s.J * s.np * s.np;
   const int npx = s.n1 * s.n2;
+  const long long per = (long long)s.np * s.np;
   hipLaunchKernelGGL(zero_c64_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st,
                      reinterpret_cast<float2*>(s.num), npx);
   hipLaunchKernelGGL(zero_c64_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, s.xbar, npx);
-  hipLaunchKernelGGL(set_state_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, s.t, v, s.pos, s.pc,
-                     s.num, s.np, s.n2, total);
+  for (int j0 = 0, gi = 0; j0 < s.J; j0 += s.chunk, ++gi) {
+    const int cnt = (s.J - j0 < s.chunk) ? (s.J - j0) : s.chunk;
+    hipLaunchKernelGGL(set_state_k, dim3(blocks_for(cnt * per, 256)), dim3(256), 0, st, s.t, v, s.pc,
+                       s.stage, s.np, j0, cnt * per);
+    switch (s.np) {
+      case 32: gather<32, false>(s, gi, j0, st); break;
+      case 64: gather<64, false>(s, gi, j0, st); break;
+      case 128: gather<128, false>(s, gi, j0, st); break;
+      default: gather<256, false>(s, gi, j0, st); break;
+    }
+  }
   hipLaunchKernelGGL(image_from_num, dim3(blocks_for(npx, 256)), dim3(256), 0, st, s.xhat,
                      reinterpret_cast<float2*>(s.num), s.laminv, npx);
   return hipGetLastError();

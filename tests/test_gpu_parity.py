@@ -280,3 +280,19 @@ def test_c3_full_size_steps(P):
     _say(f"  k=1 rel(v)={e1:.2e} rel(xhat)={ex1:.2e}")
     assert e1 < TOL and ex1 < TOL
     R.close()
+
+
+@pytest.mark.parametrize("case", sorted(SMALL_CASES))
+def test_consensus_is_deterministic(P, case):
+    """The consensus sums contributions without atomics in a fixed order, so
+    two runs are bitwise identical."""
+    n, np_, scan, step, peak, seed, chunk = SMALL_CASES[case]
+    prob = synth.make_problem(n, np_, scan, step, peak, seed)
+    _say("determinism", case)
+    out = []
+    for _ in range(2):
+        R = make_recon(P, prob, 0.5, chunk=chunk)
+        R.iterate(3)
+        out.append((R.get_state().cpu().numpy(), R.reconstruct().cpu().numpy()))
+        R.close()
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
