@@ -115,6 +115,48 @@ void pmace_destroy(pmace_ctx* ctx);
 
 const char* pmace_status_str(pmace_status s);
 
+/* NRMSE tracking (eq. (17)): a reference object xref_d (n1*n2 c64, device)
+ * and an optional region mask_d (n1*n2 bytes, nonzero = inside; NULL = every
+ * pixel).  Both stay owned by the caller and must stay alive while the
+ * context (or a batch holding it) may read them; xref_d = NULL turns tracking
+ * off.  Resets the context's NRMSE history and stop flag; synchronises. */
+pmace_status pmace_set_reference(pmace_ctx* ctx, const void* xref_d, const uint8_t* mask_d);
+
+/* NRMSE of the current reconstruction against the reference:
+ * min over theta of ||xhat - e^{i theta} xref|| / ||xref|| over the region,
+ * with theta = arg sum conj(xref) xhat.  Synchronises; *out on the host.
+ * ESTATE if no reference is set. */
+pmace_status pmace_nrmse(pmace_ctx* ctx, double* out);
+
+/* Batches: several reconstructions on one device and stream advanced
+ * together, one HIP graph launch per iteration.  Positions of members with
+ * Np <= 128 share merged launches per patch size; Np = 256 members run as
+ * parallel branches.  After every iteration each member's NRMSE (against its
+ * reference, set before pmace_batch_create) is updated on the device, and a
+ * member stops (its kernels return at once) when |e_k - e_{k-1}| < tol after
+ * at least min_iter iterations, or after max_iter iterations (members
+ * without a reference stop at max_iter). */
+typedef struct {
+  float tol;        /* NRMSE change below which a member stops (e.g. 1e-4) */
+  int32_t min_iter; /* >= 0 */
+  int32_t max_iter; /* >= 1 */
+} pmace_stop_rule;
+
+/* Device workspace bytes a batch of these members needs (0 if invalid). */
+size_t pmace_batch_footprint(pmace_ctx* const* ctxs, int32_t n);
+/* Members must be distinct, on one device and stream.  The workspace is owned
+ * by the caller.  A member's stop flag and NRMSE history belong to the member
+ * (reset by pmace_set_reference), so a member moved into a new batch carries
+ * on where it stopped; pmace_iterate clears the stop flag. */
+pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_stop_rule* rule,
+                                void* workspace_d, size_t ws_bytes, pmace_batch** out);
+/* n_iter iterations of every member still running (stream-ordered, async). */
+pmace_status pmace_batch_step(pmace_batch* batch, int32_t n_iter);
+/* Synchronise and read back per member: stop flag, last NRMSE, iterations
+ * tracked by the stop rule.  Host arrays of n entries; any may be NULL. */
+pmace_status pmace_batch_poll(pmace_batch* batch, int32_t* done, double* nrmse, int32_t* iters);
+void pmace_batch_destroy(pmace_batch* batch);
+
 /* Batched 2-D orthonormal DFT of `count` np x np c64 arrays (the operator F
  * of Sec. II, or F^* when inverse != 0), in_d and out_d may alias.
  * np in {32, 64, 128, 256}.  Stream-ordered on hip_stream. */

@@ -11,10 +11,12 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmace.so")
 SOURCES = ["pmace_api.hip", "pmace_kernels.hip"]
 
-# Packed FP32 VALU forms are kept out of the generated code on purpose.
+# Packed FP32 VALU forms are kept out of the generated code on purpose, and
+# floating-point contraction is off: every fused multiply-add is written out in
+# the source, so all instantiations of a device function round identically.
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    "-munsafe-fp-atomics",
+    "-munsafe-fp-atomics", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]

@@ -2,7 +2,8 @@
 //
 // Host responsibilities: argument validation, the workspace layout, the FP64
 // tables computed once per reconstruction (|d|^kappa, d^{-1}, Lambda^{-1} of
-// eq. (11)), and replaying one captured iteration as a HIP graph.
+// eq. (11)), the consensus tile tables, and replaying iterations as HIP
+// graphs (one per reconstruction, one per batch).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,28 +17,69 @@
 #include "pmace.h"
 #include "pmace_internal.hpp"
 
-using pmace::DevState;
+using pmace::Recon;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+bool graphs_enabled() {
+  const char* e = std::getenv("PMACE_NO_GRAPH");
+  return !(e && e[0] == '1');
+}
+
+// A stream-ordered iteration captured once and replayed.
+struct Graph {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  void release() {
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+    x = nullptr;
+    g = nullptr;
+  }
+};
+
+}  // namespace
 
 struct pmace_ctx {
   pmace_params prm;
   hipStream_t stream;
   int device;
-  DevState s;
-  // one iteration captured as a graph and replayed on `stream`
-  hipStream_t cap_stream;
-  hipGraph_t graph;
-  hipGraphExec_t exec;
-  bool graph_ready;
-  bool use_graph;
-  pmace_status sticky;  // first asynchronous failure seen
-  std::vector<int4> chunk_info;  // per chunk: (first tile, tiles, first tile row, tiles per row)
+  Recon h;                        // host copy of the device descriptor
+  Recon* dev;                     // device descriptor (in the workspace)
+  int2* items;                    // device: (0, j) agent work items
+  int2* gitems;                   // device: (0, tile) gather work items
+  int2* ritems;                   // device: (0, b) NRMSE reduction items
+  int* fitem;                     // device: {0}
+  int ngitems;
+  std::vector<int2> chunk_tiles;  // host: per chunk (first gather item, count)
+  Graph graph;
+  bool graph_tried;
+  pmace_status sticky;            // first asynchronous failure seen
+};
+
+struct pmace_batch {
+  int n;
+  hipStream_t stream;
+  std::vector<pmace_ctx*> ctxs;
+  Recon* recs;                 // device: member descriptors
+  int2* items[3];              // device: agent items per class Np = 32, 64, 128
+  int nitems[3];
+  int2* gitems[3];             // device: gather items per class
+  int ngitems[3];
+  int2* ritems;                // device: (member, block) NRMSE items
+  int nritems;
+  int* fitems;                 // device: member indices
+  pmace_stop_rule rule;
+  hipStream_t lanes[4];
+  hipEvent_t fork, join[4];
+  Graph graph;
+  bool graph_tried;
 };
 
 namespace {
-
-constexpr size_t kAlign = 256;
-
-inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 bool np_supported(int np) { return np == 32 || np == 64 || np == 128 || np == 256; }
 
@@ -45,17 +87,14 @@ bool np_supported(int np) { return np == 32 || np == 64 || np == 128 || np == 25
 // Np = 256 stages chunk*Np^2 spectra between its three passes.
 int chunk_of(const pmace_params& p) {
   int c = p.num_pos;
-  if (p.np == 256 && p.chunk > 0) c = p.chunk;
-  else if (p.np == 256) c = 128;
+  if (p.np == 256) c = p.chunk > 0 ? p.chunk : 128;
   if (c > p.num_pos) c = p.num_pos;
   return c;
 }
-
 int num_chunks(const pmace_params& p) {
   const int c = chunk_of(p);
   return (p.num_pos + c - 1) / c;
 }
-
 // Upper bounds of the gather tables (depend on sizes only, not on positions).
 size_t max_tiles(const pmace_params& p) {
   return (size_t)num_chunks(p) * ((p.n1 + pmace::GT_R - 1) / pmace::GT_R) *
@@ -63,6 +102,9 @@ size_t max_tiles(const pmace_params& p) {
 }
 size_t max_list(const pmace_params& p) {
   return (size_t)p.num_pos * ((p.np - 1) / pmace::GT_R + 2) * ((p.np - 1) / pmace::GT_C + 2);
+}
+int num_red(const pmace_params& p) {
+  return (int)(((size_t)p.n1 * p.n2 + pmace::RED_PX - 1) / pmace::RED_PX);
 }
 
 pmace_status check_params(const pmace_params* p) {
@@ -80,7 +122,8 @@ pmace_status check_params(const pmace_params* p) {
 
 // Section offsets inside the workspace (relative to the aligned base).
 struct Layout {
-  size_t t, ys, pos, d, pc, laminv, num, xbar, xhat, status, stage, tiles, list, total;
+  size_t t, ys, pos, d, pc, laminv, num, xbar, xhat, stage, tiles, list, status, desc, items,
+      gitems, ritems, red, total;
 };
 
 Layout layout_of(const pmace_params& p) {
@@ -98,18 +141,23 @@ Layout layout_of(const pmace_params& p) {
   L.num = o;     o = align_up(o + npx * 8);
   L.xbar = o;    o = align_up(o + npx * 8);
   L.xhat = o;    o = align_up(o + npx * 8);
-  L.status = o;  o = align_up(o + 16);
   L.stage = o;   o = align_up(o + (size_t)chunk_of(p) * np2 * 8);
-  L.tiles = o;   o = align_up(o + max_tiles(p) * 8);
+  L.tiles = o;   o = align_up(o + max_tiles(p) * 16);
   L.list = o;    o = align_up(o + max_list(p) * 4);
+  L.status = o;  o = align_up(o + 64);  // status word, stop flag, finish item, NRMSE track[4]
+  L.desc = o;    o = align_up(o + sizeof(Recon));
+  L.items = o;   o = align_up(o + (size_t)p.num_pos * 8);
+  L.gitems = o;  o = align_up(o + max_tiles(p) * 8);
+  L.ritems = o;  o = align_up(o + (size_t)num_red(p) * 8);
+  L.red = o;     o = align_up(o + (size_t)num_red(p) * 32);
   L.total = o;
   return L;
 }
 
-#define PM_HIP(call)                                   \
-  do {                                                 \
-    hipError_t e_ = (call);                            \
-    if (e_ != hipSuccess) return PMACE_EDEVICE;        \
+#define PM_HIP(call)                            \
+  do {                                          \
+    hipError_t e_ = (call);                     \
+    if (e_ != hipSuccess) return PMACE_EDEVICE; \
   } while (0)
 
 pmace_status record(pmace_ctx* c, pmace_status s) {
@@ -118,22 +166,43 @@ pmace_status record(pmace_ctx* c, pmace_status s) {
 }
 
 pmace_status enqueue_iteration(pmace_ctx* c, hipStream_t st) {
-  PM_HIP(pmace::launch_agent(c->s, st));
+  if (c->prm.np == 256)
+    PM_HIP(pmace::launch_256_iteration(c->h, nullptr, c->chunk_tiles.data(), st));
+  else
+    PM_HIP(pmace::launch_small_iteration(c->prm.np, c->h, c->ngitems, st));
   return PMACE_OK;
 }
 
-pmace_status build_graph(pmace_ctx* c) {
-  PM_HIP(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-  PM_HIP(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  pmace_status s = enqueue_iteration(c, c->cap_stream);
-  hipGraph_t g = nullptr;
-  hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
-  if (s != PMACE_OK) return s;
-  if (e != hipSuccess || !g) return PMACE_EDEVICE;
-  c->graph = g;
-  PM_HIP(hipGraphInstantiate(&c->exec, g, nullptr, nullptr, 0));
-  c->graph_ready = true;
-  return PMACE_OK;
+// Capture `body(stream)` into g (on a private capture stream; the graph is
+// then launched on the caller's stream).
+template <class F>
+pmace_status capture(Graph& g, F body) {
+  hipStream_t cs = nullptr;
+  PM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  pmace_status s = PMACE_OK;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    s = PMACE_EDEVICE;
+  } else {
+    s = body(cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &graph);
+    if (s == PMACE_OK && (e != hipSuccess || !graph)) s = PMACE_EDEVICE;
+    if (s == PMACE_OK && hipGraphInstantiate(&g.x, graph, nullptr, nullptr, 0) != hipSuccess)
+      s = PMACE_EDEVICE;
+    g.g = graph;
+    if (s != PMACE_OK) g.release();
+  }
+  (void)hipStreamDestroy(cs);
+  return s;
+}
+
+// Reset the stop flag and the NRMSE history of a reconstruction.
+__global__ void reset_tracking_k(int* done, double* track) {
+  *done = 0;
+  track[0] = 0.0;
+  track[1] = __builtin_inf();
+  track[2] = __builtin_inf();
+  track[3] = 0.0;
 }
 
 }  // namespace
@@ -195,7 +264,6 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
     const std::complex<double> dd(probe[i].real(), probe[i].imag());
     const double mag = std::abs(dd);
     omega[i] = std::pow(mag, (double)p.kappa);
-    if (mag == 0.0) omega[i] = (p.kappa == 0.f) ? 1.0 : 0.0;
     std::complex<double> di(0.0, 0.0);
     if (mag != 0.0) di = inv_np2 / dd;
     pc[4 * i + 0] = (float)di.real();
@@ -215,55 +283,18 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   std::vector<float> laminv(npx);
   for (size_t i = 0; i < npx; ++i) laminv[i] = lam[i] != 0.0 ? (float)(1.0 / lam[i]) : 0.f;
 
-  pmace_ctx* c = new (std::nothrow) pmace_ctx();
-  if (!c) return PMACE_ENOMEM;
-  c->prm = p;
-  c->stream = st;
-  c->sticky = PMACE_OK;
-  c->graph_ready = false;
-  c->cap_stream = nullptr;
-  c->graph = nullptr;
-  c->exec = nullptr;
-  {
-    const char* e = std::getenv("PMACE_NO_GRAPH");
-    c->use_graph = !(e && e[0] == '1');
-  }
-  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return PMACE_EDEVICE; }
-
-  const Layout L = layout_of(p);
-  char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(workspace_d)));
-  DevState& s = c->s;
-  s.t = reinterpret_cast<float2*>(base + L.t);
-  s.ys = reinterpret_cast<float*>(base + L.ys);
-  s.pos = reinterpret_cast<int2*>(base + L.pos);
-  s.d = reinterpret_cast<float2*>(base + L.d);
-  s.pc = reinterpret_cast<float4*>(base + L.pc);
-  s.laminv = reinterpret_cast<float*>(base + L.laminv);
-  s.num = reinterpret_cast<float*>(base + L.num);
-  s.xbar = reinterpret_cast<float2*>(base + L.xbar);
-  s.xhat = reinterpret_cast<float2*>(base + L.xhat);
-  s.status = reinterpret_cast<unsigned*>(base + L.status);
-  s.stage = reinterpret_cast<float2*>(base + L.stage);
-  s.tiles = reinterpret_cast<int2*>(base + L.tiles);
-  s.tile_list = reinterpret_cast<int*>(base + L.list);
-  s.n1 = n1;
-  s.n2 = n2;
-  s.np = np;
-  s.J = J;
-  s.a = p.alpha / (1.f + p.alpha);
-  s.rho = p.rho;
-  s.chunk = chunk_of(p);
   // Gather tables: per chunk, GT_R x GT_C tiles over the rows its patches
   // cover, each with the chunk's positions overlapping it in ascending order.
-  std::vector<int2> tiles;
+  const int chunk = chunk_of(p);
+  const int nch = num_chunks(p);
+  const int tiles_c = (n2 + pmace::GT_C - 1) / pmace::GT_C;
+  std::vector<int4> tiles;
   std::vector<int> list;
+  std::vector<int2> gitems, chunk_tiles(nch);
   {
-    const int nch = num_chunks(p);
-    const int tiles_c = (n2 + pmace::GT_C - 1) / pmace::GT_C;
-    c->chunk_info.resize(nch);
     std::vector<std::vector<int>> per_tile;
     for (int g = 0; g < nch; ++g) {
-      const int ja = g * s.chunk, jb = std::min(J, ja + s.chunk);
+      const int ja = g * chunk, jb = std::min(J, ja + chunk);
       int lo = n1, hi = 0;
       for (int j = ja; j < jb; ++j) {
         lo = std::min(lo, pos[2 * j]);
@@ -277,33 +308,97 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
           for (int tc = cc / pmace::GT_C; tc <= (cc + np - 1) / pmace::GT_C; ++tc)
             per_tile[(size_t)tr * tiles_c + tc].push_back(j);
       }
-      c->chunk_info[g] = make_int4((int)tiles.size(), (int)per_tile.size(), lo, tiles_c);
-      for (auto& v : per_tile) {
-        tiles.push_back(make_int2((int)list.size(), (int)v.size()));
-        list.insert(list.end(), v.begin(), v.end());
+      chunk_tiles[g] = make_int2((int)gitems.size(), 0);
+      for (size_t t = 0; t < per_tile.size(); ++t) {
+        if (per_tile[t].empty()) continue;
+        const int tr = (int)(t / tiles_c), tc = (int)(t % tiles_c);
+        gitems.push_back(make_int2(0, (int)tiles.size()));
+        tiles.push_back(make_int4((int)list.size(), (int)per_tile[t].size(), lo + tr * pmace::GT_R,
+                                  tc * pmace::GT_C));
+        list.insert(list.end(), per_tile[t].begin(), per_tile[t].end());
       }
+      chunk_tiles[g].y = (int)gitems.size() - chunk_tiles[g].x;
     }
   }
-  if (tiles.size() > max_tiles(p) || list.size() > max_list(p)) { delete c; return PMACE_EDEVICE; }
-  s.chunk_info = c->chunk_info.data();
+  if (tiles.size() > max_tiles(p) || list.size() > max_list(p)) return PMACE_EDEVICE;
+  std::vector<int2> items(J);
+  for (int j = 0; j < J; ++j) items[j] = make_int2(0, j);
+  const int nred = num_red(p);
+  std::vector<int2> ritems(nred);
+  for (int b = 0; b < nred; ++b) ritems[b] = make_int2(0, b);
 
+  pmace_ctx* c = new (std::nothrow) pmace_ctx();
+  if (!c) return PMACE_ENOMEM;
+  c->prm = p;
+  c->stream = st;
+  c->sticky = PMACE_OK;
+  c->graph_tried = false;
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return PMACE_EDEVICE; }
+
+  const Layout L = layout_of(p);
+  char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(workspace_d)));
+  Recon& h = c->h;
+  std::memset(&h, 0, sizeof(Recon));
+  h.t = reinterpret_cast<float2*>(base + L.t);
+  h.ys = reinterpret_cast<float*>(base + L.ys);
+  h.pos = reinterpret_cast<int2*>(base + L.pos);
+  h.d = reinterpret_cast<float2*>(base + L.d);
+  h.pc = reinterpret_cast<float4*>(base + L.pc);
+  h.laminv = reinterpret_cast<float*>(base + L.laminv);
+  h.num = reinterpret_cast<float2*>(base + L.num);
+  h.xbar = reinterpret_cast<float2*>(base + L.xbar);
+  h.xhat = reinterpret_cast<float2*>(base + L.xhat);
+  h.stage = reinterpret_cast<float2*>(base + L.stage);
+  h.tiles = reinterpret_cast<int4*>(base + L.tiles);
+  h.tile_list = reinterpret_cast<int*>(base + L.list);
+  h.status = reinterpret_cast<unsigned*>(base + L.status);
+  h.done = reinterpret_cast<int*>(base + L.status + 4);
+  c->fitem = reinterpret_cast<int*>(base + L.status + 8);
+  h.track = reinterpret_cast<double*>(base + L.status + 32);
+  h.red = reinterpret_cast<double*>(base + L.red);
+  h.xref = nullptr;
+  h.mask = nullptr;
+  h.n1 = n1;
+  h.n2 = n2;
+  h.np = np;
+  h.J = J;
+  h.a = p.alpha / (1.f + p.alpha);
+  h.two_rho = 2.f * p.rho;
+  h.rho = p.rho;
+  h.chunk = chunk;
+  h.n_red = nred;
+  c->dev = reinterpret_cast<Recon*>(base + L.desc);
+  c->items = reinterpret_cast<int2*>(base + L.items);
+  c->gitems = reinterpret_cast<int2*>(base + L.gitems);
+  c->ritems = reinterpret_cast<int2*>(base + L.ritems);
+  c->ngitems = (int)gitems.size();
+  c->chunk_tiles = chunk_tiles;
+
+  const int zero = 0;
   auto fail = [&](pmace_status e) { delete c; return e; };
-  if (hipMemcpyAsync(s.pos, pos.data(), (size_t)J * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(s.d, probe.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(s.pc, pc.data(), np2 * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(s.laminv, laminv.data(), npx * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(s.tiles, tiles.data(), tiles.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+  if (hipMemcpyAsync(h.pos, pos.data(), (size_t)J * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h.d, probe.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h.pc, pc.data(), np2 * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h.laminv, laminv.data(), npx * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h.tiles, tiles.data(), tiles.size() * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
       (!list.empty() &&
-       hipMemcpyAsync(s.tile_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess) ||
-      hipMemsetAsync(s.status, 0, 16, st) != hipSuccess)
+       hipMemcpyAsync(h.tile_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess) ||
+      hipMemcpyAsync(c->items, items.data(), items.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      (!gitems.empty() &&
+       hipMemcpyAsync(c->gitems, gitems.data(), gitems.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess) ||
+      hipMemcpyAsync(c->ritems, ritems.data(), ritems.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(c->fitem, &zero, 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemsetAsync(h.status, 0, 4, st) != hipSuccess ||
+      hipMemcpyAsync(c->dev, &c->h, sizeof(Recon), hipMemcpyHostToDevice, st) != hipSuccess)
     return fail(PMACE_EDEVICE);
+  hipLaunchKernelGGL(reset_tracking_k, dim3(1), dim3(1), 0, st, h.done, h.track);
   const float yscale = (float)((double)np / (1.0 + (double)p.alpha));
-  if (pmace::launch_init_amplitudes(s, intensity_d, yscale, (p.flags & PMACE_CENTERED_DC) ? 1 : 0,
-                                    st) != hipSuccess ||
-      pmace::launch_init_state(s, reinterpret_cast<const float2*>(x0_d), st) != hipSuccess)
+  if (hipGetLastError() != hipSuccess ||
+      pmace::launch_init(h, c->dev, intensity_d, yscale, (p.flags & PMACE_CENTERED_DC) ? 1 : 0,
+                         reinterpret_cast<const float2*>(x0_d), st) != hipSuccess)
     return fail(PMACE_EDEVICE);
   unsigned status = 0;
-  if (hipMemcpyAsync(&status, s.status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+  if (hipMemcpyAsync(&status, h.status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return fail(PMACE_EDEVICE);
   if (status & 2u) return fail(PMACE_EINVAL);
@@ -315,17 +410,15 @@ pmace_status pmace_iterate(pmace_ctx* c, int32_t n_iter) {
   if (!c) return PMACE_ESTATE;
   if (n_iter < 0) return PMACE_EINVAL;
   if (n_iter == 0) return PMACE_OK;
-  if (c->use_graph) {
-    if (!c->graph_ready) {
-      pmace_status s = build_graph(c);
-      if (s != PMACE_OK) {
-        c->use_graph = false;  // fall back to direct launches of the same kernels
-      }
-    }
+  // a stop flag left by a batch would make the kernels skip this reconstruction
+  if (hipMemsetAsync(c->h.done, 0, 4, c->stream) != hipSuccess) return record(c, PMACE_EDEVICE);
+  if (!c->graph_tried && graphs_enabled()) {
+    c->graph_tried = true;
+    (void)capture(c->graph, [&](hipStream_t cs) { return enqueue_iteration(c, cs); });
   }
   for (int k = 0; k < n_iter; ++k) {
-    if (c->use_graph && c->graph_ready) {
-      if (hipGraphLaunch(c->exec, c->stream) != hipSuccess) return record(c, PMACE_EDEVICE);
+    if (c->graph.x) {
+      if (hipGraphLaunch(c->graph.x, c->stream) != hipSuccess) return record(c, PMACE_EDEVICE);
     } else {
       pmace_status s = enqueue_iteration(c, c->stream);
       if (s != PMACE_OK) return record(c, s);
@@ -338,7 +431,7 @@ pmace_status pmace_reconstruct(pmace_ctx* c, void* xhat_d) {
   if (!c) return PMACE_ESTATE;
   if (!xhat_d) return PMACE_EINVAL;
   const size_t bytes = (size_t)c->prm.n1 * c->prm.n2 * 8;
-  if (hipMemcpyAsync(xhat_d, c->s.xhat, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+  if (hipMemcpyAsync(xhat_d, c->h.xhat, bytes, hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
     return record(c, PMACE_EDEVICE);
   return PMACE_OK;
 }
@@ -346,7 +439,7 @@ pmace_status pmace_reconstruct(pmace_ctx* c, void* xhat_d) {
 pmace_status pmace_get_state(pmace_ctx* c, void* v_d) {
   if (!c) return PMACE_ESTATE;
   if (!v_d) return PMACE_EINVAL;
-  if (pmace::launch_get_state(c->s, reinterpret_cast<float2*>(v_d), c->stream) != hipSuccess)
+  if (pmace::launch_get_state(c->h, c->dev, reinterpret_cast<float2*>(v_d), c->stream) != hipSuccess)
     return record(c, PMACE_EDEVICE);
   return PMACE_OK;
 }
@@ -354,7 +447,32 @@ pmace_status pmace_get_state(pmace_ctx* c, void* v_d) {
 pmace_status pmace_set_state(pmace_ctx* c, const void* v_d) {
   if (!c) return PMACE_ESTATE;
   if (!v_d) return PMACE_EINVAL;
-  if (pmace::launch_set_state(c->s, reinterpret_cast<const float2*>(v_d), c->stream) != hipSuccess)
+  if (pmace::launch_set_state(c->h, c->dev, reinterpret_cast<const float2*>(v_d),
+                              c->chunk_tiles.data(), c->stream) != hipSuccess)
+    return record(c, PMACE_EDEVICE);
+  return PMACE_OK;
+}
+
+pmace_status pmace_set_reference(pmace_ctx* c, const void* xref_d, const uint8_t* mask_d) {
+  if (!c) return PMACE_ESTATE;
+  c->h.xref = const_cast<float2*>(reinterpret_cast<const float2*>(xref_d));
+  c->h.mask = xref_d ? const_cast<unsigned char*>(mask_d) : nullptr;
+  if (hipMemcpyAsync(c->dev, &c->h, sizeof(Recon), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return record(c, PMACE_EDEVICE);
+  hipLaunchKernelGGL(reset_tracking_k, dim3(1), dim3(1), 0, c->stream, c->h.done, c->h.track);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+    return record(c, PMACE_EDEVICE);
+  return PMACE_OK;
+}
+
+pmace_status pmace_nrmse(pmace_ctx* c, double* out) {
+  if (!c) return PMACE_ESTATE;
+  if (!out) return PMACE_EINVAL;
+  if (!c->h.xref) return PMACE_ESTATE;
+  if (pmace::launch_nrmse(c->dev, c->ritems, c->h.n_red, c->fitem, 1, 0, 0.f, 0, 0, c->stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(out, c->h.track + 1, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
     return record(c, PMACE_EDEVICE);
   return PMACE_OK;
 }
@@ -362,7 +480,7 @@ pmace_status pmace_set_state(pmace_ctx* c, const void* v_d) {
 pmace_status pmace_sync(pmace_ctx* c) {
   if (!c) return PMACE_ESTATE;
   unsigned status = 0;
-  if (hipMemcpyAsync(&status, c->s.status, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+  if (hipMemcpyAsync(&status, c->h.status, 4, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return record(c, PMACE_EDEVICE);
   if (c->sticky != PMACE_OK) return c->sticky;
@@ -372,10 +490,8 @@ pmace_status pmace_sync(pmace_ctx* c) {
 
 void pmace_destroy(pmace_ctx* c) {
   if (!c) return;
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
-  if (c->exec) (void)hipGraphExecDestroy(c->exec);
-  if (c->graph) (void)hipGraphDestroy(c->graph);
-  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  (void)hipStreamSynchronize(c->stream);
+  c->graph.release();
   delete c;
 }
 
@@ -388,6 +504,221 @@ pmace_status pmace_fft2(int32_t np, int32_t count, const void* in_d, void* out_d
                                     reinterpret_cast<float2*>(out_d), inverse ? 1 : 0,
                                     reinterpret_cast<hipStream_t>(hip_stream));
   return e == hipSuccess ? PMACE_OK : PMACE_EDEVICE;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+namespace {
+
+int class_of(int np) { return np == 32 ? 0 : np == 64 ? 1 : np == 128 ? 2 : -1; }
+
+struct BatchLayout {
+  size_t recs, items[3], gitems[3], ritems, fitems, total;
+  int nitems[3], ngitems[3], nritems;
+};
+
+BatchLayout batch_layout(pmace_ctx* const* ctxs, int n) {
+  BatchLayout L{};
+  for (int i = 0; i < n; ++i) {
+    const int k = class_of(ctxs[i]->prm.np);
+    if (k >= 0) {
+      L.nitems[k] += ctxs[i]->prm.num_pos;
+      L.ngitems[k] += ctxs[i]->ngitems;
+    }
+    L.nritems += ctxs[i]->h.n_red;
+  }
+  size_t o = 0;
+  L.recs = o;    o = align_up(o + (size_t)n * sizeof(Recon));
+  for (int k = 0; k < 3; ++k) {
+    L.items[k] = o;  o = align_up(o + (size_t)L.nitems[k] * 8);
+    L.gitems[k] = o; o = align_up(o + (size_t)L.ngitems[k] * 8);
+  }
+  L.ritems = o;  o = align_up(o + (size_t)L.nritems * 8);
+  L.fitems = o;  o = align_up(o + (size_t)n * 4);
+  L.total = o;
+  return L;
+}
+
+pmace_status check_members(pmace_ctx* const* ctxs, int32_t n) {
+  if (!ctxs || n < 1) return PMACE_EINVAL;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return PMACE_ESTATE;
+    if (ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->device != ctxs[0]->device) return PMACE_EINVAL;
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == ctxs[i]) return PMACE_EINVAL;
+  }
+  return PMACE_OK;
+}
+
+pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes) {
+  for (int k = 0; k < 3; ++k)
+    if (b->nitems[k] > 0)
+      PM_HIP(pmace::launch_small_batch(32 << k, b->recs, b->items[k], b->nitems[k], b->gitems[k],
+                                       b->ngitems[k], st));
+  // Np = 256 members: independent chains of kernels, spread over lanes
+  int lane = 0;
+  bool forked = false;
+  for (int i = 0; i < b->n; ++i) {
+    pmace_ctx* c = b->ctxs[i];
+    if (c->prm.np != 256) continue;
+    hipStream_t ls = st;
+    if (lanes) {
+      if (!forked) {
+        PM_HIP(hipEventRecord(b->fork, st));
+        for (int l = 0; l < 4; ++l) PM_HIP(hipStreamWaitEvent(b->lanes[l], b->fork, 0));
+        forked = true;
+      }
+      ls = b->lanes[lane];
+      lane = (lane + 1) % 4;
+    }
+    PM_HIP(pmace::launch_256_iteration(c->h, b->recs + i, c->chunk_tiles.data(), ls));
+  }
+  if (forked)
+    for (int l = 0; l < 4; ++l) {
+      PM_HIP(hipEventRecord(b->join[l], b->lanes[l]));
+      PM_HIP(hipStreamWaitEvent(st, b->join[l], 0));
+    }
+  PM_HIP(pmace::launch_nrmse(b->recs, b->ritems, b->nritems, b->fitems, b->n, 1, b->rule.tol,
+                             b->rule.min_iter, b->rule.max_iter, st));
+  return PMACE_OK;
+}
+
+void batch_release(pmace_batch* b) {
+  b->graph.release();
+  for (int l = 0; l < 4; ++l) {
+    if (b->lanes[l]) (void)hipStreamDestroy(b->lanes[l]);
+    if (b->join[l]) (void)hipEventDestroy(b->join[l]);
+  }
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pmace_batch_footprint(pmace_ctx* const* ctxs, int32_t n) {
+  if (check_members(ctxs, n) != PMACE_OK) return 0;
+  return batch_layout(ctxs, n).total + kAlign;
+}
+
+pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_stop_rule* rule,
+                                void* workspace_d, size_t ws_bytes, pmace_batch** out) {
+  if (!out) return PMACE_EINVAL;
+  *out = nullptr;
+  pmace_status ps = check_members(ctxs, n);
+  if (ps != PMACE_OK) return ps;
+  if (!rule || !workspace_d || rule->min_iter < 0 || rule->max_iter < 1 || !std::isfinite(rule->tol))
+    return PMACE_EINVAL;
+  const BatchLayout L = batch_layout(ctxs, n);
+  if (ws_bytes < L.total + kAlign) return PMACE_ENOMEM;
+  pmace_batch* b = new (std::nothrow) pmace_batch();
+  if (!b) return PMACE_ENOMEM;
+  b->n = n;
+  b->stream = ctxs[0]->stream;
+  b->ctxs.assign(ctxs, ctxs + n);
+  b->rule = *rule;
+  b->graph_tried = false;
+  char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(workspace_d)));
+  b->recs = reinterpret_cast<Recon*>(base + L.recs);
+  std::vector<Recon> recs(n);
+  std::vector<int2> items[3], gitems[3], ritems;
+  std::vector<int> fitems(n);
+  for (int i = 0; i < n; ++i) {
+    pmace_ctx* c = ctxs[i];
+    recs[i] = c->h;
+    fitems[i] = i;
+    for (int r = 0; r < c->h.n_red; ++r) ritems.push_back(make_int2(i, r));
+    const int k = class_of(c->prm.np);
+    if (k < 0) continue;
+    for (int j = 0; j < c->prm.num_pos; ++j) items[k].push_back(make_int2(i, j));
+    for (int t = 0; t < c->ngitems; ++t) gitems[k].push_back(make_int2(i, t));
+  }
+  for (int l = 0; l < 4; ++l) {
+    if (hipStreamCreateWithFlags(&b->lanes[l], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join[l], hipEventDisableTiming) != hipSuccess) {
+      batch_release(b);
+      return PMACE_EDEVICE;
+    }
+  }
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+    batch_release(b);
+    return PMACE_EDEVICE;
+  }
+  hipStream_t st = b->stream;
+  bool ok = hipMemcpyAsync(b->recs, recs.data(), (size_t)n * sizeof(Recon), hipMemcpyHostToDevice,
+                           st) == hipSuccess;
+  for (int k = 0; k < 3; ++k) {
+    b->items[k] = reinterpret_cast<int2*>(base + L.items[k]);
+    b->gitems[k] = reinterpret_cast<int2*>(base + L.gitems[k]);
+    b->nitems[k] = (int)items[k].size();
+    b->ngitems[k] = (int)gitems[k].size();
+    if (!items[k].empty())
+      ok = ok && hipMemcpyAsync(b->items[k], items[k].data(), items[k].size() * 8,
+                                hipMemcpyHostToDevice, st) == hipSuccess;
+    if (!gitems[k].empty())
+      ok = ok && hipMemcpyAsync(b->gitems[k], gitems[k].data(), gitems[k].size() * 8,
+                                hipMemcpyHostToDevice, st) == hipSuccess;
+  }
+  b->ritems = reinterpret_cast<int2*>(base + L.ritems);
+  b->nritems = (int)ritems.size();
+  b->fitems = reinterpret_cast<int*>(base + L.fitems);
+  ok = ok && hipMemcpyAsync(b->ritems, ritems.data(), ritems.size() * 8, hipMemcpyHostToDevice, st) ==
+                 hipSuccess;
+  ok = ok && hipMemcpyAsync(b->fitems, fitems.data(), (size_t)n * 4, hipMemcpyHostToDevice, st) ==
+                 hipSuccess;
+  ok = ok && hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) {
+    batch_release(b);
+    return PMACE_EDEVICE;
+  }
+  *out = b;
+  return PMACE_OK;
+}
+
+pmace_status pmace_batch_step(pmace_batch* b, int32_t n_iter) {
+  if (!b) return PMACE_ESTATE;
+  if (n_iter < 0) return PMACE_EINVAL;
+  if (!b->graph_tried && graphs_enabled()) {
+    b->graph_tried = true;
+    (void)capture(b->graph, [&](hipStream_t cs) { return enqueue_batch_iteration(b, cs, true); });
+  }
+  for (int k = 0; k < n_iter; ++k) {
+    if (b->graph.x) {
+      if (hipGraphLaunch(b->graph.x, b->stream) != hipSuccess) return PMACE_EDEVICE;
+    } else {
+      pmace_status s = enqueue_batch_iteration(b, b->stream, false);
+      if (s != PMACE_OK) return s;
+    }
+  }
+  return PMACE_OK;
+}
+
+pmace_status pmace_batch_poll(pmace_batch* b, int32_t* done, double* nrmse, int32_t* iters) {
+  if (!b) return PMACE_ESTATE;
+  std::vector<int> dn(b->n);
+  std::vector<double> tr(4 * (size_t)b->n);
+  for (int i = 0; i < b->n; ++i) {
+    if (hipMemcpyAsync(&dn[i], b->ctxs[i]->h.done, 4, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
+        hipMemcpyAsync(&tr[4 * i], b->ctxs[i]->h.track, 32, hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+      return PMACE_EDEVICE;
+  }
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return PMACE_EDEVICE;
+  for (int i = 0; i < b->n; ++i) {
+    if (done) done[i] = dn[i];
+    if (nrmse) nrmse[i] = tr[4 * i + 1];
+    if (iters) iters[i] = (int32_t)tr[4 * i + 3];
+  }
+  return PMACE_OK;
+}
+
+void pmace_batch_destroy(pmace_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->stream);
+  batch_release(b);
 }
 
 }  // extern "C"

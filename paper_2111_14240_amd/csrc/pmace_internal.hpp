@@ -7,40 +7,68 @@
 
 namespace pmace {
 
-// Device view of one reconstruction.  All pointers live in the caller's
-// workspace.
-struct DevState {
+// Gather tile of the consensus: GT_R x GT_C object pixels, one thread each.
+constexpr int GT_R = 16, GT_C = 64;
+// NRMSE reduction: RED_PX object pixels per block of RED_T threads.
+constexpr int RED_T = 256, RED_PX = 4096;
+
+// Device-resident description of one reconstruction.  It lives in the
+// reconstruction's workspace; batched launches read an array of them.
+struct Recon {
   float2* t;            // J*Np*Np   t_j = v_j - 2 rho w_j  (v_j = t_j + 2 rho P_j xbar)
   float* ys;            // J*Np*Np   Np*sqrt(z_j)/(1+alpha), DC at [0,0]
   int2* pos;            // J         (row, col) top-left of P_j
   float2* d;            // Np*Np     probe
   float4* pc;           // Np*Np     {Re, Im of d^{-1}/Np^2, |d|^kappa, [d == 0]}
   float* laminv;        // N1*N2     Lambda^{-1} (0 where Lambda = 0)
-  float* num;           // N1*N2*2   weighted back-projection accumulator
+  float2* num;          // N1*N2     weighted back-projection accumulator (Np = 256)
   float2* xbar;         // N1*N2     consensus image of the last iteration
   float2* xhat;         // N1*N2     reconstruction (Alg. 1 output, kept by recurrence)
-  unsigned* status;     // 1 word    bit0: non-finite consensus image; bit1: bad intensity
-  float2* stage;        // chunk*Np*Np: Np = 256 spectra being transformed; for every Np
-                        // the weighted reflections |d|^kappa (2w - v) the consensus sums
-  int2* tiles;          // per gather tile: (start, count) into tile_list
+  float2* stage;        // chunk*Np*Np: Np = 256 spectra between passes; for every Np the
+                        //   weighted reflections |d|^kappa (2w - v) the consensus sums
+  int4* tiles;          // per gather tile: (list start, count, first row, first col)
   int* tile_list;       // positions overlapping each tile, ascending
+  unsigned* status;     // bit0: non-finite consensus image; bit1: bad intensity
+  int* done;            // stop flag: nonzero = skip this reconstruction's work
+  float2* xref;         // NRMSE reference object, null if none
+  unsigned char* mask;  // NRMSE region (nonzero = inside), null = every pixel
+  double* red;          // per reduction block: {Re, Im sum conj(xref) xhat, sum |xhat|^2, sum |xref|^2}
+  double* track;        // {sum |xref|^2, last nrmse, previous nrmse, iterations tracked}
   int n1, n2, np, J;
   float a;              // alpha / (1 + alpha)
+  float two_rho;
   float rho;
   int chunk;            // positions per chunk (all J when Np <= 128)
-  const int4* chunk_info;  // host, per chunk: (first tile, tile count, first tile row, tiles per row)
+  int n_red;            // NRMSE reduction blocks
 };
 
-// Gather tile of the consensus: GT_R x GT_C object pixels, one thread each.
-constexpr int GT_R = 16, GT_C = 64;
-
-// Kernel launchers (stream-ordered; return the hipError_t of the launch).
-hipError_t launch_init_amplitudes(const DevState& s, const float* z, float scale, int centered,
-                                  hipStream_t st);
-hipError_t launch_init_state(const DevState& s, const float2* x0, hipStream_t st);
-hipError_t launch_agent(const DevState& s, hipStream_t st);  // one iteration: a2-a9
-hipError_t launch_get_state(const DevState& s, float2* v, hipStream_t st);
-hipError_t launch_set_state(const DevState& s, const float2* v, hipStream_t st);
+// Kernel launchers (stream-ordered; return the hipError_t of the launches).
+// `rec` / `recs` are device addresses of Recon descriptors, `h` a host copy.
+hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float scale, int centered,
+                       const float2* x0, hipStream_t st);
+// Np <= 128, one reconstruction: fused agent over its J positions, then the
+// fused gather + image update over its ntiles tiles.
+hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_t st);
+// Np <= 128, batched: agent over `items` (recon index, position) and the fused
+// gather + image update over `gitems` (recon index, tile).
+hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int nitems,
+                              const int2* gitems, int ngitems, hipStream_t st);
+// Np = 256, one reconstruction, chunk by chunk; chunk_tiles[g] = (first tile,
+// tile count) of chunk g (host array).  batch_rec: the member's device
+// descriptor when run inside a batch (its kernels honour the stop flag), else
+// null (descriptor passed by value).
+hipError_t launch_256_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
+                                hipStream_t st);
+hipError_t launch_get_state(const Recon& h, const Recon* rec, float2* v, hipStream_t st);
+hipError_t launch_set_state(const Recon& h, const Recon* rec, const float2* v,
+                            const int2* chunk_tiles, hipStream_t st);
+// a10: NRMSE of xhat against xref for the reconstructions in `ritems`
+// (recon index, reduction block); `fitems` lists the recon indices to finish.
+// With update_stop, the stop rule (|e_k - e_{k-1}| < tol after min_iter
+// tracked iterations, or max_iter reached) sets the done flag.
+hipError_t launch_nrmse(const Recon* recs, const int2* ritems, int nritems, const int* fitems,
+                        int nf, int update_stop, float tol, int min_iter, int max_iter,
+                        hipStream_t st);
 hipError_t launch_fft2(int np, int count, const float2* in, float2* out, int inverse, hipStream_t st);
 
 }  // namespace pmace

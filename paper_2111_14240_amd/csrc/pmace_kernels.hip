@@ -5,8 +5,8 @@
 //     w_j   = F_j(v_j)                                  (eq. (9), line 3)
 //     u_j   = 2 w_j - v_j                               (reflection, line 4)
 //     t_j  <- v_j - 2 rho w_j                           (first half of line 5)
-//     num  += P_j^t |d|^kappa u_j                       (numerator of eq. (11))
-// followed by  xbar = Lambda^{-1} num  and  xhat <- (1-rho) xhat + rho xbar.
+//     xbar  = Lambda^{-1} sum_j P_j^t |d|^kappa u_j     (eq. (11))
+//     xhat <- (1 - rho) xhat + rho xbar
 // Storing t instead of v is exact algebra of line 5 (v_new = t + 2 rho P_j xbar),
 // and the xhat recurrence is exact algebra of the returned weighted average
 // (the average of P_j xbar is xbar on covered pixels; the average of w is the
@@ -18,20 +18,18 @@
 // which is the r* of eq. (8) with the phase of W, so w = d^{-1} F^*(...) needs
 // one forward and one inverse 2-D DFT per patch.  Where d = 0, eq. (6) leaves
 // v free and the agent returns its input there.
+//
+// Every kernel reads its reconstruction from a device descriptor (Recon) and
+// returns at once when that reconstruction's stop flag is set, so many
+// reconstructions can share one launch (work items name the reconstruction).
 #include "pmace_dft.hpp"
 #include "pmace_internal.hpp"
 
 namespace pmace {
 
-// -------------------------------------------------------------------------
-// helpers
-// -------------------------------------------------------------------------
-
-__device__ __forceinline__ float2 ldg2(const float2* p) { return *p; }
-
 // Fourier-domain prox of eq. (9): U = W * (a + ys / |W|), 0 where W == 0.
 __device__ __forceinline__ float2 fourier_prox(float2 W, float ysv, float a) {
-  const float m2 = W.x * W.x + W.y * W.y;
+  const float m2 = fmaf(W.x, W.x, W.y * W.y);
   const float rs = m2 > 0.f ? __builtin_amdgcn_rsqf(m2) : 0.f;
   const float g = fmaf(ysv, rs, a);
   return make_float2(W.x * g, W.y * g);
@@ -46,50 +44,37 @@ __device__ __forceinline__ void finish_pixel(float2 z, float2 v, float4 pcf, flo
   w.x = fmaf(pcf.w, v.x, w.x);
   w.y = fmaf(pcf.w, v.y, w.y);
   *t_out = make_float2(fmaf(-two_rho, w.x, v.x), fmaf(-two_rho, w.y, v.y));
-  *u_out = make_float2(pcf.z * (2.f * w.x - v.x), pcf.z * (2.f * w.y - v.y));
+  *u_out = make_float2(pcf.z * fmaf(2.f, w.x, -v.x), pcf.z * fmaf(2.f, w.y, -v.y));
 }
 
-struct AgentArgs {
-  float2* t;
-  const float* ys;
-  const int2* pos;
-  const float2* d;
-  const float4* pc;
-  const float2* xbar;
-  float* num;
-  float2* stage;
-  int n2;
-  float a;
-  float two_rho;
-  int j0;
-};
+__device__ __forceinline__ float2 mann_v(float2 t, float2 xb, float two_rho) {
+  return make_float2(fmaf(two_rho, xb.x, t.x), fmaf(two_rho, xb.y, t.y));
+}
 
 // -------------------------------------------------------------------------
-// Np <= 128: the whole patch lives in LDS; one workgroup per position does
-// a2-a8 in one pass (rows, columns, prox, columns, rows, epilogue).
+// Np <= 128: the whole patch lives in LDS; one workgroup per work item
+// (reconstruction, position) does a2-a8 in one pass (rows, columns, prox,
+// columns, rows, epilogue).
 // -------------------------------------------------------------------------
 template <int NP>
-__global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused(AgentArgs g) {
+__device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, S = NP + A, NT = NP * A, M = B / A;
   __shared__ float2 tile[NP * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
   fill_twiddles<NP>(tw, tid, NT);
-  const int j = g.j0 + blockIdx.x;
   const int2 pj = g.pos[j];
   const size_t pb = (size_t)j * NP * NP;
   const int r = tid / A, p = tid % A;
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   float2* trow = g.t + pb + (size_t)r * NP;
+  const float two_rho = g.two_rho;
 
   float2 x[B];
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) {
     const int c = p + A * nb;
-    const float2 tt = trow[c];
-    const float2 xb = xrow[c];
-    const float2 v = make_float2(fmaf(g.two_rho, xb.x, tt.x), fmaf(g.two_rho, xb.y, tt.y));
-    x[nb] = cmul(g.d[r * NP + c], v);
+    x[nb] = cmul(g.d[r * NP + c], mann_v(trow[c], xrow[c], two_rho));
   }
   __syncthreads();
   float2* row = tile + r * S;
@@ -106,12 +91,13 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused(AgentArgs g) {
   for (int nb = 0; nb < B; ++nb) x[nb] = tile[(q + A * nb) * S + c];
   col_fwd<NP>(x, tile, S, c, q, tw);
   const float* yc = g.ys + pb + c;
+  const float a = g.a;
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
     for (int ka = 0; ka < A; ++ka) {
       const int k = q + A * m + B * ka;
-      x[m * A + ka] = fourier_prox(x[m * A + ka], yc[(size_t)k * NP], g.a);
+      x[m * A + ka] = fourier_prox(x[m * A + ka], yc[(size_t)k * NP], a);
     }
   col_inv<NP>(x, tile, S, c, q, tw);
   __syncthreads();
@@ -129,11 +115,25 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused(AgentArgs g) {
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) {
     const int cc = p + A * nb;
-    const float2 tt = trow[cc];
-    const float2 xb = xrow[cc];
-    const float2 v = make_float2(fmaf(g.two_rho, xb.x, tt.x), fmaf(g.two_rho, xb.y, tt.y));
-    finish_pixel(x[nb], v, g.pc[r * NP + cc], g.two_rho, &trow[cc], &urow[cc]);
+    const float2 v = mann_v(trow[cc], xrow[cc], two_rho);
+    finish_pixel(x[nb], v, g.pc[r * NP + cc], two_rho, &trow[cc], &urow[cc]);
   }
+}
+
+// One reconstruction (descriptor passed by value): block b handles position b.
+template <int NP>
+__global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused(const Recon g) {
+  agent_fused_body<NP>(g, blockIdx.x);
+}
+
+// Batched: block b handles work item (reconstruction, position) b.
+template <int NP>
+__global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused_batch(const Recon* __restrict__ recs,
+                                                                     const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  const Recon& g = recs[it.x];
+  if (*g.done) return;
+  agent_fused_body<NP>(g, it.y);
 }
 
 // -------------------------------------------------------------------------
@@ -142,20 +142,20 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused(AgentArgs g) {
 // a chunk-sized buffer that is reused every chunk:
 //   rows   : a2, a3, forward row DFTs            -> stage
 //   cols   : forward column DFTs, a5, inverse column DFTs (in place)
-//   rowsinv: inverse row DFTs, a6-a8
+//   rowsinv: inverse row DFTs, a6-a8; stage <- weighted reflections
 // -------------------------------------------------------------------------
 constexpr int NP256 = 256;
 constexpr int RB = 16;   // rows per workgroup in the row passes
 constexpr int CB = 16;   // columns per workgroup in the column pass
 
-__global__ void __launch_bounds__(RB * 16) agent256_rows(AgentArgs g) {
+__device__ __forceinline__ void agent256_rows_body(const Recon& g, const int j0) {
   constexpr int NP = NP256, A = 16, S = NP + A;
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
   fill_twiddles<NP>(tw, tid, RB * A);
   const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
-  const int j = g.j0 + jl;
+  const int j = j0 + jl;
   const int2 pj = g.pos[j];
   const int rl = tid / A, p = tid % A, r = rb * RB + rl;
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
@@ -164,10 +164,7 @@ __global__ void __launch_bounds__(RB * 16) agent256_rows(AgentArgs g) {
 #pragma unroll
   for (int nb = 0; nb < 16; ++nb) {
     const int c = p + A * nb;
-    const float2 tt = trow[c];
-    const float2 xb = xrow[c];
-    const float2 v = make_float2(fmaf(g.two_rho, xb.x, tt.x), fmaf(g.two_rho, xb.y, tt.y));
-    x[nb] = cmul(g.d[r * NP + c], v);
+    x[nb] = cmul(g.d[r * NP + c], mann_v(trow[c], xrow[c], g.two_rho));
   }
   __syncthreads();
   row_fwd<NP>(x, tile + rl * S, p, tw);
@@ -176,14 +173,21 @@ __global__ void __launch_bounds__(RB * 16) agent256_rows(AgentArgs g) {
   for (int ka = 0; ka < 16; ++ka) out[p + 16 * ka] = x[ka];
 }
 
-__global__ void __launch_bounds__(CB * 16) agent256_cols(AgentArgs g) {
+__global__ void __launch_bounds__(RB * 16) agent256_rows(const Recon g, int j0) { agent256_rows_body(g, j0); }
+
+__global__ void __launch_bounds__(RB * 16) agent256_rows_batch(const Recon* __restrict__ rec, int j0) {
+  if (*rec->done) return;
+  agent256_rows_body(*rec, j0);
+}
+
+__device__ __forceinline__ void agent256_cols_body(const Recon& g, const int j0) {
   constexpr int NP = NP256, A = 16;
   __shared__ float2 tile[NP * CB];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
   fill_twiddles<NP>(tw, tid, CB * A);
   const int jl = blockIdx.x / (NP / CB), cb = blockIdx.x % (NP / CB);
-  const int j = g.j0 + jl;
+  const int j = j0 + jl;
   const int c = tid % CB, q = tid / CB, col = cb * CB + c;
   float2* sp = g.stage + (size_t)jl * NP * NP + col;
   float2 x[16];
@@ -192,24 +196,32 @@ __global__ void __launch_bounds__(CB * 16) agent256_cols(AgentArgs g) {
   __syncthreads();
   col_fwd<NP>(x, tile, CB, c, q, tw);
   const float* yc = g.ys + (size_t)j * NP * NP + col;
+  const float a = g.a;
 #pragma unroll
   for (int ka = 0; ka < 16; ++ka) {
     const int k = q + 16 * ka;
-    x[ka] = fourier_prox(x[ka], yc[(size_t)k * NP], g.a);
+    x[ka] = fourier_prox(x[ka], yc[(size_t)k * NP], a);
   }
   col_inv<NP>(x, tile, CB, c, q, tw);
 #pragma unroll
   for (int nb = 0; nb < 16; ++nb) sp[(size_t)(q + A * nb) * NP] = x[nb];
 }
 
-__global__ void __launch_bounds__(RB * 16) agent256_rowsinv(AgentArgs g) {
+__global__ void __launch_bounds__(CB * 16) agent256_cols(const Recon g, int j0) { agent256_cols_body(g, j0); }
+
+__global__ void __launch_bounds__(CB * 16) agent256_cols_batch(const Recon* __restrict__ rec, int j0) {
+  if (*rec->done) return;
+  agent256_cols_body(*rec, j0);
+}
+
+__device__ __forceinline__ void agent256_rowsinv_body(const Recon& g, const int j0) {
   constexpr int NP = NP256, A = 16, S = NP + A;
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
   fill_twiddles<NP>(tw, tid, RB * A);
   const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
-  const int j = g.j0 + jl;
+  const int j = j0 + jl;
   const int2 pj = g.pos[j];
   const int rl = tid / A, p = tid % A, r = rb * RB + rl;
   float2* io = g.stage + ((size_t)jl * NP + r) * NP;
@@ -220,52 +232,46 @@ __global__ void __launch_bounds__(RB * 16) agent256_rowsinv(AgentArgs g) {
   row_inv<NP>(x, tile + rl * S, p, tw);
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   float2* trow = g.t + (size_t)j * NP * NP + (size_t)r * NP;
+  const float two_rho = g.two_rho;
 #pragma unroll
   for (int nb = 0; nb < 16; ++nb) {
     const int c = p + A * nb;
-    const float2 tt = trow[c];
-    const float2 xb = xrow[c];
-    const float2 v = make_float2(fmaf(g.two_rho, xb.x, tt.x), fmaf(g.two_rho, xb.y, tt.y));
-    finish_pixel(x[nb], v, g.pc[r * NP + c], g.two_rho, &trow[c], &io[c]);
+    const float2 v = mann_v(trow[c], xrow[c], two_rho);
+    finish_pixel(x[nb], v, g.pc[r * NP + c], two_rho, &trow[c], &io[c]);
   }
 }
 
-// Consensus (eq. (11)) without atomics.  Each thread owns one object pixel
-// of a GT_R x GT_C tile and adds the weighted reflections of the chunk's
-// patches that cover it, walking the tile's position list (built on the host,
-// ascending j).  Chunks run in order on the stream, so every pixel sums its
-// contributions in ascending j and the result is bitwise reproducible.
-// FUSE: a single chunk holds every position, so the sum is complete and a9
-// (xbar, xhat) is finished here.
-struct GatherArgs {
-  const float2* u;
-  const int2* pos;
-  const int2* tiles;
-  const int* list;
-  float2* num;
-  const float* laminv;
-  float2* xbar;
-  float2* xhat;
-  unsigned* status;
-  int tile0, r0, tiles_c, n1, n2, jbase;
-  float rho;
-};
+__global__ void __launch_bounds__(RB * 16) agent256_rowsinv(const Recon g, int j0) { agent256_rowsinv_body(g, j0); }
 
+__global__ void __launch_bounds__(RB * 16) agent256_rowsinv_batch(const Recon* __restrict__ rec, int j0) {
+  if (*rec->done) return;
+  agent256_rowsinv_body(*rec, j0);
+}
+
+// -------------------------------------------------------------------------
+// Consensus (eq. (11)) without atomics.  Each thread owns one object pixel
+// of a GT_R x GT_C tile and adds the weighted reflections of the patches
+// that cover it, walking the tile's position list (built on the host,
+// ascending j).  Np = 256 chunks run in order on the stream, so every pixel
+// sums its contributions in ascending j and the result is bitwise
+// reproducible.  FUSE (Np <= 128, every position in one chunk): the sum is
+// complete, so a9 (xbar, xhat) is finished here.  `jbase` is the first
+// position held in the stage buffer.
+// -------------------------------------------------------------------------
 template <int NP, bool FUSE>
-__global__ void __launch_bounds__(GT_R * GT_C) consensus_gather(GatherArgs g) {
-  const int tid = threadIdx.x, bt = blockIdx.x;
-  const int2 ti = g.tiles[g.tile0 + bt];
-  const int R = g.r0 + (bt / g.tiles_c) * GT_R + tid / GT_C;
-  const int C = (bt % g.tiles_c) * GT_C + tid % GT_C;
+__device__ __forceinline__ void consensus_gather_body(const Recon& g, const int tile, const int jbase) {
+  const int tid = threadIdx.x;
+  const int4 ti = g.tiles[tile];
+  const int R = ti.z + tid / GT_C, C = ti.w + tid % GT_C;
   float ax = 0.f, ay = 0.f;
 #pragma unroll 4
   for (int i = 0; i < ti.y; ++i) {
-    const int j = g.list[ti.x + i];
+    const int j = g.tile_list[ti.x + i];
     const int2 pj = g.pos[j];
     const unsigned rr = (unsigned)(R - pj.x), cc = (unsigned)(C - pj.y);
     const bool in = rr < (unsigned)NP && cc < (unsigned)NP;
     // lanes outside the patch read its first pixel and discard it
-    const float2 u = g.u[((size_t)(j - g.jbase) * NP + (in ? rr : 0u)) * NP + (in ? cc : 0u)];
+    const float2 u = g.stage[((size_t)(j - jbase) * NP + (in ? rr : 0u)) * NP + (in ? cc : 0u)];
     ax += in ? u.x : 0.f;
     ay += in ? u.y : 0.f;
   }
@@ -284,106 +290,215 @@ __global__ void __launch_bounds__(GT_R * GT_C) consensus_gather(GatherArgs g) {
   }
 }
 
-// -------------------------------------------------------------------------
-// a9: consensus image and reconstruction recurrence, accumulator reset.
-// -------------------------------------------------------------------------
-__global__ void image_update(float2* xbar, float2* xhat, float2* num, const float* laminv, int npx,
-                             float rho, unsigned* status) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npx) return;
-  const float li = laminv[i];
-  const float2 n = num[i];
-  const float2 xb = make_float2(n.x * li, n.y * li);
-  const float2 xh = xhat[i];
-  xbar[i] = xb;
-  xhat[i] = make_float2(fmaf(rho, xb.x - xh.x, xh.x), fmaf(rho, xb.y - xh.y, xh.y));
-  num[i] = make_float2(0.f, 0.f);
-  if (!(isfinite(xb.x) && isfinite(xb.y))) atomicOr(status, 1u);
+// One reconstruction: block b handles tile first_tile + b.
+template <int NP, bool FUSE>
+__global__ void __launch_bounds__(GT_R * GT_C) consensus_gather(const Recon g, int first_tile,
+                                                                int jbase) {
+  consensus_gather_body<NP, FUSE>(g, first_tile + blockIdx.x, jbase);
 }
 
-// xhat = Lambda^{-1} num, num <- 0 (reconstruction from a set state)
-__global__ void image_from_num(float2* xhat, float2* num, const float* laminv, int npx) {
+// One batch member (descriptor in device memory): block b handles tile first_tile + b.
+template <int NP, bool FUSE>
+__global__ void __launch_bounds__(GT_R * GT_C) consensus_gather_member(const Recon* __restrict__ rec,
+                                                                       int first_tile, int jbase) {
+  if (*rec->done) return;
+  consensus_gather_body<NP, FUSE>(*rec, first_tile + blockIdx.x, jbase);
+}
+
+// Batched: block b handles work item (reconstruction, tile) b.
+template <int NP, bool FUSE>
+__global__ void __launch_bounds__(GT_R * GT_C) consensus_gather_batch(const Recon* __restrict__ recs,
+                                                                      const int2* __restrict__ items,
+                                                                      int jbase) {
+  const int2 it = items[blockIdx.x];
+  const Recon& g = recs[it.x];
+  if (*g.done) return;
+  consensus_gather_body<NP, FUSE>(g, it.y, jbase);
+}
+
+// a9 for Np = 256: consensus image, reconstruction recurrence, accumulator reset.
+__device__ __forceinline__ void image_update_body(const Recon& g) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npx) return;
-  const float li = laminv[i];
-  const float2 n = num[i];
-  xhat[i] = make_float2(n.x * li, n.y * li);
-  num[i] = make_float2(0.f, 0.f);
+  if (i >= g.n1 * g.n2) return;
+  const float li = g.laminv[i];
+  const float2 n = g.num[i];
+  const float2 xb = make_float2(n.x * li, n.y * li);
+  const float2 xh = g.xhat[i];
+  g.xbar[i] = xb;
+  g.xhat[i] = make_float2(fmaf(g.rho, xb.x - xh.x, xh.x), fmaf(g.rho, xb.y - xh.y, xh.y));
+  g.num[i] = make_float2(0.f, 0.f);
+  if (!(isfinite(xb.x) && isfinite(xb.y))) atomicOr(g.status, 1u);
+}
+
+__global__ void image_update(const Recon g) { image_update_body(g); }
+
+__global__ void image_update_batch(const Recon* __restrict__ rec) {
+  if (*rec->done) return;
+  image_update_body(*rec);
+}
+
+// xhat = Lambda^{-1} num, num <- 0 (reconstruction of a state set from outside)
+__global__ void image_from_num(const Recon* __restrict__ rec) {
+  const Recon& g = *rec;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n1 * g.n2) return;
+  const float li = g.laminv[i];
+  const float2 n = g.num[i];
+  g.xhat[i] = make_float2(n.x * li, n.y * li);
+  g.num[i] = make_float2(0.f, 0.f);
+}
+
+// -------------------------------------------------------------------------
+// a10: NRMSE (eq. (17)) of xhat against a reference, per reconstruction.
+// theta = arg sum conj(xref) xhat minimises the numerator, so
+//   e^2 = (sum |xhat|^2 + sum |xref|^2 - 2 |sum conj(xref) xhat|) / sum |xref|^2.
+// Two deterministic stages: per-block FP64 partial sums, then one block per
+// reconstruction sums the partials in a fixed order.
+// -------------------------------------------------------------------------
+// update_stop = 0 evaluates on demand, also for stopped reconstructions.
+__global__ void __launch_bounds__(RED_T) nrmse_partial(const Recon* __restrict__ recs,
+                                                       const int2* __restrict__ items, int update_stop) {
+  const int2 it = items[blockIdx.x];
+  const Recon& g = recs[it.x];
+  if ((update_stop && *g.done) || !g.xref) return;
+  const int npx = g.n1 * g.n2;
+  const int base = it.y * RED_PX;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < RED_PX; k += RED_T) {
+    const int i = base + k;
+    if (i < npx && (!g.mask || g.mask[i])) {
+      const float2 xr = g.xref[i], xh = g.xhat[i];
+      acc[0] += (double)xr.x * xh.x + (double)xr.y * xh.y;   // Re conj(xref) xhat
+      acc[1] += (double)xr.x * xh.y - (double)xr.y * xh.x;   // Im conj(xref) xhat
+      acc[2] += (double)xh.x * xh.x + (double)xh.y * xh.y;   // |xhat|^2
+      acc[3] += (double)xr.x * xr.x + (double)xr.y * xr.y;   // |xref|^2
+    }
+  }
+  __shared__ double sh[4][RED_T];
+  for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int w = RED_T / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 4; ++q) g.red[4 * it.y + q] = sh[q][0];
+}
+
+__global__ void __launch_bounds__(RED_T) nrmse_finish(const Recon* __restrict__ recs,
+                                                      const int* __restrict__ items, int update_stop,
+                                                      float tol, int min_iter, int max_iter) {
+  const Recon& g = recs[items[blockIdx.x]];
+  if (update_stop && *g.done) return;
+  double e = 0.0, prev = 0.0;
+  if (g.xref) {
+    __shared__ double sh[4][RED_T];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < g.n_red; b += RED_T)
+      for (int q = 0; q < 4; ++q) acc[q] += g.red[4 * b + q];
+    for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = acc[q];
+    __syncthreads();
+    for (int w = RED_T / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w)
+        for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double sref = sh[3][0];
+    const double c = sqrt(sh[0][0] * sh[0][0] + sh[1][0] * sh[1][0]);
+    const double e2 = (sh[2][0] + sref - 2.0 * c) / (sref > 0.0 ? sref : 1.0);
+    e = sqrt(e2 > 0.0 ? e2 : 0.0);
+    prev = g.track[1];
+    g.track[0] = sref;
+    g.track[2] = prev;
+    g.track[1] = e;
+  }
+  if (threadIdx.x != 0 || !update_stop) return;
+  // stop rule: NRMSE change below tol after min_iter tracked iterations (only
+  // with a reference), or max_iter iterations
+  const double k = g.track[3] + 1.0;
+  g.track[3] = k;
+  const bool settled = g.xref && k >= (double)min_iter && fabs(e - prev) < (double)tol;
+  if (settled || k >= (double)max_iter) *g.done = 1;
 }
 
 // -------------------------------------------------------------------------
 // init / state kernels
 // -------------------------------------------------------------------------
-__global__ void init_amplitudes_k(const float* z, float* ys, int np, long long total, float scale,
-                                  int centered, unsigned* status) {
+__global__ void init_amplitudes_k(const Recon* __restrict__ rec, const float* z, float scale,
+                                  int centered) {
+  const Recon& g = *rec;
+  const long long per = (long long)g.np * g.np;
+  const long long total = per * g.J;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   long long src = i;
   if (centered) {
-    const long long per = (long long)np * np;
     const long long j = i / per;
     const int rem = (int)(i - j * per);
-    const int k = rem / np, l = rem - k * np;
-    const int h = np / 2;
-    src = j * per + (long long)((k + h) % np) * np + (l + h) % np;
+    const int k = rem / g.np, l = rem - k * g.np;
+    const int h = g.np / 2;
+    src = j * per + (long long)((k + h) % g.np) * g.np + (l + h) % g.np;
   }
   const float zz = z[src];
-  if (!(zz >= 0.f) || isinf(zz)) atomicOr(status, 2u);
-  ys[i] = scale * sqrtf(fmaxf(zz, 0.f));
+  if (!(zz >= 0.f) || isinf(zz)) atomicOr(g.status, 2u);
+  g.ys[i] = scale * sqrtf(fmaxf(zz, 0.f));
 }
 
-__global__ void init_patches_k(float2* t, const float2* x0, const int2* pos, int np, int n2,
-                               long long total) {
+__global__ void init_patches_k(const Recon* __restrict__ rec, const float2* x0) {
+  const Recon& g = *rec;
+  const long long per = (long long)g.np * g.np;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const long long per = (long long)np * np;
+  if (i >= per * g.J) return;
   const int j = (int)(i / per);
   const int rem = (int)(i - (long long)j * per);
-  const int r = rem / np, c = rem - r * np;
-  const int2 pj = pos[j];
-  t[i] = x0 ? x0[(size_t)(pj.x + r) * n2 + pj.y + c] : make_float2(1.f, 0.f);
+  const int r = rem / g.np, c = rem - r * g.np;
+  const int2 pj = g.pos[j];
+  g.t[i] = x0 ? x0[(size_t)(pj.x + r) * g.n2 + pj.y + c] : make_float2(1.f, 0.f);
 }
 
-__global__ void init_images_k(float2* xbar, float2* xhat, float2* num, const float* laminv,
-                              const float2* x0, int npx) {
+__global__ void init_images_k(const Recon* __restrict__ rec, const float2* x0) {
+  const Recon& g = *rec;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= npx) return;
+  if (i >= g.n1 * g.n2) return;
   const float2 x = x0 ? x0[i] : make_float2(1.f, 0.f);
-  xhat[i] = laminv[i] > 0.f ? x : make_float2(0.f, 0.f);
-  xbar[i] = make_float2(0.f, 0.f);
-  num[i] = make_float2(0.f, 0.f);
+  g.xhat[i] = g.laminv[i] > 0.f ? x : make_float2(0.f, 0.f);
+  g.xbar[i] = make_float2(0.f, 0.f);
+  g.num[i] = make_float2(0.f, 0.f);
 }
 
-__global__ void get_state_k(const float2* t, const float2* xbar, const int2* pos, float2* v, int np,
-                            int n2, float two_rho, long long total) {
+__global__ void get_state_k(const Recon* __restrict__ rec, float2* v) {
+  const Recon& g = *rec;
+  const long long per = (long long)g.np * g.np;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const long long per = (long long)np * np;
+  if (i >= per * g.J) return;
   const int j = (int)(i / per);
   const int rem = (int)(i - (long long)j * per);
-  const int r = rem / np, c = rem - r * np;
-  const int2 pj = pos[j];
-  const float2 xb = xbar[(size_t)(pj.x + r) * n2 + pj.y + c];
-  const float2 tt = t[i];
-  v[i] = make_float2(fmaf(two_rho, xb.x, tt.x), fmaf(two_rho, xb.y, tt.y));
+  const int r = rem / g.np, c = rem - r * g.np;
+  const int2 pj = g.pos[j];
+  v[i] = mann_v(g.t[i], g.xbar[(size_t)(pj.x + r) * g.n2 + pj.y + c], g.two_rho);
 }
 
-// t <- v and u <- |d|^kappa v for positions [j0, j0 + cnt) (u indexed from j0)
-__global__ void set_state_k(float2* t, const float2* v, const float4* pc, float2* u, int np,
-                            int j0, long long cnt_px) {
+// t <- v and stage <- |d|^kappa v for positions [j0, j0 + cnt) (stage indexed from j0)
+__global__ void set_state_k(const Recon* __restrict__ rec, const float2* v, int j0, long long cnt_px) {
+  const Recon& g = *rec;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= cnt_px) return;
-  const long long per = (long long)np * np;
+  const long long per = (long long)g.np * g.np;
   const long long gi = (long long)j0 * per + i;
   const float2 vv = v[gi];
-  t[gi] = vv;
-  const float om = pc[i % per].z;
-  u[i] = make_float2(om * vv.x, om * vv.y);
+  g.t[gi] = vv;
+  const float om = g.pc[i % per].z;
+  g.stage[i] = make_float2(om * vv.x, om * vv.y);
 }
 
-__global__ void zero_c64_k(float2* a, int n) {
+__global__ void zero_images_k(const Recon* __restrict__ rec) {
+  const Recon& g = *rec;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = make_float2(0.f, 0.f);
+  if (i >= g.n1 * g.n2) return;
+  g.num[i] = make_float2(0.f, 0.f);
+  g.xbar[i] = make_float2(0.f, 0.f);
 }
 
 // -------------------------------------------------------------------------
@@ -501,131 +616,134 @@ __global__ void __launch_bounds__(CB * 16) fft256_cols(const float2* in, float2*
 // -------------------------------------------------------------------------
 // launchers
 // -------------------------------------------------------------------------
-static AgentArgs agent_args(const DevState& s, int j0) {
-  AgentArgs g;
-  g.t = s.t;
-  g.ys = s.ys;
-  g.pos = s.pos;
-  g.d = s.d;
-  g.pc = s.pc;
-  g.xbar = s.xbar;
-  g.num = s.num;
-  g.stage = s.stage;
-  g.n2 = s.n2;
-  g.a = s.a;
-  g.two_rho = 2.f * s.rho;
-  g.j0 = j0;
-  return g;
-}
-
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-static GatherArgs gather_args(const DevState& s, int g, int jbase) {
-  GatherArgs a;
-  const int4 ci = s.chunk_info[g];
-  a.u = s.stage;
-  a.pos = s.pos;
-  a.tiles = s.tiles;
-  a.list = s.tile_list;
-  a.num = reinterpret_cast<float2*>(s.num);
-  a.laminv = s.laminv;
-  a.xbar = s.xbar;
-  a.xhat = s.xhat;
-  a.status = s.status;
-  a.tile0 = ci.x;
-  a.r0 = ci.z;
-  a.tiles_c = ci.w;
-  a.n1 = s.n1;
-  a.n2 = s.n2;
-  a.jbase = jbase;
-  a.rho = s.rho;
-  return a;
-}
-
-template <int NP, bool FUSE>
-static void gather(const DevState& s, int g, int jbase, hipStream_t st) {
-  const int ntiles = s.chunk_info[g].y;
-  if (ntiles > 0)
-    hipLaunchKernelGGL((consensus_gather<NP, FUSE>), dim3(ntiles), dim3(GT_R * GT_C), 0, st,
-                       gather_args(s, g, jbase));
-}
-
-hipError_t launch_agent(const DevState& s, hipStream_t st) {
-  const AgentArgs g = agent_args(s, 0);
-  switch (s.np) {
-#define PMACE_AGENT_SMALL(N)                                                        \
-  case N:                                                                           \
-    hipLaunchKernelGGL(agent_fused<N>, dim3(s.J), dim3(N * Geo<N>::A), 0, st, g);   \
-    gather<N, true>(s, 0, 0, st);                                                   \
+hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_t st) {
+  switch (np) {
+#define PMACE_SMALL(N)                                                                            \
+  case N:                                                                                         \
+    hipLaunchKernelGGL(agent_fused<N>, dim3(h.J), dim3(N * Geo<N>::A), 0, st, h);                 \
+    if (ntiles > 0)                                                                               \
+      hipLaunchKernelGGL((consensus_gather<N, true>), dim3(ntiles), dim3(GT_R * GT_C), 0, st, h,  \
+                         0, 0);                                                                   \
     break;
-    PMACE_AGENT_SMALL(32)
-    PMACE_AGENT_SMALL(64)
-    PMACE_AGENT_SMALL(128)
-#undef PMACE_AGENT_SMALL
-    case 256: {
-      for (int j0 = 0, gi = 0; j0 < s.J; j0 += s.chunk, ++gi) {
-        const int cnt = (s.J - j0 < s.chunk) ? (s.J - j0) : s.chunk;
-        const AgentArgs gc = agent_args(s, j0);
-        hipLaunchKernelGGL(agent256_rows, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, gc);
-        hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, gc);
-        hipLaunchKernelGGL(agent256_rowsinv, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, gc);
-        gather<256, false>(s, gi, j0, st);
-      }
-      const int npx = s.n1 * s.n2;
-      hipLaunchKernelGGL(image_update, dim3(blocks_for(npx, 256)), dim3(256), 0, st, s.xbar, s.xhat,
-                         reinterpret_cast<float2*>(s.num), s.laminv, npx, s.rho, s.status);
-      break;
-    }
+    PMACE_SMALL(32)
+    PMACE_SMALL(64)
+    PMACE_SMALL(128)
+#undef PMACE_SMALL
     default:
       return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_init_amplitudes(const DevState& s, const float* z, float scale, int centered,
-                                  hipStream_t st) {
-  const long long total = (long long)s.J * s.np * s.np;
-  hipLaunchKernelGGL(init_amplitudes_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, z, s.ys, s.np,
-                     total, scale, centered, s.status);
+hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int nitems,
+                              const int2* gitems, int ngitems, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  switch (np) {
+#define PMACE_SMALL(N)                                                                              \
+  case N:                                                                                           \
+    hipLaunchKernelGGL(agent_fused_batch<N>, dim3(nitems), dim3(N * Geo<N>::A), 0, st, recs, items); \
+    if (ngitems > 0)                                                                                \
+      hipLaunchKernelGGL((consensus_gather_batch<N, true>), dim3(ngitems), dim3(GT_R * GT_C), 0,    \
+                         st, recs, gitems, 0);                                                      \
+    break;
+    PMACE_SMALL(32)
+    PMACE_SMALL(64)
+    PMACE_SMALL(128)
+#undef PMACE_SMALL
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_init_state(const DevState& s, const float2* x0, hipStream_t st) {
-  const long long total = (long long)s.J * s.np * s.np;
-  hipLaunchKernelGGL(init_patches_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, s.t, x0, s.pos,
-                     s.np, s.n2, total);
-  const int npx = s.n1 * s.n2;
-  hipLaunchKernelGGL(init_images_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, s.xbar, s.xhat,
-                     reinterpret_cast<float2*>(s.num), s.laminv, x0, npx);
-  return hipGetLastError();
-}
-
-hipError_t launch_get_state(const DevState& s, float2* v, hipStream_t st) {
-  const long long total = (long long)s.J * s.np * s.np;
-  hipLaunchKernelGGL(get_state_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, s.t, s.xbar, s.pos,
-                     v, s.np, s.n2, 2.f * s.rho, total);
-  return hipGetLastError();
-}
-
-hipError_t launch_set_state(const DevState& s, const float2* v, hipStream_t st) {
-  const int npx = s.n1 * s.n2;
-  const long long per = (long long)s.np * s.np;
-  hipLaunchKernelGGL(zero_c64_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st,
-                     reinterpret_cast<float2*>(s.num), npx);
-  hipLaunchKernelGGL(zero_c64_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, s.xbar, npx);
-  for (int j0 = 0, gi = 0; j0 < s.J; j0 += s.chunk, ++gi) {
-    const int cnt = (s.J - j0 < s.chunk) ? (s.J - j0) : s.chunk;
-    hipLaunchKernelGGL(set_state_k, dim3(blocks_for(cnt * per, 256)), dim3(256), 0, st, s.t, v, s.pc,
-                       s.stage, s.np, j0, cnt * per);
-    switch (s.np) {
-      case 32: gather<32, false>(s, gi, j0, st); break;
-      case 64: gather<64, false>(s, gi, j0, st); break;
-      case 128: gather<128, false>(s, gi, j0, st); break;
-      default: gather<256, false>(s, gi, j0, st); break;
+hipError_t launch_256_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
+                                hipStream_t st) {
+  for (int j0 = 0, g = 0; j0 < h.J; j0 += h.chunk, ++g) {
+    const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
+    const int2 ct = chunk_tiles[g];
+    if (batch_rec) {
+      hipLaunchKernelGGL(agent256_rows_batch, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, batch_rec, j0);
+      hipLaunchKernelGGL(agent256_cols_batch, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, batch_rec, j0);
+      hipLaunchKernelGGL(agent256_rowsinv_batch, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, batch_rec, j0);
+    } else {
+      hipLaunchKernelGGL(agent256_rows, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
+      hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
+      hipLaunchKernelGGL(agent256_rowsinv, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
+    }
+    if (ct.y > 0) {
+      if (batch_rec) {
+        hipLaunchKernelGGL((consensus_gather_member<256, false>), dim3(ct.y), dim3(GT_R * GT_C), 0,
+                           st, batch_rec, ct.x, j0);
+      } else {
+        hipLaunchKernelGGL((consensus_gather<256, false>), dim3(ct.y), dim3(GT_R * GT_C), 0, st, h,
+                           ct.x, j0);
+      }
     }
   }
-  hipLaunchKernelGGL(image_from_num, dim3(blocks_for(npx, 256)), dim3(256), 0, st, s.xhat,
-                     reinterpret_cast<float2*>(s.num), s.laminv, npx);
+  const unsigned nb = blocks_for((long long)h.n1 * h.n2, 256);
+  if (batch_rec)
+    hipLaunchKernelGGL(image_update_batch, dim3(nb), dim3(256), 0, st, batch_rec);
+  else
+    hipLaunchKernelGGL(image_update, dim3(nb), dim3(256), 0, st, h);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float scale,
+                           int centered, const float2* x0, hipStream_t st) {
+  const long long total = (long long)h.J * h.np * h.np;
+  hipLaunchKernelGGL(init_amplitudes_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, z, scale,
+                     centered);
+  hipLaunchKernelGGL(init_patches_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, x0);
+  hipLaunchKernelGGL(init_images_k, dim3(blocks_for((long long)h.n1 * h.n2, 256)), dim3(256), 0, st,
+                     rec, x0);
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(const Recon& h, const Recon* rec, float2* v, hipStream_t st) {
+  const long long total = (long long)h.J * h.np * h.np;
+  hipLaunchKernelGGL(get_state_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(const Recon& h, const Recon* rec, const float2* v,
+                            const int2* chunk_tiles, hipStream_t st) {
+  const long long npx = (long long)h.n1 * h.n2;
+  const long long per = (long long)h.np * h.np;
+  hipLaunchKernelGGL(zero_images_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec);
+  for (int j0 = 0, g = 0; j0 < h.J; j0 += h.chunk, ++g) {
+    const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
+    hipLaunchKernelGGL(set_state_k, dim3(blocks_for(cnt * per, 256)), dim3(256), 0, st, rec, v, j0,
+                       cnt * per);
+    const int2 ct = chunk_tiles[g];
+    if (ct.y <= 0) continue;
+    switch (h.np) {
+#define PMACE_GATHER(N)                                                                          \
+  case N:                                                                                        \
+    hipLaunchKernelGGL((consensus_gather<N, false>), dim3(ct.y), dim3(GT_R * GT_C), 0, st, h,    \
+                       ct.x, j0);                                                                \
+    break;
+      PMACE_GATHER(32)
+      PMACE_GATHER(64)
+      PMACE_GATHER(128)
+      PMACE_GATHER(256)
+#undef PMACE_GATHER
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  hipLaunchKernelGGL(image_from_num, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_nrmse(const Recon* recs, const int2* ritems, int nritems, const int* fitems, int nf,
+                        int update_stop, float tol, int min_iter, int max_iter, hipStream_t st) {
+  if (nritems > 0)
+    hipLaunchKernelGGL(nrmse_partial, dim3(nritems), dim3(RED_T), 0, st, recs, ritems, update_stop);
+  if (nf > 0)
+    hipLaunchKernelGGL(nrmse_finish, dim3(nf), dim3(RED_T), 0, st, recs, fitems, update_stop, tol,
+                       min_iter, max_iter);
   return hipGetLastError();
 }
 

@@ -39,6 +39,10 @@ class pmace_params(ctypes.Structure):
     ]
 
 
+class pmace_stop_rule(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_float), ("min_iter", ctypes.c_int32), ("max_iter", ctypes.c_int32)]
+
+
 class PMACEError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -76,6 +80,21 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pmace_status_str.restype = ctypes.c_char_p
     L.pmace_fft2.argtypes = [i32, i32, vp, vp, i32, vp]
     L.pmace_fft2.restype = ctypes.c_int
+    L.pmace_set_reference.argtypes = [vp, vp, vp]
+    L.pmace_set_reference.restype = ctypes.c_int
+    L.pmace_nrmse.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.pmace_nrmse.restype = ctypes.c_int
+    L.pmace_batch_footprint.argtypes = [ctypes.POINTER(vp), i32]
+    L.pmace_batch_footprint.restype = sz
+    L.pmace_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(pmace_stop_rule), vp, sz,
+                                     ctypes.POINTER(vp)]
+    L.pmace_batch_create.restype = ctypes.c_int
+    L.pmace_batch_step.argtypes = [vp, i32]
+    L.pmace_batch_step.restype = ctypes.c_int
+    L.pmace_batch_poll.argtypes = [vp, vp, vp, vp]
+    L.pmace_batch_poll.restype = ctypes.c_int
+    L.pmace_batch_destroy.argtypes = [vp]
+    L.pmace_batch_destroy.restype = None
     _lib = L
     return L
 
@@ -140,6 +159,51 @@ def pmace_status_str(s: int) -> str:
 
 def pmace_fft2(np_, count, in_ptr, out_ptr, inverse, stream_ptr) -> int:
     return load_library().pmace_fft2(int(np_), int(count), in_ptr, out_ptr, int(inverse), stream_ptr)
+
+
+def pmace_set_reference(ctx, xref_ptr, mask_ptr) -> int:
+    return load_library().pmace_set_reference(ctx, xref_ptr, mask_ptr)
+
+
+def pmace_nrmse(ctx):
+    out = ctypes.c_double()
+    st = load_library().pmace_nrmse(ctx, ctypes.byref(out))
+    return st, out.value
+
+
+def _ctx_array(ctxs):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
+    return ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), arr
+
+
+def pmace_batch_footprint(ctxs) -> int:
+    p, _keep = _ctx_array(ctxs)
+    return int(load_library().pmace_batch_footprint(p, len(ctxs)))
+
+
+def pmace_batch_create(ctxs, rule: pmace_stop_rule, ws_ptr, ws_bytes):
+    p, _keep = _ctx_array(ctxs)
+    out = ctypes.c_void_p()
+    st = load_library().pmace_batch_create(p, len(ctxs), ctypes.byref(rule), ws_ptr, ws_bytes,
+                                           ctypes.byref(out))
+    return st, out
+
+
+def pmace_batch_step(batch, n_iter: int) -> int:
+    return load_library().pmace_batch_step(batch, int(n_iter))
+
+
+def pmace_batch_poll(batch, n: int):
+    done = (ctypes.c_int32 * n)()
+    nr = (ctypes.c_double * n)()
+    it = (ctypes.c_int32 * n)()
+    st = load_library().pmace_batch_poll(batch, ctypes.cast(done, ctypes.c_void_p),
+                                         ctypes.cast(nr, ctypes.c_void_p), ctypes.cast(it, ctypes.c_void_p))
+    return st, np.array(done[:], dtype=np.int32), np.array(nr[:]), np.array(it[:], dtype=np.int32)
+
+
+def pmace_batch_destroy(batch) -> None:
+    load_library().pmace_batch_destroy(batch)
 
 
 # Torch-facing helpers ------------------------------------------------------
@@ -236,10 +300,74 @@ class Reconstruction:
     def sync(self):
         _check(pmace_sync(self.ctx), "pmace_sync")
 
+    def set_reference(self, xref, mask=None):
+        """NRMSE reference object (and optional boolean region); kept alive here."""
+        torch = _torch()
+        if xref is None:
+            self._ref = None
+            _check(pmace_set_reference(self.ctx, ctypes.c_void_p(0), ctypes.c_void_p(0)),
+                   "pmace_set_reference")
+            return
+        xr = to_device_c64(xref, self.device)
+        mk = None
+        if mask is not None:
+            m = mask if isinstance(mask, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(mask))
+            mk = m.to(device=self.device, dtype=torch.uint8).contiguous()
+        self._ref = (xr, mk)
+        _check(pmace_set_reference(self.ctx, ctypes.c_void_p(xr.data_ptr()),
+                                   ctypes.c_void_p(0 if mk is None else mk.data_ptr())),
+               "pmace_set_reference")
+
+    def nrmse(self) -> float:
+        st, v = pmace_nrmse(self.ctx)
+        _check(st, "pmace_nrmse")
+        return v
+
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             pmace_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several Reconstructions (same device and stream) advanced together: one
+    graph launch per iteration, NRMSE and the stop rule kept on the device."""
+
+    def __init__(self, recons, tol=1e-4, min_iter=2, max_iter=500, workspace=None):
+        torch = _torch()
+        self.recons = list(recons)
+        self.ctxs = [r.ctx for r in self.recons]
+        fp = pmace_batch_footprint(self.ctxs)
+        if fp == 0:
+            raise PMACEError(PMACE_EINVAL, "pmace_batch_footprint")
+        if workspace is None:
+            workspace = torch.empty(fp, dtype=torch.uint8, device=self.recons[0].device)
+        self.workspace = workspace
+        self.rule = pmace_stop_rule(float(tol), int(min_iter), int(max_iter))
+        st, b = pmace_batch_create(self.ctxs, self.rule, ctypes.c_void_p(workspace.data_ptr()),
+                                   workspace.numel())
+        _check(st, "pmace_batch_create")
+        self.batch = b
+
+    def step(self, n: int = 1):
+        _check(pmace_batch_step(self.batch, n), "pmace_batch_step")
+
+    def poll(self):
+        """(done flags, last NRMSE, tracked iterations) per member, numpy arrays."""
+        st, done, nr, it = pmace_batch_poll(self.batch, len(self.ctxs))
+        _check(st, "pmace_batch_poll")
+        return done, nr, it
+
+    def close(self):
+        if getattr(self, "batch", None) is not None and self.batch.value:
+            pmace_batch_destroy(self.batch)
+            self.batch = None
 
     def __del__(self):
         try:

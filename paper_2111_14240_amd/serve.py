@@ -1,0 +1,240 @@
+"""Continuous-batching server for PMACE reconstructions.
+
+Requests (one ptychography problem each) arrive over time.  The server keeps
+every admitted reconstruction's agent states resident on the GPU, admits new
+requests as soon as their workspace fits in the memory budget and a slot is
+free, advances all active reconstructions together (one batched graph launch
+per iteration, stop rule evaluated on the device), and retires each as soon as
+it has converged, copying its reconstruction back.  The same executor run with
+one request at a time, in arrival order, is the plain solver it is compared
+with.
+
+The executor interface keeps the scheduling logic testable without a GPU:
+
+    footprint(problem) -> bytes      workspace a request will hold while active
+    admit(req)                       start a reconstruction (device state resident)
+    step(n)                          n iterations of every active reconstruction
+    poll() -> {req_id: (done, nrmse, iters)}
+    retire(req_id) -> result         reconstruction back to the host, memory freed
+"""
+from __future__ import annotations
+
+import dataclasses
+import heapq
+import time
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    problem: object            # a synth.Problem (or anything the executor understands)
+    arrival: float             # seconds since the start of the run
+    admitted: Optional[float] = None
+    finished: Optional[float] = None
+    iters: int = 0
+    nrmse: float = float("nan")
+    result: object = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class WallClock:
+    """Real time since construction; sleep() waits."""
+
+    def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def now(self) -> float:
+        return time.perf_counter() - self.t0
+
+    def sleep_until(self, t: float):
+        d = t - self.now()
+        if d > 0:
+            time.sleep(d)
+
+
+class FakeClock:
+    """Deterministic clock for tests: time advances only when told to."""
+
+    def __init__(self):
+        self.t = 0.0
+
+    def now(self) -> float:
+        return self.t
+
+    def advance(self, dt: float):
+        self.t += dt
+
+    def sleep_until(self, t: float):
+        self.t = max(self.t, t)
+
+
+def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times of a Poisson process (exponential inter-arrival times)."""
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
+@dataclasses.dataclass
+class ServeStats:
+    completed: int
+    makespan: float
+    solves_per_s: float
+    p50: float
+    p99: float
+    mean_latency: float
+    max_active: int
+    steps: int
+
+    def as_dict(self):
+        return dataclasses.asdict(self)
+
+
+def _stats(reqs: Sequence[Request], makespan: float, max_active: int, steps: int) -> ServeStats:
+    lat = np.array([r.latency for r in reqs if r.finished is not None])
+    return ServeStats(completed=len(lat), makespan=makespan,
+                      solves_per_s=len(lat) / makespan if makespan > 0 else float("nan"),
+                      p50=float(np.percentile(lat, 50)) if len(lat) else float("nan"),
+                      p99=float(np.percentile(lat, 99)) if len(lat) else float("nan"),
+                      mean_latency=float(lat.mean()) if len(lat) else float("nan"),
+                      max_active=max_active, steps=steps)
+
+
+class Server:
+    """Continuous batching: admit on arrival when memory and a slot allow,
+    step every active reconstruction together, retire each on convergence.
+
+    capacity_bytes  memory budget for the workspaces of active requests
+    max_active      upper bound on concurrently active requests
+    iters_per_step  iterations launched between polls of the stop flags
+    on_step         optional hook(clock, n_active, iters) after each step (a
+                    fake clock advances there in tests)
+    """
+
+    def __init__(self, executor, capacity_bytes: int, max_active: int = 64,
+                 iters_per_step: int = 4, on_step: Optional[Callable] = None):
+        self.ex = executor
+        self.capacity = int(capacity_bytes)
+        self.max_active = int(max_active)
+        self.iters_per_step = int(iters_per_step)
+        self.on_step = on_step
+
+    def run(self, requests: List[Request], clock) -> ServeStats:
+        pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
+        for r in pending:
+            if self.ex.footprint(r.problem) > self.capacity:
+                raise ValueError(f"request {r.rid} needs more memory than the whole budget")
+        queue: List[Request] = []          # arrived, not admitted (FIFO)
+        active: Dict[int, Request] = {}
+        used = 0
+        nxt = 0
+        max_active = 0
+        steps = 0
+        while nxt < len(pending) or queue or active:
+            now = clock.now()
+            while nxt < len(pending) and pending[nxt].arrival <= now:
+                queue.append(pending[nxt])
+                nxt += 1
+            # admission: FIFO, as long as the head fits
+            while queue and len(active) < self.max_active:
+                fp = self.ex.footprint(queue[0].problem)
+                if used + fp > self.capacity:
+                    break
+                r = queue.pop(0)
+                self.ex.admit(r)
+                r.admitted = clock.now()
+                active[r.rid] = r
+                used += fp
+            max_active = max(max_active, len(active))
+            if not active:
+                if nxt < len(pending):
+                    clock.sleep_until(pending[nxt].arrival)
+                continue
+            self.ex.step(self.iters_per_step)
+            steps += 1
+            if self.on_step:
+                self.on_step(clock, len(active), self.iters_per_step)
+            for rid, (done, nr, it) in self.ex.poll().items():
+                if not done:
+                    continue
+                r = active.pop(rid)
+                r.result = self.ex.retire(rid)
+                r.finished = clock.now()
+                r.iters, r.nrmse = int(it), float(nr)
+                used -= self.ex.footprint(r.problem)
+        makespan = clock.now() - (pending[0].arrival if pending else 0.0)
+        return _stats(requests, makespan, max_active, steps)
+
+
+def run_plain(executor, requests: List[Request], clock, iters_per_step: int = 4,
+              on_step: Optional[Callable] = None) -> ServeStats:
+    """The plain solver: one request at a time, in arrival order, to convergence."""
+    srv = Server(executor, capacity_bytes=1 << 62, max_active=1, iters_per_step=iters_per_step,
+                 on_step=on_step)
+    return srv.run(requests, clock)
+
+
+class GPUExecutor:
+    """Executor on the HIP library: one Reconstruction (device-resident state)
+    per active request, re-batched whenever the active set changes."""
+
+    def __init__(self, alpha: float, kappa: float = 1.25, rho: float = 0.5, tol: float = 1e-4,
+                 min_iter: int = 2, max_iter: int = 500, device="cuda", stream=None):
+        from . import pmace, synth
+        self._pmace = pmace
+        self._synth = synth
+        self.alpha, self.kappa, self.rho = alpha, kappa, rho
+        self.tol, self.min_iter, self.max_iter = tol, min_iter, max_iter
+        self.device = device
+        self.stream = stream
+        self.active: Dict[int, object] = {}
+        self.order: List[int] = []
+        self.batch = None
+        self._fp_cache: Dict[tuple, int] = {}
+
+    def footprint(self, prob) -> int:
+        key = (prob.n1, prob.n2, prob.np_, prob.num_pos)
+        if key not in self._fp_cache:
+            prm = self._pmace.make_params(prob.n1, prob.n2, prob.np_, prob.num_pos, self.alpha,
+                                          self.kappa, self.rho)
+            self._fp_cache[key] = self._pmace.pmace_footprint(prm)
+        return self._fp_cache[key]
+
+    def admit(self, req):
+        p = req.problem
+        R = self._pmace.Reconstruction(p.n1, p.n2, p.probe, p.pos, p.z, self.alpha, self.kappa,
+                                       self.rho, device=self.device, stream=self.stream)
+        R.set_reference(p.x_true, self._synth.roi_mask(p.probe, p.pos, p.n1, p.n2))
+        self.active[req.rid] = R
+        self.order.append(req.rid)
+        self._drop_batch()
+
+    def _drop_batch(self):
+        if self.batch is not None:
+            self.batch.close()
+            self.batch = None
+
+    def step(self, n: int):
+        if self.batch is None:      # membership changed since the last step
+            self.batch = self._pmace.Batch([self.active[r] for r in self.order], tol=self.tol,
+                                           min_iter=self.min_iter, max_iter=self.max_iter)
+        self.batch.step(n)
+
+    def poll(self):
+        if self.batch is None:
+            return {}
+        done, nr, it = self.batch.poll()
+        return {rid: (bool(done[i]), float(nr[i]), int(it[i])) for i, rid in enumerate(self.order)}
+
+    def retire(self, rid):
+        R = self.active.pop(rid)
+        x = R.reconstruct().cpu().numpy()
+        self._drop_batch()           # the batch reads R's descriptor: release it first
+        self.order.remove(rid)
+        R.close()
+        return x

@@ -51,13 +51,16 @@ def test_footprint_formula(lib):
     # states 8 B + amplitudes 4 B + weighted reflections 8 B per patch pixel,
     # object images 28 B per pixel, probe tables, positions, tile tables
     lower = J * np_ * np_ * 20 + n * n * 28 + np_ * np_ * 24 + J * 8
-    tables = (n // 16) * (n // 64) * 8 + J * (31 // 16 + 2) * (31 // 64 + 2) * 4
-    assert lower <= fp <= lower + tables + 16 * 256
+    tiles = (n // 16) * (n // 64)
+    tables = tiles * 24 + J * (31 // 16 + 2) * (31 // 64 + 2) * 4 + J * 8
+    nred = n * n // 4096
+    assert lower <= fp <= lower + tables + nred * 40 + 1024 + 24 * 256
     # Np = 256 stages min(J, chunk) patches between its passes
     a = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=64))
     b = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=128))
     stage = 64 * 256 * 256 * 8
-    assert stage - 12 * 64 * 16 * 8 - 4096 <= b - a <= stage + 4096
+    tile_tables = (25 - 13) * 64 * 16 * 24     # fewer chunks, fewer tile slots
+    assert stage - tile_tables - 4096 <= b - a <= stage + 4096
 
 
 @pytest.mark.parametrize("kw", [dict(np_=0), dict(num_pos=0), dict(n1=16), dict(alpha=-1.0),
@@ -83,3 +86,16 @@ def test_init_argument_checks_before_device(lib):
     assert P.pmace_fft2(48, 1, 1, 1, 0, None) == P.PMACE_EUNSUPPORTED
     assert P.pmace_fft2(32, -1, 1, 1, 0, None) == P.PMACE_EINVAL
     P.pmace_destroy(None)
+
+
+def test_batch_argument_checks(lib):
+    assert P.pmace_batch_footprint([]) == 0
+    st, b = P.pmace_batch_create([], P.pmace_stop_rule(1e-4, 2, 10), 1, 1 << 20)
+    assert st == P.PMACE_EINVAL and not b.value
+    assert P.pmace_batch_step(None, 1) == P.PMACE_ESTATE
+    st, *_ = P.pmace_batch_poll(None, 1)
+    assert st == P.PMACE_ESTATE
+    assert P.pmace_set_reference(None, None, None) == P.PMACE_ESTATE
+    st, _ = P.pmace_nrmse(None)
+    assert st == P.PMACE_ESTATE
+    P.pmace_batch_destroy(None)
