@@ -5,6 +5,8 @@ the workload (agent F_j on all patches, consensus G, Mann update, image
 recurrence), with all inputs resident in HBM.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c3]
+  python bench.py --mode batch [--items 64]        mixed-size batch vs plain, same stop rule
+  python bench.py --mode serve [--requests 2000]   continuous batching vs plain FIFO
 """
 from __future__ import annotations
 
@@ -51,6 +53,136 @@ def cpu_baseline(prob, alpha, kappa, rho):
                       f"{dt:.1f} s, numpy FFT (single thread)"}
 
 
+def _mix_problems(count, seed=4, device="cuda"):
+    """The mixed-size workload: sizes from the seeded draw, intensities
+    simulated on the device (Poisson peak 1e5)."""
+    from paper_2111_14240_amd import pmace, synth
+    specs = synth.draw_mix_specs(count, seed=seed)
+    return [pmace.simulated_problem(s["n"], s["np_"], s["scan"], s["step"], s["peak"], s["seed"],
+                                    device=device) for s in specs]
+
+
+def _stop_rule():
+    return dict(tol=1e-4, min_iter=2, max_iter=500)
+
+
+def bench_batch(args):
+    """All reconstructions advanced together (one graph launch per iteration)
+    versus the plain solver (one at a time, in order), both to the same
+    on-device stop rule; alone and in the batch each member takes the same
+    iterations and ends at the same NRMSE (the path is deterministic)."""
+    import torch
+    from paper_2111_14240_amd import pmace, synth
+    t0 = time.perf_counter()
+    probs = _mix_problems(args.items)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    alpha = 0.5
+    rule = _stop_rule()
+    poll = 10
+
+    def make(p):
+        R = pmace.Reconstruction(p.n1, p.n2, p.probe, p.pos, p.z, alpha)
+        R.set_reference(p.x_true, synth.roi_mask(p.probe, p.pos, p.n1, p.n2))
+        return R
+
+    def drive(B, n):
+        steps = 0
+        while True:
+            B.step(poll)
+            steps += poll
+            done, nr, it = B.poll()
+            if done.all() or steps > rule["max_iter"] + poll:
+                return nr, it
+
+    # plain: one reconstruction at a time
+    plain_nr, plain_it = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p in probs:
+        R = make(p)
+        B = pmace.Batch([R], **rule)
+        nr, it = drive(B, 1)
+        plain_nr.append(nr[0])
+        plain_it.append(it[0])
+        B.close()
+        R.close()
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t0
+    # batched
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Rs = [make(p) for p in probs]
+    B = pmace.Batch(Rs, **rule)
+    nr, it = drive(B, len(Rs))
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t0
+    B.close()
+    for R in Rs:
+        R.close()
+    patch_updates = float(sum(p.num_pos * k for p, k in zip(probs, it)))
+    B_alg = sum(algorithmic_bytes(p.num_pos, p.np_, p.n1, p.n2) * k for p, k in zip(probs, it))
+    out = {
+        "metric": "batched-vs-plain solves/s",
+        "value": len(probs) / batch_s, "unit": "solves/s", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "c64", "data": "synthetic (simulated on device)",
+        "config": {"workload": f"{len(probs)} reconstructions, object {{256,512,1024}}, probe {{64,128,256}}, "
+                               "scan 7x7..30x30, Poisson peak 1e5", "stop_rule": rule, "alpha": alpha,
+                   "poll_every": poll},
+        "batched": {"seconds": batch_s, "solves_per_s": len(probs) / batch_s,
+                    "patch_updates_per_s": patch_updates / batch_s,
+                    "algorithmic_GBps": B_alg / batch_s / 1e9},
+        "plain": {"seconds": plain_s, "solves_per_s": len(probs) / plain_s,
+                  "patch_updates_per_s": patch_updates / plain_s},
+        "speedup": plain_s / batch_s,
+        "same_iterations": [int(a) for a in plain_it] == [int(b) for b in it],
+        "same_nrmse": bool(np.array_equal(np.asarray(plain_nr), np.asarray(nr))),
+        "iterations": {"min": int(min(it)), "median": float(np.median(it)), "max": int(max(it))},
+        "nrmse": {"median": float(np.median(nr)), "max": float(np.max(nr))},
+        "generation_s": gen_s,
+        "total_patch_pixels": int(sum(p.patch_pixels for p in probs)),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_serve(args):
+    """Poisson arrivals of requests drawn from the mixed-size pool: the
+    continuous-batching server against the plain FIFO solver."""
+    import torch
+    from paper_2111_14240_amd import serve
+    pool = _mix_problems(args.pool)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    pick = rng.integers(0, len(pool), size=args.requests)
+    arrivals = serve.poisson_arrivals(args.requests, args.rate, seed=5)
+    rule = _stop_rule()
+    results = {}
+    for name in ("served", "plain"):
+        reqs = [serve.Request(i, pool[pick[i]], float(arrivals[i])) for i in range(args.requests)]
+        ex = serve.GPUExecutor(alpha=0.5, **rule)
+        clock = serve.WallClock()
+        if name == "served":
+            st = serve.Server(ex, capacity_bytes=int(args.capacity_gb * 2**30),
+                              max_active=args.max_active, iters_per_step=10).run(reqs, clock)
+        else:
+            st = serve.run_plain(ex, reqs, clock, iters_per_step=10)
+        torch.cuda.synchronize()
+        results[name] = st.as_dict()
+        results[name]["median_iterations"] = float(np.median([r.iters for r in reqs]))
+        print(f"[serve] {name}: {results[name]}", file=sys.stderr, flush=True)
+    out = {
+        "metric": "served p50/p99 latency and solves/s vs plain",
+        "value": results["served"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "higher_is_better": True, "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic (simulated on device)",
+        "config": {"workload": f"{args.requests} requests, Poisson arrivals at {args.rate}/s, drawn from "
+                               f"{len(pool)} mixed-size problems", "stop_rule": rule,
+                   "capacity_GiB": args.capacity_gb, "max_active": args.max_active},
+        "served": results["served"], "plain": results["plain"],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,11 +191,23 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--chunk", type=int, default=0, help="Np=256 staging chunk (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
+    ap.add_argument("--items", type=int, default=64, help="batch mode: reconstructions")
+    ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve mode: arrivals per second")
+    ap.add_argument("--pool", type=int, default=64, help="serve mode: distinct problems")
+    ap.add_argument("--capacity-gb", type=float, default=200.0, help="serve mode: workspace budget")
+    ap.add_argument("--max-active", type=int, default=64, help="serve mode: concurrent requests")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.mode == "batch":
+        return bench_batch(args)
+    if args.mode == "serve":
+        return bench_serve(args)
 
     import torch
     from paper_2111_14240_amd import pmace, synth

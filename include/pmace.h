@@ -157,6 +157,33 @@ pmace_status pmace_batch_step(pmace_batch* batch, int32_t n_iter);
 pmace_status pmace_batch_poll(pmace_batch* batch, int32_t* done, double* nrmse, int32_t* iters);
 void pmace_batch_destroy(pmace_batch* batch);
 
+/* Simulated measurements (Sec. II eq. (1); Sec. IV eq. (16)) for synthetic
+ * problems made on the device:  I_j = |F D P_j x|^2  for every position and,
+ * when peak_photons > 0, z_j = Pois(I_j * peak_photons / max I) with the
+ * maximum over all positions and pixels (one scale per experiment); else
+ * z = I.  Poisson variates come from the counter-based generator
+ * Philox4x32-10 keyed by `seed` and counted by element index, so the output
+ * depends only on the inputs and the seed.
+ *   probe_d np*np c64; pos_d num_pos x 2 int32 (inside the object, else
+ *   EINVAL); x_d n1*n2 c64; z_d num_pos*np*np float32 (output, DC at [0,0]);
+ *   workspace_d >= pmace_simulate_footprint(np, num_pos) bytes (caller-owned);
+ *   scale_out (host, may be NULL) receives peak_photons / max I (1 if
+ *   noise-free): multiply the probe by sqrt(scale) to keep the object's units.
+ * Synchronises (positions are validated on the host). */
+size_t pmace_simulate_footprint(int32_t np, int32_t num_pos);
+pmace_status pmace_simulate(int32_t n1, int32_t n2, int32_t np, int32_t num_pos,
+                            const void* probe_d, const int32_t* pos_d, const void* x_d,
+                            double peak_photons, uint64_t seed, float* z_d, void* workspace_d,
+                            size_t ws_bytes, double* scale_out, void* hip_stream);
+/* Exposes the generator behind pmace_simulate for known-answer checks: io_d
+ * holds n records of 6 uint32 (counter[4], key[2]); the counter words are
+ * replaced by Philox4x32-10(counter, key). */
+pmace_status pmace_philox4x32_10(uint32_t* io_d, int32_t n, void* hip_stream);
+/* The Poisson sampler behind pmace_simulate on given means lam_d[n] (FP64):
+ * element i draws from the stream of element index i under `seed`. */
+pmace_status pmace_poisson(const double* lam_d, float* out_d, int32_t n, uint64_t seed,
+                           void* hip_stream);
+
 /* Batched 2-D orthonormal DFT of `count` np x np c64 arrays (the operator F
  * of Sec. II, or F^* when inverse != 0), in_d and out_d may alias.
  * np in {32, 64, 128, 256}.  Stream-ordered on hip_stream. */

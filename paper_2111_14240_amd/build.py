@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmace.so")
-SOURCES = ["pmace_api.hip", "pmace_kernels.hip"]
+SOURCES = ["pmace_api.hip", "pmace_kernels.hip", "pmace_simulate.hip"]
 
 # Packed FP32 VALU forms are kept out of the generated code on purpose, and
 # floating-point contraction is off: every fused multiply-add is written out in

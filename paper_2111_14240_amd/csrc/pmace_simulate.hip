@@ -1,0 +1,240 @@
+// Simulated ptychographic measurements on the GPU (Sec. II eq. (1) and
+// Sec. IV eq. (16)):
+//     I_j = |F D P_j x|^2                       (noise-free intensities)
+//     z_j = Pois(I_j * r_p / max_{j,k} I_j[k])  (peak photon rate r_p)
+// The maximum is taken over every position and pixel (one scale for the
+// whole experiment).  Random numbers come from a counter-based generator,
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+// easy as 1, 2, 3", SC 2011), keyed by the seed and counted by element index,
+// so every sample is reproducible and independent of the launch shape.
+// Poisson variates: the product-of-uniforms method below mean 10, and
+// Hormann's transformed rejection with squeeze (PTRS; W. Hormann, "The
+// transformed rejection method for generating Poisson random variables",
+// Insurance: Mathematics and Economics 12, 1993) from mean 10 up.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "pmace.h"
+#include "pmace_dft.hpp"
+#include "pmace_internal.hpp"
+
+namespace pmace {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10: ten rounds of two 32x32->64 multiplies, a xor with the key,
+// and a Weyl increment of the key between rounds.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+  const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
+  const uint32_t w0 = 0x9E3779B9u, w1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(m0, c.x), lo0 = m0 * c.x;
+    const uint32_t hi1 = __umulhi(m1, c.z), lo1 = m1 * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+    k.x += w0;
+    k.y += w1;
+  }
+  return c;
+}
+
+// Uniform doubles in (0, 1) for element `idx`: block n of the stream is
+// Philox(counter = (idx lo, idx hi, n, 0x50495853), key = seed).
+struct Uniforms {
+  uint2 key;
+  uint32_t i0, i1, n;
+  uint4 buf;
+  int have;
+  __device__ Uniforms(uint64_t seed, uint64_t idx)
+      : key(make_uint2((uint32_t)seed, (uint32_t)(seed >> 32))),
+        i0((uint32_t)idx), i1((uint32_t)(idx >> 32)), n(0), have(0) {}
+  __device__ double next() {
+    if (have == 0) {
+      buf = philox4x32_10(make_uint4(i0, i1, n++, 0x50495853u), key);
+      have = 2;
+    }
+    const uint32_t a = have == 2 ? buf.x : buf.z, b = have == 2 ? buf.y : buf.w;
+    --have;
+    // 53 random bits, centred in their interval: never 0 or 1
+    return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6) + 0.5) * (1.0 / 9007199254740992.0);
+  }
+};
+
+__device__ double poisson_draw(double lam, Uniforms& u) {
+  if (!(lam > 0.0)) return 0.0;
+  if (lam < 10.0) {
+    const double L = exp(-lam);
+    double p = 1.0;
+    int k = 0;
+    do {
+      ++k;
+      p *= u.next();
+    } while (p > L && k < 1000);
+    return (double)(k - 1);
+  }
+  const double slam = sqrt(lam), loglam = log(lam);
+  const double b = 0.931 + 2.53 * slam;
+  const double a = -0.059 + 0.02483 * b;
+  const double invalpha = 1.1239 + 1.1328 / (b - 3.4);
+  const double vr = 0.9277 - 3.6224 / (b - 2.0);
+  for (int it = 0; it < 1000; ++it) {  // each try accepts with probability > 0.8
+    const double U = u.next() - 0.5;
+    const double V = u.next();
+    const double us = 0.5 - fabs(U);
+    const double k = floor((2.0 * a / us + b) * U + lam + 0.43);
+    if (us >= 0.07 && V <= vr) return k;
+    if (k < 0.0 || (us < 0.013 && V > us)) continue;
+    if (log(V) + log(invalpha) - log(a / (us * us) + b) <= -lam + k * loglam - lgamma(k + 1.0))
+      return k;
+  }
+  return floor(lam + 0.5);
+}
+
+// frames[j] = d * P_j x
+__global__ void frames_k(const float2* __restrict__ d, const int2* __restrict__ pos,
+                         const float2* __restrict__ x, float2* __restrict__ fr, int np, int n2,
+                         long long total) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const long long per = (long long)np * np;
+  const int j = (int)(i / per);
+  const int rem = (int)(i - (long long)j * per);
+  const int r = rem / np, c = rem - r * np;
+  const int2 pj = pos[j];
+  fr[i] = cmul(d[rem], x[(size_t)(pj.x + r) * n2 + pj.y + c]);
+}
+
+// I = |F D P_j x|^2, and the running maximum (non-negative floats order as
+// their bit patterns, so an unsigned max is a float max)
+__global__ void intensity_k(const float2* __restrict__ spec, float* __restrict__ z,
+                           unsigned* __restrict__ maxbits, long long total) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  float v = 0.f;
+  if (i < total) {
+    const float2 s = spec[i];
+    v = fmaf(s.x, s.x, s.y * s.y);
+    z[i] = v;
+  }
+  for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(maxbits, __float_as_uint(v));
+}
+
+__global__ void poisson_k(float* __restrict__ z, const unsigned* __restrict__ maxbits, double peak,
+                          uint64_t seed, long long total) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const double mx = (double)__uint_as_float(*maxbits);
+  const double scale = mx > 0.0 ? peak / mx : 0.0;
+  Uniforms u(seed, (uint64_t)i);
+  z[i] = (float)poisson_draw((double)z[i] * scale, u);
+}
+
+__global__ void philox_k(uint32_t* io, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t* r = io + 6 * (size_t)i;
+  const uint4 o = philox4x32_10(make_uint4(r[0], r[1], r[2], r[3]), make_uint2(r[4], r[5]));
+  r[0] = o.x;
+  r[1] = o.y;
+  r[2] = o.z;
+  r[3] = o.w;
+}
+
+__global__ void poisson_test_k(const double* __restrict__ lam, float* __restrict__ out, uint64_t seed,
+                               int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Uniforms u(seed, (uint64_t)i);
+  out[i] = (float)poisson_draw(lam[i], u);
+}
+
+}  // namespace pmace
+
+namespace {
+inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+inline size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+extern "C" {
+
+size_t pmace_simulate_footprint(int32_t np, int32_t num_pos) {
+  if (np < 1 || num_pos < 1) return 0;
+  return up256((size_t)num_pos * np * np * 8) + 256 + 256;
+}
+
+pmace_status pmace_simulate(int32_t n1, int32_t n2, int32_t np, int32_t num_pos, const void* probe_d,
+                            const int32_t* pos_d, const void* x_d, double peak_photons,
+                            uint64_t seed, float* z_d, void* workspace_d, size_t ws_bytes,
+                            double* scale_out, void* hip_stream) {
+  if (np < 1 || num_pos < 1 || n1 < np || n2 < np || !probe_d || !pos_d || !x_d || !z_d ||
+      !workspace_d || !std::isfinite(peak_photons))
+    return PMACE_EINVAL;
+  if (np != 32 && np != 64 && np != 128 && np != 256) return PMACE_EUNSUPPORTED;
+  if (ws_bytes < pmace_simulate_footprint(np, num_pos)) return PMACE_ENOMEM;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  // positions are checked on the host: the frame gather reads the object there
+  const size_t J = (size_t)num_pos;
+  int32_t* pos = new (std::nothrow) int32_t[2 * J];
+  if (!pos) return PMACE_ENOMEM;
+  if (hipMemcpyAsync(pos, pos_d, J * 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    delete[] pos;
+    return PMACE_EDEVICE;
+  }
+  bool ok = true;
+  for (size_t j = 0; j < J; ++j)
+    if (pos[2 * j] < 0 || pos[2 * j + 1] < 0 || pos[2 * j] > n1 - np || pos[2 * j + 1] > n2 - np) ok = false;
+  delete[] pos;
+  if (!ok) return PMACE_EINVAL;
+
+  char* base = reinterpret_cast<char*>(up256(reinterpret_cast<size_t>(workspace_d)));
+  float2* fr = reinterpret_cast<float2*>(base);
+  unsigned* maxbits = reinterpret_cast<unsigned*>(base + up256(J * np * np * 8));
+  const long long total = (long long)J * np * np;
+  if (hipMemsetAsync(maxbits, 0, 4, st) != hipSuccess) return PMACE_EDEVICE;
+  hipLaunchKernelGGL(pmace::frames_k, dim3(nblocks(total, 256)), dim3(256), 0, st,
+                     reinterpret_cast<const float2*>(probe_d), reinterpret_cast<const int2*>(pos_d),
+                     reinterpret_cast<const float2*>(x_d), fr, np, n2, total);
+  if (hipGetLastError() != hipSuccess ||
+      pmace::launch_fft2(np, num_pos, fr, fr, 0, st) != hipSuccess)
+    return PMACE_EDEVICE;
+  hipLaunchKernelGGL(pmace::intensity_k, dim3(nblocks(total, 256)), dim3(256), 0, st, fr, z_d,
+                     maxbits, total);
+  if (peak_photons > 0.0)
+    hipLaunchKernelGGL(pmace::poisson_k, dim3(nblocks(total, 256)), dim3(256), 0, st, z_d, maxbits,
+                       peak_photons, seed, total);
+  if (hipGetLastError() != hipSuccess) return PMACE_EDEVICE;
+  if (scale_out) {
+    unsigned mb = 0;
+    if (hipMemcpyAsync(&mb, maxbits, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return PMACE_EDEVICE;
+    float mx;
+    std::memcpy(&mx, &mb, 4);
+    *scale_out = (peak_photons > 0.0 && mx > 0.f) ? peak_photons / (double)mx : 1.0;
+  }
+  return PMACE_OK;
+}
+
+pmace_status pmace_philox4x32_10(uint32_t* io_d, int32_t n, void* hip_stream) {
+  if (!io_d || n < 0) return PMACE_EINVAL;
+  if (n == 0) return PMACE_OK;
+  hipLaunchKernelGGL(pmace::philox_k, dim3(nblocks(n, 256)), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(hip_stream), io_d, n);
+  return hipGetLastError() == hipSuccess ? PMACE_OK : PMACE_EDEVICE;
+}
+
+pmace_status pmace_poisson(const double* lam_d, float* out_d, int32_t n, uint64_t seed,
+                           void* hip_stream) {
+  if (!lam_d || !out_d || n < 0) return PMACE_EINVAL;
+  if (n == 0) return PMACE_OK;
+  hipLaunchKernelGGL(pmace::poisson_test_k, dim3(nblocks(n, 256)), dim3(256), 0,
+                     reinterpret_cast<hipStream_t>(hip_stream), lam_d, out_d, seed, n);
+  return hipGetLastError() == hipSuccess ? PMACE_OK : PMACE_EDEVICE;
+}
+
+}  // extern "C"

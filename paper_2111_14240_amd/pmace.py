@@ -95,6 +95,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pmace_batch_poll.restype = ctypes.c_int
     L.pmace_batch_destroy.argtypes = [vp]
     L.pmace_batch_destroy.restype = None
+    L.pmace_simulate_footprint.argtypes = [i32, i32]
+    L.pmace_simulate_footprint.restype = sz
+    L.pmace_simulate.argtypes = [i32, i32, i32, i32, vp, vp, vp, ctypes.c_double, ctypes.c_uint64, vp,
+                                 vp, sz, ctypes.POINTER(ctypes.c_double), vp]
+    L.pmace_simulate.restype = ctypes.c_int
+    L.pmace_philox4x32_10.argtypes = [vp, i32, vp]
+    L.pmace_philox4x32_10.restype = ctypes.c_int
+    L.pmace_poisson.argtypes = [vp, vp, i32, ctypes.c_uint64, vp]
+    L.pmace_poisson.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -235,6 +244,66 @@ def fft2(x, inverse: bool = False, stream=None):
                       ctypes.c_void_p(out.data_ptr()), 1 if inverse else 0, _stream_ptr(stream)),
            "pmace_fft2")
     return out
+
+
+def simulate(x, probe, pos, peak, seed: int, device="cuda", stream=None):
+    """Intensities |F D P_j x|^2 (eq. (1)) on the device, Poisson at peak rate
+    `peak` with the global-max scaling of eq. (16) when peak > 0.
+    Returns (z float32 CUDA tensor (J, Np, Np), scale = peak / max I)."""
+    torch = _torch()
+    dev = torch.device(device)
+    x_t = to_device_c64(x, dev)
+    d_t = to_device_c64(probe, dev)
+    pos_t = torch.as_tensor(np.asarray(pos, dtype=np.int32)).to(dev).contiguous()
+    n1, n2 = x_t.shape
+    np_ = d_t.shape[-1]
+    J = pos_t.shape[0]
+    z = torch.empty((J, np_, np_), dtype=torch.float32, device=dev)
+    fp = int(load_library().pmace_simulate_footprint(np_, J))
+    ws = torch.empty(fp, dtype=torch.uint8, device=dev)
+    scale = ctypes.c_double()
+    _check(load_library().pmace_simulate(n1, n2, np_, J, ctypes.c_void_p(d_t.data_ptr()),
+                                         ctypes.c_void_p(pos_t.data_ptr()),
+                                         ctypes.c_void_p(x_t.data_ptr()), float(peak or 0.0),
+                                         int(seed), ctypes.c_void_p(z.data_ptr()),
+                                         ctypes.c_void_p(ws.data_ptr()), fp, ctypes.byref(scale),
+                                         _stream_ptr(stream)), "pmace_simulate")
+    return z, scale.value
+
+
+def simulated_problem(n, np_, scan, step, peak, seed, device="cuda"):
+    """A synth problem (object, probe, positions from the seeded generator)
+    whose intensities are simulated on the device; z stays a CUDA tensor and
+    the probe carries the photon scaling."""
+    from . import synth
+    rng = np.random.default_rng(seed)
+    x = synth.make_object(n, n, rng)
+    d = synth.make_probe(np_)
+    pos = synth.make_positions(n, np_, scan, step, rng)
+    z, scale = simulate(x, d, pos, peak, seed, device=device)
+    return synth.Problem(x_true=x, probe=d * np.sqrt(scale), pos=pos, z=z, peak_photons=peak,
+                         name=f"sim{seed}")
+
+
+def philox4x32_10(records):
+    """Philox4x32-10 on the device for (n, 6) uint32 records (counter[4], key[2])."""
+    torch = _torch()
+    r = np.ascontiguousarray(np.asarray(records, dtype=np.uint32))
+    t = torch.from_numpy(r.view(np.int32)).cuda()
+    _check(load_library().pmace_philox4x32_10(ctypes.c_void_p(t.data_ptr()), r.shape[0],
+                                              _stream_ptr()), "pmace_philox4x32_10")
+    return t.cpu().numpy().view(np.uint32)[:, :4]
+
+
+def poisson(lam, seed: int):
+    """The device Poisson sampler on given means (element i uses stream i)."""
+    torch = _torch()
+    lam_t = torch.as_tensor(np.asarray(lam, dtype=np.float64)).cuda().contiguous()
+    out = torch.empty(lam_t.numel(), dtype=torch.float32, device="cuda")
+    _check(load_library().pmace_poisson(ctypes.c_void_p(lam_t.data_ptr()),
+                                        ctypes.c_void_p(out.data_ptr()), lam_t.numel(), int(seed),
+                                        _stream_ptr()), "pmace_poisson")
+    return out.cpu().numpy()
 
 
 class Reconstruction:
