@@ -46,6 +46,10 @@ typedef enum {
  * (fftshift layout); they are reordered once at init. */
 #define PMACE_CENTERED_DC 0x1u
 
+/* Iteration run by a context (pmace_params.method). */
+#define PMACE_METHOD_PMACE 0      /* Alg. 1: Mann iteration of T = (2G - I)(2F - I) */
+#define PMACE_METHOD_SHARP_PLUS 1 /* Alg. 2: SHARP+ on frames s_j = D P_j x (Sec. III-B) */
+
 typedef struct {
   int32_t n1, n2;     /* object grid N1 x N2 (Sec. II); n1, n2 >= np */
   int32_t np;         /* probe / patch side Np; this build runs 32, 64, 128, 256 */
@@ -55,6 +59,8 @@ typedef struct {
   float rho;          /* 0 < rho < 1: Mann averaging parameter, eq. (13) */
   uint32_t flags;     /* PMACE_CENTERED_DC or 0 */
   int32_t chunk;      /* Np = 256 only: positions per staging chunk (>= 1, capped at J), 0 = 128 */
+  int32_t method;     /* PMACE_METHOD_PMACE (alpha, kappa, rho used) or PMACE_METHOD_SHARP_PLUS */
+  float beta;         /* SHARP+ relaxation, 0 <= beta <= 1 (Alg. 2); ignored by PMACE */
 } pmace_params;
 
 typedef struct pmace_ctx pmace_ctx;      /* one reconstruction */

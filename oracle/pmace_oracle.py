@@ -41,7 +41,8 @@ __all__ = [
     "fourier_magnitude_step", "agent", "agent_stack", "consensus",
     "weighted_average", "T_operator", "pmace_step", "PMACEState",
     "pmace_init", "pmace_iterate", "pmace_solve", "reconstruct", "nrmse",
-    "data_fit_cost",
+    "data_fit_cost", "sharp_magnitude_projection", "sharp_overlap_projection",
+    "sharp_plus_init", "sharp_plus_step", "sharp_plus_reconstruct",
 ]
 
 
@@ -257,3 +258,43 @@ def data_fit_cost(v: np.ndarray, d: np.ndarray, y: np.ndarray,
     """sum_j f_j(v_j) = sum_j ||y_j - |F D v_j|||^2 / (2 sigma_n^2) (eq. (4))."""
     W = dft2(np.asarray(d, dtype=np.complex128) * v)
     return float(np.sum((y - np.abs(W)) ** 2) / (2.0 * sigma_n2))
+
+
+# --------------------------------------------------------------------------
+# SHARP+ (Sec. III-B, eqs. (14)-(15), Alg. 2), the paper's comparison method
+# built from the same operators.  It acts on frames s_j = D P_j x.
+# --------------------------------------------------------------------------
+
+def sharp_magnitude_projection(s, y):
+    """P_a: F^*( y F s / |F s| ) per frame (eq. (14)); 0 where F s = 0."""
+    return idft2(fourier_magnitude_step(dft2(s), y))
+
+
+def sharp_overlap_projection(s, d, pos, shape):
+    """P_Q: D P_j (sum_k P_k^t |D|^2)^{-1} sum_i P_i^t D^* s_i (eq. (15))."""
+    d = np.asarray(d, dtype=np.complex128)
+    num = back_project(np.conj(d) * s, pos, shape)
+    lam = back_project(np.broadcast_to(np.abs(d) ** 2, s.shape), pos, shape)
+    img = inv_weight_image(lam.real) * num
+    return d * extract(img, pos, d.shape[0])
+
+
+def sharp_plus_init(x0, d, pos):
+    """Alg. 2 initialisation: s_j = D P_j x^(0)."""
+    return np.asarray(d, dtype=np.complex128) * extract(np.asarray(x0, dtype=np.complex128), pos,
+                                                         np.asarray(d).shape[0])
+
+
+def sharp_plus_step(s, d, y, pos, shape, beta):
+    """s <- [2 beta P_Q P_a + (1 - 2 beta) P_a - beta (P_Q - I)] s  (Alg. 2 loop body)."""
+    pa = sharp_magnitude_projection(s, y)
+    return (2.0 * beta * sharp_overlap_projection(pa, d, pos, shape) + (1.0 - 2.0 * beta) * pa
+            - beta * (sharp_overlap_projection(s, d, pos, shape) - s))
+
+
+def sharp_plus_reconstruct(s, d, pos, shape):
+    """Alg. 2 output: (sum_k P_k^t |D|^2)^{-1} sum_j P_j^t D^* s_j."""
+    d = np.asarray(d, dtype=np.complex128)
+    num = back_project(np.conj(d) * s, pos, shape)
+    lam = back_project(np.broadcast_to(np.abs(d) ** 2, s.shape), pos, shape)
+    return inv_weight_image(lam.real) * num

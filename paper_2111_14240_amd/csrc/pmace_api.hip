@@ -115,6 +115,9 @@ pmace_status check_params(const pmace_params* p) {
   if (!(std::isfinite(p->rho) && p->rho > 0.f && p->rho < 1.f)) return PMACE_EINVAL;
   if (p->flags & ~PMACE_CENTERED_DC) return PMACE_EINVAL;
   if (p->chunk < 0) return PMACE_EINVAL;
+  if (p->method != PMACE_METHOD_PMACE && p->method != PMACE_METHOD_SHARP_PLUS) return PMACE_EINVAL;
+  if (p->method == PMACE_METHOD_SHARP_PLUS && !(std::isfinite(p->beta) && p->beta >= 0.f && p->beta <= 1.f))
+    return PMACE_EINVAL;
   if ((long long)p->n1 * p->n2 > (1LL << 30)) return PMACE_EINVAL;
   if (!np_supported(p->np)) return PMACE_EUNSUPPORTED;
   return PMACE_OK;
@@ -257,12 +260,22 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
 
   // |d|^kappa, d^{-1} (scaled by 1/Np^2: the unnormalised forward+inverse
   // DFT pair), the d == 0 mask, and Lambda^{-1} (0 where Lambda = 0).
+  // SHARP+ (eq. (15)): weights conj(d) over the normaliser sum_k P_k^t |d|^2.
+  const bool sharp = p.method == PMACE_METHOD_SHARP_PLUS;
   std::vector<float> pc(4 * np2);
   std::vector<double> omega(np2);
   const double inv_np2 = 1.0 / ((double)np * np);
   for (size_t i = 0; i < np2; ++i) {
     const std::complex<double> dd(probe[i].real(), probe[i].imag());
     const double mag = std::abs(dd);
+    if (sharp) {
+      omega[i] = mag * mag;
+      pc[4 * i + 0] = (float)(dd.real() * inv_np2);
+      pc[4 * i + 1] = (float)(-dd.imag() * inv_np2);
+      pc[4 * i + 2] = (float)dd.real();
+      pc[4 * i + 3] = (float)(-dd.imag());
+      continue;
+    }
     omega[i] = std::pow(mag, (double)p.kappa);
     std::complex<double> di(0.0, 0.0);
     if (mag != 0.0) di = inv_np2 / dd;
@@ -362,9 +375,20 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   h.n2 = n2;
   h.np = np;
   h.J = J;
-  h.a = p.alpha / (1.f + p.alpha);
-  h.two_rho = 2.f * p.rho;
-  h.rho = p.rho;
+  h.method = p.method;
+  if (sharp) {
+    h.beta = p.beta;
+    h.a = 0.f;
+    h.two_rho = 2.f * p.beta;
+    h.rho = 1.f;
+    h.ka = (float)((1.0 - 2.0 * (double)p.beta) * inv_np2);
+  } else {
+    h.beta = 0.f;
+    h.a = p.alpha / (1.f + p.alpha);
+    h.two_rho = 2.f * p.rho;
+    h.rho = p.rho;
+    h.ka = 0.f;
+  }
   h.chunk = chunk;
   h.n_red = nred;
   c->dev = reinterpret_cast<Recon*>(base + L.desc);
@@ -392,7 +416,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
       hipMemcpyAsync(c->dev, &c->h, sizeof(Recon), hipMemcpyHostToDevice, st) != hipSuccess)
     return fail(PMACE_EDEVICE);
   hipLaunchKernelGGL(reset_tracking_k, dim3(1), dim3(1), 0, st, h.done, h.track);
-  const float yscale = (float)((double)np / (1.0 + (double)p.alpha));
+  const float yscale = (float)((double)np / (sharp ? 1.0 : 1.0 + (double)p.alpha));
   if (hipGetLastError() != hipSuccess ||
       pmace::launch_init(h, c->dev, intensity_d, yscale, (p.flags & PMACE_CENTERED_DC) ? 1 : 0,
                          reinterpret_cast<const float2*>(x0_d), st) != hipSuccess)
@@ -546,6 +570,7 @@ pmace_status check_members(pmace_ctx* const* ctxs, int32_t n) {
   if (!ctxs || n < 1) return PMACE_EINVAL;
   for (int i = 0; i < n; ++i) {
     if (!ctxs[i]) return PMACE_ESTATE;
+    if (ctxs[i]->prm.method != PMACE_METHOD_PMACE) return PMACE_EUNSUPPORTED;
     if (ctxs[i]->stream != ctxs[0]->stream || ctxs[i]->device != ctxs[0]->device) return PMACE_EINVAL;
     for (int k = 0; k < i; ++k)
       if (ctxs[k] == ctxs[i]) return PMACE_EINVAL;

@@ -40,6 +40,10 @@ struct Recon {
   float rho;
   int chunk;            // positions per chunk (all J when Np <= 128)
   int n_red;            // NRMSE reduction blocks
+  int method;           // 0 PMACE, 1 SHARP+
+  float beta;           // SHARP+: beta;  the state is then t with s = t + 2 beta d P_j xbar,
+  float ka;             //   two_rho = 2 beta, a = 0, rho = 1, ka = (1 - 2 beta)/Np^2, and
+                        //   pc = {conj(d)/Np^2, conj(d)}, laminv = 1/sum P^t |d|^2
 };
 
 // Kernel launchers (stream-ordered; return the hipError_t of the launches).

@@ -51,12 +51,42 @@ __device__ __forceinline__ float2 mann_v(float2 t, float2 xb, float two_rho) {
   return make_float2(fmaf(two_rho, xb.x, t.x), fmaf(two_rho, xb.y, t.y));
 }
 
+constexpr int kPMACE = 0, kSharpPlus = 1;
+
+// Prologue (a2-a3): the frame that is transformed.
+//   PMACE : d (t + 2 rho P_j xbar)           (v of Alg. 1 times the probe)
+//   SHARP+: t + 2 beta d P_j xbar            (the frame s of Alg. 2)
+template <int METHOD>
+__device__ __forceinline__ float2 agent_input(float2 t, float2 xb, float2 d, float two_rho) {
+  if constexpr (METHOD == kPMACE) return cmul(d, mann_v(t, xb, two_rho));
+  else return mann_v(t, cmul(d, xb), two_rho);
+}
+
+// Epilogue (a6-a8) from the unnormalised inverse transform z.
+//   PMACE : see finish_pixel.
+//   SHARP+: a = z/Np^2 = P_a s; the next state t = (1 - 2 beta) a + beta s -
+//           beta d P_j xbar (P_Q s of this iteration is d P_j xbar of the last
+//           one: P_Q is a projection, so P_Q s_{k+1} = P_Q P_a s_k), and the
+//           overlap numerator takes conj(d) a.  pcf = {conj(d)/Np^2, conj(d)}.
+template <int METHOD>
+__device__ __forceinline__ void agent_output(float2 z, float2 t_old, float2 xb, float4 pcf,
+                                             const Recon& g, float2* t_out, float2* u_out) {
+  if constexpr (METHOD == kPMACE) {
+    finish_pixel(z, mann_v(t_old, xb, g.two_rho), pcf, g.two_rho, t_out, u_out);
+  } else {
+    const float2 dx = cmul(make_float2(pcf.z, -pcf.w), xb);
+    const float2 sv = mann_v(t_old, dx, g.two_rho);
+    *t_out = make_float2(fmaf(g.ka, z.x, g.beta * (sv.x - dx.x)), fmaf(g.ka, z.y, g.beta * (sv.y - dx.y)));
+    *u_out = cmul(make_float2(pcf.x, pcf.y), z);
+  }
+}
+
 // -------------------------------------------------------------------------
 // Np <= 128: the whole patch lives in LDS; one workgroup per work item
 // (reconstruction, position) does a2-a8 in one pass (rows, columns, prox,
 // columns, rows, epilogue).
 // -------------------------------------------------------------------------
-template <int NP>
+template <int NP, int METHOD>
 __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, S = NP + A, NT = NP * A, M = B / A;
   __shared__ float2 tile[NP * S];
@@ -74,7 +104,7 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) {
     const int c = p + A * nb;
-    x[nb] = cmul(g.d[r * NP + c], mann_v(trow[c], xrow[c], two_rho));
+    x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], two_rho);
   }
   __syncthreads();
   float2* row = tile + r * S;
@@ -115,15 +145,14 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) {
     const int cc = p + A * nb;
-    const float2 v = mann_v(trow[cc], xrow[cc], two_rho);
-    finish_pixel(x[nb], v, g.pc[r * NP + cc], two_rho, &trow[cc], &urow[cc]);
+    agent_output<METHOD>(x[nb], trow[cc], xrow[cc], g.pc[r * NP + cc], g, &trow[cc], &urow[cc]);
   }
 }
 
 // One reconstruction (descriptor passed by value): block b handles position b.
-template <int NP>
+template <int NP, int METHOD>
 __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused(const Recon g) {
-  agent_fused_body<NP>(g, blockIdx.x);
+  agent_fused_body<NP, METHOD>(g, blockIdx.x);
 }
 
 // Batched: block b handles work item (reconstruction, position) b.
@@ -133,7 +162,7 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused_batch(const Recon
   const int2 it = items[blockIdx.x];
   const Recon& g = recs[it.x];
   if (*g.done) return;
-  agent_fused_body<NP>(g, it.y);
+  agent_fused_body<NP, kPMACE>(g, it.y);
 }
 
 // -------------------------------------------------------------------------
@@ -148,6 +177,7 @@ constexpr int NP256 = 256;
 constexpr int RB = 16;   // rows per workgroup in the row passes
 constexpr int CB = 16;   // columns per workgroup in the column pass
 
+template <int METHOD>
 __device__ __forceinline__ void agent256_rows_body(const Recon& g, const int j0) {
   constexpr int NP = NP256, A = 16, S = NP + A;
   __shared__ float2 tile[RB * S];
@@ -164,7 +194,7 @@ __device__ __forceinline__ void agent256_rows_body(const Recon& g, const int j0)
 #pragma unroll
   for (int nb = 0; nb < 16; ++nb) {
     const int c = p + A * nb;
-    x[nb] = cmul(g.d[r * NP + c], mann_v(trow[c], xrow[c], g.two_rho));
+    x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], g.two_rho);
   }
   __syncthreads();
   row_fwd<NP>(x, tile + rl * S, p, tw);
@@ -173,11 +203,14 @@ __device__ __forceinline__ void agent256_rows_body(const Recon& g, const int j0)
   for (int ka = 0; ka < 16; ++ka) out[p + 16 * ka] = x[ka];
 }
 
-__global__ void __launch_bounds__(RB * 16) agent256_rows(const Recon g, int j0) { agent256_rows_body(g, j0); }
+template <int METHOD>
+__global__ void __launch_bounds__(RB * 16) agent256_rows(const Recon g, int j0) {
+  agent256_rows_body<METHOD>(g, j0);
+}
 
 __global__ void __launch_bounds__(RB * 16) agent256_rows_batch(const Recon* __restrict__ rec, int j0) {
   if (*rec->done) return;
-  agent256_rows_body(*rec, j0);
+  agent256_rows_body<kPMACE>(*rec, j0);
 }
 
 __device__ __forceinline__ void agent256_cols_body(const Recon& g, const int j0) {
@@ -214,6 +247,7 @@ __global__ void __launch_bounds__(CB * 16) agent256_cols_batch(const Recon* __re
   agent256_cols_body(*rec, j0);
 }
 
+template <int METHOD>
 __device__ __forceinline__ void agent256_rowsinv_body(const Recon& g, const int j0) {
   constexpr int NP = NP256, A = 16, S = NP + A;
   __shared__ float2 tile[RB * S];
@@ -236,16 +270,18 @@ __device__ __forceinline__ void agent256_rowsinv_body(const Recon& g, const int 
 #pragma unroll
   for (int nb = 0; nb < 16; ++nb) {
     const int c = p + A * nb;
-    const float2 v = mann_v(trow[c], xrow[c], two_rho);
-    finish_pixel(x[nb], v, g.pc[r * NP + c], two_rho, &trow[c], &io[c]);
+    agent_output<METHOD>(x[nb], trow[c], xrow[c], g.pc[r * NP + c], g, &trow[c], &io[c]);
   }
 }
 
-__global__ void __launch_bounds__(RB * 16) agent256_rowsinv(const Recon g, int j0) { agent256_rowsinv_body(g, j0); }
+template <int METHOD>
+__global__ void __launch_bounds__(RB * 16) agent256_rowsinv(const Recon g, int j0) {
+  agent256_rowsinv_body<METHOD>(g, j0);
+}
 
 __global__ void __launch_bounds__(RB * 16) agent256_rowsinv_batch(const Recon* __restrict__ rec, int j0) {
   if (*rec->done) return;
-  agent256_rowsinv_body(*rec, j0);
+  agent256_rowsinv_body<kPMACE>(*rec, j0);
 }
 
 // -------------------------------------------------------------------------
@@ -455,7 +491,10 @@ __global__ void init_patches_k(const Recon* __restrict__ rec, const float2* x0) 
   const int rem = (int)(i - (long long)j * per);
   const int r = rem / g.np, c = rem - r * g.np;
   const int2 pj = g.pos[j];
-  g.t[i] = x0 ? x0[(size_t)(pj.x + r) * g.n2 + pj.y + c] : make_float2(1.f, 0.f);
+  const float2 x = x0 ? x0[(size_t)(pj.x + r) * g.n2 + pj.y + c] : make_float2(1.f, 0.f);
+  // Alg. 1: v_j = P_j x0.  Alg. 2: s_j = D P_j x0, held as t = s - 2 beta d P_j xbar
+  // with xbar = x0 (the overlap image of consistent frames), i.e. (1 - 2 beta) d x0.
+  g.t[i] = g.method == kSharpPlus ? cscale(cmul(g.d[rem], x), 1.f - g.two_rho) : x;
 }
 
 __global__ void init_images_k(const Recon* __restrict__ rec, const float2* x0) {
@@ -464,7 +503,7 @@ __global__ void init_images_k(const Recon* __restrict__ rec, const float2* x0) {
   if (i >= g.n1 * g.n2) return;
   const float2 x = x0 ? x0[i] : make_float2(1.f, 0.f);
   g.xhat[i] = g.laminv[i] > 0.f ? x : make_float2(0.f, 0.f);
-  g.xbar[i] = make_float2(0.f, 0.f);
+  g.xbar[i] = g.method == kSharpPlus ? g.xhat[i] : make_float2(0.f, 0.f);
   g.num[i] = make_float2(0.f, 0.f);
 }
 
@@ -477,7 +516,9 @@ __global__ void get_state_k(const Recon* __restrict__ rec, float2* v) {
   const int rem = (int)(i - (long long)j * per);
   const int r = rem / g.np, c = rem - r * g.np;
   const int2 pj = g.pos[j];
-  v[i] = mann_v(g.t[i], g.xbar[(size_t)(pj.x + r) * g.n2 + pj.y + c], g.two_rho);
+  const float2 xb = g.xbar[(size_t)(pj.x + r) * g.n2 + pj.y + c];
+  // PMACE: v = t + 2 rho P_j xbar;  SHARP+: s = t + 2 beta d P_j xbar
+  v[i] = mann_v(g.t[i], g.method == kSharpPlus ? cmul(g.d[rem], xb) : xb, g.two_rho);
 }
 
 // t <- v and stage <- |d|^kappa v for positions [j0, j0 + cnt) (stage indexed from j0)
@@ -489,8 +530,33 @@ __global__ void set_state_k(const Recon* __restrict__ rec, const float2* v, int 
   const long long gi = (long long)j0 * per + i;
   const float2 vv = v[gi];
   g.t[gi] = vv;
-  const float om = g.pc[i % per].z;
-  g.stage[i] = make_float2(om * vv.x, om * vv.y);
+  const float4 pcf = g.pc[i % per];
+  // weights of the average: |d|^kappa (PMACE) or conj(d) (SHARP+, eq. (15))
+  g.stage[i] = g.method == kSharpPlus ? cmul(make_float2(pcf.z, pcf.w), vv)
+                                      : make_float2(pcf.z * vv.x, pcf.z * vv.y);
+}
+
+// SHARP+ after set_state: xbar = the overlap image of s (just left in xhat),
+// then t = s - 2 beta d P_j xbar so that s = t + 2 beta d P_j xbar.
+__global__ void sharp_image_k(const Recon* __restrict__ rec) {
+  const Recon& g = *rec;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n1 * g.n2) return;
+  g.xbar[i] = g.xhat[i];
+}
+
+__global__ void sharp_state_k(const Recon* __restrict__ rec) {
+  const Recon& g = *rec;
+  const long long per = (long long)g.np * g.np;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= per * g.J) return;
+  const int j = (int)(i / per);
+  const int rem = (int)(i - (long long)j * per);
+  const int r = rem / g.np, c = rem - r * g.np;
+  const int2 pj = g.pos[j];
+  const float2 dx = cmul(g.d[rem], g.xbar[(size_t)(pj.x + r) * g.n2 + pj.y + c]);
+  const float2 t = g.t[i];
+  g.t[i] = make_float2(fmaf(-g.two_rho, dx.x, t.x), fmaf(-g.two_rho, dx.y, t.y));
 }
 
 __global__ void zero_images_k(const Recon* __restrict__ rec) {
@@ -622,7 +688,10 @@ hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_
   switch (np) {
 #define PMACE_SMALL(N)                                                                            \
   case N:                                                                                         \
-    hipLaunchKernelGGL(agent_fused<N>, dim3(h.J), dim3(N * Geo<N>::A), 0, st, h);                 \
+    if (h.method == kSharpPlus)                                                                   \
+      hipLaunchKernelGGL((agent_fused<N, kSharpPlus>), dim3(h.J), dim3(N * Geo<N>::A), 0, st, h); \
+    else                                                                                          \
+      hipLaunchKernelGGL((agent_fused<N, kPMACE>), dim3(h.J), dim3(N * Geo<N>::A), 0, st, h);     \
     if (ntiles > 0)                                                                               \
       hipLaunchKernelGGL((consensus_gather<N, true>), dim3(ntiles), dim3(GT_R * GT_C), 0, st, h,  \
                          0, 0);                                                                   \
@@ -668,9 +737,15 @@ hipError_t launch_256_iteration(const Recon& h, const Recon* batch_rec, const in
       hipLaunchKernelGGL(agent256_cols_batch, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, batch_rec, j0);
       hipLaunchKernelGGL(agent256_rowsinv_batch, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, batch_rec, j0);
     } else {
-      hipLaunchKernelGGL(agent256_rows, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
-      hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
-      hipLaunchKernelGGL(agent256_rowsinv, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
+      if (h.method == kSharpPlus) {
+        hipLaunchKernelGGL(agent256_rows<kSharpPlus>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
+        hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
+        hipLaunchKernelGGL(agent256_rowsinv<kSharpPlus>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
+      } else {
+        hipLaunchKernelGGL(agent256_rows<kPMACE>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
+        hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
+        hipLaunchKernelGGL(agent256_rowsinv<kPMACE>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
+      }
     }
     if (ct.y > 0) {
       if (batch_rec) {
@@ -734,6 +809,10 @@ hipError_t launch_set_state(const Recon& h, const Recon* rec, const float2* v,
     }
   }
   hipLaunchKernelGGL(image_from_num, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec);
+  if (h.method == kSharpPlus) {
+    hipLaunchKernelGGL(sharp_image_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec);
+    hipLaunchKernelGGL(sharp_state_k, dim3(blocks_for(per * h.J, 256)), dim3(256), 0, st, rec);
+  }
   return hipGetLastError();
 }
 

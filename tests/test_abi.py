@@ -99,3 +99,13 @@ def test_batch_argument_checks(lib):
     st, _ = P.pmace_nrmse(None)
     assert st == P.PMACE_ESTATE
     P.pmace_batch_destroy(None)
+
+
+@pytest.mark.parametrize("method,beta", [(2, 0.5), (-1, 0.5), (1, -0.1), (1, 1.5), (1, float("nan"))])
+def test_method_parameters_checked(lib, method, beta):
+    prm = P.make_params(128, 128, 32, 36, 0.5, method=method, beta=beta)
+    assert P.pmace_footprint(prm) == 0
+    st, _ = P.pmace_init(prm, 1, 1, 1, None, 1, 1 << 30, None)
+    assert st == P.PMACE_EINVAL
+    ok = P.make_params(128, 128, 32, 36, 0.5, method=P.PMACE_METHOD_SHARP_PLUS, beta=0.75)
+    assert P.pmace_footprint(ok) > 0
