@@ -126,7 +126,7 @@ pmace_status check_params(const pmace_params* p) {
 // Section offsets inside the workspace (relative to the aligned base).
 struct Layout {
   size_t t, ys, pos, d, pc, laminv, num, xbar, xhat, stage, tiles, list, status, desc, items,
-      gitems, ritems, red, total;
+      gitems, ritems, red, tw, total;
 };
 
 Layout layout_of(const pmace_params& p) {
@@ -153,6 +153,7 @@ Layout layout_of(const pmace_params& p) {
   L.gitems = o;  o = align_up(o + max_tiles(p) * 8);
   L.ritems = o;  o = align_up(o + (size_t)num_red(p) * 8);
   L.red = o;     o = align_up(o + (size_t)num_red(p) * 32);
+  L.tw = o;      o = align_up(o + 256 * 8);
   L.total = o;
   return L;
 }
@@ -369,6 +370,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   c->fitem = reinterpret_cast<int*>(base + L.status + 8);
   h.track = reinterpret_cast<double*>(base + L.status + 32);
   h.red = reinterpret_cast<double*>(base + L.red);
+  h.tw256 = reinterpret_cast<float2*>(base + L.tw);
   h.xref = nullptr;
   h.mask = nullptr;
   h.n1 = n1;
@@ -399,7 +401,16 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   c->chunk_tiles = chunk_tiles;
 
   const int zero = 0;
-  auto fail = [&](pmace_status e) { delete c; return e; };
+  std::vector<float> tw(512);
+  for (int m = 0; m < 256; ++m) {
+    const double cv = std::cos(-2.0 * M_PI * m / 256.0), sv = std::sin(-2.0 * M_PI * m / 256.0);
+    tw[2 * m] = std::fabs(cv) < 1e-15 ? 0.f : (float)cv;       // exact zeros at quarter turns
+    tw[2 * m + 1] = std::fabs(sv) < 1e-15 ? 0.f : (float)sv;
+  }
+  auto fail = [&](pmace_status e) {
+    pmace_destroy(c);
+    return e;
+  };
   if (hipMemcpyAsync(h.pos, pos.data(), (size_t)J * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.d, probe.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.pc, pc.data(), np2 * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
@@ -412,6 +423,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
        hipMemcpyAsync(c->gitems, gitems.data(), gitems.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess) ||
       hipMemcpyAsync(c->ritems, ritems.data(), ritems.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c->fitem, &zero, 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h.tw256, tw.data(), 256 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemsetAsync(h.status, 0, 4, st) != hipSuccess ||
       hipMemcpyAsync(c->dev, &c->h, sizeof(Recon), hipMemcpyHostToDevice, st) != hipSuccess)
     return fail(PMACE_EDEVICE);

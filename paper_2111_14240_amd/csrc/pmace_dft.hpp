@@ -124,7 +124,15 @@ template <> struct Geo<64>  { static constexpr int A = 8,  B = 8;  };
 template <> struct Geo<128> { static constexpr int A = 8,  B = 16; };
 template <> struct Geo<256> { static constexpr int A = 16, B = 16; };
 
-// W_N^m = exp(-2 pi i m / N) for m = 0..N-1 into LDS (FP64 sincospi, rounded once).
+// W_N^m = exp(-2 pi i m / N) for m = 0..N-1 into LDS from a table of W_256^m
+// (computed in FP64 on the host and rounded once): W_N^m = W_256^(m 256/N).
+template <int N> __device__ __forceinline__ void load_twiddles(float2* tw, const float2* tw256, int tid,
+                                                              int nthreads) {
+  for (int m = tid; m < N; m += nthreads) tw[m] = tw256[m * (256 / N)];
+}
+
+// The same values computed in place (FP64 sincospi, rounded once), for the
+// standalone transform, which has no workspace.
 template <int N> __device__ __forceinline__ void fill_twiddles(float2* tw, int tid, int nthreads) {
   for (int m = tid; m < N; m += nthreads) {
     double s, c;

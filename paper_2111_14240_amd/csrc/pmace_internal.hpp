@@ -26,6 +26,7 @@ struct Recon {
   float2* xhat;         // N1*N2     reconstruction (Alg. 1 output, kept by recurrence)
   float2* stage;        // chunk*Np*Np: Np = 256 spectra between passes; for every Np the
                         //   weighted reflections |d|^kappa (2w - v) the consensus sums
+  float2* tw256;        // 256      W_256^m = exp(-2 pi i m/256), FP64-rounded twiddles
   int4* tiles;          // per gather tile: (list start, count, first row, first col)
   int* tile_list;       // positions overlapping each tile, ascending
   unsigned* status;     // bit0: non-finite consensus image; bit1: bad intensity

@@ -92,7 +92,7 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
   __shared__ float2 tile[NP * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  fill_twiddles<NP>(tw, tid, NT);
+  load_twiddles<NP>(tw, g.tw256, tid, NT);
   const int2 pj = g.pos[j];
   const size_t pb = (size_t)j * NP * NP;
   const int r = tid / A, p = tid % A;
@@ -183,7 +183,7 @@ __device__ __forceinline__ void agent256_rows_body(const Recon& g, const int j0)
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  fill_twiddles<NP>(tw, tid, RB * A);
+  load_twiddles<NP>(tw, g.tw256, tid, RB * A);
   const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
   const int j = j0 + jl;
   const int2 pj = g.pos[j];
@@ -218,7 +218,7 @@ __device__ __forceinline__ void agent256_cols_body(const Recon& g, const int j0)
   __shared__ float2 tile[NP * CB];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  fill_twiddles<NP>(tw, tid, CB * A);
+  load_twiddles<NP>(tw, g.tw256, tid, CB * A);
   const int jl = blockIdx.x / (NP / CB), cb = blockIdx.x % (NP / CB);
   const int j = j0 + jl;
   const int c = tid % CB, q = tid / CB, col = cb * CB + c;
@@ -253,7 +253,7 @@ __device__ __forceinline__ void agent256_rowsinv_body(const Recon& g, const int 
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  fill_twiddles<NP>(tw, tid, RB * A);
+  load_twiddles<NP>(tw, g.tw256, tid, RB * A);
   const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
   const int j = j0 + jl;
   const int2 pj = g.pos[j];
@@ -296,20 +296,31 @@ __global__ void __launch_bounds__(RB * 16) agent256_rowsinv_batch(const Recon* _
 // -------------------------------------------------------------------------
 template <int NP, bool FUSE>
 __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int tile, const int jbase) {
+  constexpr int NT = GT_R * GT_C, LIST = 256;
+  __shared__ int3 sl[LIST];  // (stage slot, row, col) of the listed positions
   const int tid = threadIdx.x;
   const int4 ti = g.tiles[tile];
   const int R = ti.z + tid / GT_C, C = ti.w + tid % GT_C;
   float ax = 0.f, ay = 0.f;
-#pragma unroll 4
-  for (int i = 0; i < ti.y; ++i) {
-    const int j = g.tile_list[ti.x + i];
-    const int2 pj = g.pos[j];
-    const unsigned rr = (unsigned)(R - pj.x), cc = (unsigned)(C - pj.y);
-    const bool in = rr < (unsigned)NP && cc < (unsigned)NP;
-    // lanes outside the patch read its first pixel and discard it
-    const float2 u = g.stage[((size_t)(j - jbase) * NP + (in ? rr : 0u)) * NP + (in ? cc : 0u)];
-    ax += in ? u.x : 0.f;
-    ay += in ? u.y : 0.f;
+  for (int b0 = 0; b0 < ti.y; b0 += LIST) {
+    const int nb = ti.y - b0 < LIST ? ti.y - b0 : LIST;
+    if (b0 > 0) __syncthreads();
+    for (int i = tid; i < nb; i += NT) {
+      const int j = g.tile_list[ti.x + b0 + i];
+      const int2 pj = g.pos[j];
+      sl[i] = make_int3(j - jbase, pj.x, pj.y);
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int i = 0; i < nb; ++i) {
+      const int3 e = sl[i];
+      const unsigned rr = (unsigned)(R - e.y), cc = (unsigned)(C - e.z);
+      const bool in = rr < (unsigned)NP && cc < (unsigned)NP;
+      // lanes outside the patch read its first pixel and discard it
+      const float2 u = g.stage[((size_t)e.x * NP + (in ? rr : 0u)) * NP + (in ? cc : 0u)];
+      ax += in ? u.x : 0.f;
+      ay += in ? u.y : 0.f;
+    }
   }
   if (R >= g.n1 || C >= g.n2) return;
   const size_t px = (size_t)R * g.n2 + C;
@@ -736,25 +747,22 @@ hipError_t launch_256_iteration(const Recon& h, const Recon* batch_rec, const in
       hipLaunchKernelGGL(agent256_rows_batch, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, batch_rec, j0);
       hipLaunchKernelGGL(agent256_cols_batch, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, batch_rec, j0);
       hipLaunchKernelGGL(agent256_rowsinv_batch, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, batch_rec, j0);
+    } else if (h.method == kSharpPlus) {
+      hipLaunchKernelGGL(agent256_rows<kSharpPlus>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
+      hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
+      hipLaunchKernelGGL(agent256_rowsinv<kSharpPlus>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
     } else {
-      if (h.method == kSharpPlus) {
-        hipLaunchKernelGGL(agent256_rows<kSharpPlus>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
-        hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
-        hipLaunchKernelGGL(agent256_rowsinv<kSharpPlus>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
-      } else {
-        hipLaunchKernelGGL(agent256_rows<kPMACE>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
-        hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
-        hipLaunchKernelGGL(agent256_rowsinv<kPMACE>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
-      }
+      hipLaunchKernelGGL(agent256_rows<kPMACE>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
+      hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
+      hipLaunchKernelGGL(agent256_rowsinv<kPMACE>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
     }
     if (ct.y > 0) {
-      if (batch_rec) {
+      if (batch_rec)
         hipLaunchKernelGGL((consensus_gather_member<256, false>), dim3(ct.y), dim3(GT_R * GT_C), 0,
                            st, batch_rec, ct.x, j0);
-      } else {
+      else
         hipLaunchKernelGGL((consensus_gather<256, false>), dim3(ct.y), dim3(GT_R * GT_C), 0, st, h,
                            ct.x, j0);
-      }
     }
   }
   const unsigned nb = blocks_for((long long)h.n1 * h.n2, 256);
