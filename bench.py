@@ -22,6 +22,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmace_hbm_traffic.md")
+KERNEL_SOURCES = ["pmace_kernels.hip", "pmace_dft.hpp", "pmace_internal.hpp", "pmace_api.hip"]
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 ALPHA = {"c1": 0.1, "c2": 0.5, "c3": 0.5}
 
@@ -36,6 +38,49 @@ def algorithmic_bytes(J, np_, n1, n2):
 def algorithmic_flops(J, np_):
     """Two 2-D FFTs (5 N log2 N per 1-D transform) + 36 pointwise flops per patch pixel."""
     return J * np_ * np_ * (20.0 * np.log2(np_) + 36.0)
+
+
+def kernel_source_hash():
+    """Hash of the sources the iteration kernels are built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2111_14240_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(config):
+    """HBM bytes per iteration measured with rocprofv3 counters (FETCH_SIZE and
+    WRITE_SIZE, each scaled by the same counter on a plain copy of known size),
+    or None if not measured for the current kernel sources.  Read from the
+    table row '| <config> | <source hash> | ... | <bytes per iteration> |'."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            lines = f.read().splitlines()
+    except OSError:
+        return None
+    h = kernel_source_hash()
+    for ln in lines:
+        cells = [c.strip() for c in ln.strip().strip("|").split("|")]
+        if len(cells) >= 3 and cells[0] == config and cells[1] == h:
+            try:
+                return float(cells[-1])
+            except ValueError:
+                return None
+    return None
+
+
+def calibration_copy(mib):
+    """A plain device copy of known size (outside any timed region) whose
+    FETCH_SIZE / WRITE_SIZE calibrate the counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
 
 
 def cpu_baseline(prob, alpha, kappa, rho):
@@ -191,6 +236,8 @@ def main():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
     ap.add_argument("--chunk", type=int, default=0, help="Np=256 staging chunk (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="after the run, copy this many MiB three times (counter calibration)")
     ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
     ap.add_argument("--items", type=int, default=64, help="batch mode: reconstructions")
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests")
@@ -266,7 +313,7 @@ def main():
                    "iteration_graph": "one HIP graph replay per step"},
         "roofline": {"bound": "hbm", "kernel": "one PMACE iteration (agent passes + image update)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
                      "algorithmic_bytes_per_step": B},
         "alu": {"algorithmic_flops_per_step": Fl,
                 "achieved_tflops": Fl / (ms_per_step / 1e3) / 1e12,
@@ -276,6 +323,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, alpha, kappa, rho)
+    if args.copy_mib:
+        calibration_copy(args.copy_mib)
     print(json.dumps(out), flush=True)
 
 
