@@ -125,9 +125,16 @@ pmace_status check_params(const pmace_params* p) {
 
 // Section offsets inside the workspace (relative to the aligned base).
 struct Layout {
-  size_t t, ys, pos, d, pc, laminv, num, xbar, xhat, stage, tiles, list, status, desc, items,
-      gitems, ritems, red, tw, total;
+  size_t t, ys, pos, d, pc, omega, laminv, num, sold, xbar, xhat, stage, tiles, list, status, desc,
+      items, gitems, ritems, red, tw, total;
 };
+
+// Stage buffer: Np = 256 keeps a chunk's spectra between its passes; SHARP+
+// keeps its overlap numerators there; PMACE with Np <= 128 needs none.
+size_t stage_patches(const pmace_params& p) {
+  if (p.np == 256) return (size_t)chunk_of(p);
+  return p.method == PMACE_METHOD_SHARP_PLUS ? (size_t)chunk_of(p) : 0;
+}
 
 Layout layout_of(const pmace_params& p) {
   Layout L;
@@ -140,11 +147,13 @@ Layout layout_of(const pmace_params& p) {
   L.pos = o;     o = align_up(o + (size_t)p.num_pos * 8);
   L.d = o;       o = align_up(o + np2 * 8);
   L.pc = o;      o = align_up(o + np2 * 16);
+  L.omega = o;   o = align_up(o + np2 * 4);
   L.laminv = o;  o = align_up(o + npx * 4);
   L.num = o;     o = align_up(o + npx * 8);
+  L.sold = o;    o = align_up(o + npx * 8);
   L.xbar = o;    o = align_up(o + npx * 8);
   L.xhat = o;    o = align_up(o + npx * 8);
-  L.stage = o;   o = align_up(o + (size_t)chunk_of(p) * np2 * 8);
+  L.stage = o;   o = align_up(o + stage_patches(p) * np2 * 8);
   L.tiles = o;   o = align_up(o + max_tiles(p) * 16);
   L.list = o;    o = align_up(o + max_list(p) * 4);
   L.status = o;  o = align_up(o + 64);  // status word, stop flag, finish item, NRMSE track[4]
@@ -263,7 +272,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   // DFT pair), the d == 0 mask, and Lambda^{-1} (0 where Lambda = 0).
   // SHARP+ (eq. (15)): weights conj(d) over the normaliser sum_k P_k^t |d|^2.
   const bool sharp = p.method == PMACE_METHOD_SHARP_PLUS;
-  std::vector<float> pc(4 * np2);
+  std::vector<float> pc(4 * np2), omega_f(np2);
   std::vector<double> omega(np2);
   const double inv_np2 = 1.0 / ((double)np * np);
   for (size_t i = 0; i < np2; ++i) {
@@ -296,6 +305,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   }
   std::vector<float> laminv(npx);
   for (size_t i = 0; i < npx; ++i) laminv[i] = lam[i] != 0.0 ? (float)(1.0 / lam[i]) : 0.f;
+  for (size_t i = 0; i < np2; ++i) omega_f[i] = (float)omega[i];
 
   // Gather tables: per chunk, GT_R x GT_C tiles over the rows its patches
   // cover, each with the chunk's positions overlapping it in ascending order.
@@ -358,8 +368,10 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   h.pos = reinterpret_cast<int2*>(base + L.pos);
   h.d = reinterpret_cast<float2*>(base + L.d);
   h.pc = reinterpret_cast<float4*>(base + L.pc);
+  h.omega = reinterpret_cast<float*>(base + L.omega);
   h.laminv = reinterpret_cast<float*>(base + L.laminv);
   h.num = reinterpret_cast<float2*>(base + L.num);
+  h.sold = reinterpret_cast<float2*>(base + L.sold);
   h.xbar = reinterpret_cast<float2*>(base + L.xbar);
   h.xhat = reinterpret_cast<float2*>(base + L.xhat);
   h.stage = reinterpret_cast<float2*>(base + L.stage);
@@ -390,6 +402,11 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
     h.two_rho = 2.f * p.rho;
     h.rho = p.rho;
     h.ka = 0.f;
+    const double rho = p.rho, a = (double)p.alpha / (1.0 + (double)p.alpha);
+    h.tb = (float)(1.0 - 2.0 * rho * a);
+    h.cx = (float)(2.0 * (1.0 - rho));
+    h.co = (float)((1.0 - rho) / rho);
+    h.cn = (float)(1.0 / rho);
   }
   h.chunk = chunk;
   h.n_red = nred;
@@ -414,6 +431,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   if (hipMemcpyAsync(h.pos, pos.data(), (size_t)J * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.d, probe.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.pc, pc.data(), np2 * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h.omega, omega_f.data(), np2 * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.laminv, laminv.data(), npx * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.tiles, tiles.data(), tiles.size() * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
       (!list.empty() &&
@@ -431,7 +449,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   const float yscale = (float)((double)np / (sharp ? 1.0 : 1.0 + (double)p.alpha));
   if (hipGetLastError() != hipSuccess ||
       pmace::launch_init(h, c->dev, intensity_d, yscale, (p.flags & PMACE_CENTERED_DC) ? 1 : 0,
-                         reinterpret_cast<const float2*>(x0_d), st) != hipSuccess)
+                         reinterpret_cast<const float2*>(x0_d), c->chunk_tiles.data(), st) != hipSuccess)
     return fail(PMACE_EDEVICE);
   unsigned status = 0;
   if (hipMemcpyAsync(&status, h.status, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||

@@ -20,12 +20,14 @@ struct Recon {
   int2* pos;            // J         (row, col) top-left of P_j
   float2* d;            // Np*Np     probe
   float4* pc;           // Np*Np     {Re, Im of d^{-1}/Np^2, |d|^kappa, [d == 0]}
+  float* omega;         // Np*Np     |d|^kappa (PMACE consensus weights)
   float* laminv;        // N1*N2     Lambda^{-1} (0 where Lambda = 0)
   float2* num;          // N1*N2     weighted back-projection accumulator (Np = 256)
+  float2* sold;         // N1*N2     PMACE: S = sum_j P_j^t |d|^kappa t_j of the current states
   float2* xbar;         // N1*N2     consensus image of the last iteration
   float2* xhat;         // N1*N2     reconstruction (Alg. 1 output, kept by recurrence)
-  float2* stage;        // chunk*Np*Np: Np = 256 spectra between passes; for every Np the
-                        //   weighted reflections |d|^kappa (2w - v) the consensus sums
+  float2* stage;        // chunk*Np*Np: Np = 256 spectra between passes; SHARP+ (every Np):
+                        //   the weighted frames conj(d) P_a s the overlap projection sums
   float2* tw256;        // 256      W_256^m = exp(-2 pi i m/256), FP64-rounded twiddles
   int4* tiles;          // per gather tile: (list start, count, first row, first col)
   int* tile_list;       // positions overlapping each tile, ascending
@@ -45,12 +47,16 @@ struct Recon {
   float beta;           // SHARP+: beta;  the state is then t with s = t + 2 beta d P_j xbar,
   float ka;             //   two_rho = 2 beta, a = 0, rho = 1, ka = (1 - 2 beta)/Np^2, and
                         //   pc = {conj(d)/Np^2, conj(d)}, laminv = 1/sum P^t |d|^2
+  float tb;             // PMACE: 1 - 2 rho a (state spectrum X - 2 rho U = X (tb - 2 rho ys/|X|))
+  float cx, co, cn;     // PMACE: xbar' = cx xbar + Lambda^{-1} (co S_old - cn S_new):
+                        //   cx = 2 (1 - rho), co = (1 - rho)/rho, cn = 1/rho
 };
 
 // Kernel launchers (stream-ordered; return the hipError_t of the launches).
 // `rec` / `recs` are device addresses of Recon descriptors, `h` a host copy.
+// PMACE also forms S of the initial states (per chunk, chunk_tiles as below).
 hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float scale, int centered,
-                       const float2* x0, hipStream_t st);
+                       const float2* x0, const int2* chunk_tiles, hipStream_t st);
 // Np <= 128, one reconstruction: fused agent over its J positions, then the
 // fused gather + image update over its ntiles tiles.
 hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_t st);

@@ -10,14 +10,23 @@
 // Storing t instead of v is exact algebra of line 5 (v_new = t + 2 rho P_j xbar),
 // and the xhat recurrence is exact algebra of the returned weighted average
 // (the average of P_j xbar is xbar on covered pixels; the average of w is the
-// mean of the averages of u and v).  Each agent state is read and written once
-// per iteration.
+// mean of the averages of u and v).
 //
 // The agent applies eq. (9) in the Fourier domain: with W = F(d v),
 //     F(d w) = W (alpha + y/|W|) / (1 + alpha)   (0 where W = 0)
 // which is the r* of eq. (8) with the phase of W, so w = d^{-1} F^*(...) needs
 // one forward and one inverse 2-D DFT per patch.  Where d = 0, eq. (6) leaves
 // v free and the agent returns its input there.
+//
+// PMACE never materialises u.  With U = F(d w) and W = F(d v), the new state
+// is t = d^{-1} F^*(W - 2 rho U) (where d != 0), one inverse transform of the
+// "state spectrum" W - 2 rho U.  Since u = ((1 - rho) v - t_new) / rho and
+// v = t_old + 2 rho P_j xbar, the consensus of eq. (11) is
+//     xbar' = 2 (1 - rho) xbar + Lambda^{-1} ((1 - rho) S_old - S_new) / rho,
+//     S = sum_j P_j^t |d|^kappa t_j,
+// so the gather sums the weighted states themselves and keeps S of the last
+// iteration.  Per patch pixel an iteration then reads t and y and writes t
+// once, and the consensus reads t once more.
 //
 // Every kernel reads its reconstruction from a device descriptor (Recon) and
 // returns at once when that reconstruction's stop flag is set, so many
@@ -27,6 +36,8 @@
 
 namespace pmace {
 
+constexpr int kPMACE = 0, kSharpPlus = 1;
+
 // Fourier-domain prox of eq. (9): U = W * (a + ys / |W|), 0 where W == 0.
 __device__ __forceinline__ float2 fourier_prox(float2 W, float ysv, float a) {
   const float m2 = fmaf(W.x, W.x, W.y * W.y);
@@ -35,23 +46,26 @@ __device__ __forceinline__ float2 fourier_prox(float2 W, float ysv, float a) {
   return make_float2(W.x * g, W.y * g);
 }
 
-// State update and consensus contribution for one pixel (a6-a8): w from the
-// inverse transform z (d^{-1} and the 1/Np^2 folded into pcf.xy; w = v where
-// d == 0), t <- v - 2 rho w, and the weighted reflection |d|^kappa (2w - v).
-__device__ __forceinline__ void finish_pixel(float2 z, float2 v, float4 pcf, float two_rho,
-                                             float2* t_out, float2* u_out) {
-  float2 w = cmul(make_float2(pcf.x, pcf.y), z);
-  w.x = fmaf(pcf.w, v.x, w.x);
-  w.y = fmaf(pcf.w, v.y, w.y);
-  *t_out = make_float2(fmaf(-two_rho, w.x, v.x), fmaf(-two_rho, w.y, v.y));
-  *u_out = make_float2(pcf.z * fmaf(2.f, w.x, -v.x), pcf.z * fmaf(2.f, w.y, -v.y));
+// PMACE state spectrum W - 2 rho U = W (tb - 2 rho ys / |W|), tb = 1 - 2 rho a
+// (0 where W == 0).
+__device__ __forceinline__ float2 state_spectrum(float2 W, float ysv, float tb, float two_rho) {
+  const float m2 = fmaf(W.x, W.x, W.y * W.y);
+  const float rs = m2 > 0.f ? __builtin_amdgcn_rsqf(m2) : 0.f;
+  const float g = fmaf(-two_rho, ysv * rs, tb);
+  return make_float2(W.x * g, W.y * g);
+}
+
+// Where the agent works on the spectrum: PMACE forms the state spectrum,
+// SHARP+ the magnitude projection (a = 0).
+template <int METHOD>
+__device__ __forceinline__ float2 spectrum_step(float2 W, float ysv, const Recon& g) {
+  if constexpr (METHOD == kPMACE) return state_spectrum(W, ysv, g.tb, g.two_rho);
+  else return fourier_prox(W, ysv, 0.f);
 }
 
 __device__ __forceinline__ float2 mann_v(float2 t, float2 xb, float two_rho) {
   return make_float2(fmaf(two_rho, xb.x, t.x), fmaf(two_rho, xb.y, t.y));
 }
-
-constexpr int kPMACE = 0, kSharpPlus = 1;
 
 // Prologue (a2-a3): the frame that is transformed.
 //   PMACE : d (t + 2 rho P_j xbar)           (v of Alg. 1 times the probe)
@@ -62,21 +76,26 @@ __device__ __forceinline__ float2 agent_input(float2 t, float2 xb, float2 d, flo
   else return mann_v(t, cmul(d, xb), two_rho);
 }
 
-// Epilogue (a6-a8) from the unnormalised inverse transform z.
-//   PMACE : see finish_pixel.
+// Epilogue (a6-a8) from the unnormalised inverse transform z of the spectrum
+// step's output.
+//   PMACE : z = F^*(W - 2 rho U), t <- d^{-1} z / Np^2 (pcf.xy).  Where d == 0
+//           the agent returns its input, w = v, so t <- (1 - 2 rho) v there
+//           (the old state is read only at such pixels).  No u is written.
 //   SHARP+: a = z/Np^2 = P_a s; the next state t = (1 - 2 beta) a + beta s -
 //           beta d P_j xbar (P_Q s of this iteration is d P_j xbar of the last
 //           one: P_Q is a projection, so P_Q s_{k+1} = P_Q P_a s_k), and the
 //           overlap numerator takes conj(d) a.  pcf = {conj(d)/Np^2, conj(d)}.
 template <int METHOD>
-__device__ __forceinline__ void agent_output(float2 z, float2 t_old, float2 xb, float4 pcf,
-                                             const Recon& g, float2* t_out, float2* u_out) {
+__device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2* xp, float4 pcf,
+                                             const Recon& g, float2* u_out) {
   if constexpr (METHOD == kPMACE) {
-    finish_pixel(z, mann_v(t_old, xb, g.two_rho), pcf, g.two_rho, t_out, u_out);
+    float2 tn = cmul(make_float2(pcf.x, pcf.y), z);
+    if (pcf.w != 0.f) tn = cscale(mann_v(*tp, *xp, g.two_rho), 1.f - g.two_rho);
+    *tp = tn;
   } else {
-    const float2 dx = cmul(make_float2(pcf.z, -pcf.w), xb);
-    const float2 sv = mann_v(t_old, dx, g.two_rho);
-    *t_out = make_float2(fmaf(g.ka, z.x, g.beta * (sv.x - dx.x)), fmaf(g.ka, z.y, g.beta * (sv.y - dx.y)));
+    const float2 dx = cmul(make_float2(pcf.z, -pcf.w), *xp);
+    const float2 sv = mann_v(*tp, dx, g.two_rho);
+    *tp = make_float2(fmaf(g.ka, z.x, g.beta * (sv.x - dx.x)), fmaf(g.ka, z.y, g.beta * (sv.y - dx.y)));
     *u_out = cmul(make_float2(pcf.x, pcf.y), z);
   }
 }
@@ -121,13 +140,12 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
   for (int nb = 0; nb < B; ++nb) x[nb] = tile[(q + A * nb) * S + c];
   col_fwd<NP>(x, tile, S, c, q, tw);
   const float* yc = g.ys + pb + c;
-  const float a = g.a;
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
     for (int ka = 0; ka < A; ++ka) {
       const int k = q + A * m + B * ka;
-      x[m * A + ka] = fourier_prox(x[m * A + ka], yc[(size_t)k * NP], a);
+      x[m * A + ka] = spectrum_step<METHOD>(x[m * A + ka], yc[(size_t)k * NP], g);
     }
   col_inv<NP>(x, tile, S, c, q, tw);
   __syncthreads();
@@ -141,11 +159,11 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
     for (int ka = 0; ka < A; ++ka) x[m * A + ka] = row[p + A * m + B * ka];
   row_inv<NP>(x, row, p, tw);
 
-  float2* urow = g.stage + pb + (size_t)r * NP;
+  float2* urow = g.stage + pb + (size_t)r * NP;  // SHARP+ only
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) {
     const int cc = p + A * nb;
-    agent_output<METHOD>(x[nb], trow[cc], xrow[cc], g.pc[r * NP + cc], g, &trow[cc], &urow[cc]);
+    agent_output<METHOD>(x[nb], &trow[cc], &xrow[cc], g.pc[r * NP + cc], g, &urow[cc]);
   }
 }
 
@@ -170,8 +188,8 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused_batch(const Recon
 // agent runs as three passes over a chunk of positions, the spectra staged in
 // a chunk-sized buffer that is reused every chunk:
 //   rows   : a2, a3, forward row DFTs            -> stage
-//   cols   : forward column DFTs, a5, inverse column DFTs (in place)
-//   rowsinv: inverse row DFTs, a6-a8; stage <- weighted reflections
+//   cols   : forward column DFTs, spectrum step (a5), inverse column DFTs (in place)
+//   rowsinv: inverse row DFTs, a6-a7 (t); SHARP+: stage <- overlap numerators
 // -------------------------------------------------------------------------
 constexpr int NP256 = 256;
 constexpr int RB = 16;   // rows per workgroup in the row passes
@@ -213,6 +231,7 @@ __global__ void __launch_bounds__(RB * 16) agent256_rows_batch(const Recon* __re
   agent256_rows_body<kPMACE>(*rec, j0);
 }
 
+template <int METHOD>
 __device__ __forceinline__ void agent256_cols_body(const Recon& g, const int j0) {
   constexpr int NP = NP256, A = 16;
   __shared__ float2 tile[NP * CB];
@@ -229,22 +248,24 @@ __device__ __forceinline__ void agent256_cols_body(const Recon& g, const int j0)
   __syncthreads();
   col_fwd<NP>(x, tile, CB, c, q, tw);
   const float* yc = g.ys + (size_t)j * NP * NP + col;
-  const float a = g.a;
 #pragma unroll
   for (int ka = 0; ka < 16; ++ka) {
     const int k = q + 16 * ka;
-    x[ka] = fourier_prox(x[ka], yc[(size_t)k * NP], a);
+    x[ka] = spectrum_step<METHOD>(x[ka], yc[(size_t)k * NP], g);
   }
   col_inv<NP>(x, tile, CB, c, q, tw);
 #pragma unroll
   for (int nb = 0; nb < 16; ++nb) sp[(size_t)(q + A * nb) * NP] = x[nb];
 }
 
-__global__ void __launch_bounds__(CB * 16) agent256_cols(const Recon g, int j0) { agent256_cols_body(g, j0); }
+template <int METHOD>
+__global__ void __launch_bounds__(CB * 16) agent256_cols(const Recon g, int j0) {
+  agent256_cols_body<METHOD>(g, j0);
+}
 
 __global__ void __launch_bounds__(CB * 16) agent256_cols_batch(const Recon* __restrict__ rec, int j0) {
   if (*rec->done) return;
-  agent256_cols_body(*rec, j0);
+  agent256_cols_body<kPMACE>(*rec, j0);
 }
 
 template <int METHOD>
@@ -266,11 +287,10 @@ __device__ __forceinline__ void agent256_rowsinv_body(const Recon& g, const int 
   row_inv<NP>(x, tile + rl * S, p, tw);
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   float2* trow = g.t + (size_t)j * NP * NP + (size_t)r * NP;
-  const float two_rho = g.two_rho;
 #pragma unroll
   for (int nb = 0; nb < 16; ++nb) {
     const int c = p + A * nb;
-    agent_output<METHOD>(x[nb], trow[c], xrow[c], g.pc[r * NP + c], g, &trow[c], &io[c]);
+    agent_output<METHOD>(x[nb], &trow[c], &xrow[c], g.pc[r * NP + c], g, &io[c]);
   }
 }
 
@@ -286,21 +306,45 @@ __global__ void __launch_bounds__(RB * 16) agent256_rowsinv_batch(const Recon* _
 
 // -------------------------------------------------------------------------
 // Consensus (eq. (11)) without atomics.  Each thread owns one object pixel
-// of a GT_R x GT_C tile and adds the weighted reflections of the patches
-// that cover it, walking the tile's position list (built on the host,
-// ascending j).  Np = 256 chunks run in order on the stream, so every pixel
-// sums its contributions in ascending j and the result is bitwise
-// reproducible.  FUSE (Np <= 128, every position in one chunk): the sum is
-// complete, so a9 (xbar, xhat) is finished here.  `jbase` is the first
-// position held in the stage buffer.
+// of a GT_R x GT_C tile and adds the contributions of the patches that cover
+// it, walking the tile's position list (built on the host, ascending j):
+//   PMACE : |d|^kappa t_j (the sum S of the weighted states),
+//   SHARP+: the overlap numerators conj(d) P_a s_j left in the stage buffer
+//           (`jbase` = first position held there).
+// Np = 256 chunks run in order on the stream, so every pixel sums its
+// contributions in ascending j and the result is bitwise reproducible.  FUSE
+// (Np <= 128, every position in one chunk): the sum is complete, so a9 (xbar,
+// xhat) is finished here; otherwise it is added to num.
 // -------------------------------------------------------------------------
-template <int NP, bool FUSE>
+
+// a9 for one object pixel from the complete sum S.
+template <int METHOD>
+__device__ __forceinline__ void finish_image(const Recon& g, size_t px, float2 S) {
+  const float li = g.laminv[px];
+  float2 xb;
+  if constexpr (METHOD == kPMACE) {
+    const float2 so = g.sold[px], xo = g.xbar[px];
+    const float ex = fmaf(g.co, so.x, -g.cn * S.x), ey = fmaf(g.co, so.y, -g.cn * S.y);
+    xb = make_float2(fmaf(g.cx, xo.x, li * ex), fmaf(g.cx, xo.y, li * ey));
+    g.sold[px] = S;
+  } else {
+    xb = make_float2(S.x * li, S.y * li);
+  }
+  const float2 xh = g.xhat[px];
+  g.xbar[px] = xb;
+  g.xhat[px] = make_float2(fmaf(g.rho, xb.x - xh.x, xh.x), fmaf(g.rho, xb.y - xh.y, xh.y));
+  if (!(isfinite(xb.x) && isfinite(xb.y))) atomicOr(g.status, 1u);
+}
+
+template <int NP, bool FUSE, int METHOD>
 __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int tile, const int jbase) {
   constexpr int NT = GT_R * GT_C, LIST = 256;
-  __shared__ int3 sl[LIST];  // (stage slot, row, col) of the listed positions
+  __shared__ int3 sl[LIST];  // (patch slot, row, col) of the listed positions
   const int tid = threadIdx.x;
   const int4 ti = g.tiles[tile];
   const int R = ti.z + tid / GT_C, C = ti.w + tid % GT_C;
+  const float2* src = METHOD == kPMACE ? g.t : g.stage;
+  const int jb = METHOD == kPMACE ? 0 : jbase;
   float ax = 0.f, ay = 0.f;
   for (int b0 = 0; b0 < ti.y; b0 += LIST) {
     const int nb = ti.y - b0 < LIST ? ti.y - b0 : LIST;
@@ -308,7 +352,7 @@ __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int 
     for (int i = tid; i < nb; i += NT) {
       const int j = g.tile_list[ti.x + b0 + i];
       const int2 pj = g.pos[j];
-      sl[i] = make_int3(j - jbase, pj.x, pj.y);
+      sl[i] = make_int3(j - jb, pj.x, pj.y);
     }
     __syncthreads();
 #pragma unroll 8
@@ -317,20 +361,22 @@ __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int 
       const unsigned rr = (unsigned)(R - e.y), cc = (unsigned)(C - e.z);
       const bool in = rr < (unsigned)NP && cc < (unsigned)NP;
       // lanes outside the patch read its first pixel and discard it
-      const float2 u = g.stage[((size_t)e.x * NP + (in ? rr : 0u)) * NP + (in ? cc : 0u)];
-      ax += in ? u.x : 0.f;
-      ay += in ? u.y : 0.f;
+      const unsigned o = in ? rr * NP + cc : 0u;
+      const float2 u = src[(size_t)e.x * NP * NP + o];
+      if constexpr (METHOD == kPMACE) {
+        const float w = in ? g.omega[o] : 0.f;
+        ax = fmaf(w, u.x, ax);
+        ay = fmaf(w, u.y, ay);
+      } else {
+        ax += in ? u.x : 0.f;
+        ay += in ? u.y : 0.f;
+      }
     }
   }
   if (R >= g.n1 || C >= g.n2) return;
   const size_t px = (size_t)R * g.n2 + C;
   if constexpr (FUSE) {
-    const float li = g.laminv[px];
-    const float2 xb = make_float2(ax * li, ay * li);
-    const float2 xh = g.xhat[px];
-    g.xbar[px] = xb;
-    g.xhat[px] = make_float2(fmaf(g.rho, xb.x - xh.x, xh.x), fmaf(g.rho, xb.y - xh.y, xh.y));
-    if (!(isfinite(xb.x) && isfinite(xb.y))) atomicOr(g.status, 1u);
+    finish_image<METHOD>(g, px, make_float2(ax, ay));
   } else {
     const float2 o = g.num[px];
     g.num[px] = make_float2(o.x + ax, o.y + ay);
@@ -338,10 +384,10 @@ __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int 
 }
 
 // One reconstruction: block b handles tile first_tile + b.
-template <int NP, bool FUSE>
+template <int NP, bool FUSE, int METHOD>
 __global__ void __launch_bounds__(GT_R * GT_C) consensus_gather(const Recon g, int first_tile,
                                                                 int jbase) {
-  consensus_gather_body<NP, FUSE>(g, first_tile + blockIdx.x, jbase);
+  consensus_gather_body<NP, FUSE, METHOD>(g, first_tile + blockIdx.x, jbase);
 }
 
 // One batch member (descriptor in device memory): block b handles tile first_tile + b.
@@ -349,7 +395,7 @@ template <int NP, bool FUSE>
 __global__ void __launch_bounds__(GT_R * GT_C) consensus_gather_member(const Recon* __restrict__ rec,
                                                                        int first_tile, int jbase) {
   if (*rec->done) return;
-  consensus_gather_body<NP, FUSE>(*rec, first_tile + blockIdx.x, jbase);
+  consensus_gather_body<NP, FUSE, kPMACE>(*rec, first_tile + blockIdx.x, jbase);
 }
 
 // Batched: block b handles work item (reconstruction, tile) b.
@@ -360,21 +406,17 @@ __global__ void __launch_bounds__(GT_R * GT_C) consensus_gather_batch(const Reco
   const int2 it = items[blockIdx.x];
   const Recon& g = recs[it.x];
   if (*g.done) return;
-  consensus_gather_body<NP, FUSE>(g, it.y, jbase);
+  consensus_gather_body<NP, FUSE, kPMACE>(g, it.y, jbase);
 }
 
 // a9 for Np = 256: consensus image, reconstruction recurrence, accumulator reset.
 __device__ __forceinline__ void image_update_body(const Recon& g) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n1 * g.n2) return;
-  const float li = g.laminv[i];
   const float2 n = g.num[i];
-  const float2 xb = make_float2(n.x * li, n.y * li);
-  const float2 xh = g.xhat[i];
-  g.xbar[i] = xb;
-  g.xhat[i] = make_float2(fmaf(g.rho, xb.x - xh.x, xh.x), fmaf(g.rho, xb.y - xh.y, xh.y));
+  if (g.method == kSharpPlus) finish_image<kSharpPlus>(g, i, n);
+  else finish_image<kPMACE>(g, i, n);
   g.num[i] = make_float2(0.f, 0.f);
-  if (!(isfinite(xb.x) && isfinite(xb.y))) atomicOr(g.status, 1u);
 }
 
 __global__ void image_update(const Recon g) { image_update_body(g); }
@@ -384,7 +426,9 @@ __global__ void image_update_batch(const Recon* __restrict__ rec) {
   image_update_body(*rec);
 }
 
-// xhat = Lambda^{-1} num, num <- 0 (reconstruction of a state set from outside)
+// After the states were set from outside (xbar = 0, t = v): xhat = the
+// weighted average Lambda^{-1} num of the states; PMACE keeps S = num.
+// num <- 0.
 __global__ void image_from_num(const Recon* __restrict__ rec) {
   const Recon& g = *rec;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -392,6 +436,16 @@ __global__ void image_from_num(const Recon* __restrict__ rec) {
   const float li = g.laminv[i];
   const float2 n = g.num[i];
   g.xhat[i] = make_float2(n.x * li, n.y * li);
+  if (g.method == kPMACE) g.sold[i] = n;
+  g.num[i] = make_float2(0.f, 0.f);
+}
+
+// PMACE after init: S of the initial states; num <- 0.
+__global__ void sold_from_num(const Recon* __restrict__ rec) {
+  const Recon& g = *rec;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n1 * g.n2) return;
+  g.sold[i] = g.num[i];
   g.num[i] = make_float2(0.f, 0.f);
 }
 
@@ -532,7 +586,8 @@ __global__ void get_state_k(const Recon* __restrict__ rec, float2* v) {
   v[i] = mann_v(g.t[i], g.method == kSharpPlus ? cmul(g.d[rem], xb) : xb, g.two_rho);
 }
 
-// t <- v and stage <- |d|^kappa v for positions [j0, j0 + cnt) (stage indexed from j0)
+// t <- v for positions [j0, j0 + cnt); SHARP+ also stage <- conj(d) v (the
+// weights of eq. (15), stage indexed from j0).  PMACE's gather weights t itself.
 __global__ void set_state_k(const Recon* __restrict__ rec, const float2* v, int j0, long long cnt_px) {
   const Recon& g = *rec;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -541,10 +596,10 @@ __global__ void set_state_k(const Recon* __restrict__ rec, const float2* v, int 
   const long long gi = (long long)j0 * per + i;
   const float2 vv = v[gi];
   g.t[gi] = vv;
-  const float4 pcf = g.pc[i % per];
-  // weights of the average: |d|^kappa (PMACE) or conj(d) (SHARP+, eq. (15))
-  g.stage[i] = g.method == kSharpPlus ? cmul(make_float2(pcf.z, pcf.w), vv)
-                                      : make_float2(pcf.z * vv.x, pcf.z * vv.y);
+  if (g.method == kSharpPlus) {
+    const float4 pcf = g.pc[i % per];
+    g.stage[i] = cmul(make_float2(pcf.z, pcf.w), vv);
+  }
 }
 
 // SHARP+ after set_state: xbar = the overlap image of s (just left in xhat),
@@ -699,13 +754,17 @@ hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_
   switch (np) {
 #define PMACE_SMALL(N)                                                                            \
   case N:                                                                                         \
-    if (h.method == kSharpPlus)                                                                   \
-      hipLaunchKernelGGL((agent_fused<N, kSharpPlus>), dim3(h.J), dim3(N * Geo<N>::A), 0, st, h); \
-    else                                                                                          \
-      hipLaunchKernelGGL((agent_fused<N, kPMACE>), dim3(h.J), dim3(N * Geo<N>::A), 0, st, h);     \
-    if (ntiles > 0)                                                                               \
-      hipLaunchKernelGGL((consensus_gather<N, true>), dim3(ntiles), dim3(GT_R * GT_C), 0, st, h,  \
-                         0, 0);                                                                   \
+    if (h.method == kSharpPlus) {                                                                  \
+      hipLaunchKernelGGL((agent_fused<N, kSharpPlus>), dim3(h.J), dim3(N * Geo<N>::A), 0, st, h);  \
+      if (ntiles > 0)                                                                              \
+        hipLaunchKernelGGL((consensus_gather<N, true, kSharpPlus>), dim3(ntiles), dim3(GT_R * GT_C), \
+                           0, st, h, 0, 0);                                                        \
+    } else {                                                                                       \
+      hipLaunchKernelGGL((agent_fused<N, kPMACE>), dim3(h.J), dim3(N * Geo<N>::A), 0, st, h);      \
+      if (ntiles > 0)                                                                              \
+        hipLaunchKernelGGL((consensus_gather<N, true, kPMACE>), dim3(ntiles), dim3(GT_R * GT_C), 0, \
+                           st, h, 0, 0);                                                           \
+    }                                                                                              \
     break;
     PMACE_SMALL(32)
     PMACE_SMALL(64)
@@ -749,20 +808,23 @@ hipError_t launch_256_iteration(const Recon& h, const Recon* batch_rec, const in
       hipLaunchKernelGGL(agent256_rowsinv_batch, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, batch_rec, j0);
     } else if (h.method == kSharpPlus) {
       hipLaunchKernelGGL(agent256_rows<kSharpPlus>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
-      hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
+      hipLaunchKernelGGL(agent256_cols<kSharpPlus>, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
       hipLaunchKernelGGL(agent256_rowsinv<kSharpPlus>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
     } else {
       hipLaunchKernelGGL(agent256_rows<kPMACE>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
-      hipLaunchKernelGGL(agent256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
+      hipLaunchKernelGGL(agent256_cols<kPMACE>, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
       hipLaunchKernelGGL(agent256_rowsinv<kPMACE>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
     }
     if (ct.y > 0) {
       if (batch_rec)
         hipLaunchKernelGGL((consensus_gather_member<256, false>), dim3(ct.y), dim3(GT_R * GT_C), 0,
                            st, batch_rec, ct.x, j0);
+      else if (h.method == kSharpPlus)
+        hipLaunchKernelGGL((consensus_gather<256, false, kSharpPlus>), dim3(ct.y), dim3(GT_R * GT_C),
+                           0, st, h, ct.x, j0);
       else
-        hipLaunchKernelGGL((consensus_gather<256, false>), dim3(ct.y), dim3(GT_R * GT_C), 0, st, h,
-                           ct.x, j0);
+        hipLaunchKernelGGL((consensus_gather<256, false, kPMACE>), dim3(ct.y), dim3(GT_R * GT_C), 0,
+                           st, h, ct.x, j0);
     }
   }
   const unsigned nb = blocks_for((long long)h.n1 * h.n2, 256);
@@ -773,14 +835,45 @@ hipError_t launch_256_iteration(const Recon& h, const Recon* batch_rec, const in
   return hipGetLastError();
 }
 
+// num += the gather of chunk tiles ct (positions from j0 in the stage buffer).
+static hipError_t gather_into_num(const Recon& h, int2 ct, int j0, hipStream_t st) {
+  if (ct.y <= 0) return hipSuccess;
+  switch (h.np) {
+#define PMACE_GATHER(N)                                                                           \
+  case N:                                                                                         \
+    if (h.method == kSharpPlus)                                                                   \
+      hipLaunchKernelGGL((consensus_gather<N, false, kSharpPlus>), dim3(ct.y), dim3(GT_R * GT_C), \
+                         0, st, h, ct.x, j0);                                                     \
+    else                                                                                          \
+      hipLaunchKernelGGL((consensus_gather<N, false, kPMACE>), dim3(ct.y), dim3(GT_R * GT_C), 0,  \
+                         st, h, ct.x, j0);                                                        \
+    break;
+    PMACE_GATHER(32)
+    PMACE_GATHER(64)
+    PMACE_GATHER(128)
+    PMACE_GATHER(256)
+#undef PMACE_GATHER
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float scale,
-                           int centered, const float2* x0, hipStream_t st) {
+                       int centered, const float2* x0, const int2* chunk_tiles, hipStream_t st) {
   const long long total = (long long)h.J * h.np * h.np;
+  const long long npx = (long long)h.n1 * h.n2;
   hipLaunchKernelGGL(init_amplitudes_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, z, scale,
                      centered);
   hipLaunchKernelGGL(init_patches_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, x0);
-  hipLaunchKernelGGL(init_images_k, dim3(blocks_for((long long)h.n1 * h.n2, 256)), dim3(256), 0, st,
-                     rec, x0);
+  hipLaunchKernelGGL(init_images_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec, x0);
+  if (h.method == kPMACE) {
+    for (int j0 = 0, g = 0; j0 < h.J; j0 += h.chunk, ++g) {
+      const hipError_t e = gather_into_num(h, chunk_tiles[g], j0, st);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(sold_from_num, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec);
+  }
   return hipGetLastError();
 }
 
@@ -799,22 +892,8 @@ hipError_t launch_set_state(const Recon& h, const Recon* rec, const float2* v,
     const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
     hipLaunchKernelGGL(set_state_k, dim3(blocks_for(cnt * per, 256)), dim3(256), 0, st, rec, v, j0,
                        cnt * per);
-    const int2 ct = chunk_tiles[g];
-    if (ct.y <= 0) continue;
-    switch (h.np) {
-#define PMACE_GATHER(N)                                                                          \
-  case N:                                                                                        \
-    hipLaunchKernelGGL((consensus_gather<N, false>), dim3(ct.y), dim3(GT_R * GT_C), 0, st, h,    \
-                       ct.x, j0);                                                                \
-    break;
-      PMACE_GATHER(32)
-      PMACE_GATHER(64)
-      PMACE_GATHER(128)
-      PMACE_GATHER(256)
-#undef PMACE_GATHER
-      default:
-        return hipErrorInvalidValue;
-    }
+    const hipError_t e = gather_into_num(h, chunk_tiles[g], j0, st);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(image_from_num, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec);
   if (h.method == kSharpPlus) {

@@ -48,13 +48,17 @@ def _fp(**kw):
 def test_footprint_formula(lib):
     J, np_, n = 36, 32, 128
     fp = _fp()
-    # states 8 B + amplitudes 4 B + weighted reflections 8 B per patch pixel,
-    # object images 28 B per pixel, probe tables, positions, tile tables
-    lower = J * np_ * np_ * 20 + n * n * 28 + np_ * np_ * 24 + J * 8
+    # PMACE, Np <= 128: states 8 B + amplitudes 4 B per patch pixel (no staged
+    # patches), object images 36 B per pixel (Lambda^-1, accumulator, S, xbar,
+    # xhat), probe tables 28 B per probe pixel, positions, tile tables
+    lower = J * np_ * np_ * 12 + n * n * 36 + np_ * np_ * 28 + J * 8
     tiles = (n // 16) * (n // 64)
     tables = tiles * 24 + J * (31 // 16 + 2) * (31 // 64 + 2) * 4 + J * 8
     nred = n * n // 4096
-    assert lower <= fp <= lower + tables + nred * 40 + 1024 + 24 * 256
+    assert lower <= fp <= lower + tables + nred * 40 + 1024 + 26 * 256
+    # SHARP+ keeps its weighted frames of every position in the stage buffer
+    sharp = P.pmace_footprint(P.make_params(128, 128, 32, 36, 0.5, method=1, beta=0.75))
+    assert J * np_ * np_ * 8 <= sharp - fp <= J * np_ * np_ * 8 + 256
     # Np = 256 stages min(J, chunk) patches between its passes
     a = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=64))
     b = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=128))

@@ -226,6 +226,64 @@ def test_c2_teacher_forced_steps(P):
     R.close()
 
 
+def _support_probe(prob, frac=0.8):
+    """The problem's probe with exact zeros outside a disc (a probe with a
+    hard support), and intensities simulated from it."""
+    np_ = prob.np_
+    r = np.hypot(*np.meshgrid(np.arange(np_) - np_ / 2 + 0.5, np.arange(np_) - np_ / 2 + 0.5))
+    d = np.where(r <= frac * np_ / 2, prob.probe, 0).astype(np.complex128)
+    frames = d[None] * O.extract(prob.x_true, prob.pos, np_)
+    z = (np.abs(O.dft2(frames)) ** 2).astype(np.float32)
+    return d, z
+
+
+EDGE_CASES = {
+    # name: (n1, n2, np, scan, step, seed, chunk, kappa, rho, support)
+    "np64_support_kappa0": (200, 200, 64, 5, 30, 31, 0, 0.0, 0.5, True),
+    "np64_support_rho08": (200, 200, 64, 5, 30, 32, 0, 1.25, 0.8, True),
+    "np32_rect_rho03": (96, 160, 32, 4, 20, 33, 0, 1.25, 0.3, False),
+    "np128_rect_rho07": (200, 330, 128, 3, 36, 34, 0, 0.6, 0.7, False),
+    "np256_support_rho03_chunks": (360, 360, 256, 3, 50, 35, 4, 0.0, 0.3, True),
+}
+
+
+@pytest.mark.parametrize("case", sorted(EDGE_CASES))
+def test_teacher_forced_edge_cases(P, case):
+    """Probes with exact zeros (the agent returns its input there; with kappa
+    = 0 those pixels still carry consensus weight 1), Mann parameters other
+    than 1/2, and rectangular objects."""
+    n1, n2, np_, scan, step, seed, chunk, kappa, rho, support = EDGE_CASES[case]
+    prob = synth.make_problem(n1, np_, scan, step, None, seed, n2=n2)
+    if support:
+        d, z = _support_probe(prob)
+        prob = synth.Problem(x_true=prob.x_true, probe=d, pos=prob.pos, z=z, peak_photons=None)
+    alpha = 0.5
+    K = 3
+    vs, xs = oracle_trajectory(prob, alpha, kappa, rho, K, x0=smooth_start(prob))
+    _say("edge case", case, "J", prob.num_pos, "zeros", int(np.sum(prob.probe == 0)))
+    R = P.Reconstruction(n1, n2, prob.probe, prob.pos, prob.z, alpha, kappa, rho, chunk=chunk)
+    for k in range(K):
+        R.set_state(vs[k])
+        R.iterate(1)
+        R.sync()
+        ev = rel(R.get_state().cpu().numpy(), vs[k + 1])
+        ex = rel(R.reconstruct().cpu().numpy(), xs[k + 1])
+        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
+        assert ev < TOL and ex < TOL, (k, ev, ex)
+    # free-running from the device's own start: several passes in a row use
+    # the consensus sum kept from the previous pass
+    R2 = P.Reconstruction(n1, n2, prob.probe, prob.pos, prob.z, alpha, kappa, rho, chunk=chunk,
+                          x0=smooth_start(prob).astype(np.complex64))
+    R2.iterate(K)
+    R2.sync()
+    ev = rel(R2.get_state().cpu().numpy(), vs[K])
+    ex = rel(R2.reconstruct().cpu().numpy(), xs[K])
+    _say(f"  free-running {K} passes rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
+    assert ev < TOL and ex < TOL
+    R.close()
+    R2.close()
+
+
 def test_invalid_intensities_rejected(P):
     prob = synth.make_problem(128, 32, 4, 20, None, 3)
     for bad in (np.nan, -1.0, np.inf):
