@@ -23,7 +23,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmace_hbm_traffic.md")
-KERNEL_SOURCES = ["pmace_kernels.hip", "pmace_dft.hpp", "pmace_internal.hpp", "pmace_api.hip"]
+KERNEL_SOURCES = ["csrc/pmace_kernels.hip", "csrc/pmace_dft.hpp", "csrc/pmace_internal.hpp",
+                  "csrc/pmace_api.hip", "tuned.json"]
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 ALPHA = {"c1": 0.1, "c2": 0.5, "c3": 0.5}
 
@@ -41,12 +42,14 @@ def algorithmic_flops(J, np_):
 
 
 def kernel_source_hash():
-    """Hash of the sources the iteration kernels are built from."""
+    """Hash of the sources (and tuned launch shapes) the iteration kernels are built from."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2111_14240_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        path = os.path.join(ROOT, "paper_2111_14240_amd", f)
+        if os.path.exists(path):
+            with open(path, "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 

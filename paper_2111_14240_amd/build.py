@@ -1,6 +1,10 @@
-"""Build libpmace.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libpmace.so (HIP, gfx950) in-tree with hipcc.
+
+Launch-shape parameters come from tuned.json beside this file (written by
+tune.py) as -D flags; without it the defaults in csrc/pmace_internal.hpp hold."""
 from __future__ import annotations
 
+import json
 import os
 import subprocess
 import sys
@@ -9,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmace.so")
+TUNED = os.path.join(HERE, "tuned.json")
 SOURCES = ["pmace_api.hip", "pmace_kernels.hip", "pmace_simulate.hip"]
 
 # Packed FP32 VALU forms are kept out of the generated code on purpose, and
@@ -22,18 +27,27 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def tuned_defines() -> dict:
+    if not os.path.exists(TUNED):
+        return {}
+    with open(TUNED) as f:
+        return {k: int(v) for k, v in json.load(f).get("defines", {}).items()}
+
+
+def build(verbose: bool = False, out: str = LIB, defines: dict | None = None) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc, *FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", LIB + ".tmp"]
+    d = tuned_defines() if defines is None else defines
+    dflags = [f"-D{k}={int(v)}" for k, v in sorted(d.items())]
+    cmd = [hipcc, *FLAGS, *dflags, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           *[os.path.join(CSRC, s) for s in SOURCES], "-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libpmace.so")
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+        raise RuntimeError(f"hipcc failed building {out}")
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

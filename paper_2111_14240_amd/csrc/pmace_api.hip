@@ -87,7 +87,7 @@ bool np_supported(int np) { return np == 32 || np == 64 || np == 128 || np == 25
 // Np = 256 stages chunk*Np^2 spectra between its three passes.
 int chunk_of(const pmace_params& p) {
   int c = p.num_pos;
-  if (p.np == 256) c = p.chunk > 0 ? p.chunk : 128;
+  if (p.np == 256) c = p.chunk > 0 ? p.chunk : PMACE_CHUNK256;
   if (c > p.num_pos) c = p.num_pos;
   return c;
 }
@@ -125,7 +125,7 @@ pmace_status check_params(const pmace_params* p) {
 
 // Section offsets inside the workspace (relative to the aligned base).
 struct Layout {
-  size_t t, ys, pos, d, pc, omega, laminv, num, sold, xbar, xhat, stage, tiles, list, status, desc,
+  size_t t, ys, pos, d, pc, dinv, omega, laminv, num, sold, xbar, xhat, stage, tiles, list, status, desc,
       items, gitems, ritems, red, tw, total;
 };
 
@@ -147,6 +147,7 @@ Layout layout_of(const pmace_params& p) {
   L.pos = o;     o = align_up(o + (size_t)p.num_pos * 8);
   L.d = o;       o = align_up(o + np2 * 8);
   L.pc = o;      o = align_up(o + np2 * 16);
+  L.dinv = o;    o = align_up(o + np2 * 8);
   L.omega = o;   o = align_up(o + np2 * 4);
   L.laminv = o;  o = align_up(o + npx * 4);
   L.num = o;     o = align_up(o + npx * 8);
@@ -272,7 +273,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   // DFT pair), the d == 0 mask, and Lambda^{-1} (0 where Lambda = 0).
   // SHARP+ (eq. (15)): weights conj(d) over the normaliser sum_k P_k^t |d|^2.
   const bool sharp = p.method == PMACE_METHOD_SHARP_PLUS;
-  std::vector<float> pc(4 * np2), omega_f(np2);
+  std::vector<float> pc(4 * np2), omega_f(np2), dinv(2 * np2, 0.f);
   std::vector<double> omega(np2);
   const double inv_np2 = 1.0 / ((double)np * np);
   for (size_t i = 0; i < np2; ++i) {
@@ -291,6 +292,10 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
     if (mag != 0.0) di = inv_np2 / dd;
     pc[4 * i + 0] = (float)di.real();
     pc[4 * i + 1] = (float)di.imag();
+    dinv[2 * i + 0] = pc[4 * i + 0];
+    dinv[2 * i + 1] = pc[4 * i + 1];
+    // d != 0 must not round to the d == 0 marker: keep the smallest subnormal
+    if (mag != 0.0 && dinv[2 * i] == 0.f && dinv[2 * i + 1] == 0.f) dinv[2 * i] = 1e-45f;
     pc[4 * i + 2] = (float)omega[i];
     pc[4 * i + 3] = mag == 0.0 ? 1.f : 0.f;
   }
@@ -369,6 +374,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   h.d = reinterpret_cast<float2*>(base + L.d);
   h.pc = reinterpret_cast<float4*>(base + L.pc);
   h.omega = reinterpret_cast<float*>(base + L.omega);
+  h.dinv = reinterpret_cast<float2*>(base + L.dinv);
   h.laminv = reinterpret_cast<float*>(base + L.laminv);
   h.num = reinterpret_cast<float2*>(base + L.num);
   h.sold = reinterpret_cast<float2*>(base + L.sold);
@@ -432,6 +438,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
       hipMemcpyAsync(h.d, probe.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.pc, pc.data(), np2 * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.omega, omega_f.data(), np2 * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h.dinv, dinv.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.laminv, laminv.data(), npx * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.tiles, tiles.data(), tiles.size() * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
       (!list.empty() &&

@@ -7,8 +7,29 @@
 
 namespace pmace {
 
-// Gather tile of the consensus: GT_R x GT_C object pixels, one thread each.
-constexpr int GT_R = 16, GT_C = 64;
+// Launch-shape parameters.  The defaults are overridden at build time by the
+// values the tuner picked (tuned.json beside the package, passed as -D flags).
+#ifndef PMACE_GT_K
+#define PMACE_GT_K 1      // threads per object pixel in the consensus gather
+#endif
+#ifndef PMACE_GATHER_UNROLL
+#define PMACE_GATHER_UNROLL 8
+#endif
+#ifndef PMACE_RB
+#define PMACE_RB 16       // Np = 256: patch rows per workgroup in the row passes
+#endif
+#ifndef PMACE_CB
+#define PMACE_CB 16       // Np = 256: patch columns per workgroup in the column pass
+#endif
+#ifndef PMACE_CHUNK256
+#define PMACE_CHUNK256 128  // Np = 256: default positions per chunk
+#endif
+
+// Gather tile of the consensus: GT_R x GT_C object pixels, GT_K threads each
+// (GT_R * GT_C * GT_K = 1024 threads per workgroup).
+constexpr int GT_K = PMACE_GT_K, GT_C = 64, GT_R = 16 / GT_K;
+static_assert(GT_K == 1 || GT_K == 2 || GT_K == 4, "gather split must be 1, 2 or 4");
+constexpr int GT_THREADS = GT_R * GT_C * GT_K;
 // NRMSE reduction: RED_PX object pixels per block of RED_T threads.
 constexpr int RED_T = 256, RED_PX = 4096;
 
@@ -20,6 +41,7 @@ struct Recon {
   int2* pos;            // J         (row, col) top-left of P_j
   float2* d;            // Np*Np     probe
   float4* pc;           // Np*Np     {Re, Im of d^{-1}/Np^2, |d|^kappa, [d == 0]}
+  float2* dinv;         // Np*Np     d^{-1}/Np^2, 0 exactly where d == 0 (PMACE epilogue)
   float* omega;         // Np*Np     |d|^kappa (PMACE consensus weights)
   float* laminv;        // N1*N2     Lambda^{-1} (0 where Lambda = 0)
   float2* num;          // N1*N2     weighted back-projection accumulator (Np = 256)

@@ -77,22 +77,25 @@ __device__ __forceinline__ float2 agent_input(float2 t, float2 xb, float2 d, flo
 }
 
 // Epilogue (a6-a8) from the unnormalised inverse transform z of the spectrum
-// step's output.
-//   PMACE : z = F^*(W - 2 rho U), t <- d^{-1} z / Np^2 (pcf.xy).  Where d == 0
-//           the agent returns its input, w = v, so t <- (1 - 2 rho) v there
-//           (the old state is read only at such pixels).  No u is written.
+// step's output, for probe pixel k.
+//   PMACE : z = F^*(W - 2 rho U), t <- d^{-1} z / Np^2 (dinv table).  Where
+//           d == 0 (dinv == 0) the agent returns its input, w = v, so
+//           t <- (1 - 2 rho) v there (the old state is read only at such
+//           pixels).  No u is written.
 //   SHARP+: a = z/Np^2 = P_a s; the next state t = (1 - 2 beta) a + beta s -
 //           beta d P_j xbar (P_Q s of this iteration is d P_j xbar of the last
 //           one: P_Q is a projection, so P_Q s_{k+1} = P_Q P_a s_k), and the
-//           overlap numerator takes conj(d) a.  pcf = {conj(d)/Np^2, conj(d)}.
+//           overlap numerator takes conj(d) a.  pc = {conj(d)/Np^2, conj(d)}.
 template <int METHOD>
-__device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2* xp, float4 pcf,
+__device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2* xp, int k,
                                              const Recon& g, float2* u_out) {
   if constexpr (METHOD == kPMACE) {
-    float2 tn = cmul(make_float2(pcf.x, pcf.y), z);
-    if (pcf.w != 0.f) tn = cscale(mann_v(*tp, *xp, g.two_rho), 1.f - g.two_rho);
+    const float2 di = g.dinv[k];
+    float2 tn = cmul(di, z);
+    if (di.x == 0.f && di.y == 0.f) tn = cscale(mann_v(*tp, *xp, g.two_rho), 1.f - g.two_rho);
     *tp = tn;
   } else {
+    const float4 pcf = g.pc[k];
     const float2 dx = cmul(make_float2(pcf.z, -pcf.w), *xp);
     const float2 sv = mann_v(*tp, dx, g.two_rho);
     *tp = make_float2(fmaf(g.ka, z.x, g.beta * (sv.x - dx.x)), fmaf(g.ka, z.y, g.beta * (sv.y - dx.y)));
@@ -125,6 +128,15 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
     const int c = p + A * nb;
     x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], two_rho);
   }
+  // amplitudes of the column phase, fetched now so their latency hides
+  // behind the row transforms
+  const int c = tid % NP, q = tid / NP;
+  const float* yc = g.ys + pb + c;
+  float yv[B];
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) yv[m * A + ka] = yc[(size_t)(q + A * m + B * ka) * NP];
   __syncthreads();
   float2* row = tile + r * S;
   row_fwd<NP>(x, row, p, tw);
@@ -135,18 +147,13 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
     for (int ka = 0; ka < A; ++ka) row[p + A * m + B * ka] = x[m * A + ka];
   __syncthreads();
 
-  const int c = tid % NP, q = tid / NP;
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) x[nb] = tile[(q + A * nb) * S + c];
   col_fwd<NP>(x, tile, S, c, q, tw);
-  const float* yc = g.ys + pb + c;
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
-    for (int ka = 0; ka < A; ++ka) {
-      const int k = q + A * m + B * ka;
-      x[m * A + ka] = spectrum_step<METHOD>(x[m * A + ka], yc[(size_t)k * NP], g);
-    }
+    for (int ka = 0; ka < A; ++ka) x[m * A + ka] = spectrum_step<METHOD>(x[m * A + ka], yv[m * A + ka], g);
   col_inv<NP>(x, tile, S, c, q, tw);
   __syncthreads();
 #pragma unroll
@@ -163,7 +170,7 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) {
     const int cc = p + A * nb;
-    agent_output<METHOD>(x[nb], &trow[cc], &xrow[cc], g.pc[r * NP + cc], g, &urow[cc]);
+    agent_output<METHOD>(x[nb], &trow[cc], &xrow[cc], r * NP + cc, g, &urow[cc]);
   }
 }
 
@@ -192,8 +199,10 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused_batch(const Recon
 //   rowsinv: inverse row DFTs, a6-a7 (t); SHARP+: stage <- overlap numerators
 // -------------------------------------------------------------------------
 constexpr int NP256 = 256;
-constexpr int RB = 16;   // rows per workgroup in the row passes
-constexpr int CB = 16;   // columns per workgroup in the column pass
+constexpr int RB = PMACE_RB;   // rows per workgroup in the row passes
+constexpr int CB = PMACE_CB;   // columns per workgroup in the column pass
+static_assert(RB >= 4 && RB <= 32 && NP256 % RB == 0, "row block");
+static_assert(CB >= 8 && CB <= 32 && NP256 % CB == 0, "column block");
 
 template <int METHOD>
 __device__ __forceinline__ void agent256_rows_body(const Recon& g, const int j0) {
@@ -290,7 +299,7 @@ __device__ __forceinline__ void agent256_rowsinv_body(const Recon& g, const int 
 #pragma unroll
   for (int nb = 0; nb < 16; ++nb) {
     const int c = p + A * nb;
-    agent_output<METHOD>(x[nb], &trow[c], &xrow[c], g.pc[r * NP + c], g, &io[c]);
+    agent_output<METHOD>(x[nb], &trow[c], &xrow[c], r * NP + c, g, &io[c]);
   }
 }
 
@@ -336,13 +345,18 @@ __device__ __forceinline__ void finish_image(const Recon& g, size_t px, float2 S
   if (!(isfinite(xb.x) && isfinite(xb.y))) atomicOr(g.status, 1u);
 }
 
+#define PM_STR(x) #x
+#define PM_UNROLL(n) _Pragma(PM_STR(unroll n))
+
 template <int NP, bool FUSE, int METHOD>
 __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int tile, const int jbase) {
-  constexpr int NT = GT_R * GT_C, LIST = 256;
+  constexpr int NPX = GT_R * GT_C, NT = GT_THREADS, LIST = 256;
   __shared__ int3 sl[LIST];  // (patch slot, row, col) of the listed positions
   const int tid = threadIdx.x;
+  // GT_K threads share a pixel: part k sums list entries k, k + GT_K, ...
+  const int pxl = tid % NPX, part = tid / NPX;
   const int4 ti = g.tiles[tile];
-  const int R = ti.z + tid / GT_C, C = ti.w + tid % GT_C;
+  const int R = ti.z + pxl / GT_C, C = ti.w + pxl % GT_C;
   const float2* src = METHOD == kPMACE ? g.t : g.stage;
   const int jb = METHOD == kPMACE ? 0 : jbase;
   float ax = 0.f, ay = 0.f;
@@ -355,8 +369,8 @@ __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int 
       sl[i] = make_int3(j - jb, pj.x, pj.y);
     }
     __syncthreads();
-#pragma unroll 8
-    for (int i = 0; i < nb; ++i) {
+    PM_UNROLL(PMACE_GATHER_UNROLL)
+    for (int i = part; i < nb; i += GT_K) {
       const int3 e = sl[i];
       const unsigned rr = (unsigned)(R - e.y), cc = (unsigned)(C - e.z);
       const bool in = rr < (unsigned)NP && cc < (unsigned)NP;
@@ -373,6 +387,18 @@ __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int 
       }
     }
   }
+  if constexpr (GT_K > 1) {
+    // partial sums added in a fixed order: still bitwise reproducible
+    __shared__ float2 ps[(GT_K > 1 ? GT_K - 1 : 1) * NPX];
+    if (part > 0) ps[(part - 1) * NPX + pxl] = make_float2(ax, ay);
+    __syncthreads();
+    if (part > 0) return;
+#pragma unroll
+    for (int k = 0; k < GT_K - 1; ++k) {
+      ax += ps[k * NPX + pxl].x;
+      ay += ps[k * NPX + pxl].y;
+    }
+  }
   if (R >= g.n1 || C >= g.n2) return;
   const size_t px = (size_t)R * g.n2 + C;
   if constexpr (FUSE) {
@@ -385,14 +411,14 @@ __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int 
 
 // One reconstruction: block b handles tile first_tile + b.
 template <int NP, bool FUSE, int METHOD>
-__global__ void __launch_bounds__(GT_R * GT_C) consensus_gather(const Recon g, int first_tile,
+__global__ void __launch_bounds__(GT_THREADS) consensus_gather(const Recon g, int first_tile,
                                                                 int jbase) {
   consensus_gather_body<NP, FUSE, METHOD>(g, first_tile + blockIdx.x, jbase);
 }
 
 // One batch member (descriptor in device memory): block b handles tile first_tile + b.
 template <int NP, bool FUSE>
-__global__ void __launch_bounds__(GT_R * GT_C) consensus_gather_member(const Recon* __restrict__ rec,
+__global__ void __launch_bounds__(GT_THREADS) consensus_gather_member(const Recon* __restrict__ rec,
                                                                        int first_tile, int jbase) {
   if (*rec->done) return;
   consensus_gather_body<NP, FUSE, kPMACE>(*rec, first_tile + blockIdx.x, jbase);
@@ -400,7 +426,7 @@ __global__ void __launch_bounds__(GT_R * GT_C) consensus_gather_member(const Rec
 
 // Batched: block b handles work item (reconstruction, tile) b.
 template <int NP, bool FUSE>
-__global__ void __launch_bounds__(GT_R * GT_C) consensus_gather_batch(const Recon* __restrict__ recs,
+__global__ void __launch_bounds__(GT_THREADS) consensus_gather_batch(const Recon* __restrict__ recs,
                                                                       const int2* __restrict__ items,
                                                                       int jbase) {
   const int2 it = items[blockIdx.x];
@@ -757,12 +783,12 @@ hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_
     if (h.method == kSharpPlus) {                                                                  \
       hipLaunchKernelGGL((agent_fused<N, kSharpPlus>), dim3(h.J), dim3(N * Geo<N>::A), 0, st, h);  \
       if (ntiles > 0)                                                                              \
-        hipLaunchKernelGGL((consensus_gather<N, true, kSharpPlus>), dim3(ntiles), dim3(GT_R * GT_C), \
+        hipLaunchKernelGGL((consensus_gather<N, true, kSharpPlus>), dim3(ntiles), dim3(GT_THREADS), \
                            0, st, h, 0, 0);                                                        \
     } else {                                                                                       \
       hipLaunchKernelGGL((agent_fused<N, kPMACE>), dim3(h.J), dim3(N * Geo<N>::A), 0, st, h);      \
       if (ntiles > 0)                                                                              \
-        hipLaunchKernelGGL((consensus_gather<N, true, kPMACE>), dim3(ntiles), dim3(GT_R * GT_C), 0, \
+        hipLaunchKernelGGL((consensus_gather<N, true, kPMACE>), dim3(ntiles), dim3(GT_THREADS), 0, \
                            st, h, 0, 0);                                                           \
     }                                                                                              \
     break;
@@ -784,7 +810,7 @@ hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int 
   case N:                                                                                           \
     hipLaunchKernelGGL(agent_fused_batch<N>, dim3(nitems), dim3(N * Geo<N>::A), 0, st, recs, items); \
     if (ngitems > 0)                                                                                \
-      hipLaunchKernelGGL((consensus_gather_batch<N, true>), dim3(ngitems), dim3(GT_R * GT_C), 0,    \
+      hipLaunchKernelGGL((consensus_gather_batch<N, true>), dim3(ngitems), dim3(GT_THREADS), 0,    \
                          st, recs, gitems, 0);                                                      \
     break;
     PMACE_SMALL(32)
@@ -817,13 +843,13 @@ hipError_t launch_256_iteration(const Recon& h, const Recon* batch_rec, const in
     }
     if (ct.y > 0) {
       if (batch_rec)
-        hipLaunchKernelGGL((consensus_gather_member<256, false>), dim3(ct.y), dim3(GT_R * GT_C), 0,
+        hipLaunchKernelGGL((consensus_gather_member<256, false>), dim3(ct.y), dim3(GT_THREADS), 0,
                            st, batch_rec, ct.x, j0);
       else if (h.method == kSharpPlus)
-        hipLaunchKernelGGL((consensus_gather<256, false, kSharpPlus>), dim3(ct.y), dim3(GT_R * GT_C),
+        hipLaunchKernelGGL((consensus_gather<256, false, kSharpPlus>), dim3(ct.y), dim3(GT_THREADS),
                            0, st, h, ct.x, j0);
       else
-        hipLaunchKernelGGL((consensus_gather<256, false, kPMACE>), dim3(ct.y), dim3(GT_R * GT_C), 0,
+        hipLaunchKernelGGL((consensus_gather<256, false, kPMACE>), dim3(ct.y), dim3(GT_THREADS), 0,
                            st, h, ct.x, j0);
     }
   }
@@ -842,10 +868,10 @@ static hipError_t gather_into_num(const Recon& h, int2 ct, int j0, hipStream_t s
 #define PMACE_GATHER(N)                                                                           \
   case N:                                                                                         \
     if (h.method == kSharpPlus)                                                                   \
-      hipLaunchKernelGGL((consensus_gather<N, false, kSharpPlus>), dim3(ct.y), dim3(GT_R * GT_C), \
+      hipLaunchKernelGGL((consensus_gather<N, false, kSharpPlus>), dim3(ct.y), dim3(GT_THREADS), \
                          0, st, h, ct.x, j0);                                                     \
     else                                                                                          \
-      hipLaunchKernelGGL((consensus_gather<N, false, kPMACE>), dim3(ct.y), dim3(GT_R * GT_C), 0,  \
+      hipLaunchKernelGGL((consensus_gather<N, false, kPMACE>), dim3(ct.y), dim3(GT_THREADS), 0,  \
                          st, h, ct.x, j0);                                                        \
     break;
     PMACE_GATHER(32)

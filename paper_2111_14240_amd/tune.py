@@ -1,0 +1,215 @@
+"""Autotuner for the launch shapes of the PMACE kernels.
+
+The tunables are compile-time parameters of libpmace.so (see
+csrc/pmace_internal.hpp) plus one run-time default:
+
+    PMACE_GT_K           threads per object pixel in the consensus gather (1, 2, 4)
+    PMACE_GATHER_UNROLL  loads in flight per gather thread (8, 16)
+    PMACE_RB             Np = 256 row passes: patch rows per workgroup (8, 16, 32)
+    PMACE_CB             Np = 256 column pass: patch columns per workgroup (16, 32)
+    PMACE_CHUNK256       Np = 256: positions per chunk (stage buffer size)
+
+Search (coordinate-wise, every candidate measured on the device):
+  1. gather shape (GT_K x unroll) with the default row/column blocks, scored by
+     the iteration time of a Np = 128 and a Np = 256 workload;
+  2. row/column blocks with the default gather, scored on the Np = 256 workload;
+  3. the chunk size, at run time, with the combined choice.
+Each candidate library is built into a scratch directory and timed in a
+process of its own.  The choice is written to tuned.json beside this file;
+build.py passes it to hipcc as -D flags.
+
+    python -m paper_2111_14240_amd.tune build DIR      # compile candidates (no GPU)
+    python -m paper_2111_14240_amd.tune time DIR       # time them (GPU), write DIR/times.json
+    python -m paper_2111_14240_amd.tune pick DIR       # write tuned.json from the times
+    python -m paper_2111_14240_amd.tune chunk          # time chunk sizes with the built library
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import json
+import os
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TUNED = os.path.join(HERE, "tuned.json")
+DEFAULTS = {"PMACE_GT_K": 1, "PMACE_GATHER_UNROLL": 8, "PMACE_RB": 16, "PMACE_CB": 16}
+GATHER_SPACE = [(k, u) for k in (1, 2, 4) for u in (8, 16)]
+BLOCK_SPACE = [(rb, cb) for rb in (8, 16, 32) for cb in (16, 32)]
+CHUNKS = (64, 128, 192, 256, 400)
+
+# Tuning workloads: (object side, probe side, scan side, step, peak photons).
+WORKLOADS = {"np128": (512, 128, 15, 24, 1e5), "np256": (1024, 256, 40, 20, 1e6)}
+
+
+def candidates():
+    """Name -> defines of every candidate library."""
+    out = {}
+    for k, u in GATHER_SPACE:
+        d = dict(DEFAULTS, PMACE_GT_K=k, PMACE_GATHER_UNROLL=u)
+        out[f"g{k}u{u}"] = d
+    for rb, cb in BLOCK_SPACE:
+        d = dict(DEFAULTS, PMACE_RB=rb, PMACE_CB=cb)
+        out[f"rb{rb}cb{cb}"] = d
+    # the default appears in both families: keep one copy
+    uniq, seen = {}, set()
+    for name, d in out.items():
+        key = tuple(sorted(d.items()))
+        if key not in seen:
+            seen.add(key)
+            uniq[name] = d
+    return uniq
+
+
+def cmd_build(args):
+    from . import build as B
+    os.makedirs(args.dir, exist_ok=True)
+    cands = candidates()
+    with open(os.path.join(args.dir, "candidates.json"), "w") as f:
+        json.dump(cands, f, indent=1)
+
+    def one(item):
+        name, d = item
+        lib = os.path.join(args.dir, f"libpmace_{name}.so")
+        B.build(out=lib, defines=d)
+        return name
+
+    with cf.ThreadPoolExecutor(max_workers=args.jobs) as ex:
+        for name in ex.map(one, sorted(cands.items())):
+            print("built", name, flush=True)
+
+
+def _time_library(lib, workloads, iters, chunks=(0,)):
+    """Run in a fresh process: load `lib`, time `iters` iterations (one graph
+    replay each) per workload, return ms per iteration."""
+    import torch
+    from . import pmace
+    pmace.load_library(lib)
+    res = {}
+    for wl in workloads:
+        n, np_, scan, step, peak = WORKLOADS[wl]
+        prob = pmace.simulated_problem(n, np_, scan, step, peak, seed=7)
+        for ch in chunks:
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                R = pmace.Reconstruction(n, n, prob.probe, prob.pos, prob.z, 0.5, chunk=ch,
+                                         stream=stream)
+                R.iterate(3)
+                R.sync()
+                best = float("inf")
+                for _ in range(3):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    R.iterate(iters)
+                    e1.record(stream)
+                    R.sync()
+                    best = min(best, e0.elapsed_time(e1) / iters)
+                R.close()
+            res[wl if ch == 0 else f"{wl}_chunk{ch}"] = best
+            print(f"  {os.path.basename(lib)} {wl} chunk {ch}: {best:.4f} ms/iteration", flush=True)
+    return res
+
+
+def cmd_time(args):
+    cands = json.load(open(os.path.join(args.dir, "candidates.json")))
+    times = {}
+    for name in sorted(cands):
+        lib = os.path.join(args.dir, f"libpmace_{name}.so")
+        wl = ["np128", "np256"] if name.startswith("g") else ["np256"]
+        out = subprocess.run([sys.executable, "-m", "paper_2111_14240_amd.tune", "_one", lib,
+                              ",".join(wl), str(args.iters)],
+                             capture_output=True, text=True, timeout=300,
+                             cwd=os.path.dirname(HERE))
+        sys.stdout.write(out.stdout)
+        if out.returncode != 0:
+            sys.stderr.write(out.stderr[-2000:])
+            raise SystemExit(f"timing {name} failed with status {out.returncode}")
+        times[name] = json.loads(out.stdout.strip().splitlines()[-1])
+    with open(os.path.join(args.dir, "times.json"), "w") as f:
+        json.dump(times, f, indent=1)
+
+
+def cmd_one(args):
+    res = _time_library(args.lib, args.workloads.split(","), args.iters)
+    print(json.dumps(res), flush=True)
+
+
+def _pick(cands, times):
+    import math
+    g = {n: t for n, t in times.items() if n.startswith("g")}
+    base = g["g1u8"]
+    # geometric mean of the speedups over the default on both workloads
+    score = {n: math.sqrt((base["np128"] / t["np128"]) * (base["np256"] / t["np256"])) for n, t in g.items()}
+    best_g = max(score, key=score.get)
+    b = {n: t["np256"] for n, t in times.items() if n.startswith("rb")}
+    b["rb16cb16"] = base["np256"]
+    best_b = min(b, key=b.get)
+    d = dict(DEFAULTS)
+    d["PMACE_GT_K"] = cands[best_g]["PMACE_GT_K"]
+    d["PMACE_GATHER_UNROLL"] = cands[best_g]["PMACE_GATHER_UNROLL"]
+    rb, cb = best_b[2:].split("cb")
+    d["PMACE_RB"], d["PMACE_CB"] = int(rb), int(cb)
+    return d, score, b
+
+
+def cmd_pick(args):
+    cands = json.load(open(os.path.join(args.dir, "candidates.json")))
+    times = json.load(open(os.path.join(args.dir, "times.json")))
+    d, score, b = _pick(cands, times)
+    rec = {}
+    if os.path.exists(TUNED):
+        rec = json.load(open(TUNED))
+    rec["defines"] = dict(rec.get("defines", {}), **d)
+    rec["gather_scores"] = score
+    rec["block_ms_np256"] = b
+    rec["times_ms"] = times
+    rec["when"] = time.strftime("%Y-%m-%d %H:%M")
+    with open(TUNED, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps(rec["defines"]))
+
+
+def cmd_chunk(args):
+    from . import build as B
+    res = _time_library(B.LIB, ["np256"], args.iters, chunks=CHUNKS)
+    best = min(CHUNKS, key=lambda c: res[f"np256_chunk{c}"])
+    rec = json.load(open(TUNED)) if os.path.exists(TUNED) else {"defines": dict(DEFAULTS)}
+    rec["chunk_ms_np256"] = res
+    if args.write:
+        rec["defines"]["PMACE_CHUNK256"] = best
+        with open(TUNED, "w") as f:
+            json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps({"best_chunk": best, **res}))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    p = sub.add_parser("build")
+    p.add_argument("dir")
+    p.add_argument("--jobs", type=int, default=4)
+    p.set_defaults(fn=cmd_build)
+    p = sub.add_parser("time")
+    p.add_argument("dir")
+    p.add_argument("--iters", type=int, default=20)
+    p.set_defaults(fn=cmd_time)
+    p = sub.add_parser("_one")
+    p.add_argument("lib")
+    p.add_argument("workloads")
+    p.add_argument("iters", type=int)
+    p.set_defaults(fn=cmd_one)
+    p = sub.add_parser("pick")
+    p.add_argument("dir")
+    p.set_defaults(fn=cmd_pick)
+    p = sub.add_parser("chunk")
+    p.add_argument("--iters", type=int, default=20)
+    p.add_argument("--write", action="store_true")
+    p.set_defaults(fn=cmd_chunk)
+    args = ap.parse_args(argv)
+    args.fn(args)
+
+
+if __name__ == "__main__":
+    main()

@@ -50,10 +50,11 @@ def test_footprint_formula(lib):
     fp = _fp()
     # PMACE, Np <= 128: states 8 B + amplitudes 4 B per patch pixel (no staged
     # patches), object images 36 B per pixel (Lambda^-1, accumulator, S, xbar,
-    # xhat), probe tables 28 B per probe pixel, positions, tile tables
-    lower = J * np_ * np_ * 12 + n * n * 36 + np_ * np_ * 28 + J * 8
-    tiles = (n // 16) * (n // 64)
-    tables = tiles * 24 + J * (31 // 16 + 2) * (31 // 64 + 2) * 4 + J * 8
+    # xhat), probe tables 36 B per probe pixel, positions, tile tables
+    lower = J * np_ * np_ * 12 + n * n * 36 + np_ * np_ * 36 + J * 8
+    # gather tiles are (16 / k) x 64 pixels with k in {1, 2, 4} (a tuned build parameter)
+    tiles = (n // 4) * (n // 64)
+    tables = tiles * 24 + J * (31 // 4 + 2) * (31 // 64 + 2) * 4 + J * 8
     nred = n * n // 4096
     assert lower <= fp <= lower + tables + nred * 40 + 1024 + 26 * 256
     # SHARP+ keeps its weighted frames of every position in the stage buffer
@@ -63,7 +64,7 @@ def test_footprint_formula(lib):
     a = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=64))
     b = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=128))
     stage = 64 * 256 * 256 * 8
-    tile_tables = (25 - 13) * 64 * 16 * 24     # fewer chunks, fewer tile slots
+    tile_tables = (25 - 13) * 256 * 16 * 24    # fewer chunks, fewer tile slots
     assert stage - tile_tables - 4096 <= b - a <= stage + 4096
 
 
