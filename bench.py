@@ -110,8 +110,15 @@ def _mix_problems(count, seed=4, device="cuda"):
                                     device=device) for s in specs]
 
 
-def _stop_rule():
-    return dict(tol=1e-4, min_iter=2, max_iter=500)
+def _stop_rule(args):
+    """NRMSE change < 1e-4 (eq. (17), needs the synthetic truth), or the
+    truth-free relative change of the data-fit cost (eq. (4))."""
+    from paper_2111_14240_amd import pmace
+    if args.stop == "data_fit":
+        return dict(tol=args.fit_tol, min_iter=2, max_iter=500, criterion=pmace.PMACE_STOP_DATA_FIT,
+                    check_every=args.check_every)
+    return dict(tol=1e-4, min_iter=2, max_iter=500, criterion=pmace.PMACE_STOP_NRMSE,
+                check_every=args.check_every)
 
 
 def bench_batch(args):
@@ -126,7 +133,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - t0
     alpha = 0.5
-    rule = _stop_rule()
+    rule = _stop_rule(args)
     poll = 10
 
     def make(p):
@@ -147,11 +154,12 @@ def bench_batch(args):
     plain_nr, plain_it = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    on_demand = args.stop != "nrmse"   # the rule does not track NRMSE: measure it at the end
     for p in probs:
         R = make(p)
         B = pmace.Batch([R], **rule)
         nr, it = drive(B, 1)
-        plain_nr.append(nr[0])
+        plain_nr.append(R.nrmse() if on_demand else nr[0])
         plain_it.append(it[0])
         B.close()
         R.close()
@@ -165,6 +173,8 @@ def bench_batch(args):
     nr, it = drive(B, len(Rs))
     torch.cuda.synchronize()
     batch_s = time.perf_counter() - t0
+    if on_demand:
+        nr = np.array([R.nrmse() for R in Rs])
     B.close()
     for R in Rs:
         R.close()
@@ -203,7 +213,7 @@ def bench_serve(args):
     rng = np.random.default_rng(5)
     pick = rng.integers(0, len(pool), size=args.requests)
     arrivals = serve.poisson_arrivals(args.requests, args.rate, seed=5)
-    rule = _stop_rule()
+    rule = _stop_rule(args)
     results = {}
     for name in ("served", "plain"):
         reqs = [serve.Request(i, pool[pick[i]], float(arrivals[i])) for i in range(args.requests)]
@@ -248,6 +258,10 @@ def main():
     ap.add_argument("--pool", type=int, default=64, help="serve mode: distinct problems")
     ap.add_argument("--capacity-gb", type=float, default=200.0, help="serve mode: workspace budget")
     ap.add_argument("--max-active", type=int, default=64, help="serve mode: concurrent requests")
+    ap.add_argument("--stop", default="nrmse", choices=["nrmse", "data_fit"],
+                    help="batch/serve stop rule: NRMSE change (eq. 17) or data-fit cost change (eq. 4)")
+    ap.add_argument("--fit-tol", type=float, default=1e-3, help="relative data-fit change for --stop data_fit")
+    ap.add_argument("--check-every", type=int, default=1, help="iterations between stop-rule evaluations")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",

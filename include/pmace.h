@@ -58,7 +58,8 @@ typedef struct {
   float kappa;        /* >= 0: probe exponent of the consensus weights, eq. (11) */
   float rho;          /* 0 < rho < 1: Mann averaging parameter, eq. (13) */
   uint32_t flags;     /* PMACE_CENTERED_DC or 0 */
-  int32_t chunk;      /* Np = 256 only: positions per staging chunk (>= 1, capped at J), 0 = 128 */
+  int32_t chunk;      /* Np = 256 only: positions per staging chunk (>= 1, capped at J),
+                         0 = the build's tuned default */
   int32_t method;     /* PMACE_METHOD_PMACE (alpha, kappa, rho used) or PMACE_METHOD_SHARP_PLUS */
   float beta;         /* SHARP+ relaxation, 0 <= beta <= 1 (Alg. 2); ignored by PMACE */
 } pmace_params;
@@ -67,10 +68,11 @@ typedef struct pmace_ctx pmace_ctx;      /* one reconstruction */
 typedef struct pmace_batch pmace_batch;  /* several reconstructions stepped together */
 
 /* Bytes of device workspace one reconstruction needs (0 if params are invalid).
- * Layout: agent states J*Np^2*8, amplitudes J*Np^2*4, object images N1*N2*28,
- * probe tables Np^2*24, positions J*8, a staging buffer of chunk*Np^2*8
- * bytes (chunk = J for Np <= 128) and the consensus tile tables; each
- * section 256-byte aligned. */
+ * Layout: agent states J*Np^2*8, amplitudes J*Np^2*4, object images N1*N2*36,
+ * probe tables Np^2*36, positions J*8, a staging buffer of chunk*Np^2*8
+ * bytes (Np = 256: the chunk's spectra; SHARP+ with Np <= 128: all J frames;
+ * PMACE with Np <= 128: none), data-fit partials and the consensus tile
+ * tables; each section 256-byte aligned. */
 size_t pmace_footprint(const pmace_params* params);
 
 /* Alg. 1 initialisation: v_j = P_j x0 for every j.  Also computes
@@ -134,18 +136,36 @@ pmace_status pmace_set_reference(pmace_ctx* ctx, const void* xref_d, const uint8
  * ESTATE if no reference is set. */
 pmace_status pmace_nrmse(pmace_ctx* ctx, double* out);
 
+/* Data-fit cost of eq. (4) at the current reconstruction, with sigma_n = 1:
+ *   sum_j 1/2 || y_j - |F D P_j xhat| ||^2,  y_j = sqrt(z_j),
+ * F the orthonormal 2-D DFT.  Needs no reference object.  Uses the context's
+ * staging buffer (stream-ordered with its iterations); does not change the
+ * stop rule's history.  Synchronises; *out on the host. */
+pmace_status pmace_data_fit(pmace_ctx* ctx, double* out);
+
 /* Batches: several reconstructions on one device and stream advanced
  * together, one HIP graph launch per iteration.  Positions of members with
  * Np <= 128 share merged launches per patch size; Np = 256 members run as
- * parallel branches.  After every iteration each member's NRMSE (against its
- * reference, set before pmace_batch_create) is updated on the device, and a
- * member stops (its kernels return at once) when |e_k - e_{k-1}| < tol after
- * at least min_iter iterations, or after max_iter iterations (members
- * without a reference stop at max_iter). */
+ * parallel branches.  Every iteration counts towards max_iter; after every
+ * check_every-th iteration of the batch the stop rule is evaluated on the
+ * device, and a member stops (its kernels return at once) when
+ *   PMACE_STOP_NRMSE:    its NRMSE against its reference (set before
+ *                        pmace_batch_create) changed by less than tol,
+ *                        |e_k - e_{k-1}| < tol (eq. (17)); members without a
+ *                        reference stop only at max_iter;
+ *   PMACE_STOP_DATA_FIT: its data-fit cost C of eq. (4) (as pmace_data_fit)
+ *                        changed by at most tol relative to the previous
+ *                        evaluation, |C_k - C_{k-1}| <= tol C_{k-1}; needs no
+ *                        reference (the paper leaves its stopping test open);
+ * once at least min_iter iterations have run, or after max_iter iterations. */
+#define PMACE_STOP_NRMSE 0
+#define PMACE_STOP_DATA_FIT 1
 typedef struct {
-  float tol;        /* NRMSE change below which a member stops (e.g. 1e-4) */
-  int32_t min_iter; /* >= 0 */
-  int32_t max_iter; /* >= 1 */
+  float tol;           /* threshold of the criterion (e.g. 1e-4) */
+  int32_t min_iter;    /* >= 0 */
+  int32_t max_iter;    /* >= 1 */
+  int32_t criterion;   /* PMACE_STOP_NRMSE or PMACE_STOP_DATA_FIT */
+  int32_t check_every; /* >= 0: evaluate every this many iterations (0 = 1) */
 } pmace_stop_rule;
 
 /* Device workspace bytes a batch of these members needs (0 if invalid). */
@@ -159,8 +179,12 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
 /* n_iter iterations of every member still running (stream-ordered, async). */
 pmace_status pmace_batch_step(pmace_batch* batch, int32_t n_iter);
 /* Synchronise and read back per member: stop flag, last NRMSE, iterations
- * tracked by the stop rule.  Host arrays of n entries; any may be NULL. */
+ * counted by the stop rule.  Host arrays of n entries; any may be NULL. */
 pmace_status pmace_batch_poll(pmace_batch* batch, int32_t* done, double* nrmse, int32_t* iters);
+/* As pmace_batch_poll, plus the last data-fit cost the stop rule evaluated
+ * (infinity before the first evaluation). */
+pmace_status pmace_batch_poll_fit(pmace_batch* batch, int32_t* done, double* nrmse, int32_t* iters,
+                                  double* data_fit);
 void pmace_batch_destroy(pmace_batch* batch);
 
 /* Simulated measurements (Sec. II eq. (1); Sec. IV eq. (16)) for synthetic

@@ -75,8 +75,10 @@ struct pmace_batch {
   pmace_stop_rule rule;
   hipStream_t lanes[4];
   hipEvent_t fork, join[4];
-  Graph graph;
+  Graph graph;                 // one iteration
+  Graph graph_check;           // one iteration + stop-rule evaluation
   bool graph_tried;
+  long long iters;             // iterations launched by this batch
 };
 
 namespace {
@@ -126,7 +128,7 @@ pmace_status check_params(const pmace_params* p) {
 // Section offsets inside the workspace (relative to the aligned base).
 struct Layout {
   size_t t, ys, pos, d, pc, dinv, omega, laminv, num, sold, xbar, xhat, stage, tiles, list, status, desc,
-      items, gitems, ritems, red, tw, total;
+      items, gitems, ritems, red, tw, fit, total;
 };
 
 // Stage buffer: Np = 256 keeps a chunk's spectra between its passes; SHARP+
@@ -135,6 +137,9 @@ size_t stage_patches(const pmace_params& p) {
   if (p.np == 256) return (size_t)chunk_of(p);
   return p.method == PMACE_METHOD_SHARP_PLUS ? (size_t)chunk_of(p) : 0;
 }
+
+// Data-fit partial sums per patch: one, or one per column block for Np = 256.
+int fit_bpp(const pmace_params& p) { return p.np == 256 ? 256 / PMACE_CB : 1; }
 
 Layout layout_of(const pmace_params& p) {
   Layout L;
@@ -157,13 +162,14 @@ Layout layout_of(const pmace_params& p) {
   L.stage = o;   o = align_up(o + stage_patches(p) * np2 * 8);
   L.tiles = o;   o = align_up(o + max_tiles(p) * 16);
   L.list = o;    o = align_up(o + max_list(p) * 4);
-  L.status = o;  o = align_up(o + 64);  // status word, stop flag, finish item, NRMSE track[4]
+  L.status = o;  o = align_up(o + 128);  // status word, stop flag, finish item, track[8] at +32
   L.desc = o;    o = align_up(o + sizeof(Recon));
   L.items = o;   o = align_up(o + (size_t)p.num_pos * 8);
   L.gitems = o;  o = align_up(o + max_tiles(p) * 8);
   L.ritems = o;  o = align_up(o + (size_t)num_red(p) * 8);
   L.red = o;     o = align_up(o + (size_t)num_red(p) * 32);
   L.tw = o;      o = align_up(o + 256 * 8);
+  L.fit = o;     o = align_up(o + (size_t)p.num_pos * fit_bpp(p) * 8);
   L.total = o;
   return L;
 }
@@ -217,6 +223,9 @@ __global__ void reset_tracking_k(int* done, double* track) {
   track[1] = __builtin_inf();
   track[2] = __builtin_inf();
   track[3] = 0.0;
+  track[4] = __builtin_inf();
+  track[5] = __builtin_inf();
+  track[6] = __builtin_inf();
 }
 
 }  // namespace
@@ -389,6 +398,8 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   h.track = reinterpret_cast<double*>(base + L.status + 32);
   h.red = reinterpret_cast<double*>(base + L.red);
   h.tw256 = reinterpret_cast<float2*>(base + L.tw);
+  h.fit = reinterpret_cast<double*>(base + L.fit);
+  h.fit_bpp = fit_bpp(p);
   h.xref = nullptr;
   h.mask = nullptr;
   h.n1 = n1;
@@ -402,12 +413,14 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
     h.two_rho = 2.f * p.beta;
     h.rho = 1.f;
     h.ka = (float)((1.0 - 2.0 * (double)p.beta) * inv_np2);
+    h.yfac = 1.f;
   } else {
     h.beta = 0.f;
     h.a = p.alpha / (1.f + p.alpha);
     h.two_rho = 2.f * p.rho;
     h.rho = p.rho;
     h.ka = 0.f;
+    h.yfac = (float)(1.0 + (double)p.alpha);
     const double rho = p.rho, a = (double)p.alpha / (1.0 + (double)p.alpha);
     h.tb = (float)(1.0 - 2.0 * rho * a);
     h.cx = (float)(2.0 * (1.0 - rho));
@@ -530,9 +543,20 @@ pmace_status pmace_nrmse(pmace_ctx* c, double* out) {
   if (!c) return PMACE_ESTATE;
   if (!out) return PMACE_EINVAL;
   if (!c->h.xref) return PMACE_ESTATE;
-  if (pmace::launch_nrmse(c->dev, c->ritems, c->h.n_red, c->fitem, 1, 0, 0.f, 0, 0, c->stream) !=
+  if (pmace::launch_nrmse(c->dev, c->ritems, c->h.n_red, c->fitem, 1, 0, 0.f, 0, c->stream) !=
           hipSuccess ||
       hipMemcpyAsync(out, c->h.track + 1, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return record(c, PMACE_EDEVICE);
+  return PMACE_OK;
+}
+
+pmace_status pmace_data_fit(pmace_ctx* c, double* out) {
+  if (!c) return PMACE_ESTATE;
+  if (!out) return PMACE_EINVAL;
+  if (pmace::launch_fit_member(c->h, c->dev, 0, c->stream) != hipSuccess ||
+      pmace::launch_fit_finish(c->dev, c->fitem, 1, 0, 0.f, 0, c->stream) != hipSuccess ||
+      hipMemcpyAsync(out, c->h.track + 6, 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
       hipStreamSynchronize(c->stream) != hipSuccess)
     return record(c, PMACE_EDEVICE);
   return PMACE_OK;
@@ -615,7 +639,7 @@ pmace_status check_members(pmace_ctx* const* ctxs, int32_t n) {
   return PMACE_OK;
 }
 
-pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes) {
+pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes, bool check) {
   for (int k = 0; k < 3; ++k)
     if (b->nitems[k] > 0)
       PM_HIP(pmace::launch_small_batch(32 << k, b->recs, b->items[k], b->nitems[k], b->gitems[k],
@@ -643,13 +667,25 @@ pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes)
       PM_HIP(hipEventRecord(b->join[l], b->lanes[l]));
       PM_HIP(hipStreamWaitEvent(st, b->join[l], 0));
     }
-  PM_HIP(pmace::launch_nrmse(b->recs, b->ritems, b->nritems, b->fitems, b->n, 1, b->rule.tol,
-                             b->rule.min_iter, b->rule.max_iter, st));
+  PM_HIP(pmace::launch_tick(b->recs, b->fitems, b->n, b->rule.max_iter, 0, st));
+  if (check && b->rule.criterion == PMACE_STOP_NRMSE) {
+    PM_HIP(pmace::launch_nrmse(b->recs, b->ritems, b->nritems, b->fitems, b->n, 1, b->rule.tol,
+                               b->rule.min_iter, st));
+  } else if (check) {
+    for (int k = 0; k < 3; ++k)
+      PM_HIP(pmace::launch_fit_batch(32 << k, b->recs, b->items[k], b->nitems[k], st));
+    for (int i = 0; i < b->n; ++i)
+      if (b->ctxs[i]->prm.np == 256)
+        PM_HIP(pmace::launch_fit_member(b->ctxs[i]->h, b->recs + i, 1, st));
+    PM_HIP(pmace::launch_fit_finish(b->recs, b->fitems, b->n, 1, b->rule.tol, b->rule.min_iter, st));
+  }
+  PM_HIP(pmace::launch_tick(b->recs, b->fitems, b->n, b->rule.max_iter, 1, st));
   return PMACE_OK;
 }
 
 void batch_release(pmace_batch* b) {
   b->graph.release();
+  b->graph_check.release();
   for (int l = 0; l < 4; ++l) {
     if (b->lanes[l]) (void)hipStreamDestroy(b->lanes[l]);
     if (b->join[l]) (void)hipEventDestroy(b->join[l]);
@@ -673,7 +709,9 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
   *out = nullptr;
   pmace_status ps = check_members(ctxs, n);
   if (ps != PMACE_OK) return ps;
-  if (!rule || !workspace_d || rule->min_iter < 0 || rule->max_iter < 1 || !std::isfinite(rule->tol))
+  if (!rule || !workspace_d || rule->min_iter < 0 || rule->max_iter < 1 || !std::isfinite(rule->tol) ||
+      (rule->criterion != PMACE_STOP_NRMSE && rule->criterion != PMACE_STOP_DATA_FIT) ||
+      rule->check_every < 0)
     return PMACE_EINVAL;
   const BatchLayout L = batch_layout(ctxs, n);
   if (ws_bytes < L.total + kAlign) return PMACE_ENOMEM;
@@ -683,7 +721,9 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
   b->stream = ctxs[0]->stream;
   b->ctxs.assign(ctxs, ctxs + n);
   b->rule = *rule;
+  if (b->rule.check_every == 0) b->rule.check_every = 1;
   b->graph_tried = false;
+  b->iters = 0;
   char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(workspace_d)));
   b->recs = reinterpret_cast<Recon*>(base + L.recs);
   std::vector<Recon> recs(n);
@@ -744,37 +784,51 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
 pmace_status pmace_batch_step(pmace_batch* b, int32_t n_iter) {
   if (!b) return PMACE_ESTATE;
   if (n_iter < 0) return PMACE_EINVAL;
+  const int every = b->rule.check_every;
   if (!b->graph_tried && graphs_enabled()) {
     b->graph_tried = true;
-    (void)capture(b->graph, [&](hipStream_t cs) { return enqueue_batch_iteration(b, cs, true); });
+    (void)capture(b->graph_check,
+                  [&](hipStream_t cs) { return enqueue_batch_iteration(b, cs, true, true); });
+    if (every > 1)
+      (void)capture(b->graph, [&](hipStream_t cs) { return enqueue_batch_iteration(b, cs, true, false); });
   }
   for (int k = 0; k < n_iter; ++k) {
-    if (b->graph.x) {
-      if (hipGraphLaunch(b->graph.x, b->stream) != hipSuccess) return PMACE_EDEVICE;
+    // the stop rule is evaluated after every `every`-th iteration of the batch
+    const bool check = (b->iters + 1) % every == 0;
+    ++b->iters;
+    const Graph& g = check ? b->graph_check : b->graph;
+    if (g.x) {
+      if (hipGraphLaunch(g.x, b->stream) != hipSuccess) return PMACE_EDEVICE;
     } else {
-      pmace_status s = enqueue_batch_iteration(b, b->stream, false);
+      pmace_status s = enqueue_batch_iteration(b, b->stream, false, check);
       if (s != PMACE_OK) return s;
     }
   }
   return PMACE_OK;
 }
 
-pmace_status pmace_batch_poll(pmace_batch* b, int32_t* done, double* nrmse, int32_t* iters) {
+pmace_status pmace_batch_poll_fit(pmace_batch* b, int32_t* done, double* nrmse, int32_t* iters,
+                                  double* data_fit) {
   if (!b) return PMACE_ESTATE;
   std::vector<int> dn(b->n);
-  std::vector<double> tr(4 * (size_t)b->n);
+  std::vector<double> tr(8 * (size_t)b->n);
   for (int i = 0; i < b->n; ++i) {
     if (hipMemcpyAsync(&dn[i], b->ctxs[i]->h.done, 4, hipMemcpyDeviceToHost, b->stream) != hipSuccess ||
-        hipMemcpyAsync(&tr[4 * i], b->ctxs[i]->h.track, 32, hipMemcpyDeviceToHost, b->stream) != hipSuccess)
+        hipMemcpyAsync(&tr[8 * i], b->ctxs[i]->h.track, 64, hipMemcpyDeviceToHost, b->stream) != hipSuccess)
       return PMACE_EDEVICE;
   }
   if (hipStreamSynchronize(b->stream) != hipSuccess) return PMACE_EDEVICE;
   for (int i = 0; i < b->n; ++i) {
     if (done) done[i] = dn[i];
-    if (nrmse) nrmse[i] = tr[4 * i + 1];
-    if (iters) iters[i] = (int32_t)tr[4 * i + 3];
+    if (nrmse) nrmse[i] = tr[8 * i + 1];
+    if (iters) iters[i] = (int32_t)tr[8 * i + 3];
+    if (data_fit) data_fit[i] = tr[8 * i + 4];
   }
   return PMACE_OK;
+}
+
+pmace_status pmace_batch_poll(pmace_batch* b, int32_t* done, double* nrmse, int32_t* iters) {
+  return pmace_batch_poll_fit(b, done, nrmse, iters, nullptr);
 }
 
 void pmace_batch_destroy(pmace_batch* b) {

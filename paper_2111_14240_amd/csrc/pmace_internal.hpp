@@ -58,7 +58,9 @@ struct Recon {
   float2* xref;         // NRMSE reference object, null if none
   unsigned char* mask;  // NRMSE region (nonzero = inside), null = every pixel
   double* red;          // per reduction block: {Re, Im sum conj(xref) xhat, sum |xhat|^2, sum |xref|^2}
-  double* track;        // {sum |xref|^2, last nrmse, previous nrmse, iterations tracked}
+  double* track;        // {sum |xref|^2, last nrmse, previous nrmse, iterations counted,
+                        //  last data-fit cost, previous data-fit cost}
+  double* fit;          // J*fit_bpp per-patch (Np = 256: per column block) data-fit partials
   int n1, n2, np, J;
   float a;              // alpha / (1 + alpha)
   float two_rho;
@@ -69,6 +71,8 @@ struct Recon {
   float beta;           // SHARP+: beta;  the state is then t with s = t + 2 beta d P_j xbar,
   float ka;             //   two_rho = 2 beta, a = 0, rho = 1, ka = (1 - 2 beta)/Np^2, and
                         //   pc = {conj(d)/Np^2, conj(d)}, laminv = 1/sum P^t |d|^2
+  int fit_bpp;          // data-fit partials per patch
+  float yfac;           // yfac * ys = Np y_j  (1 + alpha for PMACE, 1 for SHARP+)
   float tb;             // PMACE: 1 - 2 rho a (state spectrum X - 2 rho U = X (tb - 2 rho ys/|X|))
   float cx, co, cn;     // PMACE: xbar' = cx xbar + Lambda^{-1} (co S_old - cn S_new):
                         //   cx = 2 (1 - rho), co = (1 - rho)/rho, cn = 1/rho
@@ -97,11 +101,24 @@ hipError_t launch_set_state(const Recon& h, const Recon* rec, const float2* v,
                             const int2* chunk_tiles, hipStream_t st);
 // a10: NRMSE of xhat against xref for the reconstructions in `ritems`
 // (recon index, reduction block); `fitems` lists the recon indices to finish.
-// With update_stop, the stop rule (|e_k - e_{k-1}| < tol after min_iter
-// tracked iterations, or max_iter reached) sets the done flag.
+// With update_stop, a member whose NRMSE changed by less than tol once
+// min_iter iterations have been counted is stopped.
 hipError_t launch_nrmse(const Recon* recs, const int2* ritems, int nritems, const int* fitems,
-                        int nf, int update_stop, float tol, int min_iter, int max_iter,
-                        hipStream_t st);
+                        int nf, int update_stop, float tol, int min_iter, hipStream_t st);
+// Data-fit cost of eq. (4) at xhat: partials of one reconstruction (all Np;
+// rec = its device descriptor, check_done: skip if stopped), or of the
+// batched Np <= 128 positions `items` (recon index, position).
+hipError_t launch_fit_member(const Recon& h, const Recon* rec, int check_done, hipStream_t st);
+hipError_t launch_fit_batch(int np, const Recon* recs, const int2* items, int nitems, hipStream_t st);
+// Sum the partials: with update_stop into track[4] (previous value to
+// track[5]), stopping members whose cost changed by at most tol (relative);
+// without, into track[6] only.
+hipError_t launch_fit_finish(const Recon* recs, const int* fitems, int nf, int update_stop, float tol,
+                             int min_iter, hipStream_t st);
+// cap = 0: count one iteration for each running member (before the stop
+// rule is evaluated); cap = 1: stop running members that reached max_iter.
+hipError_t launch_tick(const Recon* recs, const int* fitems, int nf, int max_iter, int cap,
+                       hipStream_t st);
 hipError_t launch_fft2(int np, int count, const float2* in, float2* out, int inverse, hipStream_t st);
 
 }  // namespace pmace

@@ -515,39 +515,208 @@ __global__ void __launch_bounds__(RED_T) nrmse_partial(const Recon* __restrict__
 
 __global__ void __launch_bounds__(RED_T) nrmse_finish(const Recon* __restrict__ recs,
                                                       const int* __restrict__ items, int update_stop,
-                                                      float tol, int min_iter, int max_iter) {
+                                                      float tol, int min_iter) {
+  const Recon& g = recs[items[blockIdx.x]];
+  if ((update_stop && *g.done) || !g.xref) return;
+  __shared__ double sh[4][RED_T];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < g.n_red; b += RED_T)
+    for (int q = 0; q < 4; ++q) acc[q] += g.red[4 * b + q];
+  for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int w = RED_T / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double sref = sh[3][0];
+  const double c = sqrt(sh[0][0] * sh[0][0] + sh[1][0] * sh[1][0]);
+  const double e2 = (sh[2][0] + sref - 2.0 * c) / (sref > 0.0 ? sref : 1.0);
+  const double e = sqrt(e2 > 0.0 ? e2 : 0.0);
+  const double prev = g.track[1];
+  g.track[0] = sref;
+  g.track[2] = prev;
+  g.track[1] = e;
+  // stop rule: NRMSE change below tol once min_iter iterations have run
+  if (update_stop && g.track[3] >= (double)min_iter && fabs(e - prev) < (double)tol) *g.done = 1;
+}
+
+// -------------------------------------------------------------------------
+// Truth-free stop rule: the data-fit cost of eq. (4) at the current
+// reconstruction, C = sum_j f_j(P_j xhat) = 1/2 sum_j ||y_j - |F D P_j xhat|||^2
+// (sigma_n = 1; only its relative change is used).  With the unnormalised
+// transform W = Np F(D P_j xhat) and yfac * ys = Np y_j, each patch adds
+// (yfac ys - |W|)^2 / (2 Np^2).  Per-patch (Np = 256: per column block)
+// partial sums in FP64, summed per reconstruction in a fixed order.
+// -------------------------------------------------------------------------
+__device__ __forceinline__ void block_sum_to(float v, double* out, double scale) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __shared__ double wsum[16];
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0) wsum[w] = (double)v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nw; ++i) s += wsum[i];
+    *out = s * scale;
+  }
+}
+
+__device__ __forceinline__ float fit_term(float2 W, float yv) {
+  const float m = sqrtf(fmaf(W.x, W.x, W.y * W.y));
+  const float e = yv - m;
+  return e * e;
+}
+
+template <int NP>
+__device__ __forceinline__ void fit_small_body(const Recon& g, const int j) {
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, S = NP + A, NT = NP * A, M = B / A;
+  __shared__ float2 tile[NP * S];
+  __shared__ float2 tw[NP];
+  const int tid = threadIdx.x;
+  load_twiddles<NP>(tw, g.tw256, tid, NT);
+  const int2 pj = g.pos[j];
+  const int r = tid / A, p = tid % A;
+  const float2* xrow = g.xhat + (size_t)(pj.x + r) * g.n2 + pj.y;
+  float2 x[B];
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) {
+    const int c = p + A * nb;
+    x[nb] = cmul(g.d[r * NP + c], xrow[c]);
+  }
+  __syncthreads();
+  float2* row = tile + r * S;
+  row_fwd<NP>(x, row, p, tw);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) row[p + A * m + B * ka] = x[m * A + ka];
+  __syncthreads();
+  const int c = tid % NP, q = tid / NP;
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) x[nb] = tile[(q + A * nb) * S + c];
+  col_fwd<NP>(x, tile, S, c, q, tw);
+  const float* yc = g.ys + (size_t)j * NP * NP + c;
+  float acc = 0.f;
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka)
+      acc += fit_term(x[m * A + ka], g.yfac * yc[(size_t)(q + A * m + B * ka) * NP]);
+  block_sum_to(acc, &g.fit[j], 0.5 / ((double)NP * NP));
+}
+
+template <int NP>
+__global__ void __launch_bounds__(NP * Geo<NP>::A) fit_small(const Recon* __restrict__ rec) {
+  fit_small_body<NP>(*rec, blockIdx.x);
+}
+
+template <int NP>
+__global__ void __launch_bounds__(NP * Geo<NP>::A) fit_small_batch(const Recon* __restrict__ recs,
+                                                                   const int2* __restrict__ items) {
+  const int2 it = items[blockIdx.x];
+  const Recon& g = recs[it.x];
+  if (*g.done) return;
+  fit_small_body<NP>(g, it.y);
+}
+
+// Np = 256: rows pass of F(D P_j xhat) into the stage, then columns + cost.
+__global__ void __launch_bounds__(RB * 16) fit256_rows(const Recon* __restrict__ rec, int j0,
+                                                        int check_done) {
+  const Recon& g = *rec;
+  if (check_done && *g.done) return;
+  constexpr int NP = NP256, A = 16, S = NP + A;
+  __shared__ float2 tile[RB * S];
+  __shared__ float2 tw[NP];
+  const int tid = threadIdx.x;
+  load_twiddles<NP>(tw, g.tw256, tid, RB * A);
+  const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
+  const int2 pj = g.pos[j0 + jl];
+  const int rl = tid / A, p = tid % A, r = rb * RB + rl;
+  const float2* xrow = g.xhat + (size_t)(pj.x + r) * g.n2 + pj.y;
+  float2 x[16];
+#pragma unroll
+  for (int nb = 0; nb < 16; ++nb) {
+    const int c = p + A * nb;
+    x[nb] = cmul(g.d[r * NP + c], xrow[c]);
+  }
+  __syncthreads();
+  row_fwd<NP>(x, tile + rl * S, p, tw);
+  float2* out = g.stage + ((size_t)jl * NP + r) * NP;
+#pragma unroll
+  for (int ka = 0; ka < 16; ++ka) out[p + 16 * ka] = x[ka];
+}
+
+__global__ void __launch_bounds__(CB * 16) fit256_cols(const Recon* __restrict__ rec, int j0,
+                                                        int check_done) {
+  const Recon& g = *rec;
+  if (check_done && *g.done) return;
+  constexpr int NP = NP256, A = 16;
+  __shared__ float2 tile[NP * CB];
+  __shared__ float2 tw[NP];
+  const int tid = threadIdx.x;
+  load_twiddles<NP>(tw, g.tw256, tid, CB * A);
+  const int jl = blockIdx.x / (NP / CB), cb = blockIdx.x % (NP / CB);
+  const int j = j0 + jl;
+  const int c = tid % CB, q = tid / CB, col = cb * CB + c;
+  const float2* sp = g.stage + (size_t)jl * NP * NP + col;
+  float2 x[16];
+#pragma unroll
+  for (int nb = 0; nb < 16; ++nb) x[nb] = sp[(size_t)(q + A * nb) * NP];
+  __syncthreads();
+  col_fwd<NP>(x, tile, CB, c, q, tw);
+  const float* yc = g.ys + (size_t)j * NP * NP + col;
+  float acc = 0.f;
+#pragma unroll
+  for (int ka = 0; ka < 16; ++ka) acc += fit_term(x[ka], g.yfac * yc[(size_t)(q + 16 * ka) * NP]);
+  block_sum_to(acc, &g.fit[(size_t)j * (NP / CB) + cb], 0.5 / ((double)NP * NP));
+}
+
+// Sum the partials per reconstruction; the truth-free rule stops a member when
+// |C_k - C_{k-1}| <= tol C_{k-1} once min_iter iterations have run.
+__global__ void __launch_bounds__(RED_T) fit_finish(const Recon* __restrict__ recs,
+                                                    const int* __restrict__ items, int update_stop,
+                                                    float tol, int min_iter) {
   const Recon& g = recs[items[blockIdx.x]];
   if (update_stop && *g.done) return;
-  double e = 0.0, prev = 0.0;
-  if (g.xref) {
-    __shared__ double sh[4][RED_T];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < g.n_red; b += RED_T)
-      for (int q = 0; q < 4; ++q) acc[q] += g.red[4 * b + q];
-    for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = acc[q];
+  const int n = g.J * g.fit_bpp;
+  __shared__ double sh[RED_T];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += RED_T) acc += g.fit[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = RED_T / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
     __syncthreads();
-    for (int w = RED_T / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w)
-        for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x != 0) return;
-    const double sref = sh[3][0];
-    const double c = sqrt(sh[0][0] * sh[0][0] + sh[1][0] * sh[1][0]);
-    const double e2 = (sh[2][0] + sref - 2.0 * c) / (sref > 0.0 ? sref : 1.0);
-    e = sqrt(e2 > 0.0 ? e2 : 0.0);
-    prev = g.track[1];
-    g.track[0] = sref;
-    g.track[2] = prev;
-    g.track[1] = e;
   }
-  if (threadIdx.x != 0 || !update_stop) return;
-  // stop rule: NRMSE change below tol after min_iter tracked iterations (only
-  // with a reference), or max_iter iterations
-  const double k = g.track[3] + 1.0;
-  g.track[3] = k;
-  const bool settled = g.xref && k >= (double)min_iter && fabs(e - prev) < (double)tol;
-  if (settled || k >= (double)max_iter) *g.done = 1;
+  if (threadIdx.x != 0) return;
+  const double cst = sh[0];
+  if (!update_stop) {  // on demand: leaves the stop rule's history alone
+    g.track[6] = cst;
+    return;
+  }
+  const double prev = g.track[4];
+  g.track[5] = prev;
+  g.track[4] = cst;
+  if (g.track[3] >= (double)min_iter && isfinite(prev) && fabs(cst - prev) <= (double)tol * prev)
+    *g.done = 1;
+}
+
+// One iteration done: count it for every member that ran it (before the
+// stop rule is evaluated), or (cap) stop members that reached max_iter.
+__global__ void tick_k(const Recon* __restrict__ recs, const int* __restrict__ items, int n,
+                       int max_iter, int cap) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const Recon& g = recs[items[i]];
+  if (*g.done) return;
+  if (cap) {
+    if (g.track[3] >= (double)max_iter) *g.done = 1;
+  } else {
+    g.track[3] += 1.0;
+  }
 }
 
 // -------------------------------------------------------------------------
@@ -930,12 +1099,70 @@ hipError_t launch_set_state(const Recon& h, const Recon* rec, const float2* v,
 }
 
 hipError_t launch_nrmse(const Recon* recs, const int2* ritems, int nritems, const int* fitems, int nf,
-                        int update_stop, float tol, int min_iter, int max_iter, hipStream_t st) {
+                        int update_stop, float tol, int min_iter, hipStream_t st) {
   if (nritems > 0)
     hipLaunchKernelGGL(nrmse_partial, dim3(nritems), dim3(RED_T), 0, st, recs, ritems, update_stop);
   if (nf > 0)
     hipLaunchKernelGGL(nrmse_finish, dim3(nf), dim3(RED_T), 0, st, recs, fitems, update_stop, tol,
-                       min_iter, max_iter);
+                       min_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_member(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
+  switch (h.np) {
+#define PMACE_FIT(N)                                                                               \
+  case N:                                                                                          \
+    hipLaunchKernelGGL(fit_small<N>, dim3(h.J), dim3(N * Geo<N>::A), 0, st, rec);                  \
+    break;
+    PMACE_FIT(32)
+    PMACE_FIT(64)
+    PMACE_FIT(128)
+#undef PMACE_FIT
+    case 256:
+      for (int j0 = 0; j0 < h.J; j0 += h.chunk) {
+        const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
+        hipLaunchKernelGGL(fit256_rows, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, rec, j0,
+                           check_done);
+        hipLaunchKernelGGL(fit256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, rec, j0,
+                           check_done);
+      }
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_batch(int np, const Recon* recs, const int2* items, int nitems, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  switch (np) {
+#define PMACE_FIT(N)                                                                               \
+  case N:                                                                                          \
+    hipLaunchKernelGGL(fit_small_batch<N>, dim3(nitems), dim3(N * Geo<N>::A), 0, st, recs, items); \
+    break;
+    PMACE_FIT(32)
+    PMACE_FIT(64)
+    PMACE_FIT(128)
+#undef PMACE_FIT
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_finish(const Recon* recs, const int* fitems, int nf, int update_stop, float tol,
+                             int min_iter, hipStream_t st) {
+  if (nf > 0)
+    hipLaunchKernelGGL(fit_finish, dim3(nf), dim3(RED_T), 0, st, recs, fitems, update_stop, tol,
+                       min_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_tick(const Recon* recs, const int* fitems, int nf, int max_iter, int cap,
+                       hipStream_t st) {
+  if (nf > 0)
+    hipLaunchKernelGGL(tick_k, dim3(blocks_for(nf, 256)), dim3(256), 0, st, recs, fitems, nf, max_iter,
+                       cap);
   return hipGetLastError();
 }
 

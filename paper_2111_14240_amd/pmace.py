@@ -26,6 +26,8 @@ PMACE_EDIVERGED = 6
 PMACE_CENTERED_DC = 0x1
 PMACE_METHOD_PMACE = 0
 PMACE_METHOD_SHARP_PLUS = 1
+PMACE_STOP_NRMSE = 0
+PMACE_STOP_DATA_FIT = 1
 
 STATUS_NAMES = {
     0: "PMACE_OK", 1: "PMACE_EINVAL", 2: "PMACE_EUNSUPPORTED", 3: "PMACE_ENOMEM",
@@ -43,7 +45,8 @@ class pmace_params(ctypes.Structure):
 
 
 class pmace_stop_rule(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_float), ("min_iter", ctypes.c_int32), ("max_iter", ctypes.c_int32)]
+    _fields_ = [("tol", ctypes.c_float), ("min_iter", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+                ("criterion", ctypes.c_int32), ("check_every", ctypes.c_int32)]
 
 
 class PMACEError(RuntimeError):
@@ -87,6 +90,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pmace_set_reference.restype = ctypes.c_int
     L.pmace_nrmse.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.pmace_nrmse.restype = ctypes.c_int
+    L.pmace_data_fit.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
+    L.pmace_data_fit.restype = ctypes.c_int
+    L.pmace_batch_poll_fit.argtypes = [vp, vp, vp, vp, vp]
+    L.pmace_batch_poll_fit.restype = ctypes.c_int
     L.pmace_batch_footprint.argtypes = [ctypes.POINTER(vp), i32]
     L.pmace_batch_footprint.restype = sz
     L.pmace_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(pmace_stop_rule), vp, sz,
@@ -184,6 +191,12 @@ def pmace_nrmse(ctx):
     return st, out.value
 
 
+def pmace_data_fit(ctx):
+    out = ctypes.c_double()
+    st = load_library().pmace_data_fit(ctx, ctypes.byref(out))
+    return st, out.value
+
+
 def _ctx_array(ctxs):
     arr = (ctypes.c_void_p * len(ctxs))(*[c.value if isinstance(c, ctypes.c_void_p) else c for c in ctxs])
     return ctypes.cast(arr, ctypes.POINTER(ctypes.c_void_p)), arr
@@ -213,6 +226,19 @@ def pmace_batch_poll(batch, n: int):
     st = load_library().pmace_batch_poll(batch, ctypes.cast(done, ctypes.c_void_p),
                                          ctypes.cast(nr, ctypes.c_void_p), ctypes.cast(it, ctypes.c_void_p))
     return st, np.array(done[:], dtype=np.int32), np.array(nr[:]), np.array(it[:], dtype=np.int32)
+
+
+def pmace_batch_poll_fit(batch, n: int):
+    done = (ctypes.c_int32 * n)()
+    nr = (ctypes.c_double * n)()
+    it = (ctypes.c_int32 * n)()
+    fit = (ctypes.c_double * n)()
+    st = load_library().pmace_batch_poll_fit(batch, ctypes.cast(done, ctypes.c_void_p),
+                                             ctypes.cast(nr, ctypes.c_void_p),
+                                             ctypes.cast(it, ctypes.c_void_p),
+                                             ctypes.cast(fit, ctypes.c_void_p))
+    return (st, np.array(done[:], dtype=np.int32), np.array(nr[:]), np.array(it[:], dtype=np.int32),
+            np.array(fit[:]))
 
 
 def pmace_batch_destroy(batch) -> None:
@@ -397,6 +423,12 @@ class Reconstruction:
         _check(st, "pmace_nrmse")
         return v
 
+    def data_fit(self) -> float:
+        """Data-fit cost of eq. (4) at the current reconstruction (sigma_n = 1)."""
+        st, v = pmace_data_fit(self.ctx)
+        _check(st, "pmace_data_fit")
+        return v
+
     def close(self):
         if getattr(self, "ctx", None) is not None and self.ctx.value:
             pmace_destroy(self.ctx)
@@ -413,7 +445,8 @@ class Batch:
     """Several Reconstructions (same device and stream) advanced together: one
     graph launch per iteration, NRMSE and the stop rule kept on the device."""
 
-    def __init__(self, recons, tol=1e-4, min_iter=2, max_iter=500, workspace=None):
+    def __init__(self, recons, tol=1e-4, min_iter=2, max_iter=500, workspace=None,
+                 criterion=PMACE_STOP_NRMSE, check_every=1):
         torch = _torch()
         self.recons = list(recons)
         self.ctxs = [r.ctx for r in self.recons]
@@ -423,7 +456,8 @@ class Batch:
         if workspace is None:
             workspace = torch.empty(fp, dtype=torch.uint8, device=self.recons[0].device)
         self.workspace = workspace
-        self.rule = pmace_stop_rule(float(tol), int(min_iter), int(max_iter))
+        self.rule = pmace_stop_rule(float(tol), int(min_iter), int(max_iter), int(criterion),
+                                    int(check_every))
         st, b = pmace_batch_create(self.ctxs, self.rule, ctypes.c_void_p(workspace.data_ptr()),
                                    workspace.numel())
         _check(st, "pmace_batch_create")
@@ -433,10 +467,16 @@ class Batch:
         _check(pmace_batch_step(self.batch, n), "pmace_batch_step")
 
     def poll(self):
-        """(done flags, last NRMSE, tracked iterations) per member, numpy arrays."""
+        """(done flags, last NRMSE, counted iterations) per member, numpy arrays."""
         st, done, nr, it = pmace_batch_poll(self.batch, len(self.ctxs))
         _check(st, "pmace_batch_poll")
         return done, nr, it
+
+    def poll_fit(self):
+        """poll() plus the last data-fit cost the stop rule evaluated."""
+        st, done, nr, it, fit = pmace_batch_poll_fit(self.batch, len(self.ctxs))
+        _check(st, "pmace_batch_poll_fit")
+        return done, nr, it, fit
 
     def close(self):
         if getattr(self, "batch", None) is not None and self.batch.value:

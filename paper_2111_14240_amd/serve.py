@@ -184,12 +184,14 @@ class GPUExecutor:
     per active request, re-batched whenever the active set changes."""
 
     def __init__(self, alpha: float, kappa: float = 1.25, rho: float = 0.5, tol: float = 1e-4,
-                 min_iter: int = 2, max_iter: int = 500, device="cuda", stream=None):
+                 min_iter: int = 2, max_iter: int = 500, device="cuda", stream=None,
+                 criterion: int = 0, check_every: int = 1):
         from . import pmace, synth
         self._pmace = pmace
         self._synth = synth
         self.alpha, self.kappa, self.rho = alpha, kappa, rho
         self.tol, self.min_iter, self.max_iter = tol, min_iter, max_iter
+        self.criterion, self.check_every = criterion, check_every
         self.device = device
         self.stream = stream
         self.active: Dict[int, object] = {}
@@ -222,7 +224,8 @@ class GPUExecutor:
     def step(self, n: int):
         if self.batch is None:      # membership changed since the last step
             self.batch = self._pmace.Batch([self.active[r] for r in self.order], tol=self.tol,
-                                           min_iter=self.min_iter, max_iter=self.max_iter)
+                                           min_iter=self.min_iter, max_iter=self.max_iter,
+                                           criterion=self.criterion, check_every=self.check_every)
         self.batch.step(n)
 
     def poll(self):

@@ -103,6 +103,10 @@ def test_batch_argument_checks(lib):
     assert P.pmace_set_reference(None, None, None) == P.PMACE_ESTATE
     st, _ = P.pmace_nrmse(None)
     assert st == P.PMACE_ESTATE
+    st, _ = P.pmace_data_fit(None)
+    assert st == P.PMACE_ESTATE
+    st, *_ = P.pmace_batch_poll_fit(None, 1)
+    assert st == P.PMACE_ESTATE
     P.pmace_batch_destroy(None)
 
 

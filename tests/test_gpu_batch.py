@@ -108,6 +108,23 @@ def test_batch_stop_rule(P):
     _say("stop rule: iters", iters.tolist(), "nrmse", np.round(nr, 4).tolist())
     assert done.all()
     assert np.all(iters >= 3) and np.all(iters <= 60)
+    # the same rule replayed on each reconstruction advanced alone
+    expect = []
+    for prob, cfg in zip(probs, MIX):
+        A = _recon(P, prob, cfg[-1])
+        A.set_reference(prob.x_true, synth.roi_mask(prob.probe, prob.pos, prob.n1, prob.n2))
+        prev, k = float("inf"), 0
+        while k < 60:
+            A.iterate(1)
+            k += 1
+            e = A.nrmse()
+            if k >= 3 and abs(e - prev) < 2e-3:
+                break
+            prev = e
+        expect.append(k)
+        A.close()
+    _say("stop rule alone: iters", expect)
+    assert iters.tolist() == expect
     for R, e in zip(Rs, nr):
         assert abs(R.nrmse() - e) < 1e-12       # the batch's last value is the member's NRMSE
     snap = [R.get_state().cpu().numpy() for R in Rs]
@@ -117,3 +134,96 @@ def test_batch_stop_rule(P):
     B.close()
     for R in Rs:
         R.close()
+
+
+FIT_CASES = [  # (n, np, scan, step, peak, seed, chunk)
+    (128, 32, 6, 16, 1e5, 41, 0),
+    (200, 64, 5, 30, 1e5, 42, 0),
+    (320, 128, 4, 56, 1e5, 43, 0),
+    (400, 256, 3, 60, 1e6, 44, 4),
+]
+
+
+@pytest.mark.parametrize("case", FIT_CASES, ids=lambda c: f"np{c[1]}")
+def test_data_fit_matches_oracle(P, case):
+    """eq. (4) at the device's current reconstruction, against the oracle's
+    cost evaluated at the same reconstruction."""
+    n, np_, sc, stp, pk, sd, chunk = case
+    prob = synth.make_problem(n, np_, sc, stp, pk, sd)
+    R = _recon(P, prob, chunk)
+    R.iterate(3)
+    R.sync()
+    c = R.data_fit()
+    xh = R.reconstruct().cpu().numpy().astype(np.complex128)
+    d = prob.probe.astype(np.complex64).astype(np.complex128)
+    y = O.amplitudes(prob.z.astype(np.float32))
+    ref = O.data_fit_cost(O.extract(xh, prob.pos, np_), d, y)
+    _say(f"data fit np{np_}: device {c:.8e} oracle {ref:.8e}")
+    assert abs(c - ref) <= 1e-4 * ref
+    R.close()
+
+
+def test_data_fit_vanishes_at_noise_free_truth(P):
+    prob = synth.make_problem(200, 64, 5, 30, None, 45)
+    R = P.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, 0.5,
+                         x0=prob.x_true.astype(np.complex64))
+    c = R.data_fit()
+    scale = 0.5 * float(np.sum(prob.z))     # the cost at xhat = 0
+    _say(f"data fit at the truth {c:.3e} (cost at zero {scale:.3e})")
+    assert c <= 1e-9 * scale
+    R.close()
+
+
+def _emulate_fit_rule(P, prob, chunk, tol, min_iter, max_iter, every):
+    """The truth-free rule replayed on one reconstruction advanced alone."""
+    R = _recon(P, prob, chunk)
+    prev, costs = float("inf"), []
+    for k in range(1, max_iter + 1):
+        R.iterate(1)
+        if k % every == 0:
+            c = R.data_fit()
+            costs.append(c)
+            if k >= min_iter and np.isfinite(prev) and abs(c - prev) <= tol * prev:
+                R.close()
+                return k, c
+            prev = c
+    R.close()
+    return max_iter, (costs[-1] if costs else float("inf"))
+
+
+def test_batch_data_fit_stop_rule(P):
+    probs = _problems()
+    tol, min_iter, max_iter, every = 1e-2, 4, 60, 2
+    expect = []
+    for prob, cfg in zip(probs, MIX):
+        expect.append(_emulate_fit_rule(P, prob, cfg[-1], tol, min_iter, max_iter, every))
+    _say("data-fit rule, alone:", [e[0] for e in expect])
+    assert any(k < max_iter for k, _ in expect)     # the rule itself stops some members
+    Rs = [_recon(P, prob, cfg[-1]) for prob, cfg in zip(probs, MIX)]
+    B = P.Batch(Rs, tol=tol, min_iter=min_iter, max_iter=max_iter,
+                criterion=P.PMACE_STOP_DATA_FIT, check_every=every)
+    steps = 0
+    while steps < max_iter + 4:
+        B.step(4)
+        steps += 4
+        done, _, iters, fit = B.poll_fit()
+        if done.all():
+            break
+    _say("data-fit rule, batch:", iters.tolist())
+    assert done.all()
+    assert iters.tolist() == [e[0] for e in expect]
+    for (k, c), f in zip(expect, fit):
+        assert f == c                        # same kernels, same order: the same value
+    B.close()
+    for R in Rs:
+        R.close()
+
+
+def test_invalid_stop_rule_rejected(P):
+    prob = synth.make_problem(128, 32, 4, 20, None, 3)
+    R = _recon(P, prob, 0)
+    for kw in (dict(criterion=7), dict(check_every=-1), dict(max_iter=0)):
+        with pytest.raises(P.PMACEError) as ei:
+            P.Batch([R], **kw)
+        assert ei.value.status == P.PMACE_EINVAL
+    R.close()
