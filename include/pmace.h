@@ -35,7 +35,7 @@ extern "C" {
 typedef enum {
   PMACE_OK = 0,
   PMACE_EINVAL = 1,        /* bad argument: size, range, NaN/Inf, negative intensity, position */
-  PMACE_EUNSUPPORTED = 2,  /* valid per the paper but not built here (e.g. Np not in {32,64,128,256}) */
+  PMACE_EUNSUPPORTED = 2,  /* valid per the paper but not built here (an Np without a transform here) */
   PMACE_ENOMEM = 3,        /* workspace smaller than pmace_footprint() */
   PMACE_EDEVICE = 4,       /* a HIP call failed (launch, copy, sync) */
   PMACE_ESTATE = 5,        /* call out of order (e.g. NULL or destroyed context) */
@@ -52,7 +52,8 @@ typedef enum {
 
 typedef struct {
   int32_t n1, n2;     /* object grid N1 x N2 (Sec. II); n1, n2 >= np */
-  int32_t np;         /* probe / patch side Np; this build runs 32, 64, 128, 256 */
+  int32_t np;         /* probe / patch side Np; this build runs 32, 48, 64, 96, 128, 160, 192,
+                         256 (radix 2, 3 and 5 transforms) */
   int32_t num_pos;    /* J >= 1 scan positions */
   float alpha;        /* >= 0: noise-to-signal weight of the agent, eq. (9) */
   float kappa;        /* >= 0: probe exponent of the consensus weights, eq. (11) */
@@ -216,7 +217,7 @@ pmace_status pmace_poisson(const double* lam_d, float* out_d, int32_t n, uint64_
 
 /* Batched 2-D orthonormal DFT of `count` np x np c64 arrays (the operator F
  * of Sec. II, or F^* when inverse != 0), in_d and out_d may alias.
- * np in {32, 64, 128, 256}.  Stream-ordered on hip_stream. */
+ * np in {32, 48, 64, 96, 128, 160, 192, 256}.  Stream-ordered on hip_stream. */
 pmace_status pmace_fft2(int32_t np, int32_t count, const void* in_d, void* out_d,
                         int32_t inverse, void* hip_stream);
 

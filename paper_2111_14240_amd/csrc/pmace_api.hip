@@ -22,6 +22,10 @@ using pmace::Recon;
 namespace {
 
 constexpr size_t kAlign = 256;
+// Patch sides run by the fused one-workgroup agent; larger ones (160, 192,
+// 256) by the three-pass agent.
+constexpr int kSmallNp[] = {32, 48, 64, 96, 128};
+constexpr int kClasses = 5;
 inline size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 bool graphs_enabled() {
@@ -65,10 +69,10 @@ struct pmace_batch {
   hipStream_t stream;
   std::vector<pmace_ctx*> ctxs;
   Recon* recs;                 // device: member descriptors
-  int2* items[3];              // device: agent items per class Np = 32, 64, 128
-  int nitems[3];
-  int2* gitems[3];             // device: gather items per class
-  int ngitems[3];
+  int2* items[kClasses];       // device: agent items per fused patch size (kSmallNp)
+  int nitems[kClasses];
+  int2* gitems[kClasses];      // device: gather items per class
+  int ngitems[kClasses];
   int2* ritems;                // device: (member, block) NRMSE items
   int nritems;
   int* fitems;                 // device: member indices
@@ -83,13 +87,18 @@ struct pmace_batch {
 
 namespace {
 
-bool np_supported(int np) { return np == 32 || np == 64 || np == 128 || np == 256; }
+bool np_supported(int np) {
+  for (int s : kSmallNp)
+    if (np == s) return true;
+  return np == 160 || np == 192 || np == 256;
+}
+bool np_large(int np) { return np > 128; }
 
 // Positions per chunk: Np <= 128 runs all positions in one fused launch;
-// Np = 256 stages chunk*Np^2 spectra between its three passes.
+// Np > 128 stages chunk*Np^2 spectra between its three passes.
 int chunk_of(const pmace_params& p) {
   int c = p.num_pos;
-  if (p.np == 256) c = p.chunk > 0 ? p.chunk : PMACE_CHUNK256;
+  if (np_large(p.np)) c = p.chunk > 0 ? p.chunk : PMACE_CHUNK256;
   if (c > p.num_pos) c = p.num_pos;
   return c;
 }
@@ -131,15 +140,15 @@ struct Layout {
       items, gitems, ritems, red, tw, fit, total;
 };
 
-// Stage buffer: Np = 256 keeps a chunk's spectra between its passes; SHARP+
+// Stage buffer: Np > 128 keeps a chunk's spectra between its passes; SHARP+
 // keeps its overlap numerators there; PMACE with Np <= 128 needs none.
 size_t stage_patches(const pmace_params& p) {
-  if (p.np == 256) return (size_t)chunk_of(p);
+  if (np_large(p.np)) return (size_t)chunk_of(p);
   return p.method == PMACE_METHOD_SHARP_PLUS ? (size_t)chunk_of(p) : 0;
 }
 
-// Data-fit partial sums per patch: one, or one per column block for Np = 256.
-int fit_bpp(const pmace_params& p) { return p.np == 256 ? 256 / PMACE_CB : 1; }
+// Data-fit partial sums per patch: one, or one per column block for Np > 128.
+int fit_bpp(const pmace_params& p) { return np_large(p.np) ? p.np / PMACE_CB : 1; }
 
 Layout layout_of(const pmace_params& p) {
   Layout L;
@@ -186,8 +195,8 @@ pmace_status record(pmace_ctx* c, pmace_status s) {
 }
 
 pmace_status enqueue_iteration(pmace_ctx* c, hipStream_t st) {
-  if (c->prm.np == 256)
-    PM_HIP(pmace::launch_256_iteration(c->h, nullptr, c->chunk_tiles.data(), st));
+  if (np_large(c->prm.np))
+    PM_HIP(pmace::launch_large_iteration(c->h, nullptr, c->chunk_tiles.data(), st));
   else
     PM_HIP(pmace::launch_small_iteration(c->prm.np, c->h, c->ngitems, st));
   return PMACE_OK;
@@ -397,7 +406,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   c->fitem = reinterpret_cast<int*>(base + L.status + 8);
   h.track = reinterpret_cast<double*>(base + L.status + 32);
   h.red = reinterpret_cast<double*>(base + L.red);
-  h.tw256 = reinterpret_cast<float2*>(base + L.tw);
+  h.twn = reinterpret_cast<float2*>(base + L.tw);
   h.fit = reinterpret_cast<double*>(base + L.fit);
   h.fit_bpp = fit_bpp(p);
   h.xref = nullptr;
@@ -438,8 +447,8 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
 
   const int zero = 0;
   std::vector<float> tw(512);
-  for (int m = 0; m < 256; ++m) {
-    const double cv = std::cos(-2.0 * M_PI * m / 256.0), sv = std::sin(-2.0 * M_PI * m / 256.0);
+  for (int m = 0; m < np; ++m) {
+    const double cv = std::cos(-2.0 * M_PI * m / np), sv = std::sin(-2.0 * M_PI * m / np);
     tw[2 * m] = std::fabs(cv) < 1e-15 ? 0.f : (float)cv;       // exact zeros at quarter turns
     tw[2 * m + 1] = std::fabs(sv) < 1e-15 ? 0.f : (float)sv;
   }
@@ -461,7 +470,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
        hipMemcpyAsync(c->gitems, gitems.data(), gitems.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess) ||
       hipMemcpyAsync(c->ritems, ritems.data(), ritems.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c->fitem, &zero, 4, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(h.tw256, tw.data(), 256 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h.twn, tw.data(), (size_t)np * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemsetAsync(h.status, 0, 4, st) != hipSuccess ||
       hipMemcpyAsync(c->dev, &c->h, sizeof(Recon), hipMemcpyHostToDevice, st) != hipSuccess)
     return fail(PMACE_EDEVICE);
@@ -598,11 +607,15 @@ pmace_status pmace_fft2(int32_t np, int32_t count, const void* in_d, void* out_d
 // ---------------------------------------------------------------------------
 namespace {
 
-int class_of(int np) { return np == 32 ? 0 : np == 64 ? 1 : np == 128 ? 2 : -1; }
+int class_of(int np) {
+  for (int k = 0; k < kClasses; ++k)
+    if (np == kSmallNp[k]) return k;
+  return -1;
+}
 
 struct BatchLayout {
-  size_t recs, items[3], gitems[3], ritems, fitems, total;
-  int nitems[3], ngitems[3], nritems;
+  size_t recs, items[kClasses], gitems[kClasses], ritems, fitems, total;
+  int nitems[kClasses], ngitems[kClasses], nritems;
 };
 
 BatchLayout batch_layout(pmace_ctx* const* ctxs, int n) {
@@ -617,7 +630,7 @@ BatchLayout batch_layout(pmace_ctx* const* ctxs, int n) {
   }
   size_t o = 0;
   L.recs = o;    o = align_up(o + (size_t)n * sizeof(Recon));
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kClasses; ++k) {
     L.items[k] = o;  o = align_up(o + (size_t)L.nitems[k] * 8);
     L.gitems[k] = o; o = align_up(o + (size_t)L.ngitems[k] * 8);
   }
@@ -640,16 +653,16 @@ pmace_status check_members(pmace_ctx* const* ctxs, int32_t n) {
 }
 
 pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes, bool check) {
-  for (int k = 0; k < 3; ++k)
+  for (int k = 0; k < kClasses; ++k)
     if (b->nitems[k] > 0)
-      PM_HIP(pmace::launch_small_batch(32 << k, b->recs, b->items[k], b->nitems[k], b->gitems[k],
+      PM_HIP(pmace::launch_small_batch(kSmallNp[k], b->recs, b->items[k], b->nitems[k], b->gitems[k],
                                        b->ngitems[k], st));
-  // Np = 256 members: independent chains of kernels, spread over lanes
+  // Np > 128 members: independent chains of kernels, spread over lanes
   int lane = 0;
   bool forked = false;
   for (int i = 0; i < b->n; ++i) {
     pmace_ctx* c = b->ctxs[i];
-    if (c->prm.np != 256) continue;
+    if (!np_large(c->prm.np)) continue;
     hipStream_t ls = st;
     if (lanes) {
       if (!forked) {
@@ -660,7 +673,7 @@ pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes,
       ls = b->lanes[lane];
       lane = (lane + 1) % 4;
     }
-    PM_HIP(pmace::launch_256_iteration(c->h, b->recs + i, c->chunk_tiles.data(), ls));
+    PM_HIP(pmace::launch_large_iteration(c->h, b->recs + i, c->chunk_tiles.data(), ls));
   }
   if (forked)
     for (int l = 0; l < 4; ++l) {
@@ -672,10 +685,10 @@ pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes,
     PM_HIP(pmace::launch_nrmse(b->recs, b->ritems, b->nritems, b->fitems, b->n, 1, b->rule.tol,
                                b->rule.min_iter, st));
   } else if (check) {
-    for (int k = 0; k < 3; ++k)
-      PM_HIP(pmace::launch_fit_batch(32 << k, b->recs, b->items[k], b->nitems[k], st));
+    for (int k = 0; k < kClasses; ++k)
+      PM_HIP(pmace::launch_fit_batch(kSmallNp[k], b->recs, b->items[k], b->nitems[k], st));
     for (int i = 0; i < b->n; ++i)
-      if (b->ctxs[i]->prm.np == 256)
+      if (np_large(b->ctxs[i]->prm.np))
         PM_HIP(pmace::launch_fit_member(b->ctxs[i]->h, b->recs + i, 1, st));
     PM_HIP(pmace::launch_fit_finish(b->recs, b->fitems, b->n, 1, b->rule.tol, b->rule.min_iter, st));
   }
@@ -727,7 +740,7 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
   char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(workspace_d)));
   b->recs = reinterpret_cast<Recon*>(base + L.recs);
   std::vector<Recon> recs(n);
-  std::vector<int2> items[3], gitems[3], ritems;
+  std::vector<int2> items[kClasses], gitems[kClasses], ritems;
   std::vector<int> fitems(n);
   for (int i = 0; i < n; ++i) {
     pmace_ctx* c = ctxs[i];
@@ -753,7 +766,7 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
   hipStream_t st = b->stream;
   bool ok = hipMemcpyAsync(b->recs, recs.data(), (size_t)n * sizeof(Recon), hipMemcpyHostToDevice,
                            st) == hipSuccess;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kClasses; ++k) {
     b->items[k] = reinterpret_cast<int2*>(base + L.items[k]);
     b->gitems[k] = reinterpret_cast<int2*>(base + L.gitems[k]);
     b->nitems[k] = (int)items[k].size();

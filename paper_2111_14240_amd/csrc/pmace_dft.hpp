@@ -110,25 +110,106 @@ template <bool INV> __device__ __forceinline__ void dft16(float2* a) {
   }
 }
 
+// 3 points: X1,2 = m -/+ i (sqrt3/2)(a1 - a2) with m = a0 - (a1 + a2)/2
+// (signs of i swapped for the inverse).
+template <bool INV> __device__ __forceinline__ void dft3r(float2& a0, float2& a1, float2& a2) {
+  const float s = 0.86602540378443865f;  // sin(2 pi/3)
+  const float2 t = cadd(a1, a2);
+  const float2 m = make_float2(fmaf(-0.5f, t.x, a0.x), fmaf(-0.5f, t.y, a0.y));
+  const float2 r = rotq<INV>(make_float2(s * (a1.x - a2.x), s * (a1.y - a2.y)));
+  a0 = cadd(a0, t);
+  a1 = cadd(m, r);
+  a2 = csub(m, r);
+}
+
+// 5 points, with c_k = cos(2 pi k/5), s_k = sin(2 pi k/5), t1 = a1 + a4,
+// t2 = a2 + a3, t3 = a1 - a4, t4 = a2 - a3:
+//   X1,4 = (a0 + c1 t1 + c2 t2) -/+ i (s1 t3 + s2 t4)
+//   X2,3 = (a0 + c2 t1 + c1 t2) -/+ i (s2 t3 - s1 t4)
+template <bool INV> __device__ __forceinline__ void dft5(float2* a) {
+  const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+  const float s1 = 0.95105651629515357f, s2 = 0.58778525229247313f;
+  const float2 t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+  const float2 t3 = csub(a[1], a[4]), t4 = csub(a[2], a[3]);
+  const float2 m1 = make_float2(fmaf(c2, t2.x, fmaf(c1, t1.x, a[0].x)), fmaf(c2, t2.y, fmaf(c1, t1.y, a[0].y)));
+  const float2 m2 = make_float2(fmaf(c1, t2.x, fmaf(c2, t1.x, a[0].x)), fmaf(c1, t2.y, fmaf(c2, t1.y, a[0].y)));
+  const float2 n1 = rotq<INV>(make_float2(fmaf(s1, t3.x, s2 * t4.x), fmaf(s1, t3.y, s2 * t4.y)));
+  const float2 n2 = rotq<INV>(make_float2(fmaf(s2, t3.x, -(s1 * t4.x)), fmaf(s2, t3.y, -(s1 * t4.y))));
+  a[0] = cadd(a[0], cadd(t1, t2));
+  a[1] = cadd(m1, n1);
+  a[4] = csub(m1, n1);
+  a[2] = cadd(m2, n2);
+  a[3] = csub(m2, n2);
+}
+
+template <bool INV> __device__ __forceinline__ void dft3(float2* a) { dft3r<INV>(a[0], a[1], a[2]); }
+
+constexpr int inv_mod(int a, int m) {
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 1;
+}
+
+template <int R, bool INV> __device__ __forceinline__ void dft(float2* a);
+
+// N = N1 N2 with gcd(N1, N2) = 1 (Good-Thomas prime-factor map, no
+// twiddles): input n = (N2 n1 + N1 n2) mod N, output
+// k = (N2 u k1 + N1 v k2) mod N with u = N2^-1 mod N1, v = N1^-1 mod N2, so
+// that W_N^{nk} = W_N1^{n1 k1} W_N2^{n2 k2}.
+template <int N1, int N2, bool INV> __device__ __forceinline__ void dft_pfa(float2* a) {
+  constexpr int N = N1 * N2, U = inv_mod(N2 % N1, N1), V = inv_mod(N1 % N2, N2);
+  float2 t[N1][N2];
+#pragma unroll
+  for (int n1 = 0; n1 < N1; ++n1)
+#pragma unroll
+    for (int n2 = 0; n2 < N2; ++n2) t[n1][n2] = a[(N2 * n1 + N1 * n2) % N];
+#pragma unroll
+  for (int n2 = 0; n2 < N2; ++n2) {
+    float2 col[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) col[n1] = t[n1][n2];
+    dft<N1, INV>(col);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) t[k1][n2] = col[k1];
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) dft<N2, INV>(t[k1]);
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1)
+#pragma unroll
+    for (int k2 = 0; k2 < N2; ++k2) a[(N2 * U * k1 + N1 * V * k2) % N] = t[k1][k2];
+}
+
 template <int R, bool INV> __device__ __forceinline__ void dft(float2* a) {
   if constexpr (R == 2) dft2<INV>(a);
+  else if constexpr (R == 3) dft3<INV>(a);
   else if constexpr (R == 4) dft4<INV>(a);
+  else if constexpr (R == 5) dft5<INV>(a);
   else if constexpr (R == 8) dft8<INV>(a);
+  else if constexpr (R == 12) dft_pfa<3, 4, INV>(a);
+  else if constexpr (R == 24) dft_pfa<3, 8, INV>(a);
+  else if constexpr (R == 40) dft_pfa<5, 8, INV>(a);
   else { static_assert(R == 16, "radix"); dft16<INV>(a); }
 }
 
-// Split N = A*B of a line over A threads with B registers each.
+// Split N = A*B of a line over A threads with B registers each (B a multiple
+// of A).  Powers of two use radix 16/8/4; 48, 96, 192 add a factor 3 and 160
+// a factor 5 through the prime-factor DFTs above.
 template <int N> struct Geo;
 template <> struct Geo<32>  { static constexpr int A = 4,  B = 8;  };
+template <> struct Geo<48>  { static constexpr int A = 4,  B = 12; };
 template <> struct Geo<64>  { static constexpr int A = 8,  B = 8;  };
+template <> struct Geo<96>  { static constexpr int A = 4,  B = 24; };
 template <> struct Geo<128> { static constexpr int A = 8,  B = 16; };
+template <> struct Geo<160> { static constexpr int A = 4,  B = 40; };
+template <> struct Geo<192> { static constexpr int A = 8,  B = 24; };
 template <> struct Geo<256> { static constexpr int A = 16, B = 16; };
 
-// W_N^m = exp(-2 pi i m / N) for m = 0..N-1 into LDS from a table of W_256^m
-// (computed in FP64 on the host and rounded once): W_N^m = W_256^(m 256/N).
-template <int N> __device__ __forceinline__ void load_twiddles(float2* tw, const float2* tw256, int tid,
+// W_N^m = exp(-2 pi i m / N), m = 0..N-1, into LDS from the reconstruction's
+// table (computed in FP64 on the host and rounded once).
+template <int N> __device__ __forceinline__ void load_twiddles(float2* tw, const float2* twn, int tid,
                                                               int nthreads) {
-  for (int m = tid; m < N; m += nthreads) tw[m] = tw256[m * (256 / N)];
+  for (int m = tid; m < N; m += nthreads) tw[m] = twn[m];
 }
 
 // The same values computed in place (FP64 sincospi, rounded once), for the
@@ -154,7 +235,7 @@ template <int N> __device__ __forceinline__ void row_fwd(float2 (&x)[Geo<N>::B],
   constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A;
   dft<B, false>(x);
 #pragma unroll
-  for (int kb = 1; kb < B; ++kb) x[kb] = cmul(x[kb], tw[(p * kb) & (N - 1)]);
+  for (int kb = 1; kb < B; ++kb) x[kb] = cmul(x[kb], tw[p * kb]);
   __syncthreads();
 #pragma unroll
   for (int kb = 0; kb < B; ++kb) row[p * (B + 1) + kb] = x[kb];
@@ -181,7 +262,7 @@ template <int N> __device__ __forceinline__ void row_inv(float2 (&x)[Geo<N>::B],
     const int kb = p + A * m;
     dft<A, true>(&x[m * A]);
 #pragma unroll
-    for (int na = 1; na < A; ++na) x[m * A + na] = cmulc(x[m * A + na], tw[(na * kb) & (N - 1)]);
+    for (int na = 1; na < A; ++na) x[m * A + na] = cmulc(x[m * A + na], tw[na * kb]);
   }
   __syncthreads();
 #pragma unroll
@@ -209,7 +290,7 @@ template <int N> __device__ __forceinline__ void col_fwd(float2 (&x)[Geo<N>::B],
   constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A;
   dft<B, false>(x);
 #pragma unroll
-  for (int kb = 1; kb < B; ++kb) x[kb] = cmul(x[kb], tw[(q * kb) & (N - 1)]);
+  for (int kb = 1; kb < B; ++kb) x[kb] = cmul(x[kb], tw[q * kb]);
   __syncthreads();
 #pragma unroll
   for (int kb = 0; kb < B; ++kb) tile[(kb * A + q) * S + c] = x[kb];
@@ -236,7 +317,7 @@ template <int N> __device__ __forceinline__ void col_inv(float2 (&x)[Geo<N>::B],
     const int kb = q + A * m;
     dft<A, true>(&x[m * A]);
 #pragma unroll
-    for (int na = 1; na < A; ++na) x[m * A + na] = cmulc(x[m * A + na], tw[(na * kb) & (N - 1)]);
+    for (int na = 1; na < A; ++na) x[m * A + na] = cmulc(x[m * A + na], tw[na * kb]);
   }
   __syncthreads();
 #pragma unroll

@@ -16,13 +16,13 @@ namespace pmace {
 #define PMACE_GATHER_UNROLL 8
 #endif
 #ifndef PMACE_RB
-#define PMACE_RB 16       // Np = 256: patch rows per workgroup in the row passes
+#define PMACE_RB 16       // Np > 128: patch rows per workgroup in the row passes
 #endif
 #ifndef PMACE_CB
-#define PMACE_CB 16       // Np = 256: patch columns per workgroup in the column pass
+#define PMACE_CB 16       // Np > 128: patch columns per workgroup in the column pass
 #endif
 #ifndef PMACE_CHUNK256
-#define PMACE_CHUNK256 128  // Np = 256: default positions per chunk
+#define PMACE_CHUNK256 128  // Np > 128: default positions per chunk
 #endif
 
 // Gather tile of the consensus: GT_R x GT_C object pixels, GT_K threads each
@@ -44,13 +44,13 @@ struct Recon {
   float2* dinv;         // Np*Np     d^{-1}/Np^2, 0 exactly where d == 0 (PMACE epilogue)
   float* omega;         // Np*Np     |d|^kappa (PMACE consensus weights)
   float* laminv;        // N1*N2     Lambda^{-1} (0 where Lambda = 0)
-  float2* num;          // N1*N2     weighted back-projection accumulator (Np = 256)
+  float2* num;          // N1*N2     consensus sum accumulator (Np > 128, set_state)
   float2* sold;         // N1*N2     PMACE: S = sum_j P_j^t |d|^kappa t_j of the current states
   float2* xbar;         // N1*N2     consensus image of the last iteration
   float2* xhat;         // N1*N2     reconstruction (Alg. 1 output, kept by recurrence)
-  float2* stage;        // chunk*Np*Np: Np = 256 spectra between passes; SHARP+ (every Np):
+  float2* stage;        // chunk*Np*Np: Np > 128 spectra between passes; SHARP+ (every Np):
                         //   the weighted frames conj(d) P_a s the overlap projection sums
-  float2* tw256;        // 256      W_256^m = exp(-2 pi i m/256), FP64-rounded twiddles
+  float2* twn;          // Np       W_Np^m = exp(-2 pi i m/Np), FP64-rounded twiddles
   int4* tiles;          // per gather tile: (list start, count, first row, first col)
   int* tile_list;       // positions overlapping each tile, ascending
   unsigned* status;     // bit0: non-finite consensus image; bit1: bad intensity
@@ -60,7 +60,7 @@ struct Recon {
   double* red;          // per reduction block: {Re, Im sum conj(xref) xhat, sum |xhat|^2, sum |xref|^2}
   double* track;        // {sum |xref|^2, last nrmse, previous nrmse, iterations counted,
                         //  last data-fit cost, previous data-fit cost}
-  double* fit;          // J*fit_bpp per-patch (Np = 256: per column block) data-fit partials
+  double* fit;          // J*fit_bpp per-patch (Np > 128: per column block) data-fit partials
   int n1, n2, np, J;
   float a;              // alpha / (1 + alpha)
   float two_rho;
@@ -90,12 +90,12 @@ hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_
 // gather + image update over `gitems` (recon index, tile).
 hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int nitems,
                               const int2* gitems, int ngitems, hipStream_t st);
-// Np = 256, one reconstruction, chunk by chunk; chunk_tiles[g] = (first tile,
+// Np > 128, one reconstruction, chunk by chunk; chunk_tiles[g] = (first tile,
 // tile count) of chunk g (host array).  batch_rec: the member's device
 // descriptor when run inside a batch (its kernels honour the stop flag), else
 // null (descriptor passed by value).
-hipError_t launch_256_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
-                                hipStream_t st);
+hipError_t launch_large_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
+                                  hipStream_t st);
 hipError_t launch_get_state(const Recon& h, const Recon* rec, float2* v, hipStream_t st);
 hipError_t launch_set_state(const Recon& h, const Recon* rec, const float2* v,
                             const int2* chunk_tiles, hipStream_t st);

@@ -114,7 +114,7 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
   __shared__ float2 tile[NP * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.tw256, tid, NT);
+  load_twiddles<NP>(tw, g.twn, tid, NT);
   const int2 pj = g.pos[j];
   const size_t pb = (size_t)j * NP * NP;
   const int r = tid / A, p = tid % A;
@@ -191,35 +191,38 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused_batch(const Recon
 }
 
 // -------------------------------------------------------------------------
-// Np = 256: a 256x256 complex patch (512 KB) exceeds one CU's LDS, so the
-// agent runs as three passes over a chunk of positions, the spectra staged in
-// a chunk-sized buffer that is reused every chunk:
+// Np in {160, 192, 256}: the patch (up to 512 KB) exceeds one CU's LDS, so
+// the agent runs as three passes over a chunk of positions, the spectra
+// staged in a chunk-sized buffer that is reused every chunk:
 //   rows   : a2, a3, forward row DFTs            -> stage
 //   cols   : forward column DFTs, spectrum step (a5), inverse column DFTs (in place)
 //   rowsinv: inverse row DFTs, a6-a7 (t); SHARP+: stage <- overlap numerators
+// A workgroup takes RB rows (row passes) or CB columns (column pass) of one
+// patch, with Geo<NP>::A threads per line.
 // -------------------------------------------------------------------------
-constexpr int NP256 = 256;
 constexpr int RB = PMACE_RB;   // rows per workgroup in the row passes
 constexpr int CB = PMACE_CB;   // columns per workgroup in the column pass
-static_assert(RB >= 4 && RB <= 32 && NP256 % RB == 0, "row block");
-static_assert(CB >= 8 && CB <= 32 && NP256 % CB == 0, "column block");
+static_assert(RB >= 4 && RB <= 32 && 160 % RB == 0 && 192 % RB == 0 && 256 % RB == 0, "row block");
+static_assert(CB >= 8 && CB <= 32 && 160 % CB == 0 && 192 % CB == 0 && 256 % CB == 0, "column block");
+template <int NP> constexpr int row_threads() { return RB * Geo<NP>::A; }
+template <int NP> constexpr int col_threads() { return CB * Geo<NP>::A; }
 
-template <int METHOD>
-__device__ __forceinline__ void agent256_rows_body(const Recon& g, const int j0) {
-  constexpr int NP = NP256, A = 16, S = NP + A;
+template <int NP, int METHOD>
+__device__ __forceinline__ void agent_rows_body(const Recon& g, const int j0) {
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = NP + A;
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.tw256, tid, RB * A);
+  load_twiddles<NP>(tw, g.twn, tid, RB * A);
   const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
   const int j = j0 + jl;
   const int2 pj = g.pos[j];
   const int rl = tid / A, p = tid % A, r = rb * RB + rl;
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   const float2* trow = g.t + (size_t)j * NP * NP + (size_t)r * NP;
-  float2 x[16];
+  float2 x[B];
 #pragma unroll
-  for (int nb = 0; nb < 16; ++nb) {
+  for (int nb = 0; nb < B; ++nb) {
     const int c = p + A * nb;
     x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], g.two_rho);
   }
@@ -227,90 +230,100 @@ __device__ __forceinline__ void agent256_rows_body(const Recon& g, const int j0)
   row_fwd<NP>(x, tile + rl * S, p, tw);
   float2* out = g.stage + ((size_t)jl * NP + r) * NP;
 #pragma unroll
-  for (int ka = 0; ka < 16; ++ka) out[p + 16 * ka] = x[ka];
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) out[p + A * m + B * ka] = x[m * A + ka];
 }
 
-template <int METHOD>
-__global__ void __launch_bounds__(RB * 16) agent256_rows(const Recon g, int j0) {
-  agent256_rows_body<METHOD>(g, j0);
+template <int NP, int METHOD>
+__global__ void __launch_bounds__(row_threads<NP>()) agent_rows(const Recon g, int j0) {
+  agent_rows_body<NP, METHOD>(g, j0);
 }
 
-__global__ void __launch_bounds__(RB * 16) agent256_rows_batch(const Recon* __restrict__ rec, int j0) {
+template <int NP>
+__global__ void __launch_bounds__(row_threads<NP>()) agent_rows_batch(const Recon* __restrict__ rec, int j0) {
   if (*rec->done) return;
-  agent256_rows_body<kPMACE>(*rec, j0);
+  agent_rows_body<NP, kPMACE>(*rec, j0);
 }
 
-template <int METHOD>
-__device__ __forceinline__ void agent256_cols_body(const Recon& g, const int j0) {
-  constexpr int NP = NP256, A = 16;
+template <int NP, int METHOD>
+__device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A;
   __shared__ float2 tile[NP * CB];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.tw256, tid, CB * A);
+  load_twiddles<NP>(tw, g.twn, tid, CB * A);
   const int jl = blockIdx.x / (NP / CB), cb = blockIdx.x % (NP / CB);
   const int j = j0 + jl;
   const int c = tid % CB, q = tid / CB, col = cb * CB + c;
   float2* sp = g.stage + (size_t)jl * NP * NP + col;
-  float2 x[16];
+  float2 x[B];
 #pragma unroll
-  for (int nb = 0; nb < 16; ++nb) x[nb] = sp[(size_t)(q + A * nb) * NP];
+  for (int nb = 0; nb < B; ++nb) x[nb] = sp[(size_t)(q + A * nb) * NP];
   __syncthreads();
   col_fwd<NP>(x, tile, CB, c, q, tw);
   const float* yc = g.ys + (size_t)j * NP * NP + col;
 #pragma unroll
-  for (int ka = 0; ka < 16; ++ka) {
-    const int k = q + 16 * ka;
-    x[ka] = spectrum_step<METHOD>(x[ka], yc[(size_t)k * NP], g);
-  }
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) {
+      const int k = q + A * m + B * ka;
+      x[m * A + ka] = spectrum_step<METHOD>(x[m * A + ka], yc[(size_t)k * NP], g);
+    }
   col_inv<NP>(x, tile, CB, c, q, tw);
 #pragma unroll
-  for (int nb = 0; nb < 16; ++nb) sp[(size_t)(q + A * nb) * NP] = x[nb];
+  for (int nb = 0; nb < B; ++nb) sp[(size_t)(q + A * nb) * NP] = x[nb];
 }
 
-template <int METHOD>
-__global__ void __launch_bounds__(CB * 16) agent256_cols(const Recon g, int j0) {
-  agent256_cols_body<METHOD>(g, j0);
+template <int NP, int METHOD>
+__global__ void __launch_bounds__(col_threads<NP>()) agent_cols(const Recon g, int j0) {
+  agent_cols_body<NP, METHOD>(g, j0);
 }
 
-__global__ void __launch_bounds__(CB * 16) agent256_cols_batch(const Recon* __restrict__ rec, int j0) {
+template <int NP>
+__global__ void __launch_bounds__(col_threads<NP>()) agent_cols_batch(const Recon* __restrict__ rec, int j0) {
   if (*rec->done) return;
-  agent256_cols_body<kPMACE>(*rec, j0);
+  agent_cols_body<NP, kPMACE>(*rec, j0);
 }
 
-template <int METHOD>
-__device__ __forceinline__ void agent256_rowsinv_body(const Recon& g, const int j0) {
-  constexpr int NP = NP256, A = 16, S = NP + A;
+template <int NP, int METHOD>
+__device__ __forceinline__ void agent_rowsinv_body(const Recon& g, const int j0) {
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = NP + A;
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.tw256, tid, RB * A);
+  load_twiddles<NP>(tw, g.twn, tid, RB * A);
   const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
   const int j = j0 + jl;
   const int2 pj = g.pos[j];
   const int rl = tid / A, p = tid % A, r = rb * RB + rl;
   float2* io = g.stage + ((size_t)jl * NP + r) * NP;
-  float2 x[16];
+  float2 x[B];
 #pragma unroll
-  for (int ka = 0; ka < 16; ++ka) x[ka] = io[p + 16 * ka];
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) x[m * A + ka] = io[p + A * m + B * ka];
   __syncthreads();
   row_inv<NP>(x, tile + rl * S, p, tw);
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   float2* trow = g.t + (size_t)j * NP * NP + (size_t)r * NP;
 #pragma unroll
-  for (int nb = 0; nb < 16; ++nb) {
+  for (int nb = 0; nb < B; ++nb) {
     const int c = p + A * nb;
     agent_output<METHOD>(x[nb], &trow[c], &xrow[c], r * NP + c, g, &io[c]);
   }
 }
 
-template <int METHOD>
-__global__ void __launch_bounds__(RB * 16) agent256_rowsinv(const Recon g, int j0) {
-  agent256_rowsinv_body<METHOD>(g, j0);
+template <int NP, int METHOD>
+__global__ void __launch_bounds__(row_threads<NP>()) agent_rowsinv(const Recon g, int j0) {
+  agent_rowsinv_body<NP, METHOD>(g, j0);
 }
 
-__global__ void __launch_bounds__(RB * 16) agent256_rowsinv_batch(const Recon* __restrict__ rec, int j0) {
+template <int NP>
+__global__ void __launch_bounds__(row_threads<NP>()) agent_rowsinv_batch(const Recon* __restrict__ rec,
+                                                                         int j0) {
   if (*rec->done) return;
-  agent256_rowsinv_body<kPMACE>(*rec, j0);
+  agent_rowsinv_body<NP, kPMACE>(*rec, j0);
 }
 
 // -------------------------------------------------------------------------
@@ -575,7 +588,7 @@ __device__ __forceinline__ void fit_small_body(const Recon& g, const int j) {
   __shared__ float2 tile[NP * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.tw256, tid, NT);
+  load_twiddles<NP>(tw, g.twn, tid, NT);
   const int2 pj = g.pos[j];
   const int r = tid / A, p = tid % A;
   const float2* xrow = g.xhat + (size_t)(pj.x + r) * g.n2 + pj.y;
@@ -622,23 +635,24 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) fit_small_batch(const Recon* 
   fit_small_body<NP>(g, it.y);
 }
 
-// Np = 256: rows pass of F(D P_j xhat) into the stage, then columns + cost.
-__global__ void __launch_bounds__(RB * 16) fit256_rows(const Recon* __restrict__ rec, int j0,
-                                                        int check_done) {
+// Np > 128: rows pass of F(D P_j xhat) into the stage, then columns + cost.
+template <int NP>
+__global__ void __launch_bounds__(row_threads<NP>()) fit_rows(const Recon* __restrict__ rec, int j0,
+                                                               int check_done) {
   const Recon& g = *rec;
   if (check_done && *g.done) return;
-  constexpr int NP = NP256, A = 16, S = NP + A;
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = NP + A;
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.tw256, tid, RB * A);
+  load_twiddles<NP>(tw, g.twn, tid, RB * A);
   const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
   const int2 pj = g.pos[j0 + jl];
   const int rl = tid / A, p = tid % A, r = rb * RB + rl;
   const float2* xrow = g.xhat + (size_t)(pj.x + r) * g.n2 + pj.y;
-  float2 x[16];
+  float2 x[B];
 #pragma unroll
-  for (int nb = 0; nb < 16; ++nb) {
+  for (int nb = 0; nb < B; ++nb) {
     const int c = p + A * nb;
     x[nb] = cmul(g.d[r * NP + c], xrow[c]);
   }
@@ -646,31 +660,37 @@ __global__ void __launch_bounds__(RB * 16) fit256_rows(const Recon* __restrict__
   row_fwd<NP>(x, tile + rl * S, p, tw);
   float2* out = g.stage + ((size_t)jl * NP + r) * NP;
 #pragma unroll
-  for (int ka = 0; ka < 16; ++ka) out[p + 16 * ka] = x[ka];
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) out[p + A * m + B * ka] = x[m * A + ka];
 }
 
-__global__ void __launch_bounds__(CB * 16) fit256_cols(const Recon* __restrict__ rec, int j0,
-                                                        int check_done) {
+template <int NP>
+__global__ void __launch_bounds__(col_threads<NP>()) fit_cols(const Recon* __restrict__ rec, int j0,
+                                                               int check_done) {
   const Recon& g = *rec;
   if (check_done && *g.done) return;
-  constexpr int NP = NP256, A = 16;
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A;
   __shared__ float2 tile[NP * CB];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.tw256, tid, CB * A);
+  load_twiddles<NP>(tw, g.twn, tid, CB * A);
   const int jl = blockIdx.x / (NP / CB), cb = blockIdx.x % (NP / CB);
   const int j = j0 + jl;
   const int c = tid % CB, q = tid / CB, col = cb * CB + c;
   const float2* sp = g.stage + (size_t)jl * NP * NP + col;
-  float2 x[16];
+  float2 x[B];
 #pragma unroll
-  for (int nb = 0; nb < 16; ++nb) x[nb] = sp[(size_t)(q + A * nb) * NP];
+  for (int nb = 0; nb < B; ++nb) x[nb] = sp[(size_t)(q + A * nb) * NP];
   __syncthreads();
   col_fwd<NP>(x, tile, CB, c, q, tw);
   const float* yc = g.ys + (size_t)j * NP * NP + col;
   float acc = 0.f;
 #pragma unroll
-  for (int ka = 0; ka < 16; ++ka) acc += fit_term(x[ka], g.yfac * yc[(size_t)(q + 16 * ka) * NP]);
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka)
+      acc += fit_term(x[m * A + ka], g.yfac * yc[(size_t)(q + A * m + B * ka) * NP]);
   block_sum_to(acc, &g.fit[(size_t)j * (NP / CB) + cb], 0.5 / ((double)NP * NP));
 }
 
@@ -883,10 +903,10 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) fft2_small(const float2* in, 
   }
 }
 
-// Np = 256 standalone transform: a row pass and a column pass over global memory.
-template <bool INV>
-__global__ void __launch_bounds__(RB * 16) fft256_rows(const float2* in, float2* out, float scale) {
-  constexpr int NP = NP256, A = 16, S = NP + A;
+// Np > 128 standalone transform: a row pass and a column pass over global memory.
+template <int NP, bool INV>
+__global__ void __launch_bounds__(row_threads<NP>()) fft_rows(const float2* in, float2* out, float scale) {
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = NP + A;
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
@@ -894,27 +914,31 @@ __global__ void __launch_bounds__(RB * 16) fft256_rows(const float2* in, float2*
   const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
   const int rl = tid / A, p = tid % A, r = rb * RB + rl;
   const size_t base = ((size_t)jl * NP + r) * NP;
-  float2 x[16];
+  float2 x[B];
   if constexpr (!INV) {
 #pragma unroll
-    for (int nb = 0; nb < 16; ++nb) x[nb] = in[base + p + A * nb];
+    for (int nb = 0; nb < B; ++nb) x[nb] = in[base + p + A * nb];
     __syncthreads();
     row_fwd<NP>(x, tile + rl * S, p, tw);
 #pragma unroll
-    for (int ka = 0; ka < 16; ++ka) out[base + p + 16 * ka] = cscale(x[ka], scale);
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) out[base + p + A * m + B * ka] = cscale(x[m * A + ka], scale);
   } else {
 #pragma unroll
-    for (int ka = 0; ka < 16; ++ka) x[ka] = in[base + p + 16 * ka];
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) x[m * A + ka] = in[base + p + A * m + B * ka];
     __syncthreads();
     row_inv<NP>(x, tile + rl * S, p, tw);
 #pragma unroll
-    for (int nb = 0; nb < 16; ++nb) out[base + p + A * nb] = cscale(x[nb], scale);
+    for (int nb = 0; nb < B; ++nb) out[base + p + A * nb] = cscale(x[nb], scale);
   }
 }
 
-template <bool INV>
-__global__ void __launch_bounds__(CB * 16) fft256_cols(const float2* in, float2* out, float scale) {
-  constexpr int NP = NP256, A = 16;
+template <int NP, bool INV>
+__global__ void __launch_bounds__(col_threads<NP>()) fft_cols(const float2* in, float2* out, float scale) {
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A;
   __shared__ float2 tile[NP * CB];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
@@ -922,21 +946,26 @@ __global__ void __launch_bounds__(CB * 16) fft256_cols(const float2* in, float2*
   const int jl = blockIdx.x / (NP / CB), cb = blockIdx.x % (NP / CB);
   const int c = tid % CB, q = tid / CB, col = cb * CB + c;
   const size_t base = (size_t)jl * NP * NP + col;
-  float2 x[16];
+  float2 x[B];
   if constexpr (!INV) {
 #pragma unroll
-    for (int nb = 0; nb < 16; ++nb) x[nb] = in[base + (size_t)(q + A * nb) * NP];
+    for (int nb = 0; nb < B; ++nb) x[nb] = in[base + (size_t)(q + A * nb) * NP];
     __syncthreads();
     col_fwd<NP>(x, tile, CB, c, q, tw);
 #pragma unroll
-    for (int ka = 0; ka < 16; ++ka) out[base + (size_t)(q + 16 * ka) * NP] = cscale(x[ka], scale);
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka)
+        out[base + (size_t)(q + A * m + B * ka) * NP] = cscale(x[m * A + ka], scale);
   } else {
 #pragma unroll
-    for (int ka = 0; ka < 16; ++ka) x[ka] = in[base + (size_t)(q + 16 * ka) * NP];
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) x[m * A + ka] = in[base + (size_t)(q + A * m + B * ka) * NP];
     __syncthreads();
     col_inv<NP>(x, tile, CB, c, q, tw);
 #pragma unroll
-    for (int nb = 0; nb < 16; ++nb) out[base + (size_t)(q + A * nb) * NP] = cscale(x[nb], scale);
+    for (int nb = 0; nb < B; ++nb) out[base + (size_t)(q + A * nb) * NP] = cscale(x[nb], scale);
   }
 }
 
@@ -962,7 +991,9 @@ hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_
     }                                                                                              \
     break;
     PMACE_SMALL(32)
+    PMACE_SMALL(48)
     PMACE_SMALL(64)
+    PMACE_SMALL(96)
     PMACE_SMALL(128)
 #undef PMACE_SMALL
     default:
@@ -983,7 +1014,9 @@ hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int 
                          st, recs, gitems, 0);                                                      \
     break;
     PMACE_SMALL(32)
+    PMACE_SMALL(48)
     PMACE_SMALL(64)
+    PMACE_SMALL(96)
     PMACE_SMALL(128)
 #undef PMACE_SMALL
     default:
@@ -992,33 +1025,36 @@ hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int 
   return hipGetLastError();
 }
 
-hipError_t launch_256_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
-                                hipStream_t st) {
+template <int NP>
+static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
+                            hipStream_t st) {
+  constexpr int RT = row_threads<NP>(), CT = col_threads<NP>();
   for (int j0 = 0, g = 0; j0 < h.J; j0 += h.chunk, ++g) {
     const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
+    const dim3 rgrid(cnt * (NP / RB)), cgrid(cnt * (NP / CB));
     const int2 ct = chunk_tiles[g];
     if (batch_rec) {
-      hipLaunchKernelGGL(agent256_rows_batch, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, batch_rec, j0);
-      hipLaunchKernelGGL(agent256_cols_batch, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, batch_rec, j0);
-      hipLaunchKernelGGL(agent256_rowsinv_batch, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, batch_rec, j0);
+      hipLaunchKernelGGL(agent_rows_batch<NP>, rgrid, dim3(RT), 0, st, batch_rec, j0);
+      hipLaunchKernelGGL(agent_cols_batch<NP>, cgrid, dim3(CT), 0, st, batch_rec, j0);
+      hipLaunchKernelGGL(agent_rowsinv_batch<NP>, rgrid, dim3(RT), 0, st, batch_rec, j0);
     } else if (h.method == kSharpPlus) {
-      hipLaunchKernelGGL(agent256_rows<kSharpPlus>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
-      hipLaunchKernelGGL(agent256_cols<kSharpPlus>, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
-      hipLaunchKernelGGL(agent256_rowsinv<kSharpPlus>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
+      hipLaunchKernelGGL((agent_rows<NP, kSharpPlus>), rgrid, dim3(RT), 0, st, h, j0);
+      hipLaunchKernelGGL((agent_cols<NP, kSharpPlus>), cgrid, dim3(CT), 0, st, h, j0);
+      hipLaunchKernelGGL((agent_rowsinv<NP, kSharpPlus>), rgrid, dim3(RT), 0, st, h, j0);
     } else {
-      hipLaunchKernelGGL(agent256_rows<kPMACE>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
-      hipLaunchKernelGGL(agent256_cols<kPMACE>, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, h, j0);
-      hipLaunchKernelGGL(agent256_rowsinv<kPMACE>, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, h, j0);
+      hipLaunchKernelGGL((agent_rows<NP, kPMACE>), rgrid, dim3(RT), 0, st, h, j0);
+      hipLaunchKernelGGL((agent_cols<NP, kPMACE>), cgrid, dim3(CT), 0, st, h, j0);
+      hipLaunchKernelGGL((agent_rowsinv<NP, kPMACE>), rgrid, dim3(RT), 0, st, h, j0);
     }
     if (ct.y > 0) {
       if (batch_rec)
-        hipLaunchKernelGGL((consensus_gather_member<256, false>), dim3(ct.y), dim3(GT_THREADS), 0,
+        hipLaunchKernelGGL((consensus_gather_member<NP, false>), dim3(ct.y), dim3(GT_THREADS), 0,
                            st, batch_rec, ct.x, j0);
       else if (h.method == kSharpPlus)
-        hipLaunchKernelGGL((consensus_gather<256, false, kSharpPlus>), dim3(ct.y), dim3(GT_THREADS),
+        hipLaunchKernelGGL((consensus_gather<NP, false, kSharpPlus>), dim3(ct.y), dim3(GT_THREADS),
                            0, st, h, ct.x, j0);
       else
-        hipLaunchKernelGGL((consensus_gather<256, false, kPMACE>), dim3(ct.y), dim3(GT_THREADS), 0,
+        hipLaunchKernelGGL((consensus_gather<NP, false, kPMACE>), dim3(ct.y), dim3(GT_THREADS), 0,
                            st, h, ct.x, j0);
     }
   }
@@ -1027,6 +1063,16 @@ hipError_t launch_256_iteration(const Recon& h, const Recon* batch_rec, const in
     hipLaunchKernelGGL(image_update_batch, dim3(nb), dim3(256), 0, st, batch_rec);
   else
     hipLaunchKernelGGL(image_update, dim3(nb), dim3(256), 0, st, h);
+}
+
+hipError_t launch_large_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
+                                  hipStream_t st) {
+  switch (h.np) {
+    case 160: large_iteration<160>(h, batch_rec, chunk_tiles, st); break;
+    case 192: large_iteration<192>(h, batch_rec, chunk_tiles, st); break;
+    case 256: large_iteration<256>(h, batch_rec, chunk_tiles, st); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1044,8 +1090,12 @@ static hipError_t gather_into_num(const Recon& h, int2 ct, int j0, hipStream_t s
                          st, h, ct.x, j0);                                                        \
     break;
     PMACE_GATHER(32)
+    PMACE_GATHER(48)
     PMACE_GATHER(64)
+    PMACE_GATHER(96)
     PMACE_GATHER(128)
+    PMACE_GATHER(160)
+    PMACE_GATHER(192)
     PMACE_GATHER(256)
 #undef PMACE_GATHER
     default:
@@ -1108,6 +1158,17 @@ hipError_t launch_nrmse(const Recon* recs, const int2* ritems, int nritems, cons
   return hipGetLastError();
 }
 
+template <int NP>
+static void fit_large(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
+  for (int j0 = 0; j0 < h.J; j0 += h.chunk) {
+    const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
+    hipLaunchKernelGGL(fit_rows<NP>, dim3(cnt * (NP / RB)), dim3(row_threads<NP>()), 0, st, rec, j0,
+                       check_done);
+    hipLaunchKernelGGL(fit_cols<NP>, dim3(cnt * (NP / CB)), dim3(col_threads<NP>()), 0, st, rec, j0,
+                       check_done);
+  }
+}
+
 hipError_t launch_fit_member(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
   switch (h.np) {
 #define PMACE_FIT(N)                                                                               \
@@ -1115,18 +1176,14 @@ hipError_t launch_fit_member(const Recon& h, const Recon* rec, int check_done, h
     hipLaunchKernelGGL(fit_small<N>, dim3(h.J), dim3(N * Geo<N>::A), 0, st, rec);                  \
     break;
     PMACE_FIT(32)
+    PMACE_FIT(48)
     PMACE_FIT(64)
+    PMACE_FIT(96)
     PMACE_FIT(128)
 #undef PMACE_FIT
-    case 256:
-      for (int j0 = 0; j0 < h.J; j0 += h.chunk) {
-        const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
-        hipLaunchKernelGGL(fit256_rows, dim3(cnt * (NP256 / RB)), dim3(RB * 16), 0, st, rec, j0,
-                           check_done);
-        hipLaunchKernelGGL(fit256_cols, dim3(cnt * (NP256 / CB)), dim3(CB * 16), 0, st, rec, j0,
-                           check_done);
-      }
-      break;
+    case 160: fit_large<160>(h, rec, check_done, st); break;
+    case 192: fit_large<192>(h, rec, check_done, st); break;
+    case 256: fit_large<256>(h, rec, check_done, st); break;
     default:
       return hipErrorInvalidValue;
   }
@@ -1141,7 +1198,9 @@ hipError_t launch_fit_batch(int np, const Recon* recs, const int2* items, int ni
     hipLaunchKernelGGL(fit_small_batch<N>, dim3(nitems), dim3(N * Geo<N>::A), 0, st, recs, items); \
     break;
     PMACE_FIT(32)
+    PMACE_FIT(48)
     PMACE_FIT(64)
+    PMACE_FIT(96)
     PMACE_FIT(128)
 #undef PMACE_FIT
     default:
@@ -1166,6 +1225,19 @@ hipError_t launch_tick(const Recon* recs, const int* fitems, int nf, int max_ite
   return hipGetLastError();
 }
 
+template <int NP>
+static void fft_large(int count, const float2* in, float2* out, int inverse, hipStream_t st) {
+  const float sc = 1.f / sqrtf((float)NP);  // 1/sqrt(NP) per pass
+  const dim3 rgrid(count * (NP / RB)), cgrid(count * (NP / CB));
+  if (inverse) {
+    hipLaunchKernelGGL((fft_cols<NP, true>), cgrid, dim3(col_threads<NP>()), 0, st, in, out, sc);
+    hipLaunchKernelGGL((fft_rows<NP, true>), rgrid, dim3(row_threads<NP>()), 0, st, out, out, sc);
+  } else {
+    hipLaunchKernelGGL((fft_rows<NP, false>), rgrid, dim3(row_threads<NP>()), 0, st, in, out, sc);
+    hipLaunchKernelGGL((fft_cols<NP, false>), cgrid, dim3(col_threads<NP>()), 0, st, out, out, sc);
+  }
+}
+
 hipError_t launch_fft2(int np, int count, const float2* in, float2* out, int inverse, hipStream_t st) {
   switch (np) {
 #define PMACE_FFT_SMALL(N)                                                                          \
@@ -1176,20 +1248,14 @@ hipError_t launch_fft2(int np, int count, const float2* in, float2* out, int inv
       hipLaunchKernelGGL((fft2_small<N, false>), dim3(count), dim3(N * Geo<N>::A), 0, st, in, out); \
     break;
     PMACE_FFT_SMALL(32)
+    PMACE_FFT_SMALL(48)
     PMACE_FFT_SMALL(64)
+    PMACE_FFT_SMALL(96)
     PMACE_FFT_SMALL(128)
 #undef PMACE_FFT_SMALL
-    case 256: {
-      const float sc = 1.f / 16.f;  // sqrt(1/256) per pass
-      if (inverse) {
-        hipLaunchKernelGGL(fft256_cols<true>, dim3(count * (NP256 / CB)), dim3(CB * 16), 0, st, in, out, sc);
-        hipLaunchKernelGGL(fft256_rows<true>, dim3(count * (NP256 / RB)), dim3(RB * 16), 0, st, out, out, sc);
-      } else {
-        hipLaunchKernelGGL(fft256_rows<false>, dim3(count * (NP256 / RB)), dim3(RB * 16), 0, st, in, out, sc);
-        hipLaunchKernelGGL(fft256_cols<false>, dim3(count * (NP256 / CB)), dim3(CB * 16), 0, st, out, out, sc);
-      }
-      break;
-    }
+    case 160: fft_large<160>(count, in, out, inverse, st); break;
+    case 192: fft_large<192>(count, in, out, inverse, st); break;
+    case 256: fft_large<256>(count, in, out, inverse, st); break;
     default:
       return hipErrorInvalidValue;
   }

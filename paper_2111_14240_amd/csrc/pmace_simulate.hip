@@ -173,7 +173,8 @@ pmace_status pmace_simulate(int32_t n1, int32_t n2, int32_t np, int32_t num_pos,
   if (np < 1 || num_pos < 1 || n1 < np || n2 < np || !probe_d || !pos_d || !x_d || !z_d ||
       !workspace_d || !std::isfinite(peak_photons))
     return PMACE_EINVAL;
-  if (np != 32 && np != 64 && np != 128 && np != 256) return PMACE_EUNSUPPORTED;
+  if (np != 32 && np != 48 && np != 64 && np != 96 && np != 128 && np != 160 && np != 192 && np != 256)
+    return PMACE_EUNSUPPORTED;
   if (ws_bytes < pmace_simulate_footprint(np, num_pos)) return PMACE_ENOMEM;
   hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
   // positions are checked on the host: the frame gather reads the object there

@@ -71,12 +71,12 @@ def test_footprint_formula(lib):
 @pytest.mark.parametrize("kw", [dict(np_=0), dict(num_pos=0), dict(n1=16), dict(alpha=-1.0),
                                 dict(alpha=float("nan")), dict(rho=0.0), dict(rho=1.0),
                                 dict(kappa=-0.5), dict(kappa=float("inf")), dict(flags=8),
-                                dict(chunk=-1), dict(np_=48)])
+                                dict(chunk=-1), dict(np_=40)])
 def test_invalid_params_rejected(lib, kw):
     assert _fp(**kw) == 0
     st, ctx = P.pmace_init(P.make_params(**{**dict(n1=128, n2=128, np_=32, num_pos=36, alpha=0.5), **kw}),
                            1, 1, 1, None, 1, 1 << 30, None)
-    expect = P.PMACE_EUNSUPPORTED if kw == dict(np_=48) else P.PMACE_EINVAL
+    expect = P.PMACE_EUNSUPPORTED if kw == dict(np_=40) else P.PMACE_EINVAL
     assert st == expect and not ctx.value
 
 
@@ -88,7 +88,7 @@ def test_init_argument_checks_before_device(lib):
     assert st == P.PMACE_ENOMEM
     assert P.pmace_iterate(None, 1) == P.PMACE_ESTATE
     assert P.pmace_sync(None) == P.PMACE_ESTATE
-    assert P.pmace_fft2(48, 1, 1, 1, 0, None) == P.PMACE_EUNSUPPORTED
+    assert P.pmace_fft2(40, 1, 1, 1, 0, None) == P.PMACE_EUNSUPPORTED
     assert P.pmace_fft2(32, -1, 1, 1, 0, None) == P.PMACE_EINVAL
     P.pmace_destroy(None)
 

@@ -36,6 +36,8 @@ MIX = [  # (n, np, scan, step, peak, seed, chunk)
     (320, 128, 4, 56, 1e5, 22, 0),
     (400, 256, 3, 60, 1e6, 23, 4),
     (300, 256, 2, 40, 1e5, 24, 0),
+    (288, 96, 4, 50, 1e5, 25, 0),
+    (400, 192, 2, 100, 1e5, 26, 3),
 ]
 
 
@@ -141,6 +143,8 @@ FIT_CASES = [  # (n, np, scan, step, peak, seed, chunk)
     (200, 64, 5, 30, 1e5, 42, 0),
     (320, 128, 4, 56, 1e5, 43, 0),
     (400, 256, 3, 60, 1e6, 44, 4),
+    (288, 96, 5, 40, 1e5, 46, 0),
+    (360, 160, 3, 80, 1e5, 47, 2),
 ]
 
 

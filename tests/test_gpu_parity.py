@@ -96,10 +96,15 @@ SMALL_CASES = {
     "np64": (200, 64, 5, 30, 1e5, 21, 0),
     "np128": (320, 128, 4, 56, 1e5, 22, 0),
     "np256_ragged_chunks": (400, 256, 3, 60, 1e6, 23, 4),
+    # radix-3 and radix-5 patch sides (prime-factor DFTs)
+    "np48": (160, 48, 5, 24, 1e5, 51, 0),
+    "np96": (288, 96, 5, 40, 1e5, 52, 0),
+    "np160_ragged_chunks": (360, 160, 3, 80, 1e6, 53, 4),
+    "np192": (400, 192, 3, 90, 1e5, 54, 0),
 }
 
 
-@pytest.mark.parametrize("np_", [32, 64, 128, 256])
+@pytest.mark.parametrize("np_", [32, 48, 64, 96, 128, 160, 192, 256])
 @pytest.mark.parametrize("inverse", [False, True])
 def test_fft2_matches_oracle_dft(P, np_, inverse):
     _say("fft2", np_, "inverse" if inverse else "forward")

@@ -20,6 +20,8 @@ CASES = {
     "np64": (200, 64, 5, 30, 1e5, 21, 0),
     "np128": (320, 128, 4, 56, 1e5, 22, 0),
     "np256_ragged_chunks": (400, 256, 3, 60, 1e6, 23, 4),
+    "np96": (288, 96, 5, 40, 1e5, 52, 0),
+    "np192_chunks": (400, 192, 3, 90, 1e5, 54, 4),
 }
 
 

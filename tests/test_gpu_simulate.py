@@ -46,7 +46,8 @@ def test_poisson_sampler_matches_reference(P):
     assert np.all(np.abs(got - ref)[got != ref] <= 2)
 
 
-@pytest.mark.parametrize("np_,peak", [(32, None), (64, 1e5), (128, 1e4), (256, 1e6)])
+@pytest.mark.parametrize("np_,peak", [(32, None), (64, 1e5), (96, None), (128, 1e4), (160, 1e5),
+                                      (256, 1e6)])
 def test_simulate_matches_reference(P, np_, peak):
     prob = synth.make_problem(np_ * 2, np_, 3, np_ // 3, None, seed=40 + np_)
     x = prob.x_true.astype(np.complex64).astype(np.complex128)
