@@ -215,28 +215,50 @@ def bench_serve(args):
     arrivals = serve.poisson_arrivals(args.requests, args.rate, seed=5)
     rule = _stop_rule(args)
     results = {}
-    for name in ("served", "plain"):
+    variants = [(int(v), int(a)) for v in str(args.max_large).split(",")
+                for a in str(args.max_active).split(",")]
+    names = [(f"served_max_large{v}" if v > 0 else "served_one_class") + f"_active{a}"
+             for v, a in variants]
+    for name in names + ["plain"]:
         reqs = [serve.Request(i, pool[pick[i]], float(arrivals[i])) for i in range(args.requests)]
         ex = serve.GPUExecutor(alpha=0.5, **rule)
+        retire, done_count = ex.retire, [0]
+
+        def retire_and_report(rid, _retire=retire, _name=name):
+            done_count[0] += 1
+            if done_count[0] % 250 == 0:
+                print(f"[serve] {_name}: {done_count[0]} completed", file=sys.stderr, flush=True)
+            return _retire(rid)
+
+        ex.retire = retire_and_report
         clock = serve.WallClock()
-        if name == "served":
+        if name != "plain":
+            v, a = variants[names.index(name)]
             st = serve.Server(ex, capacity_bytes=int(args.capacity_gb * 2**30),
-                              max_active=args.max_active, iters_per_step=10).run(reqs, clock)
+                              max_active=a, iters_per_step=10,
+                              large_work=args.large_work if v > 0 else None,
+                              max_large=max(v, 1)).run(reqs, clock)
         else:
             st = serve.run_plain(ex, reqs, clock, iters_per_step=10)
         torch.cuda.synchronize()
         results[name] = st.as_dict()
         results[name]["median_iterations"] = float(np.median([r.iters for r in reqs]))
+        tail = sorted(reqs, key=lambda r: -r.latency)[:max(1, len(reqs) // 100)]
+        results[name]["slowest"] = [
+            {"latency": round(r.latency, 4), "wait": round(r.admitted - r.arrival, 4),
+             "iters": r.iters, "shape": [r.problem.n1, r.problem.np_, r.problem.num_pos]} for r in tail]
         print(f"[serve] {name}: {results[name]}", file=sys.stderr, flush=True)
     out = {
         "metric": "served p50/p99 latency and solves/s vs plain",
-        "value": results["served"]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "value": results[names[0]]["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
         "higher_is_better": True, "vs_baseline": None, "dtype": "c64",
         "data": "synthetic (simulated on device)",
         "config": {"workload": f"{args.requests} requests, Poisson arrivals at {args.rate}/s, drawn from "
                                f"{len(pool)} mixed-size problems", "stop_rule": rule,
-                   "capacity_GiB": args.capacity_gb, "max_active": args.max_active},
-        "served": results["served"], "plain": results["plain"],
+                   "capacity_GiB": args.capacity_gb, "max_active": args.max_active,
+                   "large_work": args.large_work, "policy": names[0]},
+        "served": results[names[0]], "plain": results["plain"],
+        "served_variants": {n: results[n] for n in names},
     }
     print(json.dumps(out), flush=True)
 
@@ -257,7 +279,12 @@ def main():
     ap.add_argument("--rate", type=float, default=20.0, help="serve mode: arrivals per second")
     ap.add_argument("--pool", type=int, default=64, help="serve mode: distinct problems")
     ap.add_argument("--capacity-gb", type=float, default=200.0, help="serve mode: workspace budget")
-    ap.add_argument("--max-active", type=int, default=64, help="serve mode: concurrent requests")
+    ap.add_argument("--max-active", default="64",
+                    help="serve mode: concurrent requests (comma list of variants)")
+    ap.add_argument("--large-work", type=float, default=float(1 << 22),
+                    help="serve mode: patch pixels per iteration from which a request is large")
+    ap.add_argument("--max-large", default="1",
+                    help="serve mode: large requests active at once (comma list of variants; 0 = one class)")
     ap.add_argument("--stop", default="nrmse", choices=["nrmse", "data_fit"],
                     help="batch/serve stop rule: NRMSE change (eq. 17) or data-fit cost change (eq. 4)")
     ap.add_argument("--fit-tol", type=float, default=1e-3, help="relative data-fit change for --stop data_fit")

@@ -70,7 +70,7 @@ typedef struct pmace_batch pmace_batch;  /* several reconstructions stepped toge
 
 /* Bytes of device workspace one reconstruction needs (0 if params are invalid).
  * Layout: agent states J*Np^2*8, amplitudes J*Np^2*4, object images N1*N2*36,
- * probe tables Np^2*36, positions J*8, a staging buffer of chunk*Np^2*8
+ * probe tables Np^2*44, positions J*8, a staging buffer of chunk*Np^2*8
  * bytes (Np = 256: the chunk's spectra; SHARP+ with Np <= 128: all J frames;
  * PMACE with Np <= 128: none), data-fit partials and the consensus tile
  * tables; each section 256-byte aligned. */
@@ -118,6 +118,12 @@ pmace_status pmace_set_state(pmace_ctx* ctx, const void* v_d);
 /* Wait for the context's queued work; reports EDEVICE for a failed HIP call
  * and EDIVERGED if the consensus image became NaN/Inf. */
 pmace_status pmace_sync(pmace_ctx* ctx);
+
+/* Queue the context's later work on hip_stream instead (synchronises the old
+ * stream first).  A serving loop initialises a new reconstruction on a side
+ * stream, so its host-side set-up overlaps the running batch, then moves it
+ * to the batch's stream. */
+pmace_status pmace_set_stream(pmace_ctx* ctx, void* hip_stream);
 
 /* Release the host context (not the caller's workspace).  NULL is a no-op. */
 void pmace_destroy(pmace_ctx* ctx);

@@ -83,6 +83,7 @@ struct pmace_batch {
   Graph graph_check;           // one iteration + stop-rule evaluation
   bool graph_tried;
   long long iters;             // iterations launched by this batch
+  int step_calls;              // pmace_batch_step calls so far
 };
 
 namespace {
@@ -136,7 +137,7 @@ pmace_status check_params(const pmace_params* p) {
 
 // Section offsets inside the workspace (relative to the aligned base).
 struct Layout {
-  size_t t, ys, pos, d, pc, dinv, omega, laminv, num, sold, xbar, xhat, stage, tiles, list, status, desc,
+  size_t t, ys, pos, d, pc, dinv, omega, omega64, laminv, num, sold, xbar, xhat, stage, tiles, list, status, desc,
       items, gitems, ritems, red, tw, fit, total;
 };
 
@@ -163,6 +164,7 @@ Layout layout_of(const pmace_params& p) {
   L.pc = o;      o = align_up(o + np2 * 16);
   L.dinv = o;    o = align_up(o + np2 * 8);
   L.omega = o;   o = align_up(o + np2 * 4);
+  L.omega64 = o; o = align_up(o + np2 * 8);
   L.laminv = o;  o = align_up(o + npx * 4);
   L.num = o;     o = align_up(o + npx * 8);
   L.sold = o;    o = align_up(o + npx * 8);
@@ -317,17 +319,8 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
     pc[4 * i + 2] = (float)omega[i];
     pc[4 * i + 3] = mag == 0.0 ? 1.f : 0.f;
   }
-  std::vector<double> lam(npx, 0.0);
-  for (int j = 0; j < J; ++j) {
-    const int r0 = pos[2 * j], c0 = pos[2 * j + 1];
-    for (int r = 0; r < np; ++r) {
-      double* lr = &lam[(size_t)(r0 + r) * n2 + c0];
-      const double* orow = &omega[(size_t)r * np];
-      for (int c = 0; c < np; ++c) lr[c] += orow[c];
-    }
-  }
-  std::vector<float> laminv(npx);
-  for (size_t i = 0; i < npx; ++i) laminv[i] = lam[i] != 0.0 ? (float)(1.0 / lam[i]) : 0.f;
+  // Lambda = sum_j P_j^t omega and its inverse are formed on the device from
+  // the FP64 weights and the consensus tile lists (see launch_init).
   for (size_t i = 0; i < np2; ++i) omega_f[i] = (float)omega[i];
 
   // Gather tables: per chunk, GT_R x GT_C tiles over the rows its patches
@@ -392,6 +385,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   h.d = reinterpret_cast<float2*>(base + L.d);
   h.pc = reinterpret_cast<float4*>(base + L.pc);
   h.omega = reinterpret_cast<float*>(base + L.omega);
+  h.omega64 = reinterpret_cast<double*>(base + L.omega64);
   h.dinv = reinterpret_cast<float2*>(base + L.dinv);
   h.laminv = reinterpret_cast<float*>(base + L.laminv);
   h.num = reinterpret_cast<float2*>(base + L.num);
@@ -461,7 +455,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
       hipMemcpyAsync(h.pc, pc.data(), np2 * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.omega, omega_f.data(), np2 * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.dinv, dinv.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(h.laminv, laminv.data(), npx * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h.omega64, omega.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.tiles, tiles.data(), tiles.size() * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
       (!list.empty() &&
        hipMemcpyAsync(h.tile_list, list.data(), list.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess) ||
@@ -560,6 +554,16 @@ pmace_status pmace_nrmse(pmace_ctx* c, double* out) {
   return PMACE_OK;
 }
 
+pmace_status pmace_set_stream(pmace_ctx* c, void* hip_stream) {
+  if (!c) return PMACE_ESTATE;
+  hipStream_t ns = reinterpret_cast<hipStream_t>(hip_stream);
+  if (ns == c->stream) return PMACE_OK;
+  // everything queued so far completes before the context's next work
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return record(c, PMACE_EDEVICE);
+  c->stream = ns;
+  return PMACE_OK;
+}
+
 pmace_status pmace_data_fit(pmace_ctx* c, double* out) {
   if (!c) return PMACE_ESTATE;
   if (!out) return PMACE_EINVAL;
@@ -653,23 +657,26 @@ pmace_status check_members(pmace_ctx* const* ctxs, int32_t n) {
 }
 
 pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes, bool check) {
+  // Np > 128 members are independent chains of kernels spread over the lanes;
+  // they fork before the merged launches of the smaller members, so both run
+  // at once (the small ones are latency-bound and leave most CUs free)
+  bool any_large = false;
+  for (int i = 0; i < b->n; ++i) any_large = any_large || np_large(b->ctxs[i]->prm.np);
+  const bool forked = lanes && any_large;
+  if (forked) {
+    PM_HIP(hipEventRecord(b->fork, st));
+    for (int l = 0; l < 4; ++l) PM_HIP(hipStreamWaitEvent(b->lanes[l], b->fork, 0));
+  }
   for (int k = 0; k < kClasses; ++k)
     if (b->nitems[k] > 0)
       PM_HIP(pmace::launch_small_batch(kSmallNp[k], b->recs, b->items[k], b->nitems[k], b->gitems[k],
                                        b->ngitems[k], st));
-  // Np > 128 members: independent chains of kernels, spread over lanes
   int lane = 0;
-  bool forked = false;
   for (int i = 0; i < b->n; ++i) {
     pmace_ctx* c = b->ctxs[i];
     if (!np_large(c->prm.np)) continue;
     hipStream_t ls = st;
-    if (lanes) {
-      if (!forked) {
-        PM_HIP(hipEventRecord(b->fork, st));
-        for (int l = 0; l < 4; ++l) PM_HIP(hipStreamWaitEvent(b->lanes[l], b->fork, 0));
-        forked = true;
-      }
+    if (forked) {
       ls = b->lanes[lane];
       lane = (lane + 1) % 4;
     }
@@ -737,6 +744,7 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
   if (b->rule.check_every == 0) b->rule.check_every = 1;
   b->graph_tried = false;
   b->iters = 0;
+  b->step_calls = 0;
   char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(workspace_d)));
   b->recs = reinterpret_cast<Recon*>(base + L.recs);
   std::vector<Recon> recs(n);
@@ -798,7 +806,12 @@ pmace_status pmace_batch_step(pmace_batch* b, int32_t n_iter) {
   if (!b) return PMACE_ESTATE;
   if (n_iter < 0) return PMACE_EINVAL;
   const int every = b->rule.check_every;
-  if (!b->graph_tried && graphs_enabled()) {
+  // A batch whose membership changes often (a serving loop rebuilds it on
+  // every admission and retirement) would spend more host time capturing and
+  // instantiating graphs than it saves, so the first kCaptureAfter calls
+  // launch eagerly and only a batch that lives longer is captured.
+  constexpr int kCaptureAfter = 2;
+  if (!b->graph_tried && graphs_enabled() && b->step_calls >= kCaptureAfter) {
     b->graph_tried = true;
     (void)capture(b->graph_check,
                   [&](hipStream_t cs) { return enqueue_batch_iteration(b, cs, true, true); });
@@ -813,10 +826,11 @@ pmace_status pmace_batch_step(pmace_batch* b, int32_t n_iter) {
     if (g.x) {
       if (hipGraphLaunch(g.x, b->stream) != hipSuccess) return PMACE_EDEVICE;
     } else {
-      pmace_status s = enqueue_batch_iteration(b, b->stream, false, check);
+      pmace_status s = enqueue_batch_iteration(b, b->stream, true, check);
       if (s != PMACE_OK) return s;
     }
   }
+  ++b->step_calls;
   return PMACE_OK;
 }
 

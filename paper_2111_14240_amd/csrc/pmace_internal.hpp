@@ -43,6 +43,7 @@ struct Recon {
   float4* pc;           // Np*Np     {Re, Im of d^{-1}/Np^2, |d|^kappa, [d == 0]}
   float2* dinv;         // Np*Np     d^{-1}/Np^2, 0 exactly where d == 0 (PMACE epilogue)
   float* omega;         // Np*Np     |d|^kappa (PMACE consensus weights)
+  double* omega64;      // Np*Np     the weights in FP64 (SHARP+: |d|^2), for Lambda at init
   float* laminv;        // N1*N2     Lambda^{-1} (0 where Lambda = 0)
   float2* num;          // N1*N2     consensus sum accumulator (Np > 128, set_state)
   float2* sold;         // N1*N2     PMACE: S = sum_j P_j^t |d|^kappa t_j of the current states

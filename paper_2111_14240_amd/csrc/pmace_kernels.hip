@@ -777,6 +777,40 @@ __global__ void init_patches_k(const Recon* __restrict__ rec, const float2* x0) 
   g.t[i] = g.method == kSharpPlus ? cscale(cmul(g.d[rem], x), 1.f - g.two_rho) : x;
 }
 
+// Lambda = sum_j P_j^t omega (eq. (11)) in FP64 over one chunk's tiles, each
+// pixel adding its covering positions in ascending j (chunks run in order),
+// into `lam` (the accumulator image viewed as FP64, zeroed first).
+__global__ void __launch_bounds__(GT_THREADS) lambda_gather_k(const Recon* __restrict__ rec,
+                                                             int first_tile, double* __restrict__ lam) {
+  const Recon& g = *rec;
+  const int4 ti = g.tiles[first_tile + blockIdx.x];
+  const int np = g.np;
+  for (int px = threadIdx.x; px < GT_R * GT_C; px += blockDim.x) {
+    const int R = ti.z + px / GT_C, C = ti.w + px % GT_C;
+    if (R >= g.n1 || C >= g.n2) continue;
+    double acc = 0.0;
+    for (int i = 0; i < ti.y; ++i) {
+      const int2 pj = g.pos[g.tile_list[ti.x + i]];
+      const unsigned rr = (unsigned)(R - pj.x), cc = (unsigned)(C - pj.y);
+      if (rr < (unsigned)np && cc < (unsigned)np) acc += g.omega64[rr * np + cc];
+    }
+    lam[(size_t)R * g.n2 + C] += acc;
+  }
+}
+
+// Lambda^{-1}, 0 where Lambda = 0 (no patch, or only zero weights, covers the pixel).
+__global__ void laminv_k(const Recon* __restrict__ rec, const double* __restrict__ lam) {
+  const Recon& g = *rec;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n1 * g.n2) return;
+  g.laminv[i] = lam[i] != 0.0 ? (float)(1.0 / lam[i]) : 0.f;
+}
+
+__global__ void zero_f64_k(double* __restrict__ a, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0.0;
+}
+
 __global__ void init_images_k(const Recon* __restrict__ rec, const float2* x0) {
   const Recon& g = *rec;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1111,6 +1145,14 @@ hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float s
   hipLaunchKernelGGL(init_amplitudes_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, z, scale,
                      centered);
   hipLaunchKernelGGL(init_patches_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, x0);
+  // Lambda in FP64, accumulated in the (still unused) accumulator image
+  double* lam = reinterpret_cast<double*>(h.num);
+  hipLaunchKernelGGL(zero_f64_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, lam, npx);
+  for (int j0 = 0, g = 0; j0 < h.J; j0 += h.chunk, ++g)
+    if (chunk_tiles[g].y > 0)
+      hipLaunchKernelGGL(lambda_gather_k, dim3(chunk_tiles[g].y), dim3(GT_THREADS), 0, st, rec,
+                         chunk_tiles[g].x, lam);
+  hipLaunchKernelGGL(laminv_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec, lam);
   hipLaunchKernelGGL(init_images_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec, x0);
   if (h.method == kPMACE) {
     for (int j0 = 0, g = 0; j0 < h.J; j0 += h.chunk, ++g) {

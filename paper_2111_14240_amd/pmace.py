@@ -90,6 +90,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pmace_set_reference.restype = ctypes.c_int
     L.pmace_nrmse.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.pmace_nrmse.restype = ctypes.c_int
+    L.pmace_set_stream.argtypes = [vp, vp]
+    L.pmace_set_stream.restype = ctypes.c_int
     L.pmace_data_fit.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
     L.pmace_data_fit.restype = ctypes.c_int
     L.pmace_batch_poll_fit.argtypes = [vp, vp, vp, vp, vp]
@@ -189,6 +191,10 @@ def pmace_nrmse(ctx):
     out = ctypes.c_double()
     st = load_library().pmace_nrmse(ctx, ctypes.byref(out))
     return st, out.value
+
+
+def pmace_set_stream(ctx, stream_ptr):
+    return load_library().pmace_set_stream(ctx, stream_ptr)
 
 
 def pmace_data_fit(ctx):
@@ -399,6 +405,11 @@ class Reconstruction:
 
     def sync(self):
         _check(pmace_sync(self.ctx), "pmace_sync")
+
+    def set_stream(self, stream):
+        """Queue later work on `stream` (a torch stream or None for the null stream)."""
+        _check(pmace_set_stream(self.ctx, _stream_ptr(stream)), "pmace_set_stream")
+        self.stream = stream
 
     def set_reference(self, xref, mask=None):
         """NRMSE reference object (and optional boolean region); kept alive here."""

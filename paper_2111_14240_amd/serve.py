@@ -12,6 +12,8 @@ with.
 The executor interface keeps the scheduling logic testable without a GPU:
 
     footprint(problem) -> bytes      workspace a request will hold while active
+    work(problem) -> float           work per iteration (patch pixels), for the
+                                     size-class policy (optional)
     admit(req)                       start a reconstruction (device state resident)
     step(n)                          n iterations of every active reconstruction
     poll() -> {req_id: (done, nrmse, iters)}
@@ -90,19 +92,21 @@ class ServeStats:
     mean_latency: float
     max_active: int
     steps: int
+    host_s: Optional[Dict[str, float]] = None   # wall time inside admit / step / poll / retire
 
     def as_dict(self):
         return dataclasses.asdict(self)
 
 
-def _stats(reqs: Sequence[Request], makespan: float, max_active: int, steps: int) -> ServeStats:
+def _stats(reqs: Sequence[Request], makespan: float, max_active: int, steps: int,
+           host_s: Optional[Dict[str, float]] = None) -> ServeStats:
     lat = np.array([r.latency for r in reqs if r.finished is not None])
     return ServeStats(completed=len(lat), makespan=makespan,
                       solves_per_s=len(lat) / makespan if makespan > 0 else float("nan"),
                       p50=float(np.percentile(lat, 50)) if len(lat) else float("nan"),
                       p99=float(np.percentile(lat, 99)) if len(lat) else float("nan"),
                       mean_latency=float(lat.mean()) if len(lat) else float("nan"),
-                      max_active=max_active, steps=steps)
+                      max_active=max_active, steps=steps, host_s=host_s)
 
 
 class Server:
@@ -114,15 +118,29 @@ class Server:
     iters_per_step  iterations launched between polls of the stop flags
     on_step         optional hook(clock, n_active, iters) after each step (a
                     fake clock advances there in tests)
+    large_work      size-class policy: a request whose work per iteration is
+                    at least this is "large"; at most max_large large requests
+                    are active at once (FIFO among them), while smaller
+                    requests are admitted past a waiting large one.  Sharing
+                    the device equally would stretch a large request by the
+                    work of everything admitted during its lifetime; this
+                    keeps large requests close to their solo time and small
+                    ones from queueing behind them.  None: one class.
     """
 
     def __init__(self, executor, capacity_bytes: int, max_active: int = 64,
-                 iters_per_step: int = 4, on_step: Optional[Callable] = None):
+                 iters_per_step: int = 4, on_step: Optional[Callable] = None,
+                 large_work: Optional[float] = None, max_large: int = 1):
         self.ex = executor
         self.capacity = int(capacity_bytes)
         self.max_active = int(max_active)
         self.iters_per_step = int(iters_per_step)
         self.on_step = on_step
+        self.large_work = large_work
+        self.max_large = int(max_large)
+
+    def _large(self, req) -> bool:
+        return self.large_work is not None and self.ex.work(req.problem) >= self.large_work
 
     def run(self, requests: List[Request], clock) -> ServeStats:
         pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
@@ -132,43 +150,68 @@ class Server:
         queue: List[Request] = []          # arrived, not admitted (FIFO)
         active: Dict[int, Request] = {}
         used = 0
+        n_large = 0
         nxt = 0
         max_active = 0
         steps = 0
+        host = {"admit": 0.0, "step": 0.0, "poll": 0.0, "retire": 0.0}
+        tick = time.perf_counter
         while nxt < len(pending) or queue or active:
             now = clock.now()
             while nxt < len(pending) and pending[nxt].arrival <= now:
                 queue.append(pending[nxt])
                 nxt += 1
-            # admission: FIFO, as long as the head fits
-            while queue and len(active) < self.max_active:
-                fp = self.ex.footprint(queue[0].problem)
+            # launch the next iterations of the active requests first, so the
+            # host-side set-up of new admissions overlaps them on the device
+            stepped = bool(active)
+            if stepped:
+                t0 = tick()
+                self.ex.step(self.iters_per_step)
+                host["step"] += tick() - t0
+                steps += 1
+                if self.on_step:
+                    self.on_step(clock, len(active), self.iters_per_step)
+            # admission in arrival order while memory and slots allow; a large
+            # request waiting for the large slot does not block smaller ones
+            i = 0
+            while i < len(queue) and len(active) < self.max_active:
+                r = queue[i]
+                fp = self.ex.footprint(r.problem)
                 if used + fp > self.capacity:
                     break
-                r = queue.pop(0)
+                large = self._large(r)
+                if large and n_large >= self.max_large:
+                    i += 1
+                    continue
+                queue.pop(i)
+                t0 = tick()
                 self.ex.admit(r)
+                host["admit"] += tick() - t0
                 r.admitted = clock.now()
                 active[r.rid] = r
                 used += fp
+                n_large += int(large)
             max_active = max(max_active, len(active))
-            if not active:
-                if nxt < len(pending):
+            if not stepped:
+                if not active and nxt < len(pending):
                     clock.sleep_until(pending[nxt].arrival)
                 continue
-            self.ex.step(self.iters_per_step)
-            steps += 1
-            if self.on_step:
-                self.on_step(clock, len(active), self.iters_per_step)
-            for rid, (done, nr, it) in self.ex.poll().items():
+            t1 = tick()
+            polled = self.ex.poll()
+            host["poll"] += tick() - t1
+            for rid, (done, nr, it) in polled.items():
                 if not done:
                     continue
                 r = active.pop(rid)
+                t0 = tick()
                 r.result = self.ex.retire(rid)
+                host["retire"] += tick() - t0
                 r.finished = clock.now()
                 r.iters, r.nrmse = int(it), float(nr)
                 used -= self.ex.footprint(r.problem)
+                n_large -= int(self._large(r))
         makespan = clock.now() - (pending[0].arrival if pending else 0.0)
-        return _stats(requests, makespan, max_active, steps)
+        return _stats(requests, makespan, max_active, steps, host)
 
 
 def run_plain(executor, requests: List[Request], clock, iters_per_step: int = 4,
@@ -197,7 +240,13 @@ class GPUExecutor:
         self.active: Dict[int, object] = {}
         self.order: List[int] = []
         self.batch = None
+        self.dirty = False
         self._fp_cache: Dict[tuple, int] = {}
+        import torch
+        self._torch = torch
+        # new reconstructions are set up on a side stream, so their host work
+        # and synchronisations overlap the running batch
+        self.init_stream = torch.cuda.Stream(device=device)
 
     def footprint(self, prob) -> int:
         key = (prob.n1, prob.n2, prob.np_, prob.num_pos)
@@ -207,14 +256,19 @@ class GPUExecutor:
             self._fp_cache[key] = self._pmace.pmace_footprint(prm)
         return self._fp_cache[key]
 
+    def work(self, prob) -> float:
+        return float(prob.num_pos) * prob.np_ * prob.np_
+
     def admit(self, req):
         p = req.problem
-        R = self._pmace.Reconstruction(p.n1, p.n2, p.probe, p.pos, p.z, self.alpha, self.kappa,
-                                       self.rho, device=self.device, stream=self.stream)
-        R.set_reference(p.x_true, self._synth.roi_mask(p.probe, p.pos, p.n1, p.n2))
+        with self._torch.cuda.stream(self.init_stream):
+            R = self._pmace.Reconstruction(p.n1, p.n2, p.probe, p.pos, p.z, self.alpha, self.kappa,
+                                           self.rho, device=self.device, stream=self.init_stream)
+            R.set_reference(p.x_true, self._synth.roi_mask(p.probe, p.pos, p.n1, p.n2))
+        R.set_stream(self.stream)
         self.active[req.rid] = R
         self.order.append(req.rid)
-        self._drop_batch()
+        self.dirty = True            # joins the batch at the next step
 
     def _drop_batch(self):
         if self.batch is not None:
@@ -222,7 +276,11 @@ class GPUExecutor:
             self.batch = None
 
     def step(self, n: int):
+        if self.dirty:
+            self._drop_batch()
+            self.dirty = False
         if self.batch is None:      # membership changed since the last step
+            self.batch_order = list(self.order)
             self.batch = self._pmace.Batch([self.active[r] for r in self.order], tol=self.tol,
                                            min_iter=self.min_iter, max_iter=self.max_iter,
                                            criterion=self.criterion, check_every=self.check_every)
@@ -232,7 +290,9 @@ class GPUExecutor:
         if self.batch is None:
             return {}
         done, nr, it = self.batch.poll()
-        return {rid: (bool(done[i]), float(nr[i]), int(it[i])) for i, rid in enumerate(self.order)}
+        # members admitted since the last step are not in the batch yet
+        return {rid: (bool(done[i]), float(nr[i]), int(it[i]))
+                for i, rid in enumerate(self.batch_order)}
 
     def retire(self, rid):
         R = self.active.pop(rid)

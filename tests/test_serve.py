@@ -13,6 +13,7 @@ from paper_2111_14240_amd import serve
 class MockProblem:
     bytes: int
     conv_iters: int
+    work: float = 1.0
 
 
 class MockExecutor:
@@ -25,9 +26,14 @@ class MockExecutor:
     def footprint(self, prob):
         return prob.bytes
 
+    def work(self, prob):
+        return prob.work
+
     def admit(self, req):
         self.active[req.rid] = [0, req.problem]
         self.admit_log.append(req.rid)
+        self.max_large_seen = max(getattr(self, "max_large_seen", 0),
+                                  sum(p.work >= 100 for _, p in self.active.values()))
         self.max_active_seen = max(self.max_active_seen, len(self.active))
         self.max_bytes_seen = max(self.max_bytes_seen, sum(p.bytes for _, p in self.active.values()))
 
@@ -113,3 +119,33 @@ def test_idle_gaps_wait_for_arrivals():
     st = serve.Server(MockExecutor(), 10, iters_per_step=4, on_step=step_cost).run(reqs, clk)
     assert st.completed == 2
     assert reqs[1].admitted >= 100.0
+
+
+def test_size_classes_cap_large_requests_and_let_small_ones_pass():
+    """At most max_large large requests are active; a small request that
+    arrives while a large one waits for the large slot is admitted first."""
+    reqs = [serve.Request(0, MockProblem(1, 40, work=500), 0.0),
+            serve.Request(1, MockProblem(1, 40, work=500), 0.001),
+            serve.Request(2, MockProblem(1, 8, work=1), 0.002),
+            serve.Request(3, MockProblem(1, 8, work=1), 0.003)]
+    ex = MockExecutor()
+    srv = serve.Server(ex, capacity_bytes=100, max_active=8, iters_per_step=4, on_step=step_cost,
+                       large_work=100, max_large=1)
+    st = srv.run(reqs, serve.FakeClock())
+    assert st.completed == 4 and ex.max_large_seen == 1
+    assert ex.admit_log.index(2) < ex.admit_log.index(1)    # small passed the waiting large one
+    assert reqs[1].admitted >= reqs[0].finished             # large ones run one after the other
+    assert all(r.iters >= r.problem.conv_iters for r in reqs)
+
+
+def test_size_classes_complete_a_random_mix():
+    rng = np.random.default_rng(9)
+    arr = serve.poisson_arrivals(120, 30.0, 9)
+    reqs = [serve.Request(i, MockProblem(int(rng.integers(1, 5)) * 10**9, int(rng.integers(8, 80)),
+                                         work=float(rng.choice([1, 10, 1000]))), float(arr[i]))
+            for i in range(120)]
+    ex = MockExecutor()
+    st = serve.Server(ex, 20 * 10**9, max_active=12, on_step=step_cost, large_work=100,
+                      max_large=2).run(reqs, serve.FakeClock())
+    assert st.completed == 120 and ex.max_large_seen <= 2 and ex.max_active_seen <= 12
+    assert ex.max_bytes_seen <= 20 * 10**9
