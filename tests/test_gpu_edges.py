@@ -1,0 +1,159 @@
+"""Degenerate inputs and the largest workload, through the C ABI against the
+FP64 oracle.
+
+* a zero start: every spectrum is exactly zero, the zero rule of eq. (9)
+  applies everywhere and the state must stay exactly zero;
+* one patch covering the whole object (no overlap: G is the identity on it),
+  one position on the three-pass path, and every position at the same place;
+* a 2048 x 2048 object with 6400 positions of 256 x 256 (a 5.3 GB
+  workspace): one iteration on the device, checked on sampled patches whose
+  new states and reconstruction the oracle computes from the patches that
+  overlap them (the consensus at a pixel only involves the patches covering
+  it)."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pmace_oracle as O
+from paper_2111_14240_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def _say(*a):
+    print("[gpu-edges]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2111_14240_amd import pmace
+    pmace.load_library()
+    return pmace
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _f32(prob):
+    return prob.probe.astype(np.complex64).astype(np.complex128), prob.z.astype(np.float32)
+
+
+@pytest.mark.parametrize("np_,chunk", [(64, 0), (256, 2)])
+def test_zero_start_stays_zero(P, np_, chunk):
+    prob = synth.make_problem(2 * np_, np_, 3, np_ // 3, 1e5, 60 + np_)
+    zero = np.zeros((prob.n1, prob.n2), np.complex64)
+    d, z = _f32(prob)
+    st = O.pmace_iterate(O.pmace_init(zero.astype(complex), prob.pos, np_), d, O.amplitudes(z),
+                         prob.pos, (prob.n1, prob.n2), 0.5, 1.25, 0.5, 2)
+    assert not np.any(st.v)                                   # the oracle's fixed point
+    R = P.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, 0.5, x0=zero, chunk=chunk)
+    R.iterate(2)
+    R.sync()
+    _say("zero start", np_)
+    assert not torch.any(R.get_state() != 0) and not torch.any(R.reconstruct() != 0)
+    R.close()
+
+
+def _teacher_forced(P, prob, chunk=0, kappa=1.25, rho=0.5, alpha=0.5, K=2):
+    d, z = _f32(prob)
+    y = O.amplitudes(z)
+    shape = (prob.n1, prob.n2)
+    x0 = synth.make_object(prob.n1, prob.n2, np.random.default_rng(3))
+    st = O.pmace_init(x0, prob.pos, prob.np_)
+    vs = [st.v]
+    for _ in range(K):
+        st = O.pmace_iterate(st, d, y, prob.pos, shape, alpha, kappa, rho, 1)
+        vs.append(st.v)
+    R = P.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, alpha, kappa, rho, chunk=chunk)
+    worst = 0.0
+    for k in range(K):
+        R.set_state(vs[k])
+        R.iterate(1)
+        R.sync()
+        st_k = O.PMACEState(v=vs[k + 1], w=vs[k + 1], z=None, k=k + 1)
+        ev = rel(R.get_state().cpu().numpy(), vs[k + 1])
+        ex = rel(R.reconstruct().cpu().numpy(), O.reconstruct(st_k, d, prob.pos, shape, kappa))
+        worst = max(worst, ev, ex)
+    R.close()
+    return worst
+
+
+def test_single_patch_covering_the_object(P):
+    prob = synth.make_problem(64, 64, 1, 1, 1e5, 61)
+    assert prob.num_pos == 1 and tuple(prob.pos[0]) == (0, 0)
+    e = _teacher_forced(P, prob)
+    _say("single patch", e)
+    assert e < TOL
+
+
+def test_single_position_three_pass(P):
+    prob = synth.make_problem(300, 192, 1, 1, 1e5, 62)
+    e = _teacher_forced(P, prob, chunk=1)
+    _say("single position, Np 192", e)
+    assert e < TOL
+
+
+def test_all_positions_identical(P):
+    prob = synth.make_problem(128, 64, 1, 1, 1e5, 63)
+    pos = np.repeat(np.array([[20, 30]], np.int32), 5, axis=0)
+    d = prob.probe
+    frames = d[None] * O.extract(prob.x_true, pos, 64)
+    z = (np.abs(O.dft2(frames)) ** 2).astype(np.float32)
+    prob = synth.Problem(x_true=prob.x_true, probe=d, pos=pos, z=z, peak_photons=None)
+    e = _teacher_forced(P, prob)
+    _say("identical positions", e)
+    assert e < TOL
+
+
+@pytest.mark.slow
+def test_largest_workload_sampled(P):
+    """2048^2 object, 80 x 80 positions at step 22 (6400 patches of 256^2),
+    Poisson peak 1e6, intensities simulated on the device.  One iteration from
+    a smooth start; for sampled patches the oracle forms the agents of every
+    overlapping patch, the weighted average over their window, and the new
+    state and reconstruction of the sampled patch."""
+    n, np_, scan, step = 2048, 256, 80, 22
+    alpha, kappa, rho = 0.5, 1.25, 0.5
+    _say("largest: simulating", n, np_, scan * scan)
+    prob = P.simulated_problem(n, np_, scan, step, 1e6, seed=64)
+    x0 = synth.make_object(n, n, np.random.default_rng(4)).astype(np.complex64)
+    R = P.Reconstruction(n, n, prob.probe, prob.pos, prob.z, alpha, kappa, rho, x0=x0)
+    _say("largest: workspace GB", R.footprint / 1e9)
+    R.iterate(1)
+    R.sync()
+    v_dev = R.get_state()
+    xh_dev = R.reconstruct().cpu().numpy()
+    d = prob.probe.astype(np.complex64).astype(np.complex128)
+    pos = prob.pos.astype(np.int64)
+    x0d = x0.astype(np.complex128)
+    for j0 in (0, len(pos) // 2 + scan // 2, len(pos) - 1):
+        p0 = pos[j0]
+        near = np.nonzero((np.abs(pos[:, 0] - p0[0]) < np_) & (np.abs(pos[:, 1] - p0[1]) < np_))[0]
+        lo = pos[near].min(axis=0)
+        shape = tuple(pos[near].max(axis=0) - lo + np_)
+        lpos = pos[near] - lo
+        v = O.extract(x0d, pos[near], np_)                   # the initial states P_j x0
+        y = O.amplitudes(prob.z[near].cpu().numpy())
+        w = O.agent_stack(v, d, y, alpha)
+        xbar = O.weighted_average(2.0 * w - v, d, lpos, shape, kappa)
+        k0 = int(np.nonzero(near == j0)[0][0])
+        zj = O.extract(xbar, lpos[k0:k0 + 1], np_)[0]
+        v_new = v[k0] + 2.0 * rho * (zj - w[k0])
+        ev = rel(v_dev[j0].cpu().numpy(), v_new)
+        r, c = p0
+        xh_ref = (1 - rho) * x0d[r:r + np_, c:c + np_] + rho * xbar[r - lo[0]:r - lo[0] + np_,
+                                                                   c - lo[1]:c - lo[1] + np_]
+        ex = rel(xh_dev[r:r + np_, c:c + np_], xh_ref)
+        _say(f"  patch {j0} at {tuple(p0)}: {len(near)} overlapping, rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
+        assert ev < TOL and ex < TOL
+    R.close()
