@@ -59,7 +59,8 @@ typedef struct {
   float kappa;        /* >= 0: probe exponent of the consensus weights, eq. (11) */
   float rho;          /* 0 < rho < 1: Mann averaging parameter, eq. (13) */
   uint32_t flags;     /* PMACE_CENTERED_DC or 0 */
-  int32_t chunk;      /* Np = 256 only: positions per staging chunk (>= 1, capped at J),
+  int32_t chunk;      /* Np > 128 only: at most this many positions per staging chunk
+                         (>= 1, capped at J; the chunks are then evened out),
                          0 = the build's tuned default */
   int32_t method;     /* PMACE_METHOD_PMACE (alpha, kappa, rho used) or PMACE_METHOD_SHARP_PLUS */
   float beta;         /* SHARP+ relaxation, 0 <= beta <= 1 (Alg. 2); ignored by PMACE */

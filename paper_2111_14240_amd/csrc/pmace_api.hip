@@ -101,7 +101,9 @@ int chunk_of(const pmace_params& p) {
   int c = p.num_pos;
   if (np_large(p.np)) c = p.chunk > 0 ? p.chunk : PMACE_CHUNK256;
   if (c > p.num_pos) c = p.num_pos;
-  return c;
+  // the same number of chunks, evened out (no small last chunk)
+  const int n = (p.num_pos + c - 1) / c;
+  return (p.num_pos + n - 1) / n;
 }
 int num_chunks(const pmace_params& p) {
   const int c = chunk_of(p);

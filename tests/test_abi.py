@@ -60,10 +60,11 @@ def test_footprint_formula(lib):
     # SHARP+ keeps its weighted frames of every position in the stage buffer
     sharp = P.pmace_footprint(P.make_params(128, 128, 32, 36, 0.5, method=1, beta=0.75))
     assert J * np_ * np_ * 8 <= sharp - fp <= J * np_ * np_ * 8 + 256
-    # Np = 256 stages min(J, chunk) patches between its passes
+    # Np = 256 stages one chunk of patches between its passes: at most `chunk`
+    # positions, evened out over the chunks (1600 = 25 x 64 = 13 chunks of <= 124)
     a = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=64))
     b = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=128))
-    stage = 64 * 256 * 256 * 8
+    stage = (124 - 64) * 256 * 256 * 8
     tile_tables = (25 - 13) * 256 * 16 * 24    # fewer chunks, fewer tile slots
     assert stage - tile_tables - 4096 <= b - a <= stage + 4096
 
