@@ -195,10 +195,20 @@ template <int R, bool INV> __device__ __forceinline__ void dft(float2* a) {
 // Split N = A*B of a line over A threads with B registers each (B a multiple
 // of A).  Powers of two use radix 16/8/4; 48, 96, 192 add a factor 3 and 160
 // a factor 5 through the prime-factor DFTs above.
+// The splits of 32 and 64 points are build-time choices (tuned): 32 = 4x8 or
+// 2x16, 64 = 8x8 or 4x16.
+#ifndef PMACE_GEO32_A
+#define PMACE_GEO32_A 4
+#endif
+#ifndef PMACE_GEO64_A
+#define PMACE_GEO64_A 8
+#endif
+static_assert(PMACE_GEO32_A == 2 || PMACE_GEO32_A == 4, "32-point split");
+static_assert(PMACE_GEO64_A == 4 || PMACE_GEO64_A == 8, "64-point split");
 template <int N> struct Geo;
-template <> struct Geo<32>  { static constexpr int A = 4,  B = 8;  };
+template <> struct Geo<32>  { static constexpr int A = PMACE_GEO32_A, B = 32 / PMACE_GEO32_A; };
 template <> struct Geo<48>  { static constexpr int A = 4,  B = 12; };
-template <> struct Geo<64>  { static constexpr int A = 8,  B = 8;  };
+template <> struct Geo<64>  { static constexpr int A = PMACE_GEO64_A, B = 64 / PMACE_GEO64_A; };
 template <> struct Geo<96>  { static constexpr int A = 4,  B = 24; };
 template <> struct Geo<128> { static constexpr int A = 8,  B = 16; };
 template <> struct Geo<160> { static constexpr int A = 4,  B = 40; };

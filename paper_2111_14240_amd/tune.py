@@ -5,15 +5,18 @@ csrc/pmace_internal.hpp) plus one run-time default:
 
     PMACE_GT_K           threads per object pixel in the consensus gather (1, 2, 4)
     PMACE_GATHER_UNROLL  loads in flight per gather thread (8, 16)
-    PMACE_RB             Np = 256 row passes: patch rows per workgroup (8, 16, 32)
-    PMACE_CB             Np = 256 column pass: patch columns per workgroup (16, 32)
-    PMACE_CHUNK256       Np = 256: positions per chunk (stage buffer size)
+    PMACE_RB             Np > 128 row passes: patch rows per workgroup (8, 16, 32)
+    PMACE_CB             Np > 128 column pass: patch columns per workgroup (16, 32)
+    PMACE_CHUNK256       Np > 128: positions per chunk (stage buffer size)
+    PMACE_GEO32_A        32-point line split over threads: 4 x 8 or 2 x 16 registers
+    PMACE_GEO64_A        64-point line split: 8 x 8 or 4 x 16
 
 Search (coordinate-wise, every candidate measured on the device):
   1. gather shape (GT_K x unroll) with the default row/column blocks, scored by
      the iteration time of a Np = 128 and a Np = 256 workload;
   2. row/column blocks with the default gather, scored on the Np = 256 workload;
-  3. the chunk size, at run time, with the combined choice.
+  3. the line-FFT split (radix) of Np = 32 and 64, each on a workload of its size;
+  4. the chunk size, at run time, with the combined choice.
 Each candidate library is built into a scratch directory and timed in a
 process of its own.  The choice is written to tuned.json beside this file;
 build.py passes it to hipcc as -D flags.
@@ -35,13 +38,16 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned.json")
-DEFAULTS = {"PMACE_GT_K": 1, "PMACE_GATHER_UNROLL": 8, "PMACE_RB": 16, "PMACE_CB": 16}
+DEFAULTS = {"PMACE_GT_K": 1, "PMACE_GATHER_UNROLL": 8, "PMACE_RB": 16, "PMACE_CB": 16,
+            "PMACE_GEO32_A": 4, "PMACE_GEO64_A": 8}
 GATHER_SPACE = [(k, u) for k in (1, 2, 4) for u in (8, 16)]
 BLOCK_SPACE = [(rb, cb) for rb in (8, 16, 32) for cb in (16, 32)]
+GEO_SPACE = [(32, 2), (64, 4)]          # the non-default splits
 CHUNKS = (64, 128, 192, 256, 400)
 
 # Tuning workloads: (object side, probe side, scan side, step, peak photons).
-WORKLOADS = {"np128": (512, 128, 15, 24, 1e5), "np256": (1024, 256, 40, 20, 1e6)}
+WORKLOADS = {"np128": (512, 128, 15, 24, 1e5), "np256": (1024, 256, 40, 20, 1e6),
+             "np32": (256, 32, 14, 16, 1e5), "np64": (512, 64, 20, 22, 1e5)}
 
 
 def candidates():
@@ -53,6 +59,9 @@ def candidates():
     for rb, cb in BLOCK_SPACE:
         d = dict(DEFAULTS, PMACE_RB=rb, PMACE_CB=cb)
         out[f"rb{rb}cb{cb}"] = d
+    for n, a in GEO_SPACE:
+        d = dict(DEFAULTS, **{f"PMACE_GEO{n}_A": a})
+        out[f"geo{n}a{a}"] = d
     # the default appears in both families: keep one copy
     uniq, seen = {}, set()
     for name, d in out.items():
@@ -117,9 +126,18 @@ def cmd_time(args):
     times = {}
     for name in sorted(cands):
         lib = os.path.join(args.dir, f"libpmace_{name}.so")
-        wl = ["np128", "np256"] if name.startswith("g") else ["np256"]
+        if name == "g1u8":       # the default build is also timed on the small sizes
+            wl_extra = ["np32", "np64"]
+        else:
+            wl_extra = []
+        if name.startswith("geo"):
+            wl = ["np32", "np64"]
+        elif name.startswith("g"):
+            wl = ["np128", "np256"]
+        else:
+            wl = ["np256"]
         out = subprocess.run([sys.executable, "-m", "paper_2111_14240_amd.tune", "_one", lib,
-                              ",".join(wl), str(args.iters)],
+                              ",".join(wl + wl_extra), str(args.iters)],
                              capture_output=True, text=True, timeout=300,
                              cwd=os.path.dirname(HERE))
         sys.stdout.write(out.stdout)
@@ -138,7 +156,7 @@ def cmd_one(args):
 
 def _pick(cands, times):
     import math
-    g = {n: t for n, t in times.items() if n.startswith("g")}
+    g = {n: t for n, t in times.items() if n.startswith("g") and not n.startswith("geo")}
     base = g["g1u8"]
     # geometric mean of the speedups over the default on both workloads
     score = {n: math.sqrt((base["np128"] / t["np128"]) * (base["np256"] / t["np256"])) for n, t in g.items()}
@@ -151,6 +169,12 @@ def _pick(cands, times):
     d["PMACE_GATHER_UNROLL"] = cands[best_g]["PMACE_GATHER_UNROLL"]
     rb, cb = best_b[2:].split("cb")
     d["PMACE_RB"], d["PMACE_CB"] = int(rb), int(cb)
+    # line splits: the default build's time on each size against the variant's
+    if "np32" in base:
+        for n, a in GEO_SPACE:
+            key = f"geo{n}a{a}"
+            if key in times and times[key][f"np{n}"] < base[f"np{n}"]:
+                d[f"PMACE_GEO{n}_A"] = a
     return d, score, b
 
 
