@@ -72,7 +72,7 @@ typedef struct pmace_batch pmace_batch;  /* several reconstructions stepped toge
 /* Bytes of device workspace one reconstruction needs (0 if params are invalid).
  * Layout: agent states J*Np^2*8, amplitudes J*Np^2*4, object images N1*N2*36,
  * probe tables Np^2*44, positions J*8, a staging buffer of chunk*Np^2*8
- * bytes (Np = 256: the chunk's spectra; SHARP+ with Np <= 128: all J frames;
+ * bytes (Np > 128: the chunk's spectra; SHARP+ with Np <= 128: all J frames;
  * PMACE with Np <= 128: none), data-fit partials and the consensus tile
  * tables; each section 256-byte aligned. */
 size_t pmace_footprint(const pmace_params* params);
@@ -123,7 +123,8 @@ pmace_status pmace_sync(pmace_ctx* ctx);
 /* Queue the context's later work on hip_stream instead (synchronises the old
  * stream first).  A serving loop initialises a new reconstruction on a side
  * stream, so its host-side set-up overlaps the running batch, then moves it
- * to the batch's stream. */
+ * to the batch's stream.  Not for a context that a live batch holds (the
+ * batch keeps launching on the stream it was created with). */
 pmace_status pmace_set_stream(pmace_ctx* ctx, void* hip_stream);
 
 /* Release the host context (not the caller's workspace).  NULL is a no-op. */
@@ -152,9 +153,11 @@ pmace_status pmace_nrmse(pmace_ctx* ctx, double* out);
 pmace_status pmace_data_fit(pmace_ctx* ctx, double* out);
 
 /* Batches: several reconstructions on one device and stream advanced
- * together, one HIP graph launch per iteration.  Positions of members with
- * Np <= 128 share merged launches per patch size; Np = 256 members run as
- * parallel branches.  Every iteration counts towards max_iter; after every
+ * together; from the third pmace_batch_step call on, one HIP graph launch per
+ * iteration (a batch rebuilt every few steps, as in a serving loop, launches
+ * eagerly instead of paying for capture).  Positions of members with
+ * Np <= 128 share merged launches per patch size; Np > 128 members run as
+ * parallel branches beside them.  Every iteration counts towards max_iter; after every
  * check_every-th iteration of the batch the stop rule is evaluated on the
  * device, and a member stops (its kernels return at once) when
  *   PMACE_STOP_NRMSE:    its NRMSE against its reference (set before
