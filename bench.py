@@ -269,7 +269,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
-    ap.add_argument("--chunk", type=int, default=0, help="Np=256 staging chunk (0 = library default)")
+    ap.add_argument("--chunk", type=int, default=0, help="Np > 128: at most this many positions per staging chunk (0 = tuned default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB three times (counter calibration)")

@@ -105,8 +105,8 @@ __device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2*
 
 // -------------------------------------------------------------------------
 // Np <= 128: the whole patch lives in LDS; one workgroup per work item
-// (reconstruction, position) does a2-a8 in one pass (rows, columns, prox,
-// columns, rows, epilogue).
+// (reconstruction, position) does a2-a7 in one pass (rows, columns, state
+// spectrum, columns, rows, new state).
 // -------------------------------------------------------------------------
 template <int NP, int METHOD>
 __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(row_threads<NP>()) agent_rowsinv_batch(const R
 //   PMACE : |d|^kappa t_j (the sum S of the weighted states),
 //   SHARP+: the overlap numerators conj(d) P_a s_j left in the stage buffer
 //           (`jbase` = first position held there).
-// Np = 256 chunks run in order on the stream, so every pixel sums its
+// Np > 128 chunks run in order on the stream, so every pixel sums its
 // contributions in ascending j and the result is bitwise reproducible.  FUSE
 // (Np <= 128, every position in one chunk): the sum is complete, so a9 (xbar,
 // xhat) is finished here; otherwise it is added to num.
@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(GT_THREADS) consensus_gather_batch(const Recon
   consensus_gather_body<NP, FUSE, kPMACE>(g, it.y, jbase);
 }
 
-// a9 for Np = 256: consensus image, reconstruction recurrence, accumulator reset.
+// a9 for Np > 128: consensus image, reconstruction recurrence, accumulator reset.
 __device__ __forceinline__ void image_update_body(const Recon& g) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n1 * g.n2) return;
@@ -560,7 +560,7 @@ __global__ void __launch_bounds__(RED_T) nrmse_finish(const Recon* __restrict__ 
 // reconstruction, C = sum_j f_j(P_j xhat) = 1/2 sum_j ||y_j - |F D P_j xhat|||^2
 // (sigma_n = 1; only its relative change is used).  With the unnormalised
 // transform W = Np F(D P_j xhat) and yfac * ys = Np y_j, each patch adds
-// (yfac ys - |W|)^2 / (2 Np^2).  Per-patch (Np = 256: per column block)
+// (yfac ys - |W|)^2 / (2 Np^2).  Per-patch (Np > 128: per column block)
 // partial sums in FP64, summed per reconstruction in a fixed order.
 // -------------------------------------------------------------------------
 __device__ __forceinline__ void block_sum_to(float v, double* out, double scale) {
