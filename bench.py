@@ -237,7 +237,7 @@ def bench_serve(args):
             st = serve.Server(ex, capacity_bytes=int(args.capacity_gb * 2**30),
                               max_active=a, iters_per_step=10,
                               large_work=args.large_work if v > 0 else None,
-                              max_large=max(v, 1)).run(reqs, clock)
+                              max_large=max(v, 1), hold_small=args.hold_small).run(reqs, clock)
         else:
             st = serve.run_plain(ex, reqs, clock, iters_per_step=10)
         torch.cuda.synchronize()
@@ -283,6 +283,8 @@ def main():
                     help="serve mode: concurrent requests (comma list of variants)")
     ap.add_argument("--large-work", type=float, default=float(1 << 22),
                     help="serve mode: patch pixels per iteration from which a request is large")
+    ap.add_argument("--hold-small", action="store_true",
+                    help="serve mode: no small admissions while a large request waits")
     ap.add_argument("--max-large", default="1",
                     help="serve mode: large requests active at once (comma list of variants; 0 = one class)")
     ap.add_argument("--stop", default="nrmse", choices=["nrmse", "data_fit"],

@@ -126,11 +126,16 @@ class Server:
                     work of everything admitted during its lifetime; this
                     keeps large requests close to their solo time and small
                     ones from queueing behind them.  None: one class.
+    hold_small      with size classes: while a large request waits for the
+                    large slot, smaller ones are not admitted either (the
+                    running large request then shares the device with fewer
+                    others and the large queue drains sooner).
     """
 
     def __init__(self, executor, capacity_bytes: int, max_active: int = 64,
                  iters_per_step: int = 4, on_step: Optional[Callable] = None,
-                 large_work: Optional[float] = None, max_large: int = 1):
+                 large_work: Optional[float] = None, max_large: int = 1,
+                 hold_small: bool = False):
         self.ex = executor
         self.capacity = int(capacity_bytes)
         self.max_active = int(max_active)
@@ -138,6 +143,7 @@ class Server:
         self.on_step = on_step
         self.large_work = large_work
         self.max_large = int(max_large)
+        self.hold_small = bool(hold_small)
 
     def _large(self, req) -> bool:
         return self.large_work is not None and self.ex.work(req.problem) >= self.large_work
@@ -174,6 +180,7 @@ class Server:
             # admission in arrival order while memory and slots allow; a large
             # request waiting for the large slot does not block smaller ones
             i = 0
+            large_waiting = False
             while i < len(queue) and len(active) < self.max_active:
                 r = queue[i]
                 fp = self.ex.footprint(r.problem)
@@ -181,8 +188,11 @@ class Server:
                     break
                 large = self._large(r)
                 if large and n_large >= self.max_large:
+                    large_waiting = True
                     i += 1
                     continue
+                if not large and large_waiting and self.hold_small:
+                    break
                 queue.pop(i)
                 t0 = tick()
                 self.ex.admit(r)
