@@ -59,7 +59,8 @@ struct pmace_ctx {
   int* fitem;                     // device: {0}
   int ngitems;
   std::vector<int2> chunk_tiles;  // host: per chunk (first gather item, count)
-  Graph graph;
+  Graph graph;                    // one iteration
+  Graph graph_k;                  // kGraphIters iterations back to back
   bool graph_tried;
   pmace_status sticky;            // first asynchronous failure seen
 };
@@ -491,11 +492,26 @@ pmace_status pmace_iterate(pmace_ctx* c, int32_t n_iter) {
   if (n_iter == 0) return PMACE_OK;
   // a stop flag left by a batch would make the kernels skip this reconstruction
   if (hipMemsetAsync(c->h.done, 0, 4, c->stream) != hipSuccess) return record(c, PMACE_EDEVICE);
+  // One graph replays one iteration; a second replays kGraphIters of them in
+  // a row, so long runs pay one launch per kGraphIters iterations.
+  constexpr int kGraphIters = 8;
   if (!c->graph_tried && graphs_enabled()) {
     c->graph_tried = true;
     (void)capture(c->graph, [&](hipStream_t cs) { return enqueue_iteration(c, cs); });
+    if (c->graph.x)
+      (void)capture(c->graph_k, [&](hipStream_t cs) {
+        for (int i = 0; i < kGraphIters; ++i) {
+          const pmace_status s = enqueue_iteration(c, cs);
+          if (s != PMACE_OK) return s;
+        }
+        return PMACE_OK;
+      });
   }
-  for (int k = 0; k < n_iter; ++k) {
+  int k = 0;
+  if (c->graph_k.x)
+    for (; k + kGraphIters <= n_iter; k += kGraphIters)
+      if (hipGraphLaunch(c->graph_k.x, c->stream) != hipSuccess) return record(c, PMACE_EDEVICE);
+  for (; k < n_iter; ++k) {
     if (c->graph.x) {
       if (hipGraphLaunch(c->graph.x, c->stream) != hipSuccess) return record(c, PMACE_EDEVICE);
     } else {
@@ -592,6 +608,7 @@ void pmace_destroy(pmace_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   c->graph.release();
+  c->graph_k.release();
   delete c;
 }
 
