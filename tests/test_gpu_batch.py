@@ -231,3 +231,23 @@ def test_invalid_stop_rule_rejected(P):
             P.Batch([R], **kw)
         assert ei.value.status == P.PMACE_EINVAL
     R.close()
+
+
+def test_set_stream_moves_a_reconstruction(P):
+    """A reconstruction set up on one stream and moved to another (as the
+    serving loop does) iterates exactly like one that never moved."""
+    prob = synth.make_problem(200, 64, 5, 30, 1e5, 48)
+    side, main = torch.cuda.Stream(), torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        A = P.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, 0.5, stream=side)
+    A.set_stream(main)
+    with torch.cuda.stream(main):
+        A.iterate(5)
+        A.sync()
+        va = A.get_state().cpu().numpy()
+    B = _recon(P, prob, 0)
+    B.iterate(5)
+    B.sync()
+    assert np.array_equal(va, B.get_state().cpu().numpy())
+    A.close()
+    B.close()
