@@ -124,3 +124,15 @@ def test_data_fit_cost_values():
     y = np.abs(O.dft2(d * x))
     assert O.data_fit_cost(x, d, y) == pytest.approx(0, abs=1e-20)
     assert O.data_fit_cost(np.zeros_like(x), d, y, 2.0) == pytest.approx(np.sum(y ** 2) / 4)
+
+
+def test_data_fit_cost_scale_by_parseval():
+    """eq. (4) with y = 0 is ||F D v||^2 / (2 sigma^2) = ||D v||^2 / (2 sigma^2)
+    for the orthonormal F (a missing 1/Np in F would scale it by Np^2), and it
+    is quadratic in a common scale of v."""
+    rng = np.random.default_rng(13)
+    d = synth.make_probe(8)
+    v = _rand_c(rng, (2, 8, 8))
+    y0 = np.zeros((2, 8, 8))
+    assert O.data_fit_cost(v, d, y0, 0.5) == pytest.approx(np.sum(np.abs(d * v) ** 2), rel=1e-12)
+    assert O.data_fit_cost(3 * v, d, y0) == pytest.approx(9 * O.data_fit_cost(v, d, y0), rel=1e-12)
