@@ -441,7 +441,12 @@ class Reconstruction:
         return v
 
     def close(self):
+        """Release the context.  A batch that holds this reconstruction must be
+        closed first (it launches from the context's tables)."""
         if getattr(self, "ctx", None) is not None and self.ctx.value:
+            live = [b for b in getattr(self, "_batches", ()) if b.batch is not None]
+            if live:
+                raise RuntimeError("close the Batch holding this Reconstruction first")
             pmace_destroy(self.ctx)
             self.ctx = None
 
@@ -473,6 +478,11 @@ class Batch:
                                    workspace.numel())
         _check(st, "pmace_batch_create")
         self.batch = b
+        import weakref
+        for r in self.recons:
+            if not hasattr(r, "_batches"):
+                r._batches = weakref.WeakSet()
+            r._batches.add(self)
 
     def step(self, n: int = 1):
         _check(pmace_batch_step(self.batch, n), "pmace_batch_step")

@@ -251,3 +251,13 @@ def test_set_stream_moves_a_reconstruction(P):
     assert np.array_equal(va, B.get_state().cpu().numpy())
     A.close()
     B.close()
+
+
+def test_closing_a_member_of_an_open_batch_is_refused(P):
+    prob = synth.make_problem(128, 32, 4, 20, None, 3)
+    R = _recon(P, prob, 0)
+    B = P.Batch([R])
+    with pytest.raises(RuntimeError):
+        R.close()
+    B.close()
+    R.close()
