@@ -39,6 +39,13 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
+def elem(a, b):
+    """Element by element: the largest pointwise error over the largest value."""
+    a = np.asarray(a, np.complex128)
+    b = np.asarray(b, np.complex128)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
 def as_f32_inputs(prob):
     """The exact values the device sees, widened to FP64 for the oracle."""
     d = prob.probe.astype(np.complex64).astype(np.complex128)
@@ -149,8 +156,10 @@ def test_teacher_forced_steps(P, case, alpha):
         v = R.get_state().cpu().numpy()
         xh = R.reconstruct().cpu().numpy()
         ev, ex = rel(v, vs[k + 1]), rel(xh, xs[k + 1])
-        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
+        mv, mx = elem(v, vs[k + 1]), elem(xh, xs[k + 1])
+        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e} elementwise {mv:.2e} {mx:.2e}")
         assert ev < TOL and ex < TOL, (k, ev, ex)
+        assert mv < TOL and mx < TOL, (k, mv, mx)
     R.close()
 
 
@@ -172,10 +181,12 @@ def test_flat_start(P, case):
     for k in (1, 2):
         R.set_state(vs[k])
         R.iterate(1)
-        ev = rel(R.get_state().cpu().numpy(), vs[k + 1])
-        ex = rel(R.reconstruct().cpu().numpy(), xs[k + 1])
-        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
+        v, xh = R.get_state().cpu().numpy(), R.reconstruct().cpu().numpy()
+        ev, ex = rel(v, vs[k + 1]), rel(xh, xs[k + 1])
+        mv, mx = elem(v, vs[k + 1]), elem(xh, xs[k + 1])
+        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e} elementwise {mv:.2e} {mx:.2e}")
         assert ev < TOL and ex < TOL
+        assert mv < TOL and mx < TOL
     R.close()
 
 
@@ -224,10 +235,12 @@ def test_c2_teacher_forced_steps(P):
     for k in ks:
         R.set_state(vs[k])
         R.iterate(1)
-        ev = rel(R.get_state().cpu().numpy(), vs[k + 1])
-        ex = rel(R.reconstruct().cpu().numpy(), xs[k + 1])
-        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
+        v, xh = R.get_state().cpu().numpy(), R.reconstruct().cpu().numpy()
+        ev, ex = rel(v, vs[k + 1]), rel(xh, xs[k + 1])
+        mv, mx = elem(v, vs[k + 1]), elem(xh, xs[k + 1])
+        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e} elementwise {mv:.2e} {mx:.2e}")
         assert ev < TOL and ex < TOL
+        assert mv < TOL and mx < TOL
     R.close()
 
 
@@ -271,10 +284,12 @@ def test_teacher_forced_edge_cases(P, case):
         R.set_state(vs[k])
         R.iterate(1)
         R.sync()
-        ev = rel(R.get_state().cpu().numpy(), vs[k + 1])
-        ex = rel(R.reconstruct().cpu().numpy(), xs[k + 1])
-        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
-        assert ev < TOL and ex < TOL, (k, ev, ex)
+        v, xh = R.get_state().cpu().numpy(), R.reconstruct().cpu().numpy()
+        ev, ex = rel(v, vs[k + 1]), rel(xh, xs[k + 1])
+        mv, mx = elem(v, vs[k + 1]), elem(xh, xs[k + 1])
+        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e} elementwise {mv:.2e} {mx:.2e}")
+        assert ev < TOL and ex < TOL
+        assert mv < TOL and mx < TOL, (k, ev, ex)
     # free-running from the device's own start: several passes in a row use
     # the consensus sum kept from the previous pass
     R2 = P.Reconstruction(n1, n2, prob.probe, prob.pos, prob.z, alpha, kappa, rho, chunk=chunk,
@@ -338,10 +353,12 @@ def test_c3_full_size_steps(P):
     assert e0 < tol0 and ex0 < tol0
     R.set_state(vs[1])
     R.iterate(1)
-    e1 = rel(R.get_state().cpu().numpy(), vs[2])
-    ex1 = rel(R.reconstruct().cpu().numpy(), xs[2])
-    _say(f"  k=1 rel(v)={e1:.2e} rel(xhat)={ex1:.2e}")
+    v1, xh1 = R.get_state().cpu().numpy(), R.reconstruct().cpu().numpy()
+    e1, ex1 = rel(v1, vs[2]), rel(xh1, xs[2])
+    m1, mx1 = elem(v1, vs[2]), elem(xh1, xs[2])
+    _say(f"  k=1 rel(v)={e1:.2e} rel(xhat)={ex1:.2e} elementwise {m1:.2e} {mx1:.2e}")
     assert e1 < TOL and ex1 < TOL
+    assert m1 < TOL and mx1 < TOL
     R.close()
 
 
