@@ -13,6 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmace.so")
+DEMO = os.path.join(HERE, "pmace_demo")
 TUNED = os.path.join(HERE, "tuned.json")
 SOURCES = ["pmace_api.hip", "pmace_kernels.hip", "pmace_simulate.hip"]
 
@@ -50,5 +51,23 @@ def build(verbose: bool = False, out: str = LIB, defines: dict | None = None) ->
     return out
 
 
+def build_demo(verbose: bool = False, lib: str = LIB, out: str = DEMO) -> str:
+    """The C++ example that drives the C ABI without Python, linked against
+    `lib` (found beside the executable at run time)."""
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    cmd = [hipcc, "-O2", "-std=c++17", "-I", os.path.join(ROOT, "include"),
+           os.path.join(CSRC, "pmace_demo.cpp"), "-L", os.path.dirname(lib), "-l:" + os.path.basename(lib),
+           "-Wl,-rpath,$ORIGIN", "-o", out + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError(f"hipcc failed building {out}")
+    os.replace(out + ".tmp", out)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_demo(verbose=True))
