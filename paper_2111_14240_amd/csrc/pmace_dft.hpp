@@ -236,20 +236,31 @@ template <int N> __device__ __forceinline__ void fill_twiddles(float2* tw, int t
 // Row-direction line FFT.  Thread (r, p), p in [0, A), owns row r of a tile
 // whose rows start at row_base (float2 units) with the row exchanged through
 // a skewed layout  n_a*(B+1) + k_b  (row capacity N + A float2).
+// The A threads of a row are consecutive lanes of one wavefront (A divides
+// 64), and only they touch the row's LDS, so the exchange is ordered within
+// the wave: a wave's LDS operations execute in order, and wave_sync keeps the
+// compiler from moving them across it.  The caller orders any use of the row
+// by other waves (the transposes) with workgroup barriers.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // in : x[n_b] = row[p + A n_b]
 // out: x[m*A + k_a] = X[(p + A m) + B k_a]
 template <int N> __device__ __forceinline__ void row_fwd(float2 (&x)[Geo<N>::B], float2* row, int p,
                                                          const float2* tw) {
   constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A;
+  static_assert(64 % A == 0, "a row's threads must share a wavefront");
   dft<B, false>(x);
 #pragma unroll
   for (int kb = 1; kb < B; ++kb) x[kb] = cmul(x[kb], tw[p * kb]);
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int kb = 0; kb < B; ++kb) row[p * (B + 1) + kb] = x[kb];
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int kb = p + A * m;
@@ -274,14 +285,14 @@ template <int N> __device__ __forceinline__ void row_inv(float2 (&x)[Geo<N>::B],
 #pragma unroll
     for (int na = 1; na < A; ++na) x[m * A + na] = cmulc(x[m * A + na], tw[na * kb]);
   }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int kb = p + A * m;
 #pragma unroll
     for (int na = 0; na < A; ++na) row[na * (B + 1) + kb] = x[m * A + na];
   }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int kb = 0; kb < B; ++kb) x[kb] = row[p * (B + 1) + kb];
   dft<B, true>(x);
