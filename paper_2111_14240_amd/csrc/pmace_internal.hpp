@@ -12,6 +12,9 @@ namespace pmace {
 #ifndef PMACE_GT_K
 #define PMACE_GT_K 1      // threads per object pixel in the consensus gather
 #endif
+#ifndef PMACE_GT_C
+#define PMACE_GT_C 64     // consensus gather tile width in object pixels (32 or 64)
+#endif
 #ifndef PMACE_GATHER_UNROLL
 #define PMACE_GATHER_UNROLL 8
 #endif
@@ -26,9 +29,11 @@ namespace pmace {
 #endif
 
 // Gather tile of the consensus: GT_R x GT_C object pixels, GT_K threads each
-// (GT_R * GT_C * GT_K = 1024 threads per workgroup).
-constexpr int GT_K = PMACE_GT_K, GT_C = 64, GT_R = 16 / GT_K;
+// (GT_R * GT_C * GT_K = 16 GT_C threads per workgroup).  A narrower tile lists
+// fewer patches that miss most of its pixels.
+constexpr int GT_K = PMACE_GT_K, GT_C = PMACE_GT_C, GT_R = 16 / GT_K;
 static_assert(GT_K == 1 || GT_K == 2 || GT_K == 4, "gather split must be 1, 2 or 4");
+static_assert(GT_C == 32 || GT_C == 64, "gather tile width must be 32 or 64");
 constexpr int GT_THREADS = GT_R * GT_C * GT_K;
 // NRMSE reduction: RED_PX object pixels per block of RED_T threads.
 constexpr int RED_T = 256, RED_PX = 4096;

@@ -5,6 +5,7 @@ csrc/pmace_internal.hpp) plus one run-time default:
 
     PMACE_GT_K           threads per object pixel in the consensus gather (1, 2, 4)
     PMACE_GATHER_UNROLL  loads in flight per gather thread (8, 16)
+    PMACE_GT_C           gather tile width in object pixels (32, 64)
     PMACE_RB             Np > 128 row passes: patch rows per workgroup (8, 16, 32)
     PMACE_CB             Np > 128 column pass: patch columns per workgroup (16, 32)
     PMACE_CHUNK256       Np > 128: positions per chunk (stage buffer size)
@@ -12,7 +13,7 @@ csrc/pmace_internal.hpp) plus one run-time default:
     PMACE_GEO64_A        64-point line split: 8 x 8 or 4 x 16
 
 Search (coordinate-wise, every candidate measured on the device):
-  1. gather shape (GT_K x unroll) with the default row/column blocks, scored by
+  1. gather shape (GT_K x unroll x tile width) with the default row/column blocks, scored by
      the iteration time of a Np = 128 and a Np = 256 workload;
   2. row/column blocks with the default gather, scored on the Np = 256 workload;
   3. the line-FFT split (radix) of Np = 32 and 64, each on a workload of its size;
@@ -38,9 +39,9 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned.json")
-DEFAULTS = {"PMACE_GT_K": 1, "PMACE_GATHER_UNROLL": 8, "PMACE_RB": 16, "PMACE_CB": 16,
+DEFAULTS = {"PMACE_GT_K": 1, "PMACE_GATHER_UNROLL": 8, "PMACE_GT_C": 64, "PMACE_RB": 16, "PMACE_CB": 16,
             "PMACE_GEO32_A": 4, "PMACE_GEO64_A": 8}
-GATHER_SPACE = [(k, u) for k in (1, 2, 4) for u in (8, 16)]
+GATHER_SPACE = [(k, u, c) for k in (1, 2, 4) for u in (8, 16) for c in (64, 32)]
 BLOCK_SPACE = [(rb, cb) for rb in (8, 16, 32) for cb in (16, 32)]
 GEO_SPACE = [(32, 2), (64, 4)]          # the non-default splits
 CHUNKS = (64, 128, 192, 256, 400)
@@ -53,9 +54,9 @@ WORKLOADS = {"np128": (512, 128, 15, 24, 1e5), "np256": (1024, 256, 40, 20, 1e6)
 def candidates():
     """Name -> defines of every candidate library."""
     out = {}
-    for k, u in GATHER_SPACE:
-        d = dict(DEFAULTS, PMACE_GT_K=k, PMACE_GATHER_UNROLL=u)
-        out[f"g{k}u{u}"] = d
+    for k, u, c in GATHER_SPACE:
+        d = dict(DEFAULTS, PMACE_GT_K=k, PMACE_GATHER_UNROLL=u, PMACE_GT_C=c)
+        out[f"g{k}u{u}" + ("" if c == 64 else f"c{c}")] = d
     for rb, cb in BLOCK_SPACE:
         d = dict(DEFAULTS, PMACE_RB=rb, PMACE_CB=cb)
         out[f"rb{rb}cb{cb}"] = d
@@ -167,6 +168,7 @@ def _pick(cands, times):
     d = dict(DEFAULTS)
     d["PMACE_GT_K"] = cands[best_g]["PMACE_GT_K"]
     d["PMACE_GATHER_UNROLL"] = cands[best_g]["PMACE_GATHER_UNROLL"]
+    d["PMACE_GT_C"] = cands[best_g].get("PMACE_GT_C", 64)
     rb, cb = best_b[2:].split("cb")
     d["PMACE_RB"], d["PMACE_CB"] = int(rb), int(cb)
     # line splits: the default build's time on each size against the variant's

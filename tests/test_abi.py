@@ -52,9 +52,10 @@ def test_footprint_formula(lib):
     # patches), object images 36 B per pixel (Lambda^-1, accumulator, S, xbar,
     # xhat), probe tables 44 B per probe pixel, positions, tile tables
     lower = J * np_ * np_ * 12 + n * n * 36 + np_ * np_ * 44 + J * 8
-    # gather tiles are (16 / k) x 64 pixels with k in {1, 2, 4} (a tuned build parameter)
-    tiles = (n // 4) * (n // 64)
-    tables = tiles * 24 + J * (31 // 4 + 2) * (31 // 64 + 2) * 4 + J * 8
+    # gather tiles are (16 / k) x w pixels with k in {1, 2, 4} and w in {32, 64}
+    # (tuned build parameters)
+    tiles = (n // 4) * (n // 32)
+    tables = tiles * 24 + J * (31 // 4 + 2) * (31 // 32 + 2) * 4 + J * 8
     nred = n * n // 4096
     assert lower <= fp <= lower + tables + nred * 40 + 1024 + 26 * 256
     # SHARP+ keeps its weighted frames of every position in the stage buffer
@@ -65,7 +66,7 @@ def test_footprint_formula(lib):
     a = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=64))
     b = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=128))
     stage = (124 - 64) * 256 * 256 * 8
-    tile_tables = (25 - 13) * 256 * 16 * 24    # fewer chunks, fewer tile slots
+    tile_tables = (25 - 13) * 256 * 32 * 24    # fewer chunks, fewer tile slots (at most)
     assert stage - tile_tables - 4096 <= b - a <= stage + 4096
 
 
