@@ -53,6 +53,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def iteration_kernels(np_, J):
+    """The kernels one timed iteration (the roofline's unit) launches."""
+    if np_ <= 128:
+        return (f"one PMACE iteration: agent_fused<{np_}> ({J} workgroups) + "
+                f"consensus_gather<{np_}> (a9 fused)")
+    return (f"one PMACE iteration: per chunk of positions agent_rows, agent_cols, "
+            f"agent_rowsinv <{np_}> + consensus_gather<{np_}>, then image_update")
+
+
 def measured_traffic(config):
     """HBM bytes per iteration measured with rocprofv3 counters (FETCH_SIZE and
     WRITE_SIZE, each scaled by the same counter on a plain copy of known size),
@@ -357,7 +366,7 @@ def main():
                                f"Poisson peak {cfg['peak']}",
                    "alpha": alpha, "kappa": kappa, "rho": rho, "chunk": args.chunk,
                    "iteration_graph": "HIP graphs of 8 iterations (single-iteration graph for the rest)"},
-        "roofline": {"bound": "hbm", "kernel": "one PMACE iteration (agent passes + image update)",
+        "roofline": {"bound": "hbm", "kernel": iteration_kernels(np_, J),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
                      "algorithmic_bytes_per_step": B},
