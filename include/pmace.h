@@ -71,7 +71,7 @@ typedef struct pmace_batch pmace_batch;  /* several reconstructions stepped toge
 
 /* Bytes of device workspace one reconstruction needs (0 if params are invalid).
  * Layout: agent states J*Np^2*8, amplitudes J*Np^2*4, object images N1*N2*36,
- * probe tables Np^2*44, positions J*8, a staging buffer of chunk*Np^2*8
+ * probe tables Np^2*48, positions J*8, a staging buffer of chunk*Np^2*8
  * bytes (Np > 128: the chunk's spectra; SHARP+ with Np <= 128: all J frames;
  * PMACE with Np <= 128: none), data-fit partials and the consensus tile
  * tables; each section 256-byte aligned. */

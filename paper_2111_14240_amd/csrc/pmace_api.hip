@@ -140,7 +140,7 @@ pmace_status check_params(const pmace_params* p) {
 
 // Section offsets inside the workspace (relative to the aligned base).
 struct Layout {
-  size_t t, ys, pos, d, pc, dinv, omega, omega64, laminv, num, sold, xbar, xhat, stage, tiles, list, status, desc,
+  size_t t, ys, pos, d, pc, dinv, gw, omega64, laminv, num, sold, xbar, xhat, stage, tiles, list, status, desc,
       items, gitems, ritems, red, tw, fit, total;
 };
 
@@ -166,7 +166,7 @@ Layout layout_of(const pmace_params& p) {
   L.d = o;       o = align_up(o + np2 * 8);
   L.pc = o;      o = align_up(o + np2 * 16);
   L.dinv = o;    o = align_up(o + np2 * 8);
-  L.omega = o;   o = align_up(o + np2 * 4);
+  L.gw = o;      o = align_up(o + np2 * 8);
   L.omega64 = o; o = align_up(o + np2 * 8);
   L.laminv = o;  o = align_up(o + npx * 4);
   L.num = o;     o = align_up(o + npx * 8);
@@ -296,7 +296,8 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   // DFT pair), the d == 0 mask, and Lambda^{-1} (0 where Lambda = 0).
   // SHARP+ (eq. (15)): weights conj(d) over the normaliser sum_k P_k^t |d|^2.
   const bool sharp = p.method == PMACE_METHOD_SHARP_PLUS;
-  std::vector<float> pc(4 * np2), omega_f(np2), dinv(2 * np2, 0.f);
+  std::vector<float> pc(4 * np2), gw(2 * np2, 0.f), dinv(2 * np2, 0.f);
+  bool has_zero = false;
   std::vector<double> omega(np2);
   const double inv_np2 = 1.0 / ((double)np * np);
   for (size_t i = 0; i < np2; ++i) {
@@ -312,7 +313,15 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
     }
     omega[i] = std::pow(mag, (double)p.kappa);
     std::complex<double> di(0.0, 0.0);
-    if (mag != 0.0) di = inv_np2 / dd;
+    if (mag != 0.0) {
+      di = inv_np2 / dd;
+      const std::complex<double> w = omega[i] / dd;  // weights on the stored d t
+      gw[2 * i + 0] = (float)w.real();
+      gw[2 * i + 1] = (float)w.imag();
+    } else {
+      has_zero = true;   // the stored state is t itself there: weight |d|^kappa (1 if kappa = 0)
+      gw[2 * i + 0] = (float)omega[i];
+    }
     pc[4 * i + 0] = (float)di.real();
     pc[4 * i + 1] = (float)di.imag();
     dinv[2 * i + 0] = pc[4 * i + 0];
@@ -324,7 +333,6 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   }
   // Lambda = sum_j P_j^t omega and its inverse are formed on the device from
   // the FP64 weights and the consensus tile lists (see launch_init).
-  for (size_t i = 0; i < np2; ++i) omega_f[i] = (float)omega[i];
 
   // Gather tables: per chunk, GT_R x GT_C tiles over the rows its patches
   // cover, each with the chunk's positions overlapping it in ascending order.
@@ -387,7 +395,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   h.pos = reinterpret_cast<int2*>(base + L.pos);
   h.d = reinterpret_cast<float2*>(base + L.d);
   h.pc = reinterpret_cast<float4*>(base + L.pc);
-  h.omega = reinterpret_cast<float*>(base + L.omega);
+  h.gw = reinterpret_cast<float2*>(base + L.gw);
   h.omega64 = reinterpret_cast<double*>(base + L.omega64);
   h.dinv = reinterpret_cast<float2*>(base + L.dinv);
   h.laminv = reinterpret_cast<float*>(base + L.laminv);
@@ -411,6 +419,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   h.n1 = n1;
   h.n2 = n2;
   h.np = np;
+  h.np2f = (float)((double)np * np);
   h.J = J;
   h.method = p.method;
   if (sharp) {
@@ -428,7 +437,9 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
     h.ka = 0.f;
     h.yfac = (float)(1.0 + (double)p.alpha);
     const double rho = p.rho, a = (double)p.alpha / (1.0 + (double)p.alpha);
-    h.tb = (float)(1.0 - 2.0 * rho * a);
+    h.sb = (float)((1.0 - 2.0 * rho * a) * inv_np2);
+    h.s2r = (float)(2.0 * rho * inv_np2);
+    h.has_zero = has_zero ? 1 : 0;
     h.cx = (float)(2.0 * (1.0 - rho));
     h.co = (float)((1.0 - rho) / rho);
     h.cn = (float)(1.0 / rho);
@@ -456,7 +467,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   if (hipMemcpyAsync(h.pos, pos.data(), (size_t)J * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.d, probe.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.pc, pc.data(), np2 * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(h.omega, omega_f.data(), np2 * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(h.gw, gw.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.dinv, dinv.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.omega64, omega.data(), np2 * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.tiles, tiles.data(), tiles.size() * 16, hipMemcpyHostToDevice, st) != hipSuccess ||

@@ -41,13 +41,15 @@ constexpr int RED_T = 256, RED_PX = 4096;
 // Device-resident description of one reconstruction.  It lives in the
 // reconstruction's workspace; batched launches read an array of them.
 struct Recon {
-  float2* t;            // J*Np*Np   t_j = v_j - 2 rho w_j  (v_j = t_j + 2 rho P_j xbar)
+  float2* t;            // J*Np*Np   PMACE: d t_j (t_j where d == 0), t_j = v_j - 2 rho w_j,
+                        //   v_j = t_j + 2 rho P_j xbar;  SHARP+: t_j (see beta)
   float* ys;            // J*Np*Np   Np*sqrt(z_j)/(1+alpha), DC at [0,0]
   int2* pos;            // J         (row, col) top-left of P_j
   float2* d;            // Np*Np     probe
-  float4* pc;           // Np*Np     {Re, Im of d^{-1}/Np^2, |d|^kappa, [d == 0]}
-  float2* dinv;         // Np*Np     d^{-1}/Np^2, 0 exactly where d == 0 (PMACE epilogue)
-  float* omega;         // Np*Np     |d|^kappa (PMACE consensus weights)
+  float4* pc;           // Np*Np     PMACE: {Re, Im of d^{-1}/Np^2, |d|^kappa, [d == 0]}
+  float2* dinv;         // Np*Np     d^{-1}/Np^2, 0 exactly where d == 0 (reading states out)
+  float2* gw;           // Np*Np     PMACE consensus weights on the stored states: |d|^kappa / d,
+                        //           and |d|^kappa where d == 0 (the state is t there)
   double* omega64;      // Np*Np     the weights in FP64 (SHARP+: |d|^2), for Lambda at init
   float* laminv;        // N1*N2     Lambda^{-1} (0 where Lambda = 0)
   float2* num;          // N1*N2     consensus sum accumulator (Np > 128, set_state)
@@ -79,7 +81,10 @@ struct Recon {
                         //   pc = {conj(d)/Np^2, conj(d)}, laminv = 1/sum P^t |d|^2
   int fit_bpp;          // data-fit partials per patch
   float yfac;           // yfac * ys = Np y_j  (1 + alpha for PMACE, 1 for SHARP+)
-  float tb;             // PMACE: 1 - 2 rho a (state spectrum X - 2 rho U = X (tb - 2 rho ys/|X|))
+  float sb, s2r;        // PMACE: (1 - 2 rho a)/Np^2 and 2 rho/Np^2, the state spectrum
+                        //   (X - 2 rho U)/Np^2 = X (sb - s2r ys/|X|)
+  float np2f;           // Np^2
+  int has_zero;         // the probe has exact zeros (the agent's d == 0 rule applies)
   float cx, co, cn;     // PMACE: xbar' = cx xbar + Lambda^{-1} (co S_old - cn S_new):
                         //   cx = 2 (1 - rho), co = (1 - rho)/rho, cn = 1/rho
 };

@@ -20,13 +20,17 @@
 //
 // PMACE never materialises u.  With U = F(d w) and W = F(d v), the new state
 // is t = d^{-1} F^*(W - 2 rho U) (where d != 0), one inverse transform of the
-// "state spectrum" W - 2 rho U.  Since u = ((1 - rho) v - t_new) / rho and
-// v = t_old + 2 rho P_j xbar, the consensus of eq. (11) is
+// "state spectrum" W - 2 rho U.  Each state is stored probe-weighted, s = d t
+// (t itself where d = 0): the inverse transform is then the new stored state
+// as it is, and the next forward frame is d v = s + 2 rho d P_j xbar, so no
+// division by d (and no rounding it would amplify) happens in the loop; d^{-1}
+// is applied only when a state is read out.  Since u = ((1 - rho) v - t_new) / rho
+// and v = t_old + 2 rho P_j xbar, the consensus of eq. (11) is
 //     xbar' = 2 (1 - rho) xbar + Lambda^{-1} ((1 - rho) S_old - S_new) / rho,
-//     S = sum_j P_j^t |d|^kappa t_j,
+//     S = sum_j P_j^t |d|^kappa t_j = sum_j P_j^t (|d|^kappa / d) s_j,
 // so the gather sums the weighted states themselves and keeps S of the last
-// iteration.  Per patch pixel an iteration then reads t and y and writes t
-// once, and the consensus reads t once more.
+// iteration.  Per patch pixel an iteration then reads s and y and writes s
+// once, and the consensus reads s once more.
 //
 // Every kernel reads its reconstruction from a device descriptor (Recon) and
 // returns at once when that reconstruction's stop flag is set, so many
@@ -47,11 +51,12 @@ __device__ __forceinline__ float2 fourier_prox(float2 W, float ysv, float a) {
 }
 
 // PMACE state spectrum W - 2 rho U = W (tb - 2 rho ys / |W|), tb = 1 - 2 rho a
-// (0 where W == 0).
-__device__ __forceinline__ float2 state_spectrum(float2 W, float ysv, float tb, float two_rho) {
+// (0 where W == 0), scaled by 1/Np^2 (sb = tb/Np^2, s2r = 2 rho/Np^2) so that
+// its unnormalised inverse transform is the new stored state d t.
+__device__ __forceinline__ float2 state_spectrum(float2 W, float ysv, float sb, float s2r) {
   const float m2 = fmaf(W.x, W.x, W.y * W.y);
   const float rs = m2 > 0.f ? __builtin_amdgcn_rsqf(m2) : 0.f;
-  const float g = fmaf(-two_rho, ysv * rs, tb);
+  const float g = fmaf(-s2r, ysv * rs, sb);
   return make_float2(W.x * g, W.y * g);
 }
 
@@ -59,7 +64,7 @@ __device__ __forceinline__ float2 state_spectrum(float2 W, float ysv, float tb, 
 // SHARP+ the magnitude projection (a = 0).
 template <int METHOD>
 __device__ __forceinline__ float2 spectrum_step(float2 W, float ysv, const Recon& g) {
-  if constexpr (METHOD == kPMACE) return state_spectrum(W, ysv, g.tb, g.two_rho);
+  if constexpr (METHOD == kPMACE) return state_spectrum(W, ysv, g.sb, g.s2r);
   else return fourier_prox(W, ysv, 0.f);
 }
 
@@ -68,20 +73,26 @@ __device__ __forceinline__ float2 mann_v(float2 t, float2 xb, float two_rho) {
 }
 
 // Prologue (a2-a3): the frame that is transformed.
-//   PMACE : d (t + 2 rho P_j xbar)           (v of Alg. 1 times the probe)
+//   PMACE : d v = s + 2 rho d P_j xbar       (v of Alg. 1 times the probe, from the
+//                                             stored s = d t; 0 where d == 0)
 //   SHARP+: t + 2 beta d P_j xbar            (the frame s of Alg. 2)
 template <int METHOD>
-__device__ __forceinline__ float2 agent_input(float2 t, float2 xb, float2 d, float two_rho) {
-  if constexpr (METHOD == kPMACE) return cmul(d, mann_v(t, xb, two_rho));
-  else return mann_v(t, cmul(d, xb), two_rho);
+__device__ __forceinline__ float2 agent_input(float2 s, float2 xb, float2 d, float two_rho) {
+  const float2 dx = cmul(d, xb);
+  if constexpr (METHOD == kPMACE) {
+    const bool nz = d.x != 0.f || d.y != 0.f;
+    return make_float2(fmaf(two_rho, dx.x, nz ? s.x : 0.f), fmaf(two_rho, dx.y, nz ? s.y : 0.f));
+  } else {
+    return mann_v(s, dx, two_rho);
+  }
 }
 
 // Epilogue (a6-a8) from the unnormalised inverse transform z of the spectrum
 // step's output, for probe pixel k.
-//   PMACE : z = F^*(W - 2 rho U), t <- d^{-1} z / Np^2 (dinv table).  Where
-//           d == 0 (dinv == 0) the agent returns its input, w = v, so
-//           t <- (1 - 2 rho) v there (the old state is read only at such
-//           pixels).  No u is written.
+//   PMACE : z = F^*((W - 2 rho U)/Np^2) is the new d t, stored as it is.  Where
+//           d == 0 the agent returns its input, w = v, so the state there is
+//           t <- (1 - 2 rho) v (the old state and xbar are read only at such
+//           pixels, and only for a probe with zeros).  No u is written.
 //   SHARP+: a = z/Np^2 = P_a s; the next state t = (1 - 2 beta) a + beta s -
 //           beta d P_j xbar (P_Q s of this iteration is d P_j xbar of the last
 //           one: P_Q is a projection, so P_Q s_{k+1} = P_Q P_a s_k), and the
@@ -90,10 +101,12 @@ template <int METHOD>
 __device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2* xp, int k,
                                              const Recon& g, float2* u_out) {
   if constexpr (METHOD == kPMACE) {
-    const float2 di = g.dinv[k];
-    float2 tn = cmul(di, z);
-    if (di.x == 0.f && di.y == 0.f) tn = cscale(mann_v(*tp, *xp, g.two_rho), 1.f - g.two_rho);
-    *tp = tn;
+    float2 sn = z;
+    if (g.has_zero) {
+      const float2 dk = g.d[k];
+      if (dk.x == 0.f && dk.y == 0.f) sn = cscale(mann_v(*tp, *xp, g.two_rho), 1.f - g.two_rho);
+    }
+    *tp = sn;
   } else {
     const float4 pcf = g.pc[k];
     const float2 dx = cmul(make_float2(pcf.z, -pcf.w), *xp);
@@ -330,7 +343,8 @@ __global__ void __launch_bounds__(row_threads<NP>()) agent_rowsinv_batch(const R
 // Consensus (eq. (11)) without atomics.  Each thread owns one object pixel
 // of a GT_R x GT_C tile and adds the contributions of the patches that cover
 // it, walking the tile's position list (built on the host, ascending j):
-//   PMACE : |d|^kappa t_j (the sum S of the weighted states),
+//   PMACE : |d|^kappa t_j = (|d|^kappa / d) s_j, |d|^kappa t_j where d == 0 (the
+//           sum S of the weighted states),
 //   SHARP+: the overlap numerators conj(d) P_a s_j left in the stage buffer
 //           (`jbase` = first position held there).
 // Np > 128 chunks run in order on the stream, so every pixel sums its
@@ -391,9 +405,9 @@ __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int 
       const unsigned o = in ? rr * NP + cc : 0u;
       const float2 u = src[(size_t)e.x * NP * NP + o];
       if constexpr (METHOD == kPMACE) {
-        const float w = in ? g.omega[o] : 0.f;
-        ax = fmaf(w, u.x, ax);
-        ay = fmaf(w, u.y, ay);
+        const float2 w = in ? g.gw[o] : make_float2(0.f, 0.f);
+        ax = fmaf(w.x, u.x, fmaf(-w.y, u.y, ax));
+        ay = fmaf(w.x, u.y, fmaf(w.y, u.x, ay));
       } else {
         ax += in ? u.x : 0.f;
         ay += in ? u.y : 0.f;
@@ -772,9 +786,12 @@ __global__ void init_patches_k(const Recon* __restrict__ rec, const float2* x0) 
   const int r = rem / g.np, c = rem - r * g.np;
   const int2 pj = g.pos[j];
   const float2 x = x0 ? x0[(size_t)(pj.x + r) * g.n2 + pj.y + c] : make_float2(1.f, 0.f);
-  // Alg. 1: v_j = P_j x0.  Alg. 2: s_j = D P_j x0, held as t = s - 2 beta d P_j xbar
-  // with xbar = x0 (the overlap image of consistent frames), i.e. (1 - 2 beta) d x0.
-  g.t[i] = g.method == kSharpPlus ? cscale(cmul(g.d[rem], x), 1.f - g.two_rho) : x;
+  // Alg. 1: v_j = P_j x0 (= t, xbar = 0), stored as d t (t where d == 0).
+  // Alg. 2: s_j = D P_j x0, held as t = s - 2 beta d P_j xbar with xbar = x0
+  // (the overlap image of consistent frames), i.e. (1 - 2 beta) d x0.
+  const float2 dd = g.d[rem];
+  if (g.method == kSharpPlus) g.t[i] = cscale(cmul(dd, x), 1.f - g.two_rho);
+  else g.t[i] = (dd.x != 0.f || dd.y != 0.f) ? cmul(dd, x) : x;
 }
 
 // Lambda = sum_j P_j^t omega (eq. (11)) in FP64 over one chunk's tiles, each
@@ -831,12 +848,20 @@ __global__ void get_state_k(const Recon* __restrict__ rec, float2* v) {
   const int r = rem / g.np, c = rem - r * g.np;
   const int2 pj = g.pos[j];
   const float2 xb = g.xbar[(size_t)(pj.x + r) * g.n2 + pj.y + c];
-  // PMACE: v = t + 2 rho P_j xbar;  SHARP+: s = t + 2 beta d P_j xbar
-  v[i] = mann_v(g.t[i], g.method == kSharpPlus ? cmul(g.d[rem], xb) : xb, g.two_rho);
+  // PMACE: v = t + 2 rho P_j xbar with t = d^{-1} s (dinv = d^{-1}/Np^2; s where
+  // d == 0);  SHARP+: s = t + 2 beta d P_j xbar
+  if (g.method == kSharpPlus) {
+    v[i] = mann_v(g.t[i], cmul(g.d[rem], xb), g.two_rho);
+  } else {
+    const float2 di = g.dinv[rem], s = g.t[i];
+    const float2 t = (di.x != 0.f || di.y != 0.f) ? cscale(cmul(di, s), g.np2f) : s;
+    v[i] = mann_v(t, xb, g.two_rho);
+  }
 }
 
-// t <- v for positions [j0, j0 + cnt); SHARP+ also stage <- conj(d) v (the
-// weights of eq. (15), stage indexed from j0).  PMACE's gather weights t itself.
+// t <- v for positions [j0, j0 + cnt), PMACE stored as d v (v where d == 0);
+// SHARP+ also stage <- conj(d) v (the weights of eq. (15), stage indexed from
+// j0).  PMACE's gather weights the stored states themselves.
 __global__ void set_state_k(const Recon* __restrict__ rec, const float2* v, int j0, long long cnt_px) {
   const Recon& g = *rec;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -844,10 +869,13 @@ __global__ void set_state_k(const Recon* __restrict__ rec, const float2* v, int 
   const long long per = (long long)g.np * g.np;
   const long long gi = (long long)j0 * per + i;
   const float2 vv = v[gi];
-  g.t[gi] = vv;
   if (g.method == kSharpPlus) {
+    g.t[gi] = vv;
     const float4 pcf = g.pc[i % per];
     g.stage[i] = cmul(make_float2(pcf.z, pcf.w), vv);
+  } else {
+    const float2 dd = g.d[i % per];
+    g.t[gi] = (dd.x != 0.f || dd.y != 0.f) ? cmul(dd, vv) : vv;
   }
 }
 

@@ -50,8 +50,8 @@ def test_footprint_formula(lib):
     fp = _fp()
     # PMACE, Np <= 128: states 8 B + amplitudes 4 B per patch pixel (no staged
     # patches), object images 36 B per pixel (Lambda^-1, accumulator, S, xbar,
-    # xhat), probe tables 44 B per probe pixel, positions, tile tables
-    lower = J * np_ * np_ * 12 + n * n * 36 + np_ * np_ * 44 + J * 8
+    # xhat), probe tables 48 B per probe pixel, positions, tile tables
+    lower = J * np_ * np_ * 12 + n * n * 36 + np_ * np_ * 48 + J * 8
     # gather tiles are (16 / k) x w pixels with k in {1, 2, 4} and w in {32, 64}
     # (tuned build parameters)
     tiles = (n // 4) * (n // 32)
