@@ -230,7 +230,8 @@ def bench_serve(args):
              for v, a in variants]
     for name in names + ["plain"]:
         reqs = [serve.Request(i, pool[pick[i]], float(arrivals[i])) for i in range(args.requests)]
-        ex = serve.GPUExecutor(alpha=0.5, **rule)
+        v_split = variants[names.index(name)][0] if name != "plain" else 0
+        ex = serve.GPUExecutor(alpha=0.5, split_work=args.large_work if v_split > 0 else None, **rule)
         retire, done_count = ex.retire, [0]
 
         def retire_and_report(rid, _retire=retire, _name=name):

@@ -234,11 +234,18 @@ def run_plain(executor, requests: List[Request], clock, iters_per_step: int = 4,
 
 class GPUExecutor:
     """Executor on the HIP library: one Reconstruction (device-resident state)
-    per active request, re-batched whenever the active set changes."""
+    per active request, re-batched whenever the active set changes.
+
+    split_work: requests with at least this much work per iteration (patch
+    pixels) are stepped in a batch and on a stream of their own, so the churn
+    of small requests (each admission or retirement rebuilds a batch, and a
+    rebuilt batch runs uncaptured for its first steps) leaves the large
+    requests' batch, and its captured graph, alone; the two batches advance
+    concurrently.  None: one batch for everything."""
 
     def __init__(self, alpha: float, kappa: float = 1.25, rho: float = 0.5, tol: float = 1e-4,
                  min_iter: int = 2, max_iter: int = 500, device="cuda", stream=None,
-                 criterion: int = 0, check_every: int = 1):
+                 criterion: int = 0, check_every: int = 1, split_work: Optional[float] = None):
         from . import pmace, synth
         self._pmace = pmace
         self._synth = synth
@@ -246,17 +253,19 @@ class GPUExecutor:
         self.tol, self.min_iter, self.max_iter = tol, min_iter, max_iter
         self.criterion, self.check_every = criterion, check_every
         self.device = device
-        self.stream = stream
+        self.split_work = split_work
         self.active: Dict[int, object] = {}
-        self.order: List[int] = []
-        self.batch = None
-        self.dirty = False
         self._fp_cache: Dict[tuple, int] = {}
         import torch
         self._torch = torch
         # new reconstructions are set up on a side stream, so their host work
-        # and synchronisations overlap the running batch
+        # and synchronisations overlap the running batches
         self.init_stream = torch.cuda.Stream(device=device)
+        streams = [stream, torch.cuda.Stream(device=device) if split_work is not None else stream]
+        # group 0: all requests (or the small ones), group 1: the large ones
+        self.groups = [{"order": [], "batch": None, "dirty": False, "stream": st, "batch_order": []}
+                       for st in streams]
+        self.group_of: Dict[int, int] = {}
 
     def footprint(self, prob) -> int:
         key = (prob.n1, prob.n2, prob.np_, prob.num_pos)
@@ -271,43 +280,59 @@ class GPUExecutor:
 
     def admit(self, req):
         p = req.problem
+        gi = int(self.split_work is not None and self.work(p) >= self.split_work)
+        g = self.groups[gi]
         with self._torch.cuda.stream(self.init_stream):
             R = self._pmace.Reconstruction(p.n1, p.n2, p.probe, p.pos, p.z, self.alpha, self.kappa,
                                            self.rho, device=self.device, stream=self.init_stream)
             R.set_reference(p.x_true, self._synth.roi_mask(p.probe, p.pos, p.n1, p.n2))
-        R.set_stream(self.stream)
+        R.set_stream(g["stream"])
         self.active[req.rid] = R
-        self.order.append(req.rid)
-        self.dirty = True            # joins the batch at the next step
+        self.group_of[req.rid] = gi
+        g["order"].append(req.rid)
+        g["dirty"] = True            # joins its group's batch at the next step
 
-    def _drop_batch(self):
-        if self.batch is not None:
-            self.batch.close()
-            self.batch = None
+    @staticmethod
+    def _drop(g):
+        if g["batch"] is not None:
+            g["batch"].close()
+            g["batch"] = None
 
     def step(self, n: int):
-        if self.dirty:
-            self._drop_batch()
-            self.dirty = False
-        if self.batch is None:      # membership changed since the last step
-            self.batch_order = list(self.order)
-            self.batch = self._pmace.Batch([self.active[r] for r in self.order], tol=self.tol,
-                                           min_iter=self.min_iter, max_iter=self.max_iter,
-                                           criterion=self.criterion, check_every=self.check_every)
-        self.batch.step(n)
+        for g in reversed(self.groups):      # the large requests' batch is launched first
+            if g["dirty"]:
+                self._drop(g)
+                g["dirty"] = False
+            if not g["order"]:
+                continue
+            if g["batch"] is None:           # membership changed since the last step
+                g["batch_order"] = list(g["order"])
+                g["batch"] = self._pmace.Batch([self.active[r] for r in g["order"]], tol=self.tol,
+                                               min_iter=self.min_iter, max_iter=self.max_iter,
+                                               criterion=self.criterion, check_every=self.check_every)
+            g["batch"].step(n)
+            if self.split_work is None:
+                break
 
     def poll(self):
-        if self.batch is None:
-            return {}
-        done, nr, it = self.batch.poll()
-        # members admitted since the last step are not in the batch yet
-        return {rid: (bool(done[i]), float(nr[i]), int(it[i]))
-                for i, rid in enumerate(self.batch_order)}
+        out = {}
+        for g in self.groups:
+            if g["batch"] is None:
+                continue
+            done, nr, it = g["batch"].poll()
+            # members admitted since the last step are not in the batch yet
+            out.update({rid: (bool(done[i]), float(nr[i]), int(it[i]))
+                        for i, rid in enumerate(g["batch_order"])})
+            if self.split_work is None:
+                break
+        return out
 
     def retire(self, rid):
         R = self.active.pop(rid)
-        x = R.reconstruct().cpu().numpy()
-        self._drop_batch()           # the batch reads R's descriptor: release it first
-        self.order.remove(rid)
+        g = self.groups[self.group_of.pop(rid)]
+        with self._torch.cuda.stream(g["stream"]):   # the copy follows R's own work
+            x = R.reconstruct().cpu().numpy()
+        self._drop(g)                # the batch reads R's descriptor: release it first
+        g["order"].remove(rid)
         R.close()
         return x
