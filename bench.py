@@ -112,7 +112,7 @@ def cpu_baseline(prob, alpha, kappa, rho, min_seconds=12.0, max_iters=6):
             break
     return {"value": k * prob.num_pos / dt, "unit": "patch-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{k} iterations of the full workload ({prob.num_pos} positions each), "
-                      f"{dt:.1f} s, numpy FFT (single thread)"}
+                      f"{dt:.2f} s, numpy FFT (single thread)"}
 
 
 def _mix_problems(count, seed=4, device="cuda"):
