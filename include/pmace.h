@@ -112,7 +112,10 @@ pmace_status pmace_reconstruct(pmace_ctx* ctx, void* xhat_d);
 
 /* Copy the stacked agent states v (num_pos*np*np c64, device) out / in.
  * set_state also recomputes the reconstruction as the weighted average of
- * the new v (checkpoint resume; one-step parity checks). */
+ * the new v (checkpoint resume; one-step parity checks).  PMACE keeps each
+ * state multiplied by the probe (as it is where d == 0); get_state divides by
+ * d again, so v there carries the conditioning of d^{-1}, as the agent's own
+ * output does (eq. (9)). */
 pmace_status pmace_get_state(pmace_ctx* ctx, void* v_d);
 pmace_status pmace_set_state(pmace_ctx* ctx, const void* v_d);
 
