@@ -66,6 +66,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
                            "(the PMACE path has no CPU fallback)")
+    # The device memory and streams passed in come from PyTorch's HIP runtime,
+    # which PyTorch ships as its own libamdhip64.  Loaded first, it is the one
+    # the library's HIP dependency binds to; loaded after the library, the
+    # process holds two HIP runtimes and the library rejects PyTorch's pointers.
+    _torch()
     L = ctypes.CDLL(path)
     vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
     P = ctypes.POINTER(pmace_params)

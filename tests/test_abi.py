@@ -120,3 +120,17 @@ def test_method_parameters_checked(lib, method, beta):
     assert st == P.PMACE_EINVAL
     ok = P.make_params(128, 128, 32, 36, 0.5, method=P.PMACE_METHOD_SHARP_PLUS, beta=0.75)
     assert P.pmace_footprint(ok) > 0
+
+
+def test_binding_shares_pytorch_hip_runtime():
+    """Loading the library through the binding in a fresh process, before
+    anything else imported PyTorch, maps one HIP runtime: the one PyTorch's
+    device pointers belong to."""
+    import subprocess
+    import sys
+    code = ("from paper_2111_14240_amd import pmace; pmace.load_library(); "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
