@@ -193,7 +193,11 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
 /* n_iter iterations of every member still running (stream-ordered, async). */
 pmace_status pmace_batch_step(pmace_batch* batch, int32_t n_iter);
 /* Synchronise and read back per member: stop flag, last NRMSE, iterations
- * counted by the stop rule.  Host arrays of n entries; any may be NULL. */
+ * counted by the stop rule.  Host arrays of n entries; any may be NULL.
+ * Np > 128 members found stopped are left out of the batch's later launches
+ * (the graphs are captured again on the next step); a member whose stop flag
+ * the host clears (pmace_iterate, pmace_set_reference) is launched again from
+ * the next pmace_batch_step on.  Results are the same either way. */
 pmace_status pmace_batch_poll(pmace_batch* batch, int32_t* done, double* nrmse, int32_t* iters);
 /* As pmace_batch_poll, plus the last data-fit cost the stop rule evaluated
  * (infinity before the first evaluation). */

@@ -63,6 +63,7 @@ struct pmace_ctx {
   Graph graph_k;                  // kGraphIters iterations back to back
   bool graph_tried;
   pmace_status sticky;            // first asynchronous failure seen
+  unsigned long long resets;      // times the host cleared the stop flag
 };
 
 struct pmace_batch {
@@ -85,6 +86,12 @@ struct pmace_batch {
   bool graph_tried;
   long long iters;             // iterations launched by this batch
   int step_calls;              // pmace_batch_step calls so far
+  // Np > 128 members a poll found stopped: their kernel chains are left out
+  // of the launches (they would only read the flag and exit), until the host
+  // clears the member's flag (pmace_iterate, pmace_set_reference), seen as a
+  // change of its reset count from the one recorded here.
+  std::vector<char> pruned;
+  std::vector<unsigned long long> pruned_at;
 };
 
 namespace {
@@ -384,6 +391,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   c->stream = st;
   c->sticky = PMACE_OK;
   c->graph_tried = false;
+  c->resets = 0;
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return PMACE_EDEVICE; }
 
   const Layout L = layout_of(p);
@@ -503,6 +511,7 @@ pmace_status pmace_iterate(pmace_ctx* c, int32_t n_iter) {
   if (n_iter == 0) return PMACE_OK;
   // a stop flag left by a batch would make the kernels skip this reconstruction
   if (hipMemsetAsync(c->h.done, 0, 4, c->stream) != hipSuccess) return record(c, PMACE_EDEVICE);
+  ++c->resets;
   // One graph replays one iteration; a second replays kGraphIters of them in
   // a row, so long runs pay one launch per kGraphIters iterations.
   constexpr int kGraphIters = 8;
@@ -566,6 +575,7 @@ pmace_status pmace_set_reference(pmace_ctx* c, const void* xref_d, const uint8_t
   if (hipMemcpyAsync(c->dev, &c->h, sizeof(Recon), hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return record(c, PMACE_EDEVICE);
   hipLaunchKernelGGL(reset_tracking_k, dim3(1), dim3(1), 0, c->stream, c->h.done, c->h.track);
+  ++c->resets;
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
     return record(c, PMACE_EDEVICE);
   return PMACE_OK;
@@ -691,7 +701,7 @@ pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes,
   // they fork before the merged launches of the smaller members, so both run
   // at once (the small ones are latency-bound and leave most CUs free)
   bool any_large = false;
-  for (int i = 0; i < b->n; ++i) any_large = any_large || np_large(b->ctxs[i]->prm.np);
+  for (int i = 0; i < b->n; ++i) any_large = any_large || (np_large(b->ctxs[i]->prm.np) && !b->pruned[i]);
   const bool forked = lanes && any_large;
   if (forked) {
     PM_HIP(hipEventRecord(b->fork, st));
@@ -704,7 +714,7 @@ pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes,
   int lane = 0;
   for (int i = 0; i < b->n; ++i) {
     pmace_ctx* c = b->ctxs[i];
-    if (!np_large(c->prm.np)) continue;
+    if (!np_large(c->prm.np) || b->pruned[i]) continue;
     hipStream_t ls = st;
     if (forked) {
       ls = b->lanes[lane];
@@ -725,11 +735,22 @@ pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes,
     for (int k = 0; k < kClasses; ++k)
       PM_HIP(pmace::launch_fit_batch(kSmallNp[k], b->recs, b->items[k], b->nitems[k], st));
     for (int i = 0; i < b->n; ++i)
-      if (np_large(b->ctxs[i]->prm.np))
+      if (np_large(b->ctxs[i]->prm.np) && !b->pruned[i])
         PM_HIP(pmace::launch_fit_member(b->ctxs[i]->h, b->recs + i, 1, st));
     PM_HIP(pmace::launch_fit_finish(b->recs, b->fitems, b->n, 1, b->rule.tol, b->rule.min_iter, st));
   }
   PM_HIP(pmace::launch_tick(b->recs, b->fitems, b->n, b->rule.max_iter, 1, st));
+  return PMACE_OK;
+}
+
+// The launches of the batch changed: the captured graphs are destroyed once
+// the launches of them in flight have finished, and captured again on the next
+// step.
+pmace_status drop_graphs(pmace_batch* b) {
+  if (hipStreamSynchronize(b->stream) != hipSuccess) return PMACE_EDEVICE;
+  b->graph.release();
+  b->graph_check.release();
+  b->graph_tried = false;
   return PMACE_OK;
 }
 
@@ -775,6 +796,8 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
   b->graph_tried = false;
   b->iters = 0;
   b->step_calls = 0;
+  b->pruned.assign(n, 0);
+  b->pruned_at.assign(n, 0);
   char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(workspace_d)));
   b->recs = reinterpret_cast<Recon*>(base + L.recs);
   std::vector<Recon> recs(n);
@@ -836,6 +859,14 @@ pmace_status pmace_batch_step(pmace_batch* b, int32_t n_iter) {
   if (!b) return PMACE_ESTATE;
   if (n_iter < 0) return PMACE_EINVAL;
   const int every = b->rule.check_every;
+  // a pruned member whose stop flag the host has cleared runs again
+  bool changed = false;
+  for (int i = 0; i < b->n; ++i)
+    if (b->pruned[i] && b->ctxs[i]->resets != b->pruned_at[i]) {
+      b->pruned[i] = 0;
+      changed = true;
+    }
+  if (changed && drop_graphs(b) != PMACE_OK) return PMACE_EDEVICE;
   // A batch whose membership changes often (a serving loop rebuilds it on
   // every admission and retirement) would spend more host time capturing and
   // instantiating graphs than it saves, so the first kCaptureAfter calls
@@ -875,6 +906,14 @@ pmace_status pmace_batch_poll_fit(pmace_batch* b, int32_t* done, double* nrmse, 
       return PMACE_EDEVICE;
   }
   if (hipStreamSynchronize(b->stream) != hipSuccess) return PMACE_EDEVICE;
+  bool changed = false;
+  for (int i = 0; i < b->n; ++i)
+    if (dn[i] && np_large(b->ctxs[i]->prm.np) && !b->pruned[i]) {
+      b->pruned[i] = 1;
+      b->pruned_at[i] = b->ctxs[i]->resets;
+      changed = true;
+    }
+  if (changed && drop_graphs(b) != PMACE_OK) return PMACE_EDEVICE;
   for (int i = 0; i < b->n; ++i) {
     if (done) done[i] = dn[i];
     if (nrmse) nrmse[i] = tr[8 * i + 1];

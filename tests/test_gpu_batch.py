@@ -138,6 +138,42 @@ def test_batch_stop_rule(P):
         R.close()
 
 
+def test_stopped_large_member_restarts_when_cleared(P):
+    """A poll that finds an Np > 128 member stopped leaves its kernels out of
+    the batch's later launches; clearing its flag on the host (pmace_iterate,
+    pmace_set_reference) puts it back, inside the captured graph too.  The
+    member's history is then 4 batched iterations, 2 alone and the batch's
+    iterations up to the rule again: it must equal the same count alone."""
+    cases = [(400, 256, 3, 60, 1e6, 23, 4), (400, 192, 2, 100, 1e5, 26, 3), (128, 32, 6, 16, None, 1, 0)]
+    probs = [synth.make_problem(n, np_, sc, st, pk, sd) for (n, np_, sc, st, pk, sd, _) in cases]
+    Rs = [_recon(P, prob, c[-1]) for prob, c in zip(probs, cases)]
+    B = P.Batch(Rs, tol=0.0, min_iter=0, max_iter=4)
+    for k in (2, 1, 1):       # the third call runs the captured graph
+        B.step(k)
+    done, _, iters = B.poll()
+    assert done.tolist() == [1, 1, 1] and iters.tolist() == [4, 4, 4]
+    _say("cleared member: 4 batched, 2 alone, then the batch again")
+    Rs[0].iterate(2)
+    B.step(3)                 # one more iteration for member 0 (5 counted >= 4), none for the others
+    done, _, iters = B.poll()
+    assert done.tolist() == [1, 1, 1] and iters.tolist() == [5, 4, 4]
+    Rs[1].set_reference(None)  # counts from zero again: four more batched iterations
+    B.step(2)
+    B.step(3)
+    done, _, iters = B.poll()
+    assert done.tolist() == [1, 1, 1] and iters.tolist() == [5, 4, 4]
+    for R, prob, c, total in zip(Rs, probs, cases, (7, 8, 4)):
+        A = _recon(P, prob, c[-1])
+        A.iterate(total)
+        same = (np.array_equal(R.get_state().cpu().numpy(), A.get_state().cpu().numpy()) and
+                np.array_equal(R.reconstruct().cpu().numpy(), A.reconstruct().cpu().numpy()))
+        assert same, (c, total)
+        A.close()
+    B.close()
+    for R in Rs:
+        R.close()
+
+
 FIT_CASES = [  # (n, np, scan, step, peak, seed, chunk)
     (128, 32, 6, 16, 1e5, 41, 0),
     (200, 64, 5, 30, 1e5, 42, 0),
