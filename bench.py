@@ -5,6 +5,9 @@ the workload (agent F_j on all patches, consensus G, Mann update, image
 recurrence), with all inputs resident in HBM.  Prints one JSON line.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c3]
+  python bench.py --method sharp [--beta 0.8]      SHARP+ (Alg. 2) on the same workload
+  python bench.py --np 192                         the workload with another probe side
+  python bench.py --mode simulate                  the device measurement simulator (eq. (1), (16))
   python bench.py --mode batch [--items 64]        mixed-size batch vs plain, same stop rule
   python bench.py --mode serve [--requests 2000]   continuous batching vs plain FIFO
 """
@@ -32,7 +35,8 @@ ALPHA = {"c1": 0.1, "c2": 0.5, "c3": 0.5}
 def algorithmic_bytes(J, np_, n1, n2):
     """Per iteration: read state 8 B + amplitudes 4 B, write state 8 B per
     patch pixel; read numerator 8 B + Lambda^{-1} 4 B, write xbar 8 B per
-    object pixel."""
+    object pixel.  SHARP+ (Alg. 2) is counted the same way: its state is the
+    frame s_j, and the overlap projection's sums are object-sized."""
     return 20.0 * J * np_ * np_ + 20.0 * n1 * n2
 
 
@@ -53,13 +57,25 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def iteration_kernels(np_, J):
+def iteration_kernels(np_, J, method="pmace"):
     """The kernels one timed iteration (the roofline's unit) launches."""
+    name = "PMACE" if method == "pmace" else "SHARP+"
     if np_ <= 128:
-        return (f"one PMACE iteration: agent_fused<{np_}> ({J} workgroups) + "
+        return (f"one {name} iteration: agent_fused<{np_}> ({J} workgroups) + "
                 f"consensus_gather<{np_}> (a9 fused)")
-    return (f"one PMACE iteration: per chunk of positions agent_rows, agent_cols, "
+    return (f"one {name} iteration: per chunk of positions agent_rows, agent_cols, "
             f"agent_rowsinv <{np_}> + consensus_gather<{np_}>, then image_update")
+
+
+def workload_key(config, method, np_override):
+    """Row name of a workload in the traffic table: the config, then the
+    variant ('c3', 'c3-sharp', 'c3-np192')."""
+    key = config
+    if method != "pmace":
+        key += "-" + method
+    if np_override:
+        key += f"-np{np_override}"
+    return key
 
 
 def measured_traffic(config):
@@ -95,17 +111,23 @@ def calibration_copy(mib):
     torch.cuda.synchronize()
 
 
-def cpu_baseline(prob, alpha, kappa, rho, min_seconds=12.0, max_iters=6):
+def cpu_baseline(prob, alpha, kappa, rho, min_seconds=12.0, max_iters=6, method="pmace", beta=0.0):
     """The FP64 oracle, as it stands, timed on whole iterations of the same
     workload until at least min_seconds have passed (at most max_iters)."""
     from oracle import pmace_oracle as O
     d = prob.probe.astype(np.complex64).astype(np.complex128)
     y = O.amplitudes(prob.z)
     shape = (prob.n1, prob.n2)
-    st = O.pmace_init(np.ones(shape, complex), prob.pos, prob.np_)
+    x0 = np.ones(shape, complex)
+    if method == "pmace":
+        st = O.pmace_init(x0, prob.pos, prob.np_)
+        step = lambda st: O.pmace_iterate(st, d, y, prob.pos, shape, alpha, kappa, rho, 1)
+    else:
+        st = O.sharp_plus_init(x0, d, prob.pos)
+        step = lambda st: O.sharp_plus_step(st, d, y, prob.pos, shape, beta)
     k, t0 = 0, time.perf_counter()
     while True:
-        st = O.pmace_iterate(st, d, y, prob.pos, shape, alpha, kappa, rho, 1)
+        st = step(st)
         k += 1
         dt = time.perf_counter() - t0
         if dt >= min_seconds or k >= max_iters:
@@ -217,6 +239,88 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def simulate_cpu_baseline(x, d, pos, peak, seed, min_seconds=10.0):
+    """The oracle's simulator (forward model, Philox4x32-10, Poisson draws in
+    plain Python) on the first k frames of the workload, k sized from one
+    timed frame so the sample takes about min_seconds; the photon scale of
+    eq. (16) is taken over the sample."""
+    from oracle import simulate_oracle as SO
+    t0 = time.perf_counter()
+    SO.simulate(x, d, pos[:1], peak, seed)
+    one = time.perf_counter() - t0
+    k = int(min(len(pos), max(1, np.ceil(min_seconds / max(one, 1e-9)))))
+    t0 = time.perf_counter()
+    SO.simulate(x, d, pos[:k], peak, seed)
+    dt = time.perf_counter() - t0
+    return {"value": k / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {k} frames of the workload ({d.shape[0]}x{d.shape[0]}), {dt:.2f} s, "
+                      "numpy FFT, Poisson draws in plain Python (single thread)"}
+
+
+def bench_simulate(args):
+    """The measurement simulator of eq. (1) and eq. (16) on the workload's
+    geometry: frames d P_j x, 2-D DFTs, intensities and their maximum, Poisson
+    draws.  One step = one pmace_simulate call over every position (it
+    synchronises twice: positions are checked on the host, the photon scale is
+    read back)."""
+    import torch
+    from paper_2111_14240_amd import pmace, synth
+    cfg = dict(synth.CONFIGS[args.config])
+    if args.np:
+        cfg["np_"] = args.np
+    peak = cfg["peak"] or 1e5
+    rng = np.random.default_rng(cfg["seed"])
+    n, np_ = cfg["n"], cfg["np_"]
+    x = synth.make_object(n, n, rng)
+    d = synth.make_probe(np_)
+    pos = synth.make_positions(n, np_, cfg["scan"], cfg["step"], rng)
+    J = len(pos)
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    x_t = pmace.to_device_c64(x, dev)
+    d_t = pmace.to_device_c64(d, dev)
+    pos_t = torch.as_tensor(pos, dtype=torch.int32).to(dev)
+    z = torch.empty((J, np_, np_), dtype=torch.float32, device=dev)
+    ws = torch.empty(int(pmace.load_library().pmace_simulate_footprint(np_, J)), dtype=torch.uint8,
+                     device=dev)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        for i in range(args.warmup):
+            pmace.simulate(x_t, d_t, pos_t, peak, 1000 + i, device=dev, stream=stream, out=z, workspace=ws)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(stream)
+        for i in range(args.steps):
+            _, scale = pmace.simulate(x_t, d_t, pos_t, peak, 2000 + i, device=dev, stream=stream, out=z,
+                                      workspace=ws)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gpu_ms = ev0.elapsed_time(ev1)
+    ms = gpu_ms / args.steps
+    # algorithmic bytes: the object and probe read once, the counts written once
+    B = 8.0 * n * n + 8.0 * np_ * np_ + 4.0 * J * np_ * np_
+    achieved = B / (ms / 1e3) / 1e9
+    zs = z.float().sum().item()
+    out = {
+        "metric": "simulated frames/s", "value": J / (ms / 1e3), "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (Poisson draws in f64)",
+        "data": "synthetic",
+        "config": {"workload": f"simulate {args.config}: object {n}x{n}, probe {np_}x{np_}, {J} positions, "
+                               f"Poisson peak {peak:g}"},
+        "roofline": {"bound": "hbm", "kernel": "pmace_simulate: frames_k, fft2 passes, intensity_k, poisson_k",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "algorithmic_bytes_per_step": B},
+        "wall_s": wall, "photon_scale": scale, "mean_count": zs / z.numel(),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = simulate_cpu_baseline(x, d, pos, peak, 7)
+    print(json.dumps(out), flush=True)
+
+
 def bench_serve(args):
     """Poisson arrivals of requests drawn from the mixed-size pool: the
     continuous-batching server against the plain FIFO solver."""
@@ -284,11 +388,16 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--method", default="pmace", choices=["pmace", "sharp"],
+                    help="plain mode: PMACE (Alg. 1) or SHARP+ (Alg. 2) on the same workload")
+    ap.add_argument("--beta", type=float, default=0.8, help="SHARP+ relaxation (the paper grid-searches it)")
+    ap.add_argument("--np", type=int, default=0,
+                    help="plain mode: probe side other than the config's (same object, raster and step)")
     ap.add_argument("--chunk", type=int, default=0, help="Np > 128: at most this many positions per staging chunk (0 = tuned default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB three times (counter calibration)")
-    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve"])
+    ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "simulate"])
     ap.add_argument("--items", type=int, default=64, help="batch mode: reconstructions")
     ap.add_argument("--requests", type=int, default=2000, help="serve mode: requests")
     ap.add_argument("--rate", type=float, default=20.0, help="serve mode: arrivals per second")
@@ -316,18 +425,28 @@ def main():
         return bench_batch(args)
     if args.mode == "serve":
         return bench_serve(args)
+    if args.mode == "simulate":
+        return bench_simulate(args)
 
     import torch
     from paper_2111_14240_amd import pmace, synth
 
-    cfg = synth.CONFIGS[args.config]
-    prob = synth.make_config_problem(args.config)
+    cfg = dict(synth.CONFIGS[args.config])
+    if args.np:
+        cfg["np_"] = args.np
+        prob = synth.make_problem(cfg["n"], cfg["np_"], cfg["scan"], cfg["step"], cfg["peak"], cfg["seed"],
+                                  name=f"{args.config}-np{args.np}")
+    else:
+        prob = synth.make_config_problem(args.config)
     alpha, kappa, rho = ALPHA[args.config], synth.KAPPA, synth.RHO
+    sharp = args.method == "sharp"
+    mkw = dict(method=pmace.PMACE_METHOD_SHARP_PLUS, beta=args.beta) if sharp else {}
+    key = workload_key(args.config, args.method, args.np)
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):
         R = pmace.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, alpha, kappa, rho,
-                                 device=dev, stream=stream, chunk=args.chunk)
+                                 device=dev, stream=stream, chunk=args.chunk, **mkw)
         R.iterate(args.warmup)
         R.sync()
         torch.cuda.synchronize()
@@ -355,7 +474,7 @@ def main():
     nrmse = float(np.linalg.norm(a - np.exp(1j * np.angle(c)) * b) / np.linalg.norm(b))
 
     out = {
-        "metric": "PMACE patch-updates/s",
+        "metric": ("SHARP+" if sharp else "PMACE") + " patch-updates/s",
         "value": value,
         "unit": "patch-updates/s",
         "n_gpus": 1,
@@ -367,14 +486,16 @@ def main():
         "vs_baseline": None,
         "dtype": "c64",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: object {prob.n1}x{prob.n2}, probe {np_}x{np_}, "
+        "config": {"workload": f"{key}: object {prob.n1}x{prob.n2}, probe {np_}x{np_}, "
                                f"{J} positions ({cfg['scan']}x{cfg['scan']} raster, step {cfg['step']} px), "
                                f"Poisson peak {cfg['peak']}",
-                   "alpha": alpha, "kappa": kappa, "rho": rho, "chunk": args.chunk,
+                   "method": "SHARP+ (Alg. 2)" if sharp else "PMACE (Alg. 1)",
+                   **({"beta": args.beta} if sharp else {"alpha": alpha, "kappa": kappa, "rho": rho}),
+                   "chunk": args.chunk,
                    "iteration_graph": "HIP graphs of 8 iterations (single-iteration graph for the rest)"},
-        "roofline": {"bound": "hbm", "kernel": iteration_kernels(np_, J),
+        "roofline": {"bound": "hbm", "kernel": iteration_kernels(np_, J, args.method),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(args.config),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(key),
                      "algorithmic_bytes_per_step": B},
         "alu": {"algorithmic_flops_per_step": Fl,
                 "achieved_tflops": Fl / (ms_per_step / 1e3) / 1e12,
@@ -383,7 +504,7 @@ def main():
         "nrmse_after_run": nrmse,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(prob, alpha, kappa, rho)
+        out["cpu_baseline"] = cpu_baseline(prob, alpha, kappa, rho, method=args.method, beta=args.beta)
     if args.copy_mib:
         calibration_copy(args.copy_mib)
     print(json.dumps(out), flush=True)

@@ -13,6 +13,7 @@
 // Insurance: Mathematics and Economics 12, 1993) from mean 10 up.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -109,18 +110,29 @@ __global__ void frames_k(const float2* __restrict__ d, const int2* __restrict__ 
 }
 
 // I = |F D P_j x|^2, and the running maximum (non-negative floats order as
-// their bit patterns, so an unsigned max is a float max)
-__global__ void intensity_k(const float2* __restrict__ spec, float* __restrict__ z,
-                           unsigned* __restrict__ maxbits, long long total) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+// their bit patterns, so an unsigned max is a float max).  Grid-stride over
+// the elements; each workgroup folds its maximum into one atomic (one atomic
+// per wave on one address serialised into most of the simulator's time).
+constexpr int kIntensityThreads = 256;
+__global__ void __launch_bounds__(kIntensityThreads)
+intensity_k(const float2* __restrict__ spec, float* __restrict__ z, unsigned* __restrict__ maxbits,
+            long long total) {
+  __shared__ float wmax[kIntensityThreads / 64];
   float v = 0.f;
-  if (i < total) {
+  for (long long i = (long long)blockIdx.x * kIntensityThreads + threadIdx.x; i < total;
+       i += (long long)gridDim.x * kIntensityThreads) {
     const float2 s = spec[i];
-    v = fmaf(s.x, s.x, s.y * s.y);
-    z[i] = v;
+    const float e = fmaf(s.x, s.x, s.y * s.y);
+    z[i] = e;
+    v = fmaxf(v, e);
   }
   for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
-  if ((threadIdx.x & 63) == 0) atomicMax(maxbits, __float_as_uint(v));
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kIntensityThreads / 64; ++w) v = fmaxf(v, wmax[w]);
+    atomicMax(maxbits, __float_as_uint(v));
+  }
 }
 
 __global__ void poisson_k(float* __restrict__ z, const unsigned* __restrict__ maxbits, double peak,
@@ -203,7 +215,9 @@ pmace_status pmace_simulate(int32_t n1, int32_t n2, int32_t np, int32_t num_pos,
   if (hipGetLastError() != hipSuccess ||
       pmace::launch_fft2(np, num_pos, fr, fr, 0, st) != hipSuccess)
     return PMACE_EDEVICE;
-  hipLaunchKernelGGL(pmace::intensity_k, dim3(nblocks(total, 256)), dim3(256), 0, st, fr, z_d,
+  // a few workgroups per CU, each striding over the elements
+  const unsigned iblocks = (unsigned)std::min<long long>(nblocks(total, pmace::kIntensityThreads), 2048);
+  hipLaunchKernelGGL(pmace::intensity_k, dim3(iblocks), dim3(pmace::kIntensityThreads), 0, st, fr, z_d,
                      maxbits, total);
   if (peak_photons > 0.0)
     hipLaunchKernelGGL(pmace::poisson_k, dim3(nblocks(total, 256)), dim3(256), 0, st, z_d, maxbits,

@@ -287,27 +287,41 @@ def fft2(x, inverse: bool = False, stream=None):
     return out
 
 
-def simulate(x, probe, pos, peak, seed: int, device="cuda", stream=None):
+def simulate(x, probe, pos, peak, seed: int, device="cuda", stream=None, out=None, workspace=None):
     """Intensities |F D P_j x|^2 (eq. (1)) on the device, Poisson at peak rate
     `peak` with the global-max scaling of eq. (16) when peak > 0.
-    Returns (z float32 CUDA tensor (J, Np, Np), scale = peak / max I)."""
+    Returns (z float32 CUDA tensor (J, Np, Np), scale = peak / max I).
+    `out` (float32, (J, Np, Np), contiguous) and `workspace` (uint8, at least
+    pmace_simulate_footprint bytes) are used instead of new allocations."""
     torch = _torch()
     dev = torch.device(device)
     x_t = to_device_c64(x, dev)
     d_t = to_device_c64(probe, dev)
-    pos_t = torch.as_tensor(np.asarray(pos, dtype=np.int32)).to(dev).contiguous()
+    pos_t = (pos if isinstance(pos, torch.Tensor) and pos.dtype == torch.int32
+             else torch.as_tensor(np.asarray(pos, dtype=np.int32))).to(dev).contiguous()
     n1, n2 = x_t.shape
     np_ = d_t.shape[-1]
     J = pos_t.shape[0]
-    z = torch.empty((J, np_, np_), dtype=torch.float32, device=dev)
     fp = int(load_library().pmace_simulate_footprint(np_, J))
-    ws = torch.empty(fp, dtype=torch.uint8, device=dev)
+    if out is None:
+        z = torch.empty((J, np_, np_), dtype=torch.float32, device=dev)
+    else:
+        if (out.dtype != torch.float32 or tuple(out.shape) != (J, np_, np_) or not out.is_contiguous()
+                or out.device != dev):
+            raise ValueError(f"out must be a contiguous float32 ({J},{np_},{np_}) tensor on {dev}")
+        z = out
+    if workspace is None:
+        ws = torch.empty(fp, dtype=torch.uint8, device=dev)
+    else:
+        if workspace.dtype != torch.uint8 or workspace.numel() < fp or workspace.device != dev:
+            raise ValueError(f"workspace must be a uint8 tensor of at least {fp} bytes on {dev}")
+        ws = workspace
     scale = ctypes.c_double()
     _check(load_library().pmace_simulate(n1, n2, np_, J, ctypes.c_void_p(d_t.data_ptr()),
                                          ctypes.c_void_p(pos_t.data_ptr()),
                                          ctypes.c_void_p(x_t.data_ptr()), float(peak or 0.0),
                                          int(seed), ctypes.c_void_p(z.data_ptr()),
-                                         ctypes.c_void_p(ws.data_ptr()), fp, ctypes.byref(scale),
+                                         ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(scale),
                                          _stream_ptr(stream)), "pmace_simulate")
     return z, scale.value
 

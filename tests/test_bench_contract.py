@@ -45,3 +45,29 @@ def test_bench_line_has_the_contract_fields():
     assert "traffic" in rl
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("args,metric", [
+    (["--config", "c1", "--method", "sharp", "--steps", "4", "--warmup", "1"], "SHARP+ patch-updates/s"),
+    (["--config", "c1", "--np", "48", "--steps", "4", "--warmup", "1"], "PMACE patch-updates/s"),
+    (["--mode", "simulate", "--config", "c1", "--steps", "3", "--warmup", "1"], "simulated frames/s"),
+])
+def test_variant_lines(args, metric):
+    """SHARP+, another probe side and the simulator print the same kind of
+    line, each with its roofline and the oracle's baseline."""
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    print("[bench-contract]", " ".join(args), flush=True)
+    r = _run(args)
+    assert r.returncode == 0, r.stderr[-2000:]
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    assert len(lines) == 1
+    d = json.loads(lines[0])
+    assert d["metric"] == metric and d["value"] > 0 and d["n_gpus"] == 1
+    rl = d["roofline"]
+    assert rl["bound"] == "hbm" and abs(rl["frac"] - rl["achieved"] / rl["peak"]) < 1e-12
+    assert d["cpu_baseline"]["kind"] == "oracle" and d["cpu_baseline"]["value"] > 0
+    if "--np" in args:
+        assert "probe 48x48" in d["config"]["workload"]
