@@ -215,6 +215,17 @@ template <> struct Geo<160> { static constexpr int A = 4,  B = 40; };
 template <> struct Geo<192> { static constexpr int A = 8,  B = 24; };
 template <> struct Geo<256> { static constexpr int A = 16, B = 16; };
 
+// Exchange phases H: the LDS exchange of a line transform moves its B/A
+// groups of second-stage inputs in H rounds of B/(H A) groups each, so a
+// line needs LDS for N/H points (+ skew) instead of N.  Np = 160 splits only
+// as 4 threads x 40 points, and two rounds halve the 320 B of LDS each
+// thread would otherwise hold; every other side exchanges in one round.
+template <int N> constexpr int exch_phases() { return N == 160 ? 2 : 1; }
+// LDS a row-direction line occupies (float2), and the rows a column tile
+// needs, with the phases above.
+template <int N> constexpr int row_cap() { return N / exch_phases<N>() + Geo<N>::A; }
+template <int N> constexpr int col_rows() { return N / exch_phases<N>(); }
+
 // W_N^m = exp(-2 pi i m / N), m = 0..N-1, into LDS from the reconstruction's
 // table (computed in FP64 on the host and rounded once).
 template <int N> __device__ __forceinline__ void load_twiddles(float2* tw, const float2* twn, int tid,
@@ -235,7 +246,8 @@ template <int N> __device__ __forceinline__ void fill_twiddles(float2* tw, int t
 // ---------------------------------------------------------------------------
 // Row-direction line FFT.  Thread (r, p), p in [0, A), owns row r of a tile
 // whose rows start at row_base (float2 units) with the row exchanged through
-// a skewed layout  n_a*(B+1) + k_b  (row capacity N + A float2).
+// a skewed layout  n_a*(B/H+1) + k_b  (row capacity row_cap<N>() float2),
+// one round per exchange phase.
 // The A threads of a row are consecutive lanes of one wavefront (A divides
 // 64), and only they touch the row's LDS, so the exchange is ordered within
 // the wave: a wave's LDS operations execute in order, and wave_sync keeps the
@@ -250,26 +262,33 @@ __device__ __forceinline__ void wave_sync() {
 
 // in : x[n_b] = row[p + A n_b]
 // out: x[m*A + k_a] = X[(p + A m) + B k_a]
+// Round h moves k_b in [h B/H, (h+1) B/H): the groups m in [h M/H, (h+1) M/H)
+// read exactly those (k_b = p + A m), and their outputs land in x[m A + k_a],
+// the same register range the round has just written out.
 template <int N> __device__ __forceinline__ void row_fwd(float2 (&x)[Geo<N>::B], float2* row, int p,
                                                          const float2* tw) {
-  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A;
+  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A, H = exch_phases<N>(), BH = B / H, MH = M / H;
   static_assert(64 % A == 0, "a row's threads must share a wavefront");
+  static_assert(M % H == 0, "exchange phases must split the groups evenly");
   dft<B, false>(x);
 #pragma unroll
   for (int kb = 1; kb < B; ++kb) x[kb] = cmul(x[kb], tw[p * kb]);
-  wave_sync();
 #pragma unroll
-  for (int kb = 0; kb < B; ++kb) row[p * (B + 1) + kb] = x[kb];
-  wave_sync();
+  for (int h = 0; h < H; ++h) {
+    wave_sync();
 #pragma unroll
-  for (int m = 0; m < M; ++m) {
-    const int kb = p + A * m;
-    float2 g[A];
+    for (int kb = 0; kb < BH; ++kb) row[p * (BH + 1) + kb] = x[h * BH + kb];
+    wave_sync();
 #pragma unroll
-    for (int na = 0; na < A; ++na) g[na] = row[na * (B + 1) + kb];
-    dft<A, false>(g);
+    for (int m = h * MH; m < (h + 1) * MH; ++m) {
+      const int kb = p + A * m - h * BH;
+      float2 g[A];
 #pragma unroll
-    for (int ka = 0; ka < A; ++ka) x[m * A + ka] = g[ka];
+      for (int na = 0; na < A; ++na) g[na] = row[na * (BH + 1) + kb];
+      dft<A, false>(g);
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) x[m * A + ka] = g[ka];
+    }
   }
 }
 
@@ -277,7 +296,7 @@ template <int N> __device__ __forceinline__ void row_fwd(float2 (&x)[Geo<N>::B],
 // out: x[n_b] = unnormalised inverse row[p + A n_b]
 template <int N> __device__ __forceinline__ void row_inv(float2 (&x)[Geo<N>::B], float2* row, int p,
                                                          const float2* tw) {
-  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A;
+  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A, H = exch_phases<N>(), BH = B / H, MH = M / H;
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int kb = p + A * m;
@@ -285,46 +304,53 @@ template <int N> __device__ __forceinline__ void row_inv(float2 (&x)[Geo<N>::B],
 #pragma unroll
     for (int na = 1; na < A; ++na) x[m * A + na] = cmulc(x[m * A + na], tw[na * kb]);
   }
-  wave_sync();
 #pragma unroll
-  for (int m = 0; m < M; ++m) {
-    const int kb = p + A * m;
+  for (int h = 0; h < H; ++h) {
+    wave_sync();
 #pragma unroll
-    for (int na = 0; na < A; ++na) row[na * (B + 1) + kb] = x[m * A + na];
+    for (int m = h * MH; m < (h + 1) * MH; ++m) {
+      const int kb = p + A * m - h * BH;
+#pragma unroll
+      for (int na = 0; na < A; ++na) row[na * (BH + 1) + kb] = x[m * A + na];
+    }
+    wave_sync();
+#pragma unroll
+    for (int kb = 0; kb < BH; ++kb) x[h * BH + kb] = row[p * (BH + 1) + kb];
   }
-  wave_sync();
-#pragma unroll
-  for (int kb = 0; kb < B; ++kb) x[kb] = row[p * (B + 1) + kb];
   dft<B, true>(x);
 }
 
 // ---------------------------------------------------------------------------
 // Column-direction line FFT.  Thread (c, q), q in [0, A), owns column c of a
-// tile with N rows and row stride S (float2); lanes run along c so every LDS
-// access is contiguous across a wave.
+// tile with col_rows<N>() rows and row stride S (float2); lanes run along c so
+// every LDS access is contiguous across a wave.  The exchange rounds are as
+// in the row transforms, ordered by workgroup barriers.
 // ---------------------------------------------------------------------------
 
 // in : x[n_b] = col[q + A n_b]
 // out: x[m*A + k_a] = X[(q + A m) + B k_a]
 template <int N> __device__ __forceinline__ void col_fwd(float2 (&x)[Geo<N>::B], float2* tile, int S,
                                                          int c, int q, const float2* tw) {
-  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A;
+  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A, H = exch_phases<N>(), BH = B / H, MH = M / H;
   dft<B, false>(x);
 #pragma unroll
   for (int kb = 1; kb < B; ++kb) x[kb] = cmul(x[kb], tw[q * kb]);
-  __syncthreads();
 #pragma unroll
-  for (int kb = 0; kb < B; ++kb) tile[(kb * A + q) * S + c] = x[kb];
-  __syncthreads();
+  for (int h = 0; h < H; ++h) {
+    __syncthreads();
 #pragma unroll
-  for (int m = 0; m < M; ++m) {
-    const int kb = q + A * m;
-    float2 g[A];
+    for (int kb = 0; kb < BH; ++kb) tile[(kb * A + q) * S + c] = x[h * BH + kb];
+    __syncthreads();
 #pragma unroll
-    for (int na = 0; na < A; ++na) g[na] = tile[(kb * A + na) * S + c];
-    dft<A, false>(g);
+    for (int m = h * MH; m < (h + 1) * MH; ++m) {
+      const int kb = q + A * m - h * BH;
+      float2 g[A];
 #pragma unroll
-    for (int ka = 0; ka < A; ++ka) x[m * A + ka] = g[ka];
+      for (int na = 0; na < A; ++na) g[na] = tile[(kb * A + na) * S + c];
+      dft<A, false>(g);
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) x[m * A + ka] = g[ka];
+    }
   }
 }
 
@@ -332,7 +358,7 @@ template <int N> __device__ __forceinline__ void col_fwd(float2 (&x)[Geo<N>::B],
 // out: x[n_b] = unnormalised inverse col[q + A n_b]
 template <int N> __device__ __forceinline__ void col_inv(float2 (&x)[Geo<N>::B], float2* tile, int S,
                                                          int c, int q, const float2* tw) {
-  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A;
+  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A, H = exch_phases<N>(), BH = B / H, MH = M / H;
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int kb = q + A * m;
@@ -340,16 +366,19 @@ template <int N> __device__ __forceinline__ void col_inv(float2 (&x)[Geo<N>::B],
 #pragma unroll
     for (int na = 1; na < A; ++na) x[m * A + na] = cmulc(x[m * A + na], tw[na * kb]);
   }
-  __syncthreads();
 #pragma unroll
-  for (int m = 0; m < M; ++m) {
-    const int kb = q + A * m;
+  for (int h = 0; h < H; ++h) {
+    __syncthreads();
 #pragma unroll
-    for (int na = 0; na < A; ++na) tile[(kb * A + na) * S + c] = x[m * A + na];
+    for (int m = h * MH; m < (h + 1) * MH; ++m) {
+      const int kb = q + A * m - h * BH;
+#pragma unroll
+      for (int na = 0; na < A; ++na) tile[(kb * A + na) * S + c] = x[m * A + na];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kb = 0; kb < BH; ++kb) x[h * BH + kb] = tile[(kb * A + q) * S + c];
   }
-  __syncthreads();
-#pragma unroll
-  for (int kb = 0; kb < B; ++kb) x[kb] = tile[(kb * A + q) * S + c];
   dft<B, true>(x);
 }
 

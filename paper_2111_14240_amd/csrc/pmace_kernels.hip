@@ -124,6 +124,7 @@ __device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2*
 template <int NP, int METHOD>
 __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, S = NP + A, NT = NP * A, M = B / A;
+  static_assert(exch_phases<NP>() == 1, "the whole-patch tile exchanges in one round");
   __shared__ float2 tile[NP * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
@@ -222,7 +223,7 @@ template <int NP> constexpr int col_threads() { return CB * Geo<NP>::A; }
 
 template <int NP, int METHOD>
 __device__ __forceinline__ void agent_rows_body(const Recon& g, const int j0) {
-  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = NP + A;
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = row_cap<NP>();
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
@@ -262,7 +263,7 @@ __global__ void __launch_bounds__(row_threads<NP>()) agent_rows_batch(const Reco
 template <int NP, int METHOD>
 __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A;
-  __shared__ float2 tile[NP * CB];
+  __shared__ float2 tile[col_rows<NP>() * CB];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
   load_twiddles<NP>(tw, g.twn, tid, CB * A);
@@ -301,7 +302,7 @@ __global__ void __launch_bounds__(col_threads<NP>()) agent_cols_batch(const Reco
 
 template <int NP, int METHOD>
 __device__ __forceinline__ void agent_rowsinv_body(const Recon& g, const int j0) {
-  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = NP + A;
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = row_cap<NP>();
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
@@ -599,6 +600,7 @@ __device__ __forceinline__ float fit_term(float2 W, float yv) {
 template <int NP>
 __device__ __forceinline__ void fit_small_body(const Recon& g, const int j) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, S = NP + A, NT = NP * A, M = B / A;
+  static_assert(exch_phases<NP>() == 1, "the whole-patch tile exchanges in one round");
   __shared__ float2 tile[NP * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
@@ -655,7 +657,7 @@ __global__ void __launch_bounds__(row_threads<NP>()) fit_rows(const Recon* __res
                                                                int check_done) {
   const Recon& g = *rec;
   if (check_done && *g.done) return;
-  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = NP + A;
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = row_cap<NP>();
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
@@ -685,7 +687,7 @@ __global__ void __launch_bounds__(col_threads<NP>()) fit_cols(const Recon* __res
   const Recon& g = *rec;
   if (check_done && *g.done) return;
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A;
-  __shared__ float2 tile[NP * CB];
+  __shared__ float2 tile[col_rows<NP>() * CB];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
   load_twiddles<NP>(tw, g.twn, tid, CB * A);
@@ -916,6 +918,7 @@ __global__ void zero_images_k(const Recon* __restrict__ rec) {
 template <int NP, bool INV>
 __global__ void __launch_bounds__(NP * Geo<NP>::A) fft2_small(const float2* in, float2* out) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, S = NP + A, NT = NP * A, M = B / A;
+  static_assert(exch_phases<NP>() == 1, "the whole-patch tile exchanges in one round");
   __shared__ float2 tile[NP * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
@@ -968,7 +971,7 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) fft2_small(const float2* in, 
 // Np > 128 standalone transform: a row pass and a column pass over global memory.
 template <int NP, bool INV>
 __global__ void __launch_bounds__(row_threads<NP>()) fft_rows(const float2* in, float2* out, float scale) {
-  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = NP + A;
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = row_cap<NP>();
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
@@ -1001,7 +1004,7 @@ __global__ void __launch_bounds__(row_threads<NP>()) fft_rows(const float2* in, 
 template <int NP, bool INV>
 __global__ void __launch_bounds__(col_threads<NP>()) fft_cols(const float2* in, float2* out, float scale) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A;
-  __shared__ float2 tile[NP * CB];
+  __shared__ float2 tile[col_rows<NP>() * CB];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
   fill_twiddles<NP>(tw, tid, CB * A);

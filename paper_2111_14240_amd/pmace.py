@@ -307,14 +307,14 @@ def simulate(x, probe, pos, peak, seed: int, device="cuda", stream=None, out=Non
         z = torch.empty((J, np_, np_), dtype=torch.float32, device=dev)
     else:
         if (out.dtype != torch.float32 or tuple(out.shape) != (J, np_, np_) or not out.is_contiguous()
-                or out.device != dev):
-            raise ValueError(f"out must be a contiguous float32 ({J},{np_},{np_}) tensor on {dev}")
+                or out.device != x_t.device):
+            raise ValueError(f"out must be a contiguous float32 ({J},{np_},{np_}) tensor on {x_t.device}")
         z = out
     if workspace is None:
         ws = torch.empty(fp, dtype=torch.uint8, device=dev)
     else:
-        if workspace.dtype != torch.uint8 or workspace.numel() < fp or workspace.device != dev:
-            raise ValueError(f"workspace must be a uint8 tensor of at least {fp} bytes on {dev}")
+        if workspace.dtype != torch.uint8 or workspace.numel() < fp or workspace.device != x_t.device:
+            raise ValueError(f"workspace must be a uint8 tensor of at least {fp} bytes on {x_t.device}")
         ws = workspace
     scale = ctypes.c_double()
     _check(load_library().pmace_simulate(n1, n2, np_, J, ctypes.c_void_p(d_t.data_ptr()),

@@ -69,3 +69,24 @@ def test_simulate_matches_reference(P, np_, peak):
         sub = slice(0, 2000)
         ref = S.poisson(lam.ravel()[sub], seed=77)
         assert np.mean(z.ravel()[sub] == ref) >= 0.99        # same streams, FP32 vs FP64 means
+
+
+def test_simulate_into_caller_buffers(P):
+    """Caller-owned output and workspace (reused across calls, stale
+    contents left in both) give exactly the freshly allocated call's counts;
+    a wrong output shape is refused before anything runs."""
+    prob = synth.make_problem(320, 128, 4, 60, None, seed=91)
+    dev = torch.device("cuda")
+    ref, s_ref = P.simulate(prob.x_true, prob.probe, prob.pos, 1e5, seed=5)
+    fp = int(P.load_library().pmace_simulate_footprint(128, len(prob.pos)))
+    ws = torch.full((fp,), 0xAB, dtype=torch.uint8, device=dev)
+    out = torch.full((len(prob.pos), 128, 128), -1.0, dtype=torch.float32, device=dev)
+    _say("simulate into caller buffers, twice")
+    for _ in range(2):
+        z, s = P.simulate(prob.x_true, prob.probe, prob.pos, 1e5, seed=5, out=out, workspace=ws)
+        assert z.data_ptr() == out.data_ptr() and s == s_ref
+        assert torch.equal(z, ref)
+    with pytest.raises(ValueError):
+        P.simulate(prob.x_true, prob.probe, prob.pos, 1e5, seed=5, out=out[:-1], workspace=ws)
+    with pytest.raises(ValueError):
+        P.simulate(prob.x_true, prob.probe, prob.pos, 1e5, seed=5, out=out, workspace=ws[:16])
