@@ -337,14 +337,25 @@ def test_centered_dc_layout(P):
     assert rel(B.get_state().cpu().numpy(), A.get_state().cpu().numpy()) < 1e-6
 
 
+def c3_geometry_problem(np_):
+    """The C3 workload, or (as bench.py --np builds it) the same object,
+    raster, step and seed with another probe side."""
+    if np_ == synth.CONFIGS["c3"]["np_"]:
+        return synth.make_config_problem("c3")
+    c = synth.CONFIGS["c3"]
+    return synth.make_problem(c["n"], np_, c["scan"], c["step"], c["peak"], c["seed"], name=f"c3-np{np_}")
+
+
 @pytest.mark.slow
-def test_c3_full_size_steps(P):
-    """The full 1024^2 / Np 256 / 1600-position workload in the launch
+@pytest.mark.parametrize("np_", [256, 192, 160])
+def test_c3_full_size_steps(P, np_):
+    """The full 1024^2 / 1600-position workload (probe 256^2, and the 192^2 and
+    160^2 sides bench.py times on the same geometry) in the launch
     configuration the benchmark times: the first pass from the default start
     and a teacher-forced second pass, on every patch."""
-    prob = synth.make_config_problem("c3")
+    prob = c3_geometry_problem(np_)
     alpha = 0.5
-    _say("c3: oracle, 2 passes")
+    _say(f"c3 np{np_}: oracle, 2 passes")
     vs, xs = oracle_trajectory(prob, alpha, synth.KAPPA, synth.RHO, 2)
     tol0 = max(TOL, 3.0 * single_precision_step_error(prob, vs[0], alpha, synth.KAPPA, synth.RHO))
     _say(f"c3: device, tol0={tol0:.2e}")

@@ -75,3 +75,42 @@ def test_sharp_plus_teacher_forced(P, case, beta):
     assert rel(R2.get_state().cpu().numpy(), ss[4]) < 10 * TOL
     R.close()
     R2.close()
+
+
+def elem(a, b):
+    """Element by element: the largest pointwise error over the largest value."""
+    a = np.asarray(a, np.complex128)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.slow
+def test_sharp_plus_c3_full_size(P):
+    """SHARP+ on the full C3 workload (1024^2 object, 1600 positions of
+    256^2) in the launch configuration bench.py --method sharp times (beta
+    0.8, tuned chunks): the first pass from a smooth start and a
+    teacher-forced second pass, on every frame."""
+    beta = 0.8
+    prob = synth.make_config_problem("c3")
+    n = prob.n1
+    d = prob.probe.astype(np.complex64).astype(np.complex128)
+    y = O.amplitudes(prob.z.astype(np.float32))
+    shape = (n, n)
+    x0 = synth.make_object(n, n, np.random.default_rng(99))
+    _say("c3 sharp+: oracle, 2 steps")
+    ss = [O.sharp_plus_init(x0, d, prob.pos)]
+    for _ in range(2):
+        ss.append(O.sharp_plus_step(ss[-1], d, y, prob.pos, shape, beta))
+    R = P.Reconstruction(n, n, prob.probe, prob.pos, prob.z, 0.5, x0=x0.astype(np.complex64),
+                         method=P.PMACE_METHOD_SHARP_PLUS, beta=beta)
+    for k in range(2):
+        if k:
+            R.set_state(ss[k])
+        R.iterate(1)
+        s1 = R.get_state().cpu().numpy()
+        xr = O.sharp_plus_reconstruct(ss[k + 1], d, prob.pos, shape)
+        xh = R.reconstruct().cpu().numpy()
+        es, ex = rel(s1, ss[k + 1]), rel(xh, xr)
+        ms, mx = elem(s1, ss[k + 1]), elem(xh, xr)
+        _say(f"  k={k} rel(s)={es:.2e} rel(xhat)={ex:.2e} elementwise {ms:.2e} {mx:.2e}")
+        assert es < TOL and ex < TOL and ms < TOL and mx < TOL
+    R.close()
