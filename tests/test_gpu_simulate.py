@@ -90,3 +90,37 @@ def test_simulate_into_caller_buffers(P):
         P.simulate(prob.x_true, prob.probe, prob.pos, 1e5, seed=5, out=out[:-1], workspace=ws)
     with pytest.raises(ValueError):
         P.simulate(prob.x_true, prob.probe, prob.pos, 1e5, seed=5, out=out, workspace=ws[:16])
+
+
+@pytest.mark.slow
+def test_simulate_c3_geometry_full_size(P):
+    """The simulator as bench.py --mode simulate runs it: the C3 geometry
+    (1024^2 object, 1600 positions of 256^2, peak 1e6).  Noise-free
+    intensities on every frame against the oracle's forward model; the photon
+    scale of eq. (16) against the oracle's global maximum; Poisson counts on
+    sampled elements against the oracle's sampler on the same streams."""
+    c = synth.CONFIGS["c3"]
+    rng = np.random.default_rng(c["seed"])
+    n, np_ = c["n"], c["np_"]
+    x = synth.make_object(n, n, rng).astype(np.complex64).astype(np.complex128)
+    d = synth.make_probe(np_).astype(np.complex64).astype(np.complex128)
+    pos = synth.make_positions(n, np_, c["scan"], c["step"], rng)
+    _say("simulate c3 geometry: oracle intensities")
+    inten = S.forward_intensities(x, d, pos)
+    z0, s0 = P.simulate(x, d, pos, None, seed=3)
+    assert s0 == 1.0
+    e = np.linalg.norm(z0.cpu().numpy() - inten) / np.linalg.norm(inten)
+    _say(f"  noise-free rel {e:.2e}")
+    assert e < 2e-6
+    z, scale = P.simulate(x, d, pos, 1e6, seed=3)
+    assert scale == pytest.approx(1e6 / inten.max(), rel=1e-5)
+    zc = z.cpu().numpy().ravel()
+    lam = (inten * scale).ravel()
+    pick = np.random.default_rng(1).choice(lam.size, 3000, replace=False)
+    pick.sort()
+    # the oracle's streams are counted by element index, so each sampled element
+    # is drawn from its own stream
+    ref = np.array([S.poisson_draw(float(lam[i]), S.Uniforms(3, int(i))) for i in pick])
+    same = np.mean(zc[pick] == ref)
+    _say(f"  sampled counts equal: {same:.4f}")
+    assert same >= 0.99
