@@ -228,12 +228,17 @@ def test_c1_every_iteration_teacher_forced_and_free_running(P):
     R2.close()
 
 
-def test_c2_teacher_forced_steps(P):
-    prob = synth.make_config_problem("c2")
+@pytest.mark.parametrize("np_", [128, 96, 48])
+def test_c2_teacher_forced_steps(P, np_):
+    """The C2 workload (512^2 object, 225 positions; probe 128^2, and the 96^2
+    and 48^2 sides bench.py --np times on the same geometry), whole."""
+    c = synth.CONFIGS["c2"]
+    prob = (synth.make_config_problem("c2") if np_ == c["np_"] else
+            synth.make_problem(c["n"], np_, c["scan"], c["step"], c["peak"], c["seed"], name=f"c2-np{np_}"))
     alpha = 0.5
     ks = [1, 2, 5]
     vs, xs = oracle_trajectory(prob, alpha, synth.KAPPA, synth.RHO, max(ks) + 1)
-    _say("c2 teacher-forced at", ks)
+    _say(f"c2 np{np_} teacher-forced at", ks)
     R = make_recon(P, prob, alpha)
     for k in ks:
         R.set_state(vs[k])

@@ -84,19 +84,20 @@ def elem(a, b):
 
 
 @pytest.mark.slow
-def test_sharp_plus_c3_full_size(P):
-    """SHARP+ on the full C3 workload (1024^2 object, 1600 positions of
-    256^2) in the launch configuration bench.py --method sharp times (beta
-    0.8, tuned chunks): the first pass from a smooth start and a
-    teacher-forced second pass, on every frame."""
+@pytest.mark.parametrize("config", ["c3", "c2"])
+def test_sharp_plus_full_size(P, config):
+    """SHARP+ on the full C3 (1024^2 object, 1600 positions of 256^2) and C2
+    (512^2, 225 of 128^2) workloads in the launch configuration
+    bench.py --method sharp times (beta 0.8, tuned chunks): the first pass
+    from a smooth start and a teacher-forced second pass, on every frame."""
     beta = 0.8
-    prob = synth.make_config_problem("c3")
+    prob = synth.make_config_problem(config)
     n = prob.n1
     d = prob.probe.astype(np.complex64).astype(np.complex128)
     y = O.amplitudes(prob.z.astype(np.float32))
     shape = (n, n)
     x0 = synth.make_object(n, n, np.random.default_rng(99))
-    _say("c3 sharp+: oracle, 2 steps")
+    _say(f"{config} sharp+: oracle, 2 steps")
     ss = [O.sharp_plus_init(x0, d, prob.pos)]
     for _ in range(2):
         ss.append(O.sharp_plus_step(ss[-1], d, y, prob.pos, shape, beta))
