@@ -13,7 +13,6 @@
 // Insurance: Mathematics and Economics 12, 1993) from mean 10 up.
 #include <hip/hip_runtime.h>
 
-#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -95,44 +94,152 @@ __device__ double poisson_draw(double lam, Uniforms& u) {
   return floor(lam + 0.5);
 }
 
-// frames[j] = d * P_j x
-__global__ void frames_k(const float2* __restrict__ d, const int2* __restrict__ pos,
-                         const float2* __restrict__ x, float2* __restrict__ fr, int np, int n2,
-                         long long total) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const long long per = (long long)np * np;
-  const int j = (int)(i / per);
-  const int rem = (int)(i - (long long)j * per);
-  const int r = rem / np, c = rem - r * np;
-  const int2 pj = pos[j];
-  fr[i] = cmul(d[rem], x[(size_t)(pj.x + r) * n2 + pj.y + c]);
-}
+// ---------------------------------------------------------------------------
+// Noise-free intensities I_j = |F D P_j x|^2 (F orthonormal) and their
+// maximum, with the frames d P_j x formed as the transform loads them and the
+// intensities as it stores them.  The maximum is folded per workgroup into
+// one atomic (non-negative floats order as their bit patterns, so an
+// unsigned max is a float max).
+// ---------------------------------------------------------------------------
+constexpr int kSimRB = PMACE_RB;   // rows per workgroup of the row pass (Np > 128)
+constexpr int kSimCB = PMACE_CB;   // columns per workgroup of the column pass
+static_assert(160 % kSimRB == 0 && 192 % kSimRB == 0 && 256 % kSimRB == 0, "row block");
+static_assert(160 % kSimCB == 0 && 192 % kSimCB == 0 && 256 % kSimCB == 0, "column block");
 
-// I = |F D P_j x|^2, and the running maximum (non-negative floats order as
-// their bit patterns, so an unsigned max is a float max).  Grid-stride over
-// the elements; each workgroup folds its maximum into one atomic (one atomic
-// per wave on one address serialised into most of the simulator's time).
-constexpr int kIntensityThreads = 256;
-__global__ void __launch_bounds__(kIntensityThreads)
-intensity_k(const float2* __restrict__ spec, float* __restrict__ z, unsigned* __restrict__ maxbits,
-            long long total) {
-  __shared__ float wmax[kIntensityThreads / 64];
-  float v = 0.f;
-  for (long long i = (long long)blockIdx.x * kIntensityThreads + threadIdx.x; i < total;
-       i += (long long)gridDim.x * kIntensityThreads) {
-    const float2 s = spec[i];
-    const float e = fmaf(s.x, s.x, s.y * s.y);
-    z[i] = e;
-    v = fmaxf(v, e);
-  }
+template <int NT>
+__device__ __forceinline__ void block_max_to(float v, unsigned* maxbits) {
+  static_assert(NT % 64 == 0 && NT <= 1024, "whole wavefronts");
+  __shared__ float wmax[NT / 64];
   for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
   if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = v;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < kIntensityThreads / 64; ++w) v = fmaxf(v, wmax[w]);
+    for (int w = 1; w < NT / 64; ++w) v = fmaxf(v, wmax[w]);
     atomicMax(maxbits, __float_as_uint(v));
   }
+}
+
+// Np <= 128: one position per workgroup, the whole frame in LDS.
+template <int NP>
+__global__ void __launch_bounds__(NP * Geo<NP>::A)
+sim_small_k(const float2* __restrict__ d, const int2* __restrict__ pos, const float2* __restrict__ x,
+            int n2, float* __restrict__ z, unsigned* __restrict__ maxbits) {
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, S = NP + A, NT = NP * A, M = B / A;
+  static_assert(exch_phases<NP>() == 1, "the whole-frame tile exchanges in one round");
+  __shared__ float2 tile[NP * S];
+  __shared__ float2 tw[NP];
+  const int tid = threadIdx.x;
+  fill_twiddles<NP>(tw, tid, NT);
+  const int j = blockIdx.x;
+  const int2 pj = pos[j];
+  const int r = tid / A, p = tid % A, c = tid % NP, q = tid / NP;
+  const float2* xrow = x + (size_t)(pj.x + r) * n2 + pj.y;
+  float2* row = tile + r * S;
+  float2 v[B];
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) {
+    const int cc = p + A * nb;
+    v[nb] = cmul(d[r * NP + cc], xrow[cc]);
+  }
+  __syncthreads();
+  row_fwd<NP>(v, row, p, tw);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) row[p + A * m + B * ka] = v[m * A + ka];
+  __syncthreads();
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) v[nb] = tile[(q + A * nb) * S + c];
+  col_fwd<NP>(v, tile, S, c, q, tw);
+  const float scale = 1.f / NP;
+  float* zj = z + (size_t)j * NP * NP;
+  float mx = 0.f;
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) {
+      const float2 s = cscale(v[m * A + ka], scale);
+      const float e = fmaf(s.x, s.x, s.y * s.y);
+      zj[(size_t)(q + A * m + B * ka) * NP + c] = e;
+      mx = fmaxf(mx, e);
+    }
+  block_max_to<NT>(mx, maxbits);
+}
+
+// Np > 128, row pass: frames and forward row DFTs (scaled 1/sqrt(Np)) to fr.
+template <int NP>
+__global__ void __launch_bounds__(kSimRB * Geo<NP>::A)
+sim_rows_k(const float2* __restrict__ d, const int2* __restrict__ pos, const float2* __restrict__ x,
+           int n2, float2* __restrict__ fr, float sc) {
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = row_cap<NP>();
+  __shared__ float2 tile[kSimRB * S];
+  __shared__ float2 tw[NP];
+  const int tid = threadIdx.x;
+  fill_twiddles<NP>(tw, tid, kSimRB * A);
+  const int j = blockIdx.x / (NP / kSimRB), rb = blockIdx.x % (NP / kSimRB);
+  const int rl = tid / A, p = tid % A, r = rb * kSimRB + rl;
+  const int2 pj = pos[j];
+  const float2* xrow = x + (size_t)(pj.x + r) * n2 + pj.y;
+  float2 v[B];
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) {
+    const int cc = p + A * nb;
+    v[nb] = cmul(d[r * NP + cc], xrow[cc]);
+  }
+  __syncthreads();
+  row_fwd<NP>(v, tile + rl * S, p, tw);
+  float2* out = fr + ((size_t)j * NP + r) * NP;
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) out[p + A * m + B * ka] = cscale(v[m * A + ka], sc);
+}
+
+// Np > 128, column pass: forward column DFTs (scaled 1/sqrt(Np)) and the
+// intensities.
+template <int NP>
+__global__ void __launch_bounds__(kSimCB * Geo<NP>::A)
+sim_cols_k(const float2* __restrict__ fr, float* __restrict__ z, unsigned* __restrict__ maxbits, float sc) {
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, NT = kSimCB * A;
+  __shared__ float2 tile[col_rows<NP>() * kSimCB];
+  __shared__ float2 tw[NP];
+  const int tid = threadIdx.x;
+  fill_twiddles<NP>(tw, tid, NT);
+  const int j = blockIdx.x / (NP / kSimCB), cb = blockIdx.x % (NP / kSimCB);
+  const int c = tid % kSimCB, q = tid / kSimCB, col = cb * kSimCB + c;
+  const size_t base = (size_t)j * NP * NP + col;
+  float2 v[B];
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) v[nb] = fr[base + (size_t)(q + A * nb) * NP];
+  __syncthreads();
+  col_fwd<NP>(v, tile, kSimCB, c, q, tw);
+  float mx = 0.f;
+#pragma unroll
+  for (int m = 0; m < M; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) {
+      const float2 s = cscale(v[m * A + ka], sc);
+      const float e = fmaf(s.x, s.x, s.y * s.y);
+      z[base + (size_t)(q + A * m + B * ka) * NP] = e;
+      mx = fmaxf(mx, e);
+    }
+  block_max_to<NT>(mx, maxbits);
+}
+
+template <int NP>
+hipError_t launch_sim_intensities(int J, const float2* d, const int2* pos, const float2* x, int n2,
+                                  float2* fr, float* z, unsigned* maxbits, hipStream_t st) {
+  if constexpr (NP <= 128) {
+    hipLaunchKernelGGL(sim_small_k<NP>, dim3(J), dim3(NP * Geo<NP>::A), 0, st, d, pos, x, n2, z, maxbits);
+  } else {
+    const float sc = 1.f / sqrtf((float)NP);  // 1/sqrt(Np) per pass
+    hipLaunchKernelGGL(sim_rows_k<NP>, dim3(J * (NP / kSimRB)), dim3(kSimRB * Geo<NP>::A), 0, st, d, pos,
+                       x, n2, fr, sc);
+    hipLaunchKernelGGL(sim_cols_k<NP>, dim3(J * (NP / kSimCB)), dim3(kSimCB * Geo<NP>::A), 0, st, fr, z,
+                       maxbits, sc);
+  }
+  return hipGetLastError();
 }
 
 __global__ void poisson_k(float* __restrict__ z, const unsigned* __restrict__ maxbits, double peak,
@@ -209,16 +316,22 @@ pmace_status pmace_simulate(int32_t n1, int32_t n2, int32_t np, int32_t num_pos,
   unsigned* maxbits = reinterpret_cast<unsigned*>(base + up256(J * np * np * 8));
   const long long total = (long long)J * np * np;
   if (hipMemsetAsync(maxbits, 0, 4, st) != hipSuccess) return PMACE_EDEVICE;
-  hipLaunchKernelGGL(pmace::frames_k, dim3(nblocks(total, 256)), dim3(256), 0, st,
-                     reinterpret_cast<const float2*>(probe_d), reinterpret_cast<const int2*>(pos_d),
-                     reinterpret_cast<const float2*>(x_d), fr, np, n2, total);
-  if (hipGetLastError() != hipSuccess ||
-      pmace::launch_fft2(np, num_pos, fr, fr, 0, st) != hipSuccess)
-    return PMACE_EDEVICE;
-  // a few workgroups per CU, each striding over the elements
-  const unsigned iblocks = (unsigned)std::min<long long>(nblocks(total, pmace::kIntensityThreads), 2048);
-  hipLaunchKernelGGL(pmace::intensity_k, dim3(iblocks), dim3(pmace::kIntensityThreads), 0, st, fr, z_d,
-                     maxbits, total);
+  const float2* dd = reinterpret_cast<const float2*>(probe_d);
+  const int2* pp = reinterpret_cast<const int2*>(pos_d);
+  const float2* xx = reinterpret_cast<const float2*>(x_d);
+  hipError_t e = hipErrorInvalidValue;
+  switch (np) {
+    case 32: e = pmace::launch_sim_intensities<32>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 48: e = pmace::launch_sim_intensities<48>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 64: e = pmace::launch_sim_intensities<64>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 96: e = pmace::launch_sim_intensities<96>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 128: e = pmace::launch_sim_intensities<128>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 160: e = pmace::launch_sim_intensities<160>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 192: e = pmace::launch_sim_intensities<192>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 256: e = pmace::launch_sim_intensities<256>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    default: break;
+  }
+  if (e != hipSuccess) return PMACE_EDEVICE;
   if (peak_photons > 0.0)
     hipLaunchKernelGGL(pmace::poisson_k, dim3(nblocks(total, 256)), dim3(256), 0, st, z_d, maxbits,
                        peak_photons, seed, total);
