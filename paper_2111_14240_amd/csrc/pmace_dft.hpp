@@ -233,6 +233,32 @@ template <int N> __device__ __forceinline__ void load_twiddles(float2* tw, const
   for (int m = tid; m < N; m += nthreads) tw[m] = twn[m];
 }
 
+// The same table through registers: fetch() issues the loads and store()
+// writes them to LDS, so a kernel can issue its own loads in between instead
+// of waiting for the table first (the staged passes, whose many workgroups
+// each start with that wait).  Every lane loads (an index clamped into the
+// table, no branch to wait at); only m < N is written.  The whole-patch
+// kernels and the SHARP+ staged passes keep load_twiddles: measured, they
+// were slower with it.
+template <int N, int NT> struct TwiddleFetch {
+  static constexpr int K = (N + NT - 1) / NT;
+  float2 v[K];
+  __device__ __forceinline__ void fetch(const float2* twn, int tid) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int m = tid + k * NT;
+      v[k] = twn[m < N ? m : N - 1];
+    }
+  }
+  __device__ __forceinline__ void store(float2* tw, int tid) const {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int m = tid + k * NT;
+      if (m < N) tw[m] = v[k];
+    }
+  }
+};
+
 // The same values computed in place (FP64 sincospi, rounded once), for the
 // standalone transform, which has no workspace.
 template <int N> __device__ __forceinline__ void fill_twiddles(float2* tw, int tid, int nthreads) {

@@ -227,7 +227,11 @@ __device__ __forceinline__ void agent_rows_body(const Recon& g, const int j0) {
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.twn, tid, RB * A);
+  // PMACE: the table is written to LDS once the loads below are issued;
+  // SHARP+ loads it first (each measured the faster for its method)
+  TwiddleFetch<NP, RB * A> twf;
+  if constexpr (METHOD == kPMACE) twf.fetch(g.twn, tid);
+  else load_twiddles<NP>(tw, g.twn, tid, RB * A);
   const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
   const int j = j0 + jl;
   const int2 pj = g.pos[j];
@@ -240,6 +244,7 @@ __device__ __forceinline__ void agent_rows_body(const Recon& g, const int j0) {
     const int c = p + A * nb;
     x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], g.two_rho);
   }
+  if constexpr (METHOD == kPMACE) twf.store(tw, tid);
   __syncthreads();
   row_fwd<NP>(x, tile + rl * S, p, tw);
   float2* out = g.stage + ((size_t)jl * NP + r) * NP;
@@ -266,7 +271,11 @@ __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
   __shared__ float2 tile[col_rows<NP>() * CB];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.twn, tid, CB * A);
+  // PMACE: the table is written to LDS once the loads below are issued;
+  // SHARP+ loads it first (each measured the faster for its method)
+  TwiddleFetch<NP, CB * A> twf;
+  if constexpr (METHOD == kPMACE) twf.fetch(g.twn, tid);
+  else load_twiddles<NP>(tw, g.twn, tid, CB * A);
   const int jl = blockIdx.x / (NP / CB), cb = blockIdx.x % (NP / CB);
   const int j = j0 + jl;
   const int c = tid % CB, q = tid / CB, col = cb * CB + c;
@@ -274,6 +283,7 @@ __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
   float2 x[B];
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) x[nb] = sp[(size_t)(q + A * nb) * NP];
+  if constexpr (METHOD == kPMACE) twf.store(tw, tid);
   __syncthreads();
   col_fwd<NP>(x, tile, CB, c, q, tw);
   const float* yc = g.ys + (size_t)j * NP * NP + col;
@@ -306,7 +316,11 @@ __device__ __forceinline__ void agent_rowsinv_body(const Recon& g, const int j0)
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.twn, tid, RB * A);
+  // PMACE: the table is written to LDS once the loads below are issued;
+  // SHARP+ loads it first (each measured the faster for its method)
+  TwiddleFetch<NP, RB * A> twf;
+  if constexpr (METHOD == kPMACE) twf.fetch(g.twn, tid);
+  else load_twiddles<NP>(tw, g.twn, tid, RB * A);
   const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
   const int j = j0 + jl;
   const int2 pj = g.pos[j];
@@ -317,6 +331,7 @@ __device__ __forceinline__ void agent_rowsinv_body(const Recon& g, const int j0)
   for (int m = 0; m < M; ++m)
 #pragma unroll
     for (int ka = 0; ka < A; ++ka) x[m * A + ka] = io[p + A * m + B * ka];
+  if constexpr (METHOD == kPMACE) twf.store(tw, tid);
   __syncthreads();
   row_inv<NP>(x, tile + rl * S, p, tw);
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
@@ -661,7 +676,8 @@ __global__ void __launch_bounds__(row_threads<NP>()) fit_rows(const Recon* __res
   __shared__ float2 tile[RB * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.twn, tid, RB * A);
+  TwiddleFetch<NP, RB * A> twf;  // written to LDS once the loads below are issued
+  twf.fetch(g.twn, tid);
   const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
   const int2 pj = g.pos[j0 + jl];
   const int rl = tid / A, p = tid % A, r = rb * RB + rl;
@@ -672,6 +688,7 @@ __global__ void __launch_bounds__(row_threads<NP>()) fit_rows(const Recon* __res
     const int c = p + A * nb;
     x[nb] = cmul(g.d[r * NP + c], xrow[c]);
   }
+  twf.store(tw, tid);
   __syncthreads();
   row_fwd<NP>(x, tile + rl * S, p, tw);
   float2* out = g.stage + ((size_t)jl * NP + r) * NP;
@@ -690,7 +707,8 @@ __global__ void __launch_bounds__(col_threads<NP>()) fit_cols(const Recon* __res
   __shared__ float2 tile[col_rows<NP>() * CB];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.twn, tid, CB * A);
+  TwiddleFetch<NP, CB * A> twf;  // written to LDS once the loads below are issued
+  twf.fetch(g.twn, tid);
   const int jl = blockIdx.x / (NP / CB), cb = blockIdx.x % (NP / CB);
   const int j = j0 + jl;
   const int c = tid % CB, q = tid / CB, col = cb * CB + c;
@@ -698,6 +716,7 @@ __global__ void __launch_bounds__(col_threads<NP>()) fit_cols(const Recon* __res
   float2 x[B];
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) x[nb] = sp[(size_t)(q + A * nb) * NP];
+  twf.store(tw, tid);
   __syncthreads();
   col_fwd<NP>(x, tile, CB, c, q, tw);
   const float* yc = g.ys + (size_t)j * NP * NP + col;
