@@ -369,23 +369,41 @@ __global__ void __launch_bounds__(row_threads<NP>()) agent_rowsinv_batch(const R
 // xhat) is finished here; otherwise it is added to num.
 // -------------------------------------------------------------------------
 
+// The per-pixel images the a9 update reads, loaded ahead of the sum that
+// it combines them with.
+struct ImageIn {
+  float li;
+  float2 so, xo, xh;
+};
+template <int METHOD>
+__device__ __forceinline__ ImageIn load_image_in(const Recon& g, size_t px) {
+  ImageIn v;
+  v.li = g.laminv[px];
+  if constexpr (METHOD == kPMACE) {
+    v.so = g.sold[px];
+    v.xo = g.xbar[px];
+  }
+  v.xh = g.xhat[px];
+  return v;
+}
 // a9 for one object pixel from the complete sum S.
 template <int METHOD>
-__device__ __forceinline__ void finish_image(const Recon& g, size_t px, float2 S) {
-  const float li = g.laminv[px];
+__device__ __forceinline__ void finish_image(const Recon& g, size_t px, float2 S, const ImageIn& v) {
   float2 xb;
   if constexpr (METHOD == kPMACE) {
-    const float2 so = g.sold[px], xo = g.xbar[px];
-    const float ex = fmaf(g.co, so.x, -g.cn * S.x), ey = fmaf(g.co, so.y, -g.cn * S.y);
-    xb = make_float2(fmaf(g.cx, xo.x, li * ex), fmaf(g.cx, xo.y, li * ey));
+    const float ex = fmaf(g.co, v.so.x, -g.cn * S.x), ey = fmaf(g.co, v.so.y, -g.cn * S.y);
+    xb = make_float2(fmaf(g.cx, v.xo.x, v.li * ex), fmaf(g.cx, v.xo.y, v.li * ey));
     g.sold[px] = S;
   } else {
-    xb = make_float2(S.x * li, S.y * li);
+    xb = make_float2(S.x * v.li, S.y * v.li);
   }
-  const float2 xh = g.xhat[px];
   g.xbar[px] = xb;
-  g.xhat[px] = make_float2(fmaf(g.rho, xb.x - xh.x, xh.x), fmaf(g.rho, xb.y - xh.y, xh.y));
+  g.xhat[px] = make_float2(fmaf(g.rho, xb.x - v.xh.x, v.xh.x), fmaf(g.rho, xb.y - v.xh.y, v.xh.y));
   if (!(isfinite(xb.x) && isfinite(xb.y))) atomicOr(g.status, 1u);
+}
+template <int METHOD>
+__device__ __forceinline__ void finish_image(const Recon& g, size_t px, float2 S) {
+  finish_image<METHOD>(g, px, S, load_image_in<METHOD>(g, px));
 }
 
 #define PM_STR(x) #x
@@ -400,6 +418,16 @@ __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int 
   const int pxl = tid % NPX, part = tid / NPX;
   const int4 ti = g.tiles[tile];
   const int R = ti.z + pxl / GT_C, C = ti.w + pxl % GT_C;
+  // the pixel's thread (part 0) loads what it combines the sum with now, so
+  // those loads overlap the list and state loads instead of following them
+  const bool own = part == 0 && R < g.n1 && C < g.n2;
+  const size_t px = own ? (size_t)R * g.n2 + C : 0;
+  ImageIn img{};
+  float2 acc0 = make_float2(0.f, 0.f);
+  if (own) {
+    if constexpr (FUSE) img = load_image_in<METHOD>(g, px);
+    else acc0 = g.num[px];
+  }
   const float2* src = METHOD == kPMACE ? g.t : g.stage;
   const int jb = METHOD == kPMACE ? 0 : jbase;
   float ax = 0.f, ay = 0.f;
@@ -442,13 +470,11 @@ __device__ __forceinline__ void consensus_gather_body(const Recon& g, const int 
       ay += ps[k * NPX + pxl].y;
     }
   }
-  if (R >= g.n1 || C >= g.n2) return;
-  const size_t px = (size_t)R * g.n2 + C;
+  if (!own) return;
   if constexpr (FUSE) {
-    finish_image<METHOD>(g, px, make_float2(ax, ay));
+    finish_image<METHOD>(g, px, make_float2(ax, ay), img);
   } else {
-    const float2 o = g.num[px];
-    g.num[px] = make_float2(o.x + ax, o.y + ay);
+    g.num[px] = make_float2(acc0.x + ax, acc0.y + ay);
   }
 }
 
