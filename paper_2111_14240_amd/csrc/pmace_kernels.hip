@@ -128,7 +128,6 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
   __shared__ float2 tile[NP * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  load_twiddles<NP>(tw, g.twn, tid, NT);
   const int2 pj = g.pos[j];
   const size_t pb = (size_t)j * NP * NP;
   const int r = tid / A, p = tid % A;
@@ -142,6 +141,9 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
     const int c = p + A * nb;
     x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], two_rho);
   }
+  // the twiddle table after the frame's loads, so the two are in flight
+  // together (the row transforms wait for both anyway)
+  load_twiddles<NP>(tw, g.twn, tid, NT);
   // amplitudes of the column phase, fetched now so their latency hides
   // behind the row transforms
   const int c = tid % NP, q = tid / NP;
