@@ -97,6 +97,15 @@ __device__ __forceinline__ float2 agent_input(float2 s, float2 xb, float2 d, flo
 //           beta d P_j xbar (P_Q s of this iteration is d P_j xbar of the last
 //           one: P_Q is a projection, so P_Q s_{k+1} = P_Q P_a s_k), and the
 //           overlap numerator takes conj(d) a.  pc = {conj(d)/Np^2, conj(d)}.
+// SHARP+ epilogue with the old state t_old = *tp already loaded.
+__device__ __forceinline__ void sharp_output(float2 z, float2 t_old, float2* tp, const float2* xp, int k,
+                                             const Recon& g, float2* u_out) {
+  const float4 pcf = g.pc[k];
+  const float2 dx = cmul(make_float2(pcf.z, -pcf.w), *xp);
+  const float2 sv = mann_v(t_old, dx, g.two_rho);
+  *tp = make_float2(fmaf(g.ka, z.x, g.beta * (sv.x - dx.x)), fmaf(g.ka, z.y, g.beta * (sv.y - dx.y)));
+  *u_out = cmul(make_float2(pcf.x, pcf.y), z);
+}
 template <int METHOD>
 __device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2* xp, int k,
                                              const Recon& g, float2* u_out) {
@@ -108,11 +117,7 @@ __device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2*
     }
     *tp = sn;
   } else {
-    const float4 pcf = g.pc[k];
-    const float2 dx = cmul(make_float2(pcf.z, -pcf.w), *xp);
-    const float2 sv = mann_v(*tp, dx, g.two_rho);
-    *tp = make_float2(fmaf(g.ka, z.x, g.beta * (sv.x - dx.x)), fmaf(g.ka, z.y, g.beta * (sv.y - dx.y)));
-    *u_out = cmul(make_float2(pcf.x, pcf.y), z);
+    sharp_output(z, *tp, tp, xp, k, g, u_out);
   }
 }
 
@@ -285,17 +290,19 @@ __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
   float2 x[B];
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) x[nb] = sp[(size_t)(q + A * nb) * NP];
-  if constexpr (METHOD == kPMACE) twf.store(tw, tid);
-  __syncthreads();
-  col_fwd<NP>(x, tile, CB, c, q, tw);
+  // amplitudes of the spectrum step, fetched now so their latency hides
+  // behind the forward column transforms
   const float* yc = g.ys + (size_t)j * NP * NP + col;
+  float yv[B];
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
-    for (int ka = 0; ka < A; ++ka) {
-      const int k = q + A * m + B * ka;
-      x[m * A + ka] = spectrum_step<METHOD>(x[m * A + ka], yc[(size_t)k * NP], g);
-    }
+    for (int ka = 0; ka < A; ++ka) yv[m * A + ka] = yc[(size_t)(q + A * m + B * ka) * NP];
+  if constexpr (METHOD == kPMACE) twf.store(tw, tid);
+  __syncthreads();
+  col_fwd<NP>(x, tile, CB, c, q, tw);
+#pragma unroll
+  for (int k = 0; k < B; ++k) x[k] = spectrum_step<METHOD>(x[k], yv[k], g);
   col_inv<NP>(x, tile, CB, c, q, tw);
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) sp[(size_t)(q + A * nb) * NP] = x[nb];
@@ -328,20 +335,29 @@ __device__ __forceinline__ void agent_rowsinv_body(const Recon& g, const int j0)
   const int2 pj = g.pos[j];
   const int rl = tid / A, p = tid % A, r = rb * RB + rl;
   float2* io = g.stage + ((size_t)jl * NP + r) * NP;
+  const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
+  float2* trow = g.t + (size_t)j * NP * NP + (size_t)r * NP;
   float2 x[B];
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
     for (int ka = 0; ka < A; ++ka) x[m * A + ka] = io[p + A * m + B * ka];
+  // SHARP+ needs the old state again: fetched now, behind the transform
+  // (not for 40-point lines, where the registers would halve occupancy)
+  constexpr bool kOldAhead = METHOD == kSharpPlus && B <= 24;
+  float2 t_old[B];
+  if constexpr (kOldAhead) {
+#pragma unroll
+    for (int nb = 0; nb < B; ++nb) t_old[nb] = trow[p + A * nb];
+  }
   if constexpr (METHOD == kPMACE) twf.store(tw, tid);
   __syncthreads();
   row_inv<NP>(x, tile + rl * S, p, tw);
-  const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
-  float2* trow = g.t + (size_t)j * NP * NP + (size_t)r * NP;
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) {
     const int c = p + A * nb;
-    agent_output<METHOD>(x[nb], &trow[c], &xrow[c], r * NP + c, g, &io[c]);
+    if constexpr (kOldAhead) sharp_output(x[nb], t_old[nb], &trow[c], &xrow[c], r * NP + c, g, &io[c]);
+    else agent_output<METHOD>(x[nb], &trow[c], &xrow[c], r * NP + c, g, &io[c]);
   }
 }
 
@@ -744,16 +760,19 @@ __global__ void __launch_bounds__(col_threads<NP>()) fit_cols(const Recon* __res
   float2 x[B];
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) x[nb] = sp[(size_t)(q + A * nb) * NP];
-  twf.store(tw, tid);
-  __syncthreads();
-  col_fwd<NP>(x, tile, CB, c, q, tw);
+  // amplitudes fetched now, behind the column transforms
   const float* yc = g.ys + (size_t)j * NP * NP + col;
-  float acc = 0.f;
+  float yv[B];
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
-    for (int ka = 0; ka < A; ++ka)
-      acc += fit_term(x[m * A + ka], g.yfac * yc[(size_t)(q + A * m + B * ka) * NP]);
+    for (int ka = 0; ka < A; ++ka) yv[m * A + ka] = yc[(size_t)(q + A * m + B * ka) * NP];
+  twf.store(tw, tid);
+  __syncthreads();
+  col_fwd<NP>(x, tile, CB, c, q, tw);
+  float acc = 0.f;
+#pragma unroll
+  for (int k = 0; k < B; ++k) acc += fit_term(x[k], g.yfac * yv[k]);
   block_sum_to(acc, &g.fit[(size_t)j * (NP / CB) + cb], 0.5 / ((double)NP * NP));
 }
 
