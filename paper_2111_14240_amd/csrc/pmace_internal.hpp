@@ -19,7 +19,10 @@ namespace pmace {
 #define PMACE_GATHER_UNROLL 8
 #endif
 #ifndef PMACE_RB
-#define PMACE_RB 16       // Np > 128: patch rows per workgroup in the row passes
+#define PMACE_RB 16       // Np = 160, 192: patch rows per workgroup in the row passes
+#endif
+#ifndef PMACE_RB256
+#define PMACE_RB256 PMACE_RB  // Np = 256: patch rows per workgroup in the row passes
 #endif
 #ifndef PMACE_CB
 #define PMACE_CB 16       // Np > 128: patch columns per workgroup in the column pass

@@ -218,31 +218,35 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused_batch(const Recon
 //   rows   : a2, a3, forward row DFTs            -> stage
 //   cols   : forward column DFTs, spectrum step (a5), inverse column DFTs (in place)
 //   rowsinv: inverse row DFTs, a6-a7 (t); SHARP+: stage <- overlap numerators
-// A workgroup takes RB rows (row passes) or CB columns (column pass) of one
+// A workgroup takes rb_of<NP>() rows (row passes) or CB columns (column pass) of one
 // patch, with Geo<NP>::A threads per line.
 // -------------------------------------------------------------------------
-constexpr int RB = PMACE_RB;   // rows per workgroup in the row passes
+constexpr int RB = PMACE_RB;        // rows per workgroup in the row passes (160, 192)
+constexpr int RB256 = PMACE_RB256;  // ... and for 256-point lines (tuned apart)
 constexpr int CB = PMACE_CB;   // columns per workgroup in the column pass
-static_assert(RB >= 4 && RB <= 32 && 160 % RB == 0 && 192 % RB == 0 && 256 % RB == 0, "row block");
+static_assert(RB >= 4 && RB <= 32 && 160 % RB == 0 && 192 % RB == 0, "row block");
+static_assert(RB256 >= 4 && RB256 <= 32 && 256 % RB256 == 0, "row block (256)");
+template <int NP> constexpr int rb_of() { return NP == 256 ? RB256 : RB; }
 static_assert(CB >= 8 && CB <= 32 && 160 % CB == 0 && 192 % CB == 0 && 256 % CB == 0, "column block");
-template <int NP> constexpr int row_threads() { return RB * Geo<NP>::A; }
+template <int NP> constexpr int row_threads() { return rb_of<NP>() * Geo<NP>::A; }
 template <int NP> constexpr int col_threads() { return CB * Geo<NP>::A; }
 
 template <int NP, int METHOD>
 __device__ __forceinline__ void agent_rows_body(const Recon& g, const int j0) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = row_cap<NP>();
-  __shared__ float2 tile[RB * S];
+  constexpr int RBn = rb_of<NP>();
+  __shared__ float2 tile[RBn * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
   // PMACE: the table is written to LDS once the loads below are issued;
   // SHARP+ loads it first (each measured the faster for its method)
-  TwiddleFetch<NP, RB * A> twf;
+  TwiddleFetch<NP, RBn * A> twf;
   if constexpr (METHOD == kPMACE) twf.fetch(g.twn, tid);
-  else load_twiddles<NP>(tw, g.twn, tid, RB * A);
-  const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
+  else load_twiddles<NP>(tw, g.twn, tid, RBn * A);
+  const int jl = blockIdx.x / (NP / RBn), rb = blockIdx.x % (NP / RBn);
   const int j = j0 + jl;
   const int2 pj = g.pos[j];
-  const int rl = tid / A, p = tid % A, r = rb * RB + rl;
+  const int rl = tid / A, p = tid % A, r = rb * RBn + rl;
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   const float2* trow = g.t + (size_t)j * NP * NP + (size_t)r * NP;
   float2 x[B];
@@ -322,18 +326,19 @@ __global__ void __launch_bounds__(col_threads<NP>()) agent_cols_batch(const Reco
 template <int NP, int METHOD>
 __device__ __forceinline__ void agent_rowsinv_body(const Recon& g, const int j0) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = row_cap<NP>();
-  __shared__ float2 tile[RB * S];
+  constexpr int RBn = rb_of<NP>();
+  __shared__ float2 tile[RBn * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
   // PMACE: the table is written to LDS once the loads below are issued;
   // SHARP+ loads it first (each measured the faster for its method)
-  TwiddleFetch<NP, RB * A> twf;
+  TwiddleFetch<NP, RBn * A> twf;
   if constexpr (METHOD == kPMACE) twf.fetch(g.twn, tid);
-  else load_twiddles<NP>(tw, g.twn, tid, RB * A);
-  const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
+  else load_twiddles<NP>(tw, g.twn, tid, RBn * A);
+  const int jl = blockIdx.x / (NP / RBn), rb = blockIdx.x % (NP / RBn);
   const int j = j0 + jl;
   const int2 pj = g.pos[j];
-  const int rl = tid / A, p = tid % A, r = rb * RB + rl;
+  const int rl = tid / A, p = tid % A, r = rb * RBn + rl;
   float2* io = g.stage + ((size_t)jl * NP + r) * NP;
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   float2* trow = g.t + (size_t)j * NP * NP + (size_t)r * NP;
@@ -717,14 +722,15 @@ __global__ void __launch_bounds__(row_threads<NP>()) fit_rows(const Recon* __res
   const Recon& g = *rec;
   if (check_done && *g.done) return;
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = row_cap<NP>();
-  __shared__ float2 tile[RB * S];
+  constexpr int RBn = rb_of<NP>();
+  __shared__ float2 tile[RBn * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  TwiddleFetch<NP, RB * A> twf;  // written to LDS once the loads below are issued
+  TwiddleFetch<NP, RBn * A> twf;  // written to LDS once the loads below are issued
   twf.fetch(g.twn, tid);
-  const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
+  const int jl = blockIdx.x / (NP / RBn), rb = blockIdx.x % (NP / RBn);
   const int2 pj = g.pos[j0 + jl];
-  const int rl = tid / A, p = tid % A, r = rb * RB + rl;
+  const int rl = tid / A, p = tid % A, r = rb * RBn + rl;
   const float2* xrow = g.xhat + (size_t)(pj.x + r) * g.n2 + pj.y;
   float2 x[B];
 #pragma unroll
@@ -1038,12 +1044,13 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) fft2_small(const float2* in, 
 template <int NP, bool INV>
 __global__ void __launch_bounds__(row_threads<NP>()) fft_rows(const float2* in, float2* out, float scale) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = row_cap<NP>();
-  __shared__ float2 tile[RB * S];
+  constexpr int RBn = rb_of<NP>();
+  __shared__ float2 tile[RBn * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
-  fill_twiddles<NP>(tw, tid, RB * A);
-  const int jl = blockIdx.x / (NP / RB), rb = blockIdx.x % (NP / RB);
-  const int rl = tid / A, p = tid % A, r = rb * RB + rl;
+  fill_twiddles<NP>(tw, tid, RBn * A);
+  const int jl = blockIdx.x / (NP / RBn), rb = blockIdx.x % (NP / RBn);
+  const int rl = tid / A, p = tid % A, r = rb * RBn + rl;
   const size_t base = ((size_t)jl * NP + r) * NP;
   float2 x[B];
   if constexpr (!INV) {
@@ -1162,7 +1169,7 @@ static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* 
   constexpr int RT = row_threads<NP>(), CT = col_threads<NP>();
   for (int j0 = 0, g = 0; j0 < h.J; j0 += h.chunk, ++g) {
     const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
-    const dim3 rgrid(cnt * (NP / RB)), cgrid(cnt * (NP / CB));
+    const dim3 rgrid(cnt * (NP / rb_of<NP>())), cgrid(cnt * (NP / CB));
     const int2 ct = chunk_tiles[g];
     if (batch_rec) {
       hipLaunchKernelGGL(agent_rows_batch<NP>, rgrid, dim3(RT), 0, st, batch_rec, j0);
@@ -1301,7 +1308,7 @@ template <int NP>
 static void fit_large(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
   for (int j0 = 0; j0 < h.J; j0 += h.chunk) {
     const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
-    hipLaunchKernelGGL(fit_rows<NP>, dim3(cnt * (NP / RB)), dim3(row_threads<NP>()), 0, st, rec, j0,
+    hipLaunchKernelGGL(fit_rows<NP>, dim3(cnt * (NP / rb_of<NP>())), dim3(row_threads<NP>()), 0, st, rec, j0,
                        check_done);
     hipLaunchKernelGGL(fit_cols<NP>, dim3(cnt * (NP / CB)), dim3(col_threads<NP>()), 0, st, rec, j0,
                        check_done);
@@ -1367,7 +1374,7 @@ hipError_t launch_tick(const Recon* recs, const int* fitems, int nf, int max_ite
 template <int NP>
 static void fft_large(int count, const float2* in, float2* out, int inverse, hipStream_t st) {
   const float sc = 1.f / sqrtf((float)NP);  // 1/sqrt(NP) per pass
-  const dim3 rgrid(count * (NP / RB)), cgrid(count * (NP / CB));
+  const dim3 rgrid(count * (NP / rb_of<NP>())), cgrid(count * (NP / CB));
   if (inverse) {
     hipLaunchKernelGGL((fft_cols<NP, true>), cgrid, dim3(col_threads<NP>()), 0, st, in, out, sc);
     hipLaunchKernelGGL((fft_rows<NP, true>), rgrid, dim3(row_threads<NP>()), 0, st, out, out, sc);

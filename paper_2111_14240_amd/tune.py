@@ -6,7 +6,8 @@ csrc/pmace_internal.hpp) plus one run-time default:
     PMACE_GT_K           threads per object pixel in the consensus gather (1, 2, 4)
     PMACE_GATHER_UNROLL  loads in flight per gather thread (8, 16)
     PMACE_GT_C           gather tile width in object pixels (32, 64)
-    PMACE_RB             Np > 128 row passes: patch rows per workgroup (8, 16, 32)
+    PMACE_RB256          Np = 256 row passes: patch rows per workgroup (8, 16, 32)
+    PMACE_RB             Np = 160, 192 row passes: patch rows per workgroup (fixed, 32)
     PMACE_CB             Np > 128 column pass: patch columns per workgroup (16, 32)
     PMACE_CHUNK256       Np > 128: positions per chunk (stage buffer size)
     PMACE_GEO32_A        32-point line split over threads: 4 x 8 or 2 x 16 registers
@@ -15,7 +16,8 @@ csrc/pmace_internal.hpp) plus one run-time default:
 Search (coordinate-wise, every candidate measured on the device):
   1. gather shape (GT_K x unroll x tile width) with the default row/column blocks, scored by
      the iteration time of a Np = 128 and a Np = 256 workload;
-  2. row/column blocks with the default gather, scored on the Np = 256 workload;
+  2. row/column blocks with the default gather, scored on the Np = 256 workload
+     (the row block found applies to 256-point lines; 160 and 192 keep PMACE_RB);
   3. the line-FFT split (radix) of Np = 32 and 64, each on a workload of its size;
   4. the chunk size, at run time, with the combined choice.
 Each candidate library is built into a scratch directory and timed in a
@@ -39,8 +41,8 @@ import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned.json")
-DEFAULTS = {"PMACE_GT_K": 1, "PMACE_GATHER_UNROLL": 8, "PMACE_GT_C": 64, "PMACE_RB": 16, "PMACE_CB": 16,
-            "PMACE_GEO32_A": 4, "PMACE_GEO64_A": 8}
+DEFAULTS = {"PMACE_GT_K": 1, "PMACE_GATHER_UNROLL": 8, "PMACE_GT_C": 64, "PMACE_RB": 32, "PMACE_RB256": 16,
+            "PMACE_CB": 16, "PMACE_GEO32_A": 4, "PMACE_GEO64_A": 8}
 GATHER_SPACE = [(k, u, c) for k in (1, 2, 4) for u in (8, 16) for c in (64, 32)]
 BLOCK_SPACE = [(rb, cb) for rb in (8, 16, 32) for cb in (16, 32)]
 GEO_SPACE = [(32, 2), (64, 4)]          # the non-default splits
@@ -58,7 +60,7 @@ def candidates():
         d = dict(DEFAULTS, PMACE_GT_K=k, PMACE_GATHER_UNROLL=u, PMACE_GT_C=c)
         out[f"g{k}u{u}" + ("" if c == 64 else f"c{c}")] = d
     for rb, cb in BLOCK_SPACE:
-        d = dict(DEFAULTS, PMACE_RB=rb, PMACE_CB=cb)
+        d = dict(DEFAULTS, PMACE_RB256=rb, PMACE_CB=cb)
         out[f"rb{rb}cb{cb}"] = d
     for n, a in GEO_SPACE:
         d = dict(DEFAULTS, **{f"PMACE_GEO{n}_A": a})
@@ -170,7 +172,7 @@ def _pick(cands, times):
     d["PMACE_GATHER_UNROLL"] = cands[best_g]["PMACE_GATHER_UNROLL"]
     d["PMACE_GT_C"] = cands[best_g].get("PMACE_GT_C", 64)
     rb, cb = best_b[2:].split("cb")
-    d["PMACE_RB"], d["PMACE_CB"] = int(rb), int(cb)
+    d["PMACE_RB256"], d["PMACE_CB"] = int(rb), int(cb)
     # line splits: the default build's time on each size against the variant's
     if "np32" in base:
         for n, a in GEO_SPACE:
