@@ -164,8 +164,9 @@ def _pick(cands, times):
     # geometric mean of the speedups over the default on both workloads
     score = {n: math.sqrt((base["np128"] / t["np128"]) * (base["np256"] / t["np256"])) for n, t in g.items()}
     best_g = max(score, key=score.get)
-    b = {n: t["np256"] for n, t in times.items() if n.startswith("rb")}
-    b["rb16cb16"] = base["np256"]
+    # the default first, so that a tie keeps it
+    b = {"rb16cb16": base["np256"]}
+    b.update({n: t["np256"] for n, t in times.items() if n.startswith("rb")})
     best_b = min(b, key=b.get)
     d = dict(DEFAULTS)
     d["PMACE_GT_K"] = cands[best_g]["PMACE_GT_K"]
