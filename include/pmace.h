@@ -61,7 +61,8 @@ typedef struct {
   uint32_t flags;     /* PMACE_CENTERED_DC or 0 */
   int32_t chunk;      /* Np > 128 only: at most this many positions per staging chunk
                          (>= 1, capped at J; the chunks are then evened out),
-                         0 = the build's tuned default */
+                         0 = the build's tuned default for Np = 256, scaled by
+                         256^2/Np^2 so that every side stages about as many bytes */
   int32_t method;     /* PMACE_METHOD_PMACE (alpha, kappa, rho used) or PMACE_METHOD_SHARP_PLUS */
   float beta;         /* SHARP+ relaxation, 0 <= beta <= 1 (Alg. 2); ignored by PMACE */
 } pmace_params;

@@ -107,7 +107,10 @@ bool np_large(int np) { return np > 128; }
 // Np > 128 stages chunk*Np^2 spectra between its three passes.
 int chunk_of(const pmace_params& p) {
   int c = p.num_pos;
-  if (np_large(p.np)) c = p.chunk > 0 ? p.chunk : PMACE_CHUNK256;
+  // default: the tuned bound for 256-point patches, scaled so that every
+  // patch side stages about the same bytes per chunk
+  if (np_large(p.np))
+    c = p.chunk > 0 ? p.chunk : (int)((long long)PMACE_CHUNK256 * 256 * 256 / ((long long)p.np * p.np));
   if (c > p.num_pos) c = p.num_pos;
   // the same number of chunks, evened out (no small last chunk)
   const int n = (p.num_pos + c - 1) / c;
