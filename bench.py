@@ -492,7 +492,7 @@ def main():
                    "method": "SHARP+ (Alg. 2)" if sharp else "PMACE (Alg. 1)",
                    **({"beta": args.beta} if sharp else {"alpha": alpha, "kappa": kappa, "rho": rho}),
                    "chunk": args.chunk,
-                   "iteration_graph": "HIP graphs of 8 iterations (single-iteration graph for the rest)"},
+                   "iteration_graph": "HIP graphs of 32 iterations (single-iteration graph for the rest)"},
         "roofline": {"bound": "hbm", "kernel": iteration_kernels(np_, J, args.method),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(key),

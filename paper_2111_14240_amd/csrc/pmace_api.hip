@@ -517,7 +517,7 @@ pmace_status pmace_iterate(pmace_ctx* c, int32_t n_iter) {
   ++c->resets;
   // One graph replays one iteration; a second replays kGraphIters of them in
   // a row, so long runs pay one launch per kGraphIters iterations.
-  constexpr int kGraphIters = 8;
+  constexpr int kGraphIters = 32;
   if (!c->graph_tried && graphs_enabled()) {
     c->graph_tried = true;
     (void)capture(c->graph, [&](hipStream_t cs) { return enqueue_iteration(c, cs); });
