@@ -67,6 +67,13 @@ def iteration_kernels(np_, J, method="pmace"):
             f"agent_rowsinv <{np_}> + consensus_gather<{np_}>, then image_update")
 
 
+def raster_overhang(n, np_, scan, step):
+    """Note for a centred raster wider than the object: its edge positions are
+    clamped to the object (so the outermost steps are shorter)."""
+    ov = (scan - 1) * step + np_ - n
+    return f"; the raster overhangs the object by {ov} px, edge rows and columns clamped" if ov > 0 else ""
+
+
 def workload_key(config, method, np_override):
     """Row name of a workload in the traffic table: the config, then the
     variant ('c3', 'c3-sharp', 'c3-np192')."""
@@ -487,7 +494,8 @@ def main():
         "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": f"{key}: object {prob.n1}x{prob.n2}, probe {np_}x{np_}, "
-                               f"{J} positions ({cfg['scan']}x{cfg['scan']} raster, step {cfg['step']} px), "
+                               f"{J} positions ({cfg['scan']}x{cfg['scan']} raster, step {cfg['step']} px"
+                               f"{raster_overhang(prob.n1, np_, cfg['scan'], cfg['step'])}), "
                                f"Poisson peak {cfg['peak']}",
                    "method": "SHARP+ (Alg. 2)" if sharp else "PMACE (Alg. 1)",
                    **({"beta": args.beta} if sharp else {"alpha": alpha, "kappa": kappa, "rho": rho}),

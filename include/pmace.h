@@ -45,6 +45,18 @@ typedef enum {
 /* Intensities are stored with the zero frequency at the array centre
  * (fftshift layout); they are reordered once at init. */
 #define PMACE_CENTERED_DC 0x1u
+/* Agent variant for large patches (results agree to rounding; both are
+ * exact algebra of eq. (9) and Alg. 1).  By default PMACE with np = 192 or
+ * 256 and a probe without exact zeros keeps each state as the four coset
+ * blocks of the top radix-2 step of its 2-D DFT, so every agent runs on
+ * (np/2)^2 blocks held on chip and no spectrum is staged through memory;
+ * SHARP+, and probes with zeros (where eq. (9)'s d = 0 rule acts per pixel),
+ * run the three-pass agent that stages each chunk's spectra.
+ *   PMACE_STAGED_AGENT: use the three-pass agent for np = 192, 256 as well.
+ *   PMACE_SPLIT_AGENT:  use the coset-block agent for np = 128 too (64^2
+ *                       blocks) instead of the one-workgroup-per-patch one. */
+#define PMACE_STAGED_AGENT 0x2u
+#define PMACE_SPLIT_AGENT 0x4u
 
 /* Iteration run by a context (pmace_params.method). */
 #define PMACE_METHOD_PMACE 0      /* Alg. 1: Mann iteration of T = (2G - I)(2F - I) */
@@ -58,7 +70,7 @@ typedef struct {
   float alpha;        /* >= 0: noise-to-signal weight of the agent, eq. (9) */
   float kappa;        /* >= 0: probe exponent of the consensus weights, eq. (11) */
   float rho;          /* 0 < rho < 1: Mann averaging parameter, eq. (13) */
-  uint32_t flags;     /* PMACE_CENTERED_DC or 0 */
+  uint32_t flags;     /* PMACE_CENTERED_DC, PMACE_STAGED_AGENT, PMACE_SPLIT_AGENT or 0 */
   int32_t chunk;      /* Np > 128 only: at most this many positions per staging chunk
                          (>= 1, capped at J; the chunks are then evened out),
                          0 = the build's tuned default for Np = 256, scaled by
@@ -185,8 +197,10 @@ typedef struct {
 
 /* Device workspace bytes a batch of these members needs (0 if invalid). */
 size_t pmace_batch_footprint(pmace_ctx* const* ctxs, int32_t n);
-/* Members must be distinct, on one device and stream.  The workspace is owned
- * by the caller.  A member's stop flag and NRMSE history belong to the member
+/* Members must be distinct, on one device and stream, and stay alive until
+ * the batch is destroyed (pmace_batch_destroy first, then pmace_destroy).
+ * pmace_set_reference on a member also updates the batch's copy of it.  The
+ * workspace is owned by the caller.  A member's stop flag and NRMSE history belong to the member
  * (reset by pmace_set_reference), so a member moved into a new batch carries
  * on where it stopped; pmace_iterate clears the stop flag. */
 pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_stop_rule* rule,

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "pmace.h"
@@ -64,6 +65,9 @@ struct pmace_ctx {
   bool graph_tried;
   pmace_status sticky;            // first asynchronous failure seen
   unsigned long long resets;      // times the host cleared the stop flag
+  // batches holding a copy of this context's descriptor (and its index there):
+  // pmace_set_reference updates those copies too
+  std::vector<std::pair<pmace_batch*, int>> holders;
 };
 
 struct pmace_batch {
@@ -251,6 +255,11 @@ __global__ void reset_tracking_k(int* done, double* track) {
   track[5] = __builtin_inf();
   track[6] = __builtin_inf();
 }
+
+// Copy a member's host descriptor into a batch's descriptor array.
+hipError_t batch_recs_update(pmace_batch* b, int i, const Recon& h, hipStream_t st);
+// Drop a destroyed member's entry from a batch (the batch can then only be destroyed).
+void batch_forget(pmace_batch* b, int i);
 
 }  // namespace
 
@@ -577,6 +586,9 @@ pmace_status pmace_set_reference(pmace_ctx* c, const void* xref_d, const uint8_t
   c->h.mask = xref_d ? const_cast<unsigned char*>(mask_d) : nullptr;
   if (hipMemcpyAsync(c->dev, &c->h, sizeof(Recon), hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return record(c, PMACE_EDEVICE);
+  // a batch reads its members through its own copies of their descriptors
+  for (const auto& hb : c->holders)
+    if (batch_recs_update(hb.first, hb.second, c->h, c->stream) != hipSuccess) return record(c, PMACE_EDEVICE);
   hipLaunchKernelGGL(reset_tracking_k, dim3(1), dim3(1), 0, c->stream, c->h.done, c->h.track);
   ++c->resets;
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
@@ -630,6 +642,8 @@ pmace_status pmace_sync(pmace_ctx* c) {
 
 void pmace_destroy(pmace_ctx* c) {
   if (!c) return;
+  // a batch still holding this context (a caller error) must not reach it
+  for (const auto& hb : c->holders) batch_forget(hb.first, hb.second);
   (void)hipStreamSynchronize(c->stream);
   c->graph.release();
   c->graph_k.release();
@@ -757,7 +771,20 @@ pmace_status drop_graphs(pmace_batch* b) {
   return PMACE_OK;
 }
 
+hipError_t batch_recs_update(pmace_batch* b, int i, const Recon& h, hipStream_t st) {
+  return hipMemcpyAsync(b->recs + i, &h, sizeof(Recon), hipMemcpyHostToDevice, st);
+}
+
+void batch_forget(pmace_batch* b, int i) { b->ctxs[i] = nullptr; }
+
 void batch_release(pmace_batch* b) {
+  for (pmace_ctx* c : b->ctxs) {
+    if (!c) continue;
+    auto& hs = c->holders;
+    for (size_t k = 0; k < hs.size();)
+      if (hs[k].first == b) hs.erase(hs.begin() + (long)k);
+      else ++k;
+  }
   b->graph.release();
   b->graph_check.release();
   for (int l = 0; l < 4; ++l) {
@@ -854,6 +881,7 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
     batch_release(b);
     return PMACE_EDEVICE;
   }
+  for (int i = 0; i < n; ++i) ctxs[i]->holders.emplace_back(b, i);
   *out = b;
   return PMACE_OK;
 }

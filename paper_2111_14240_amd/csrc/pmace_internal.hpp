@@ -40,6 +40,8 @@ static_assert(GT_C == 32 || GT_C == 64, "gather tile width must be 32 or 64");
 constexpr int GT_THREADS = GT_R * GT_C * GT_K;
 // NRMSE reduction: RED_PX object pixels per block of RED_T threads.
 constexpr int RED_T = 256, RED_PX = 4096;
+// Base tile of the split-layout consensus: QT_R x QT_C pixels, one thread each.
+constexpr int QT_R = 8, QT_C = 32, QT_THREADS = QT_R * QT_C;
 
 // Device-resident description of one reconstruction.  It lives in the
 // reconstruction's workspace; batched launches read an array of them.
@@ -90,6 +92,20 @@ struct Recon {
   int has_zero;         // the probe has exact zeros (the agent's d == 0 rule applies)
   float cx, co, cn;     // PMACE: xbar' = cx xbar + Lambda^{-1} (co S_old - cn S_new):
                         //   cx = 2 (1 - rho), co = (1 - rho)/rho, cn = 1/rho
+  // Split (coset) layout, PMACE with Np = 2M and a probe without zeros: each
+  // state is kept as its four blocks Z_ab (a, b in {0, 1}) of the top radix-2
+  // step of the transform,
+  //   Z_ab[m] = W_Np^{a m1 + b m2} sum_q (-1)^{a q1 + b q2} s[m + M q],  m, q in [0,M)^2 x {0,1}^2,
+  // whose M x M DFT is the patch spectrum at the frequencies (2 k1 + a, 2 k2 + b);
+  // the amplitudes are stored in the same coset order.
+  int split;            // 1: t, ys and the data-fit partials in the split layout
+  float2* etab;         // 16 M^2: window coefficients 2 rho (-1)^{a q1 + b q2} W_Np^{a m1 + b m2} d[m + M q],
+                        //   table (2a + b) * 4 + (2 q1 + q2)
+  float2* part;         // 4 N1 N2: partial consensus sums, one image per quadrant q = 2 q1 + q2
+  int4* qtiles;         // per base tile: (list start, count, first row, first col)
+  int* qlist;           // positions whose quadrant-0 block meets each base tile, ascending
+  int qrows, qcols;     // base tiles cover rows [0, qrows) and columns [0, qcols)
+  int nqt;              // number of base tiles
 };
 
 // Kernel launchers (stream-ordered; return the hipError_t of the launches).
@@ -134,5 +150,13 @@ hipError_t launch_fit_finish(const Recon* recs, const int* fitems, int nf, int u
 hipError_t launch_tick(const Recon* recs, const int* fitems, int nf, int max_iter, int cap,
                        hipStream_t st);
 hipError_t launch_fft2(int np, int count, const float2* in, float2* out, int inverse, hipStream_t st);
+// Split layout (h.split): one iteration (agent on every (position, coset),
+// consensus over the base tiles, image update); rec = the device descriptor,
+// check_done: skip if the stop flag is set (batch members).
+hipError_t launch_split_iteration(const Recon& h, const Recon* rec, int check_done, hipStream_t st);
+// Split layout: the consensus sum of the current states into part, then
+// mode 0: sold = S (after init), mode 1: xhat = Lambda^{-1} S and sold = S
+// (after set_state).
+hipError_t launch_split_consensus(const Recon& h, const Recon* rec, int mode, hipStream_t st);
 
 }  // namespace pmace

@@ -125,30 +125,62 @@ __device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2*
 // Np <= 128: the whole patch lives in LDS; one workgroup per work item
 // (reconstruction, position) does a2-a7 in one pass (rows, columns, state
 // spectrum, columns, rows, new state).
+//
+// SPLIT: the same pass on one coset block of a split-layout state (Np = 2 NP,
+// see Recon::split).  The top radix-2 step of the Np-point transform, taken
+// outside, turns the patch into four independent NP x NP problems: the block
+// Z_ab of the frame d v = s + 2 rho d P_j xbar is the stored block of s plus
+//     sum_q e_{ab,q}[m] xbar[p_j + m + NP q]   (e = etab: 2 rho, sign, twiddle, d),
+// its NP x NP DFT is the patch spectrum at the frequencies (2 k1 + a, 2 k2 + b),
+// the state spectrum is formed there with the amplitudes stored in the same
+// order, and 4 x its unnormalised inverse is the block Z_ab of the new state
+// (the inverse of the split step gives 4 s' per block).  The NP-point
+// transforms use W_NP^m = W_Np^{2m}.
 // -------------------------------------------------------------------------
-template <int NP, int METHOD>
-__device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
+__device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 acc) {
+  return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
+}
+
+template <int NP, int METHOD, bool SPLIT = false>
+__device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, const int ab = 0) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, S = NP + A, NT = NP * A, M = B / A;
   static_assert(exch_phases<NP>() == 1, "the whole-patch tile exchanges in one round");
+  static_assert(!SPLIT || METHOD == kPMACE, "the split layout is PMACE's");
   __shared__ float2 tile[NP * S];
   __shared__ float2 tw[NP];
   const int tid = threadIdx.x;
   const int2 pj = g.pos[j];
-  const size_t pb = (size_t)j * NP * NP;
+  const size_t pb = SPLIT ? ((size_t)j * 4 + ab) * NP * NP : (size_t)j * NP * NP;
   const int r = tid / A, p = tid % A;
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   float2* trow = g.t + pb + (size_t)r * NP;
   const float two_rho = g.two_rho;
 
   float2 x[B];
+  if constexpr (SPLIT) {
+    const float2* e = g.etab + (size_t)ab * 4 * NP * NP + (size_t)r * NP;
+    const size_t down = (size_t)NP * g.n2;   // NP object rows further
 #pragma unroll
-  for (int nb = 0; nb < B; ++nb) {
-    const int c = p + A * nb;
-    x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], two_rho);
+    for (int nb = 0; nb < B; ++nb) {
+      const int c = p + A * nb;
+      float2 f = trow[c];
+      f = cfma(e[c], xrow[c], f);
+      f = cfma(e[NP * NP + c], xrow[c + NP], f);
+      f = cfma(e[2 * NP * NP + c], xrow[down + c], f);
+      f = cfma(e[3 * NP * NP + c], xrow[down + c + NP], f);
+      x[nb] = f;
+    }
+    for (int m = tid; m < NP; m += NT) tw[m] = g.twn[2 * m];
+  } else {
+#pragma unroll
+    for (int nb = 0; nb < B; ++nb) {
+      const int c = p + A * nb;
+      x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], two_rho);
+    }
+    // the twiddle table after the frame's loads, so the two are in flight
+    // together (the row transforms wait for both anyway)
+    load_twiddles<NP>(tw, g.twn, tid, NT);
   }
-  // the twiddle table after the frame's loads, so the two are in flight
-  // together (the row transforms wait for both anyway)
-  load_twiddles<NP>(tw, g.twn, tid, NT);
   // amplitudes of the column phase, fetched now so their latency hides
   // behind the row transforms
   const int c = tid % NP, q = tid / NP;
@@ -171,10 +203,16 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) x[nb] = tile[(q + A * nb) * S + c];
   col_fwd<NP>(x, tile, S, c, q, tw);
+  if constexpr (SPLIT) {
+    const float sb = 4.f * g.sb, s2r = 4.f * g.s2r;   // exact: powers of two
 #pragma unroll
-  for (int m = 0; m < M; ++m)
+    for (int k = 0; k < B; ++k) x[k] = state_spectrum(x[k], yv[k], sb, s2r);
+  } else {
 #pragma unroll
-    for (int ka = 0; ka < A; ++ka) x[m * A + ka] = spectrum_step<METHOD>(x[m * A + ka], yv[m * A + ka], g);
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) x[m * A + ka] = spectrum_step<METHOD>(x[m * A + ka], yv[m * A + ka], g);
+  }
   col_inv<NP>(x, tile, S, c, q, tw);
   __syncthreads();
 #pragma unroll
@@ -187,11 +225,16 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j) {
     for (int ka = 0; ka < A; ++ka) x[m * A + ka] = row[p + A * m + B * ka];
   row_inv<NP>(x, row, p, tw);
 
-  float2* urow = g.stage + pb + (size_t)r * NP;  // SHARP+ only
+  if constexpr (SPLIT) {
 #pragma unroll
-  for (int nb = 0; nb < B; ++nb) {
-    const int cc = p + A * nb;
-    agent_output<METHOD>(x[nb], &trow[cc], &xrow[cc], r * NP + cc, g, &urow[cc]);
+    for (int nb = 0; nb < B; ++nb) trow[p + A * nb] = x[nb];
+  } else {
+    float2* urow = g.stage + pb + (size_t)r * NP;  // SHARP+ only
+#pragma unroll
+    for (int nb = 0; nb < B; ++nb) {
+      const int cc = p + A * nb;
+      agent_output<METHOD>(x[nb], &trow[cc], &xrow[cc], r * NP + cc, g, &urow[cc]);
+    }
   }
 }
 
@@ -209,6 +252,23 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused_batch(const Recon
   const Recon& g = recs[it.x];
   if (*g.done) return;
   agent_fused_body<NP, kPMACE>(g, it.y);
+}
+
+// Split layout, Np = 2 M: one workgroup per (position, coset).  Workgroups
+// are dealt to the XCDs in turn (block b runs on XCD b mod 8), so block b
+// takes position xcd * jper + (b / 8) / 4 and coset (b / 8) mod 4: the four
+// cosets of a position, which read the same consensus window, share an XCD's
+// L2, and each XCD works through a contiguous run of positions (a band of
+// the object).
+template <int M>
+__global__ void __launch_bounds__(M * Geo<M>::A) agent_split(const Recon* __restrict__ rec, int check_done,
+                                                             int jper) {
+  const Recon& g = *rec;
+  if (check_done && *g.done) return;
+  const int b = blockIdx.x, slot = b >> 3;
+  const int j = (b & 7) * jper + (slot >> 2);
+  if (j >= g.J) return;
+  agent_fused_body<M, kPMACE, true>(g, j, slot & 3);
 }
 
 // -------------------------------------------------------------------------
@@ -571,9 +631,36 @@ __global__ void sold_from_num(const Recon* __restrict__ rec) {
 // a10: NRMSE (eq. (17)) of xhat against a reference, per reconstruction.
 // theta = arg sum conj(xref) xhat minimises the numerator, so
 //   e^2 = (sum |xhat|^2 + sum |xref|^2 - 2 |sum conj(xref) xhat|) / sum |xref|^2.
-// Two deterministic stages: per-block FP64 partial sums, then one block per
-// reconstruction sums the partials in a fixed order.
+// Two deterministic stages: per-block FP64 partial sums (wavefront shuffles,
+// then the waves in order), then one block per reconstruction sums the
+// partials the same way.
 // -------------------------------------------------------------------------
+// Sums v[0..N) over a block of RED_T threads: a butterfly of wavefront
+// shuffles inside each wave, then the per-wave sums added in wave order by
+// thread 0 (the only thread whose v holds the totals afterwards).  The order
+// is fixed, so the result is bitwise reproducible.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N]) {
+  static_assert(RED_T % 64 == 0 && RED_T <= 1024, "whole wavefronts");
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += __shfl_xor(v[q], off);
+  __shared__ double ws[N][RED_T / 64];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int q = 0; q < N; ++q) ws[q][w] = v[q];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      double t = ws[q][0];
+      for (int k = 1; k < RED_T / 64; ++k) t += ws[q][k];
+      v[q] = t;
+    }
+}
+
 // update_stop = 0 evaluates on demand, also for stopped reconstructions.
 __global__ void __launch_bounds__(RED_T) nrmse_partial(const Recon* __restrict__ recs,
                                                        const int2* __restrict__ items, int update_stop) {
@@ -593,16 +680,9 @@ __global__ void __launch_bounds__(RED_T) nrmse_partial(const Recon* __restrict__
       acc[3] += (double)xr.x * xr.x + (double)xr.y * xr.y;   // |xref|^2
     }
   }
-  __shared__ double sh[4][RED_T];
-  for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = acc[q];
-  __syncthreads();
-  for (int w = RED_T / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
-    __syncthreads();
-  }
+  block_sum<4>(acc);
   if (threadIdx.x == 0)
-    for (int q = 0; q < 4; ++q) g.red[4 * it.y + q] = sh[q][0];
+    for (int q = 0; q < 4; ++q) g.red[4 * it.y + q] = acc[q];
 }
 
 __global__ void __launch_bounds__(RED_T) nrmse_finish(const Recon* __restrict__ recs,
@@ -610,21 +690,14 @@ __global__ void __launch_bounds__(RED_T) nrmse_finish(const Recon* __restrict__ 
                                                       float tol, int min_iter) {
   const Recon& g = recs[items[blockIdx.x]];
   if ((update_stop && *g.done) || !g.xref) return;
-  __shared__ double sh[4][RED_T];
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < g.n_red; b += RED_T)
     for (int q = 0; q < 4; ++q) acc[q] += g.red[4 * b + q];
-  for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = acc[q];
-  __syncthreads();
-  for (int w = RED_T / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
-    __syncthreads();
-  }
+  block_sum<4>(acc);
   if (threadIdx.x != 0) return;
-  const double sref = sh[3][0];
-  const double c = sqrt(sh[0][0] * sh[0][0] + sh[1][0] * sh[1][0]);
-  const double e2 = (sh[2][0] + sref - 2.0 * c) / (sref > 0.0 ? sref : 1.0);
+  const double sref = acc[3];
+  const double c = sqrt(acc[0] * acc[0] + acc[1] * acc[1]);
+  const double e2 = (acc[2] + sref - 2.0 * c) / (sref > 0.0 ? sref : 1.0);
   const double e = sqrt(e2 > 0.0 ? e2 : 0.0);
   const double prev = g.track[1];
   g.track[0] = sref;
@@ -790,17 +863,11 @@ __global__ void __launch_bounds__(RED_T) fit_finish(const Recon* __restrict__ re
   const Recon& g = recs[items[blockIdx.x]];
   if (update_stop && *g.done) return;
   const int n = g.J * g.fit_bpp;
-  __shared__ double sh[RED_T];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < n; i += RED_T) acc += g.fit[i];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = RED_T / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-    __syncthreads();
-  }
+  double acc[1] = {0.0};
+  for (int i = threadIdx.x; i < n; i += RED_T) acc[0] += g.fit[i];
+  block_sum<1>(acc);
   if (threadIdx.x != 0) return;
-  const double cst = sh[0];
+  const double cst = acc[0];
   if (!update_stop) {  // on demand: leaves the stop rule's history alone
     g.track[6] = cst;
     return;
@@ -838,11 +905,16 @@ __global__ void init_amplitudes_k(const Recon* __restrict__ rec, const float* z,
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   long long src = i;
-  if (centered) {
+  if (centered || g.split) {
     const long long j = i / per;
     const int rem = (int)(i - j * per);
-    const int k = rem / g.np, l = rem - k * g.np;
-    const int h = g.np / 2;
+    int k = rem / g.np, l = rem - k * g.np;
+    if (g.split) {  // element m of coset block ab holds the frequency (2 m1 + a, 2 m2 + b)
+      const int M = g.np / 2, ab = rem / (M * M), m = rem - ab * M * M;
+      k = 2 * (m / M) + (ab >> 1);
+      l = 2 * (m % M) + (ab & 1);
+    }
+    const int h = centered ? g.np / 2 : 0;
     src = j * per + (long long)((k + h) % g.np) * g.np + (l + h) % g.np;
   }
   const float zz = z[src];
@@ -1108,6 +1180,227 @@ __global__ void __launch_bounds__(col_threads<NP>()) fft_cols(const float2* in, 
 }
 
 // -------------------------------------------------------------------------
+// Split layout (Np = 2M): consensus, image update, states, data fit
+// -------------------------------------------------------------------------
+// Consensus sum S = sum_j P_j^t (|d|^kappa / d) s_j from split-layout states.
+// A workgroup owns a QT_R x QT_C base tile T; for every position whose
+// quadrant-0 block [p_j, p_j + M)^2 meets T (list ascending in j), each pixel
+// of T at m = R - p_j undoes the split step from the four blocks at m,
+//     s[m + M q] = 1/4 sum_ab (-1)^{a q1 + b q2} W_Np^{-(a m1 + b m2)} Z_ab[m],
+// and adds the weighted values to the pixels T + M q: one partial sum per
+// quadrant q, written to part[q] (each block value is read once).  The image
+// update adds the four partials in the order q = 0..3.
+template <int M>
+__device__ __forceinline__ void consensus_split_body(const Recon& g, const int tile) {
+  constexpr int NP = 2 * M, MM = M * M, LIST = 256;
+  __shared__ int3 sl[LIST];
+  __shared__ float2 tw[NP];
+  const int tid = threadIdx.x;
+  for (int m = tid; m < NP; m += QT_THREADS) tw[m] = g.twn[m];
+  const int4 ti = g.qtiles[tile];
+  const int R = ti.z + tid / QT_C, C = ti.w + tid % QT_C;
+  float2 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = make_float2(0.f, 0.f);
+  for (int b0 = 0; b0 < ti.y; b0 += LIST) {
+    const int nb = ti.y - b0 < LIST ? ti.y - b0 : LIST;
+    if (b0 > 0) __syncthreads();
+    for (int i = tid; i < nb; i += QT_THREADS) {
+      const int j = g.qlist[ti.x + b0 + i];
+      const int2 pj = g.pos[j];
+      sl[i] = make_int3(j, pj.x, pj.y);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int i = 0; i < nb; ++i) {
+      const int3 e = sl[i];
+      const unsigned rr = (unsigned)(R - e.y), cc = (unsigned)(C - e.z);
+      const bool in = rr < (unsigned)M && cc < (unsigned)M;
+      // lanes outside the block read its first pixel with zero weights
+      const int m1 = in ? (int)rr : 0, m2 = in ? (int)cc : 0;
+      const float2* z = g.t + (size_t)e.x * 4 * MM + m1 * M + m2;
+      const float2 z00 = z[0], z01 = z[MM], z10 = z[2 * MM], z11 = z[3 * MM];
+      const float2* w = g.gw + m1 * NP + m2;
+      const float2 zero = make_float2(0.f, 0.f);
+      const float2 c0 = in ? w[0] : zero, c1 = in ? w[M] : zero;
+      const float2 c2 = in ? w[M * NP] : zero, c3 = in ? w[M * NP + M] : zero;
+      const float2 t01 = cmulc(z01, tw[m2]), t10 = cmulc(z10, tw[m1]), t11 = cmulc(z11, tw[m1 + m2]);
+      const float2 u0 = cadd(z00, t01), u1 = csub(z00, t01), u2 = cadd(t10, t11), u3 = csub(t10, t11);
+      acc[0] = cfma(c0, cadd(u0, u2), acc[0]);
+      acc[1] = cfma(c1, cadd(u1, u3), acc[1]);
+      acc[2] = cfma(c2, csub(u0, u2), acc[2]);
+      acc[3] = cfma(c3, csub(u1, u3), acc[3]);
+    }
+  }
+  const size_t npx = (size_t)g.n1 * g.n2;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int Rq = R + M * (q >> 1), Cq = C + M * (q & 1);
+    if (Rq < g.n1 && Cq < g.n2) g.part[q * npx + (size_t)Rq * g.n2 + Cq] = cscale(acc[q], 0.25f);
+  }
+}
+
+template <int M>
+__global__ void __launch_bounds__(QT_THREADS) consensus_split(const Recon* __restrict__ rec, int check_done) {
+  const Recon& g = *rec;
+  if (check_done && *g.done) return;
+  consensus_split_body<M>(g, blockIdx.x);
+}
+
+// S at one pixel: the partial sums of the quadrants whose base tiles cover
+// it, added in the order q = 0..3.
+__device__ __forceinline__ float2 split_sum(const Recon& g, int R, int C) {
+  const size_t npx = (size_t)g.n1 * g.n2, px = (size_t)R * g.n2 + C;
+  const int M = g.np / 2;
+  float2 S = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int rb = R - M * (q >> 1), cb = C - M * (q & 1);
+    if (rb >= 0 && rb < g.qrows && cb >= 0 && cb < g.qcols) S = cadd(S, g.part[q * npx + px]);
+  }
+  return S;
+}
+
+// a9 for the split layout.
+__global__ void image_update_split(const Recon* __restrict__ rec, int check_done) {
+  const Recon& g = *rec;
+  if (check_done && *g.done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n1 * g.n2) return;
+  finish_image<kPMACE>(g, i, split_sum(g, i / g.n2, i % g.n2));
+}
+
+// After init (mode 0): S of the initial states; after set_state (mode 1):
+// also xhat = Lambda^{-1} S (xbar was cleared).
+__global__ void image_from_split(const Recon* __restrict__ rec, int mode) {
+  const Recon& g = *rec;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n1 * g.n2) return;
+  const float2 S = split_sum(g, i / g.n2, i % g.n2);
+  g.sold[i] = S;
+  if (mode == 1) g.xhat[i] = cscale(S, g.laminv[i]);
+}
+
+// The split step of a frame f = d * (patch of img) for block ab at m:
+//   W_Np^{a m1 + b m2} sum_q (-1)^{a q1 + b q2} d[m + M q] img[p + m + M q].
+// img == nullptr stands for the object 1 + 0i (the default start).
+__device__ __forceinline__ float2 split_frame(const Recon& g, int2 pj, int ab, int m1, int m2,
+                                              const float2* img) {
+  const int M = g.np / 2, a = ab >> 1, b = ab & 1;
+  float2 h = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int q1 = q >> 1, q2 = q & 1;
+    const int r = m1 + M * q1, c = m2 + M * q2;
+    const float2 x = img ? img[(size_t)(pj.x + r) * g.n2 + pj.y + c] : make_float2(1.f, 0.f);
+    const float2 f = cmul(g.d[r * g.np + c], x);
+    h = ((a * q1 + b * q2) & 1) ? csub(h, f) : cadd(h, f);
+  }
+  return cmul(h, g.twn[a * m1 + b * m2]);
+}
+
+// Split-layout states from an object (Alg. 1 line 1, v_j = P_j x0, stored
+// as d v in blocks): element i of block ab of position j.
+__global__ void init_split_k(const Recon* __restrict__ rec, const float2* x0) {
+  const Recon& g = *rec;
+  const int M = g.np / 2, MM = M * M;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)g.J * 4 * MM) return;
+  const int j = (int)(i / (4 * MM)), rem = (int)(i - (long long)j * 4 * MM);
+  const int ab = rem / MM, m = rem - ab * MM;
+  g.t[i] = split_frame(g, g.pos[j], ab, m / M, m % M, x0);
+}
+
+// set_state in the split layout: blocks of d v from the given states v.
+__global__ void set_state_split_k(const Recon* __restrict__ rec, const float2* __restrict__ v) {
+  const Recon& g = *rec;
+  const int M = g.np / 2, MM = M * M, np = g.np;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long long)g.J * 4 * MM) return;
+  const int j = (int)(i / (4 * MM)), rem = (int)(i - (long long)j * 4 * MM);
+  const int ab = rem / MM, m = rem - ab * MM, m1 = m / M, m2 = m % M, a = ab >> 1, b = ab & 1;
+  const float2* vj = v + (size_t)j * np * np;
+  float2 h = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int q1 = q >> 1, q2 = q & 1, k = (m1 + M * q1) * np + m2 + M * q2;
+    const float2 f = cmul(g.d[k], vj[k]);
+    h = ((a * q1 + b * q2) & 1) ? csub(h, f) : cadd(h, f);
+  }
+  g.t[i] = cmul(h, g.twn[a * m1 + b * m2]);
+}
+
+// get_state in the split layout: v = d^{-1} s + 2 rho P_j xbar with s undone
+// from the four blocks.
+__global__ void get_state_split_k(const Recon* __restrict__ rec, float2* v) {
+  const Recon& g = *rec;
+  const int np = g.np, M = np / 2, MM = M * M;
+  const long long per = (long long)np * np;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= per * g.J) return;
+  const int j = (int)(i / per);
+  const int rem = (int)(i - (long long)j * per);
+  const int r = rem / np, c = rem - r * np;
+  const int m1 = r % M, m2 = c % M, q1 = r / M, q2 = c / M;
+  const float2* z = g.t + (size_t)j * 4 * MM + m1 * M + m2;
+  float2 s = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int ab = 0; ab < 4; ++ab) {
+    const int a = ab >> 1, b = ab & 1;
+    const float2 u = cmulc(z[ab * MM], g.twn[a * m1 + b * m2]);
+    s = ((a * q1 + b * q2) & 1) ? csub(s, u) : cadd(s, u);
+  }
+  const int2 pj = g.pos[j];
+  const float2 xb = g.xbar[(size_t)(pj.x + r) * g.n2 + pj.y + c];
+  const float2 t = cscale(cmul(g.dinv[rem], cscale(s, 0.25f)), g.np2f);
+  v[i] = mann_v(t, xb, g.two_rho);
+}
+
+// Data-fit cost of eq. (4) in the split layout: the block ab of F(D P_j xhat)
+// per workgroup (frame split as above, M x M forward DFT), against the
+// amplitudes of the same coset.
+template <int M>
+__global__ void __launch_bounds__(M * Geo<M>::A) fit_split(const Recon* __restrict__ rec, int check_done,
+                                                           int jper) {
+  const Recon& g = *rec;
+  if (check_done && *g.done) return;
+  constexpr int A = Geo<M>::A, B = Geo<M>::B, S = M + A, NT = M * A, MB = B / A;
+  const int bi = blockIdx.x, slot = bi >> 3;
+  const int j = (bi & 7) * jper + (slot >> 2), ab = slot & 3;
+  if (j >= g.J) return;
+  __shared__ float2 tile[M * S];
+  __shared__ float2 tw[M];
+  const int tid = threadIdx.x;
+  const int2 pj = g.pos[j];
+  const int r = tid / A, p = tid % A;
+  float2 x[B];
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) x[nb] = split_frame(g, pj, ab, r, p + A * nb, g.xhat);
+  for (int m = tid; m < M; m += NT) tw[m] = g.twn[2 * m];
+  __syncthreads();
+  float2* row = tile + r * S;
+  row_fwd<M>(x, row, p, tw);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) row[p + A * m + B * ka] = x[m * A + ka];
+  __syncthreads();
+  const int c = tid % M, q = tid / M;
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) x[nb] = tile[(q + A * nb) * S + c];
+  col_fwd<M>(x, tile, S, c, q, tw);
+  const float* yc = g.ys + ((size_t)j * 4 + ab) * M * M + c;
+  float acc = 0.f;
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka)
+      acc += fit_term(x[m * A + ka], g.yfac * yc[(size_t)(q + A * m + B * ka) * M]);
+  block_sum_to(acc, &g.fit[(size_t)j * 4 + ab], 0.5 / ((double)g.np * g.np));
+}
+
+// -------------------------------------------------------------------------
 // launchers
 // -------------------------------------------------------------------------
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -1242,13 +1535,59 @@ static hipError_t gather_into_num(const Recon& h, int2 ct, int j0, hipStream_t s
   return hipGetLastError();
 }
 
+template <int M>
+static void split_iteration(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
+  const int jper = (h.J + 7) / 8;
+  hipLaunchKernelGGL(agent_split<M>, dim3(8 * jper * 4), dim3(M * Geo<M>::A), 0, st, rec, check_done, jper);
+  hipLaunchKernelGGL(consensus_split<M>, dim3(h.nqt), dim3(QT_THREADS), 0, st, rec, check_done);
+  hipLaunchKernelGGL(image_update_split, dim3(blocks_for((long long)h.n1 * h.n2, 256)), dim3(256), 0, st,
+                     rec, check_done);
+}
+
+hipError_t launch_split_iteration(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
+  switch (h.np) {
+    case 128: split_iteration<64>(h, rec, check_done, st); break;
+    case 192: split_iteration<96>(h, rec, check_done, st); break;
+    case 256: split_iteration<128>(h, rec, check_done, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_split_consensus(const Recon& h, const Recon* rec, int mode, hipStream_t st) {
+  switch (h.np) {
+    case 128: hipLaunchKernelGGL(consensus_split<64>, dim3(h.nqt), dim3(QT_THREADS), 0, st, rec, 0); break;
+    case 192: hipLaunchKernelGGL(consensus_split<96>, dim3(h.nqt), dim3(QT_THREADS), 0, st, rec, 0); break;
+    case 256: hipLaunchKernelGGL(consensus_split<128>, dim3(h.nqt), dim3(QT_THREADS), 0, st, rec, 0); break;
+    default: return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(image_from_split, dim3(blocks_for((long long)h.n1 * h.n2, 256)), dim3(256), 0, st, rec,
+                     mode);
+  return hipGetLastError();
+}
+
+static hipError_t launch_fit_split(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
+  const int jper = (h.J + 7) / 8;
+  const dim3 grid(8 * jper * 4);
+  switch (h.np) {
+    case 128: hipLaunchKernelGGL(fit_split<64>, grid, dim3(64 * Geo<64>::A), 0, st, rec, check_done, jper); break;
+    case 192: hipLaunchKernelGGL(fit_split<96>, grid, dim3(96 * Geo<96>::A), 0, st, rec, check_done, jper); break;
+    case 256: hipLaunchKernelGGL(fit_split<128>, grid, dim3(128 * Geo<128>::A), 0, st, rec, check_done, jper); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float scale,
                        int centered, const float2* x0, const int2* chunk_tiles, hipStream_t st) {
   const long long total = (long long)h.J * h.np * h.np;
   const long long npx = (long long)h.n1 * h.n2;
   hipLaunchKernelGGL(init_amplitudes_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, z, scale,
                      centered);
-  hipLaunchKernelGGL(init_patches_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, x0);
+  if (h.split)
+    hipLaunchKernelGGL(init_split_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, x0);
+  else
+    hipLaunchKernelGGL(init_patches_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, x0);
   // Lambda in FP64, accumulated in the (still unused) accumulator image
   double* lam = reinterpret_cast<double*>(h.num);
   hipLaunchKernelGGL(zero_f64_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, lam, npx);
@@ -1258,6 +1597,7 @@ hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float s
                          chunk_tiles[g].x, lam);
   hipLaunchKernelGGL(laminv_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec, lam);
   hipLaunchKernelGGL(init_images_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec, x0);
+  if (h.split) return launch_split_consensus(h, rec, 0, st);
   if (h.method == kPMACE) {
     for (int j0 = 0, g = 0; j0 < h.J; j0 += h.chunk, ++g) {
       const hipError_t e = gather_into_num(h, chunk_tiles[g], j0, st);
@@ -1270,7 +1610,10 @@ hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float s
 
 hipError_t launch_get_state(const Recon& h, const Recon* rec, float2* v, hipStream_t st) {
   const long long total = (long long)h.J * h.np * h.np;
-  hipLaunchKernelGGL(get_state_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, v);
+  if (h.split)
+    hipLaunchKernelGGL(get_state_split_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, v);
+  else
+    hipLaunchKernelGGL(get_state_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, v);
   return hipGetLastError();
 }
 
@@ -1279,6 +1622,10 @@ hipError_t launch_set_state(const Recon& h, const Recon* rec, const float2* v,
   const long long npx = (long long)h.n1 * h.n2;
   const long long per = (long long)h.np * h.np;
   hipLaunchKernelGGL(zero_images_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec);
+  if (h.split) {
+    hipLaunchKernelGGL(set_state_split_k, dim3(blocks_for(per * h.J, 256)), dim3(256), 0, st, rec, v);
+    return launch_split_consensus(h, rec, 1, st);
+  }
   for (int j0 = 0, g = 0; j0 < h.J; j0 += h.chunk, ++g) {
     const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
     hipLaunchKernelGGL(set_state_k, dim3(blocks_for(cnt * per, 256)), dim3(256), 0, st, rec, v, j0,
@@ -1316,6 +1663,7 @@ static void fit_large(const Recon& h, const Recon* rec, int check_done, hipStrea
 }
 
 hipError_t launch_fit_member(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
+  if (h.split) return launch_fit_split(h, rec, check_done, st);
   switch (h.np) {
 #define PMACE_FIT(N)                                                                               \
   case N:                                                                                          \

@@ -24,6 +24,8 @@ PMACE_EDEVICE = 4
 PMACE_ESTATE = 5
 PMACE_EDIVERGED = 6
 PMACE_CENTERED_DC = 0x1
+PMACE_STAGED_AGENT = 0x2
+PMACE_SPLIT_AGENT = 0x4
 PMACE_METHOD_PMACE = 0
 PMACE_METHOD_SHARP_PLUS = 1
 PMACE_STOP_NRMSE = 0

@@ -39,6 +39,7 @@ class Request:
     iters: int = 0
     nrmse: float = float("nan")
     result: object = None
+    x0: object = None          # starting object (None: the default start, 1 everywhere)
 
     @property
     def latency(self) -> float:
@@ -268,11 +269,18 @@ class GPUExecutor:
         self.group_of: Dict[int, int] = {}
 
     def footprint(self, prob) -> int:
+        """Device bytes a request holds while active: its workspace, its NRMSE
+        reference and region (8 + 1 B per object pixel), the reconstruction
+        copied out at retirement (8 B per pixel), and a bound on its share of
+        a batch workspace (descriptor, work items, gather items, reduction
+        items)."""
         key = (prob.n1, prob.n2, prob.np_, prob.num_pos)
         if key not in self._fp_cache:
             prm = self._pmace.make_params(prob.n1, prob.n2, prob.np_, prob.num_pos, self.alpha,
                                           self.kappa, self.rho)
-            self._fp_cache[key] = self._pmace.pmace_footprint(prm)
+            npx = prob.n1 * prob.n2
+            batch_share = 1024 + 8 * prob.num_pos + npx // 16 + 8 * (npx // 4096 + 1)
+            self._fp_cache[key] = self._pmace.pmace_footprint(prm) + 17 * npx + batch_share
         return self._fp_cache[key]
 
     def work(self, prob) -> float:
@@ -284,7 +292,8 @@ class GPUExecutor:
         g = self.groups[gi]
         with self._torch.cuda.stream(self.init_stream):
             R = self._pmace.Reconstruction(p.n1, p.n2, p.probe, p.pos, p.z, self.alpha, self.kappa,
-                                           self.rho, device=self.device, stream=self.init_stream)
+                                           self.rho, x0=req.x0, device=self.device,
+                                           stream=self.init_stream)
             R.set_reference(p.x_true, self._synth.roi_mask(p.probe, p.pos, p.n1, p.n2))
         R.set_stream(g["stream"])
         self.active[req.rid] = R

@@ -39,7 +39,7 @@ import numpy as np
 from scipy import ndimage
 
 __all__ = [
-    "Problem", "CONFIGS", "make_object", "make_probe", "make_positions",
+    "Problem", "CONFIGS", "make_object", "make_probe", "make_positions", "make_positions_rect",
     "simulate_intensities", "make_problem", "make_config_problem",
     "draw_mix_specs", "roi_mask",
 ]
@@ -122,6 +122,21 @@ def make_positions(n_obj: int, np_: int, scan: int, step: int,
     jit = rng.integers(-jitter, jitter + 1, size=(scan * scan, 2))
     pos = np.stack([rows, cols], axis=1) + jit
     pos = np.clip(pos, 0, n_obj - np_)
+    return pos.astype(np.int32)
+
+
+def make_positions_rect(n1: int, n2: int, np_: int, scan1: int, scan2: int, step: int,
+                        rng: np.random.Generator, jitter: int = 2) -> np.ndarray:
+    """As make_positions for a rectangular object: a centred scan1 x scan2
+    raster (row-major, jittered, clamped)."""
+    def axis(n, scan):
+        return (n - ((scan - 1) * step + np_)) // 2 + step * np.arange(scan)
+    rows = np.repeat(axis(n1, scan1), scan2)
+    cols = np.tile(axis(n2, scan2), scan1)
+    jit = rng.integers(-jitter, jitter + 1, size=(scan1 * scan2, 2))
+    pos = np.stack([rows, cols], axis=1) + jit
+    pos[:, 0] = np.clip(pos[:, 0], 0, n1 - np_)
+    pos[:, 1] = np.clip(pos[:, 1], 0, n2 - np_)
     return pos.astype(np.int32)
 
 

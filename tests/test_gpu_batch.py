@@ -297,3 +297,61 @@ def test_closing_a_member_of_an_open_batch_is_refused(P):
         R.close()
     B.close()
     R.close()
+
+
+def test_batch_member_new_reference(P):
+    """A batched member given a new reference: the batch's stop rule measures
+    against the new one (its copy of the member's descriptor is updated)."""
+    probs = [synth.make_problem(128, 32, 6, 16, None, 1), synth.make_problem(320, 128, 4, 56, 1e5, 22)]
+    Rs = [_recon(P, p, 0) for p in probs]
+    for R, p in zip(Rs, probs):
+        R.set_reference(p.x_true, synth.roi_mask(p.probe, p.pos, p.n1, p.n2))
+    B = P.Batch(Rs, tol=0.0, min_iter=0, max_iter=100)
+    B.step(3)
+    _, nr0, _ = B.poll()
+    # a different reference for member 0 (its object conjugated and scaled),
+    # set while the batch holds it
+    new_ref = 0.7 * np.conj(probs[0].x_true)
+    Rs[0].set_reference(new_ref)
+    B.step(1)
+    _, nr, iters = B.poll()
+    e0 = Rs[0].nrmse()
+    _say("new reference: batch", nr[0], "member", e0, "before", nr0[0])
+    assert abs(nr[0] - e0) < 1e-12 * max(1.0, abs(e0))
+    assert abs(nr[0] - nr0[0]) > 1e-3
+    assert abs(nr[1] - Rs[1].nrmse()) < 1e-12
+    B.close()
+    for R in Rs:
+        R.close()
+
+
+def test_batched_members_match_oracle(P):
+    """Members advanced inside a mixed batch (fused sides, and a chunked
+    Np = 256 member), from smooth starts: every member's state and
+    reconstruction after K iterations equal the FP64 oracle's at 1e-4, in L2
+    and element by element."""
+    cfgs = [MIX[1], MIX[3], MIX[4]]             # Np 64, 128, 256 (4 positions per chunk)
+    probs = [synth.make_problem(n, np_, sc, st, pk, sd) for (n, np_, sc, st, pk, sd, _) in cfgs]
+    K = 3
+    x0s = [synth.make_object(p.n1, p.n2, np.random.default_rng(200 + i)).astype(np.complex64)
+           for i, p in enumerate(probs)]
+    Rs = [P.Reconstruction(p.n1, p.n2, p.probe, p.pos, p.z, 0.5, chunk=cfg[-1], x0=x0)
+          for p, cfg, x0 in zip(probs, cfgs, x0s)]
+    B = P.Batch(Rs, tol=0.0, min_iter=0, max_iter=K)
+    B.step(K)
+    for i, (R, p) in enumerate(zip(Rs, probs)):
+        d = p.probe.astype(np.complex64).astype(np.complex128)
+        shape = (p.n1, p.n2)
+        st = O.pmace_init(x0s[i].astype(np.complex128), p.pos, p.np_)
+        st = O.pmace_iterate(st, d, O.amplitudes(p.z.astype(np.float32)), p.pos, shape, 0.5, 1.25, 0.5, K)
+        xr = O.reconstruct(st, d, p.pos, shape, 1.25)
+        v, xh = R.get_state().cpu().numpy(), R.reconstruct().cpu().numpy()
+        ev = np.linalg.norm(v - st.v) / np.linalg.norm(st.v)
+        ex = np.linalg.norm(xh - xr) / np.linalg.norm(xr)
+        mv = np.max(np.abs(v - st.v)) / np.max(np.abs(st.v))
+        mx = np.max(np.abs(xh - xr)) / np.max(np.abs(xr))
+        _say(f"batched member Np {p.np_}: rel(v)={ev:.2e} rel(xhat)={ex:.2e} elementwise {mv:.2e} {mx:.2e}")
+        assert ev < 1e-4 and ex < 1e-4 and mv < 1e-4 and mx < 1e-4
+    B.close()
+    for R in Rs:
+        R.close()

@@ -157,3 +157,90 @@ def test_largest_workload_sampled(P):
         _say(f"  patch {j0} at {tuple(p0)}: {len(near)} overlapping, rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
         assert ev < TOL and ex < TOL
     R.close()
+
+
+@pytest.mark.parametrize("np_,n,scan,step,chunk", [(64, 160, 4, 30, 0), (256, 400, 3, 70, 4)])
+def test_long_graph_replay_equals_single_iterations(P, np_, n, scan, step, chunk):
+    """iterate(40) replays one 32-iteration graph and 8 single ones; 40 calls
+    of iterate(1) replay the single graph only: both are bitwise equal."""
+    prob = synth.make_problem(n, np_, scan, step, 1e5, 90 + np_)
+    _say("graph replay", np_, len(prob.pos), "chunk", chunk)
+    A = P.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, 0.5, chunk=chunk)
+    A.iterate(40)
+    B = P.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, 0.5, chunk=chunk)
+    for _ in range(40):
+        B.iterate(1)
+    va, vb = A.get_state().cpu().numpy(), B.get_state().cpu().numpy()
+    xa, xb = A.reconstruct().cpu().numpy(), B.reconstruct().cpu().numpy()
+    A.sync()
+    B.sync()
+    assert np.array_equal(va, vb) and np.array_equal(xa, xb)
+    A.close()
+    B.close()
+
+
+def _sampled_one_pass(P, n1, n2, np_, pos, z_dev, probe, x0, samples, alpha=0.5, kappa=1.25, rho=0.5,
+                      flags=0):
+    """One device pass from x0 on the whole workload; for each sampled
+    position the oracle forms the agents of every overlapping patch, the
+    weighted average over their window, and the sampled patch's new state and
+    reconstruction.  Returns the worst (L2, element-wise) errors."""
+    R = P.Reconstruction(n1, n2, probe, pos, z_dev, alpha, kappa, rho, x0=x0, flags=flags)
+    _say("  workspace GB", round(R.footprint / 1e9, 2))
+    R.iterate(1)
+    R.sync()
+    v_dev = R.get_state()
+    xh_dev = R.reconstruct().cpu().numpy()
+    d = probe.astype(np.complex64).astype(np.complex128)
+    pos = np.asarray(pos, np.int64)
+    x0d = x0.astype(np.complex128)
+    zc = z_dev if isinstance(z_dev, np.ndarray) else None
+    worst = (0.0, 0.0)
+    for j0 in samples:
+        p0 = pos[j0]
+        near = np.nonzero((np.abs(pos[:, 0] - p0[0]) < np_) & (np.abs(pos[:, 1] - p0[1]) < np_))[0]
+        lo = pos[near].min(axis=0)
+        shape = tuple(pos[near].max(axis=0) - lo + np_)
+        lpos = pos[near] - lo
+        v = O.extract(x0d, pos[near], np_)
+        zn = zc[near] if zc is not None else z_dev[torch.as_tensor(near, device=z_dev.device)].cpu().numpy()
+        w = O.agent_stack(v, d, O.amplitudes(zn), alpha)
+        xbar = O.weighted_average(2.0 * w - v, d, lpos, shape, kappa)
+        k0 = int(np.nonzero(near == j0)[0][0])
+        v_new = v[k0] + 2.0 * rho * (O.extract(xbar, lpos[k0:k0 + 1], np_)[0] - w[k0])
+        r, c = p0
+        xh_ref = (1 - rho) * x0d[r:r + np_, c:c + np_] + rho * xbar[r - lo[0]:r - lo[0] + np_,
+                                                                   c - lo[1]:c - lo[1] + np_]
+        vg = v_dev[j0].cpu().numpy()
+        xg = xh_dev[r:r + np_, c:c + np_]
+        ev, ex = rel(vg, v_new), rel(xg, xh_ref)
+        mv = float(np.max(np.abs(vg - v_new)) / np.max(np.abs(v_new)))
+        mx = float(np.max(np.abs(xg - xh_ref)) / np.max(np.abs(xh_ref)))
+        _say(f"  patch {j0} at {tuple(p0)}: {len(near)} overlapping, rel(v)={ev:.2e} rel(xhat)={ex:.2e} "
+             f"elementwise {mv:.2e} {mx:.2e}")
+        worst = (max(worst[0], ev, ex), max(worst[1], mv, mx))
+    R.close()
+    return worst
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n1,n2,np_,step,peak", [(1024, 2048, 256, 20, 1e6), (768, 1280, 192, 16, 1e5)])
+def test_rectangular_at_scale_sampled(P, n1, n2, np_, step, peak):
+    """Rectangular objects at full scale on the large-side path (default
+    chunks): 1024 x 2048 with 39 x 90 positions of 256^2, and 768 x 1280 with
+    37 x 69 positions of 192^2; intensities simulated on the device (eq. (1),
+    eq. (16)), one pass from a smooth start, checked on sampled patches at
+    the corners, the edges and the middle."""
+    s1, s2 = (n1 - np_) // step + 1, (n2 - np_) // step + 1
+    rng = np.random.default_rng(n2 + np_)
+    x = synth.make_object(n1, n2, rng)
+    d = synth.make_probe(np_)
+    pos = synth.make_positions_rect(n1, n2, np_, s1, s2, step, rng)
+    _say("rect", n1, n2, np_, "positions", len(pos))
+    z, scale = P.simulate(x, d, pos, peak, seed=n1 + np_)
+    probe = d * np.sqrt(scale)
+    x0 = synth.make_object(n1, n2, np.random.default_rng(5)).astype(np.complex64)
+    J = len(pos)
+    samples = [0, s2 - 1, J // 2 + s2 // 2, J - s2, J - 1, s2 * (s1 // 3) + 1]
+    ev, em = _sampled_one_pass(P, n1, n2, np_, pos, z, probe, x0, samples)
+    assert ev < TOL and em < TOL

@@ -92,9 +92,44 @@ def single_precision_step_error(prob, v, alpha, kappa, rho):
     return rel(v1, ref)
 
 
-def make_recon(P, prob, alpha, kappa=1.25, rho=0.5, chunk=0):
+def make_recon(P, prob, alpha, kappa=1.25, rho=0.5, chunk=0, flags=0):
     return P.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, alpha, kappa, rho,
-                            chunk=chunk)
+                            chunk=chunk, flags=flags)
+
+
+# The first pass from the default flat start x0 = 1 is the one pass that is
+# not held to 1e-4: there the patch spectra F(d v) occupy a few bins and the
+# phase W/|W| of every other bin is FP32 rounding noise, in any single-
+# precision evaluation.  It is held to 1.5x the error of a plain complex64
+# evaluation of the same pass (single_precision_step_error), and reported.
+FLAT_FACTOR = 1.5
+
+
+def flat_start_bound(prob, v0, alpha, kappa, rho):
+    return max(TOL, FLAT_FACTOR * single_precision_step_error(prob, v0, alpha, kappa, rho))
+
+
+def teacher_forced(P, R, vs, xs, ks, tol0=None, say=""):
+    """Set the oracle's state k, run one device pass, compare with k+1 (L2 and
+    element by element at 1e-4; k = 0 from the flat start at tol0, L2 only).
+    Returns the worst L2 error over the passes held to 1e-4."""
+    worst = 0.0
+    for k in ks:
+        R.set_state(vs[k])
+        R.iterate(1)
+        v, xh = R.get_state().cpu().numpy(), R.reconstruct().cpu().numpy()
+        ev, ex = rel(v, vs[k + 1]), rel(xh, xs[k + 1])
+        if k == 0 and tol0 is not None:
+            _say(f"  {say} k=0 (flat start) rel(v)={ev:.2e} rel(xhat)={ex:.2e} bound {tol0:.2e}")
+            assert ev < tol0 and ex < tol0, (k, ev, ex, tol0)
+            continue
+        mv, mx = elem(v, vs[k + 1]), elem(xh, xs[k + 1])
+        if k < 3 or k % 10 == 9 or k == ks[-1]:
+            _say(f"  {say} k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e} elementwise {mv:.2e} {mx:.2e}")
+        assert ev < TOL and ex < TOL, (k, ev, ex)
+        assert mv < TOL and mx < TOL, (k, mv, mx)
+        worst = max(worst, ev, ex, mv, mx)
+    return worst
 
 
 SMALL_CASES = {
@@ -174,7 +209,7 @@ def test_flat_start(P, case):
     prob = synth.make_problem(n, np_, scan, step, peak, seed)
     alpha = 0.5
     vs, xs = oracle_trajectory(prob, alpha, 1.25, 0.5, 3)
-    tol0 = max(TOL, 3.0 * single_precision_step_error(prob, vs[0], alpha, 1.25, 0.5))
+    tol0 = flat_start_bound(prob, vs[0], alpha, 1.25, 0.5)
     _say("flat start", case, f"tol0={tol0:.2e}")
     R = make_recon(P, prob, alpha, chunk=chunk)
     R.iterate(1)
@@ -198,17 +233,11 @@ def test_c1_every_iteration_teacher_forced_and_free_running(P):
     K = synth.CONFIGS["c1"]["iters"]
     alpha = 0.1
     vs, xs = oracle_trajectory(prob, alpha, synth.KAPPA, synth.RHO, K)
-    _say("c1 teacher-forced, K", K)
+    _say("c1 teacher-forced, every k of", K)
     R = make_recon(P, prob, alpha)
-    worst = 0.0
-    for k in range(1, K):
-        R.set_state(vs[k])
-        R.iterate(1)
-        v = R.get_state().cpu().numpy()
-        xh = R.reconstruct().cpu().numpy()
-        worst = max(worst, rel(v, vs[k + 1]), rel(xh, xs[k + 1]))
-    _say(f"  worst teacher-forced rel = {worst:.2e}")
-    assert worst < TOL
+    tol0 = flat_start_bound(prob, vs[0], alpha, synth.KAPPA, synth.RHO)
+    worst = teacher_forced(P, R, vs, xs, list(range(K)), tol0=tol0, say="c1")
+    _say(f"  worst teacher-forced error (k >= 1, L2 and element-wise) = {worst:.2e}")
     # free-running from the same start: report the drift, bound it loosely
     R2 = make_recon(P, prob, alpha)
     drift = []
@@ -221,8 +250,7 @@ def test_c1_every_iteration_teacher_forced_and_free_running(P):
     e_gpu, e_ref = O.nrmse(xh, prob.x_true, mask), O.nrmse(xs[-1], prob.x_true, mask)
     _say(f"  free-running rel(v) at k=1,10,{K}: {drift[0]:.2e} {drift[9]:.2e} {drift[-1]:.2e};"
          f" NRMSE gpu {e_gpu:.6f} oracle {e_ref:.6f}")
-    assert drift[0] < max(TOL, 3.0 * single_precision_step_error(prob, vs[0], alpha, synth.KAPPA,
-                                                                 synth.RHO))
+    assert drift[0] < tol0
     assert abs(e_gpu - e_ref) < 1e-3
     R.close()
     R2.close()
@@ -231,24 +259,36 @@ def test_c1_every_iteration_teacher_forced_and_free_running(P):
 @pytest.mark.parametrize("np_", [128, 96, 48])
 def test_c2_teacher_forced_steps(P, np_):
     """The C2 workload (512^2 object, 225 positions; probe 128^2, and the 96^2
-    and 48^2 sides bench.py --np times on the same geometry), whole."""
+    and 48^2 sides bench.py --np times on the same geometry), whole: every
+    pass of its 100-iteration budget for the 128^2 probe, passes 1, 2 and 5
+    for the other sides."""
     c = synth.CONFIGS["c2"]
     prob = (synth.make_config_problem("c2") if np_ == c["np_"] else
             synth.make_problem(c["n"], np_, c["scan"], c["step"], c["peak"], c["seed"], name=f"c2-np{np_}"))
     alpha = 0.5
-    ks = [1, 2, 5]
+    ks = list(range(c["iters"])) if np_ == c["np_"] else [1, 2, 5]
     vs, xs = oracle_trajectory(prob, alpha, synth.KAPPA, synth.RHO, max(ks) + 1)
-    _say(f"c2 np{np_} teacher-forced at", ks)
+    _say(f"c2 np{np_} teacher-forced at {len(ks)} passes")
     R = make_recon(P, prob, alpha)
-    for k in ks:
-        R.set_state(vs[k])
-        R.iterate(1)
-        v, xh = R.get_state().cpu().numpy(), R.reconstruct().cpu().numpy()
-        ev, ex = rel(v, vs[k + 1]), rel(xh, xs[k + 1])
-        mv, mx = elem(v, vs[k + 1]), elem(xh, xs[k + 1])
-        _say(f"  k={k} rel(v)={ev:.2e} rel(xhat)={ex:.2e} elementwise {mv:.2e} {mx:.2e}")
-        assert ev < TOL and ex < TOL
-        assert mv < TOL and mx < TOL
+    tol0 = flat_start_bound(prob, vs[0], alpha, synth.KAPPA, synth.RHO) if 0 in ks else None
+    teacher_forced(P, R, vs, xs, ks, tol0=tol0, say=f"c2 np{np_}")
+    R.close()
+
+
+@pytest.mark.parametrize("flags", [0])
+def test_large_side_every_iteration_to_50(P, flags):
+    """Np = 256 on a 640^2 object, 144 positions in three chunks of 48:
+    teacher-forced at every pass k = 0..49 (k = 0 from the flat start), so
+    the near-converged regime of the kept consensus sums is covered."""
+    prob = synth.make_problem(640, 256, 12, 32, 1e6, 57)
+    alpha = 0.5
+    K = 50
+    _say("np256 640^2: oracle trajectory", K)
+    vs, xs = oracle_trajectory(prob, alpha, synth.KAPPA, synth.RHO, K)
+    R = make_recon(P, prob, alpha, chunk=48, flags=flags)
+    tol0 = flat_start_bound(prob, vs[0], alpha, synth.KAPPA, synth.RHO)
+    worst = teacher_forced(P, R, vs, xs, list(range(K)), tol0=tol0, say=f"np256 flags={flags}")
+    _say(f"  worst (k >= 1) = {worst:.2e}")
     R.close()
 
 
@@ -362,7 +402,7 @@ def test_c3_full_size_steps(P, np_):
     alpha = 0.5
     _say(f"c3 np{np_}: oracle, 2 passes")
     vs, xs = oracle_trajectory(prob, alpha, synth.KAPPA, synth.RHO, 2)
-    tol0 = max(TOL, 3.0 * single_precision_step_error(prob, vs[0], alpha, synth.KAPPA, synth.RHO))
+    tol0 = flat_start_bound(prob, vs[0], alpha, synth.KAPPA, synth.RHO)
     _say(f"c3: device, tol0={tol0:.2e}")
     R = make_recon(P, prob, alpha)
     R.iterate(1)

@@ -57,3 +57,32 @@ def test_served_equals_alone(P, split):
         print(f"  request {a.rid}: {a.iters} iterations served, {b.iters} alone", flush=True)
         assert a.iters == b.iters and a.nrmse == b.nrmse
         assert np.array_equal(a.result, b.result)
+
+
+def test_served_request_matches_oracle(P):
+    """One request served beside others (admitted while they run), from a
+    smooth start, for a fixed number of iterations: its reconstruction equals
+    the FP64 oracle's at 1e-4, in L2 and element by element."""
+    from oracle import pmace_oracle as O
+    probs = [synth.make_problem(*m) for m in MIX[:4]]
+    K = 3
+    rule = dict(tol=0.0, min_iter=0, max_iter=K)
+    reqs = [serve.Request(i, p, 0.002 * i) for i, p in enumerate(probs)]
+    target = 3                                  # Np 128, admitted last
+    p = probs[target]
+    x0 = synth.make_object(p.n1, p.n2, np.random.default_rng(123))
+    reqs[target].x0 = x0.astype(np.complex64)
+    ex = serve.GPUExecutor(alpha=0.5, **rule)
+    st = serve.Server(ex, 1 << 40, iters_per_step=1, on_step=_tick).run(reqs, serve.FakeClock())
+    assert st.completed == len(reqs) and st.max_active > 1
+    assert reqs[target].iters == K
+    d = p.probe.astype(np.complex64).astype(np.complex128)
+    shape = (p.n1, p.n2)
+    ost = O.pmace_init(x0.astype(np.complex64).astype(np.complex128), p.pos, p.np_)
+    ost = O.pmace_iterate(ost, d, O.amplitudes(p.z.astype(np.float32)), p.pos, shape, 0.5, 1.25, 0.5, K)
+    xr = O.reconstruct(ost, d, p.pos, shape, 1.25)
+    got = np.asarray(reqs[target].result, np.complex128)
+    e = np.linalg.norm(got - xr) / np.linalg.norm(xr)
+    m = np.max(np.abs(got - xr)) / np.max(np.abs(xr))
+    print(f"  served request vs oracle after {K} iterations: rel {e:.2e} elementwise {m:.2e}", flush=True)
+    assert e < 1e-4 and m < 1e-4

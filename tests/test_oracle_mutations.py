@@ -10,6 +10,7 @@ import test_oracle_consensus as TC
 import test_oracle_dft as TD
 import test_oracle_iteration as TI
 import test_oracle_nrmse as TN
+import test_oracle_sharp as TS
 
 
 def _small():
@@ -37,6 +38,8 @@ PINS = [
     lambda: TI.test_step_equals_mann_update_of_T(),
     lambda: TN.test_nrmse_special_values(),
     lambda: TN.test_nrmse_theta_is_grid_minimiser(),
+    lambda: TS.test_init_golden_hand_example(),
+    lambda: TS.test_reconstruct_inverts_init_on_covered_pixels(3),
 ]
 
 
@@ -93,6 +96,18 @@ def _nrmse_conj_theta(xhat, x, mask=None):
     return float(np.linalg.norm(xhat - np.exp(1j * th) * x) / np.linalg.norm(x))
 
 
+def _sharp_init_conj_probe(x0, d, pos):
+    return np.conj(np.asarray(d, complex)) * O.extract(np.asarray(x0, complex), pos, np.asarray(d).shape[0])
+
+
+def _sharp_init_transposed_probe(x0, d, pos):
+    return np.asarray(d, complex).T * O.extract(np.asarray(x0, complex), pos, np.asarray(d).shape[0])
+
+
+def _sharp_init_magnitude(x0, d, pos):
+    return np.abs(np.asarray(d, complex)) * O.extract(np.asarray(x0, complex), pos, np.asarray(d).shape[0])
+
+
 MUTATIONS = {
     "dft_sign": ("dft2", lambda a: np.fft.ifft2(np.asarray(a, complex), norm="ortho")),
     "dft_unnormalised": ("dft2", lambda a: np.fft.fft2(np.asarray(a, complex))),
@@ -104,6 +119,9 @@ MUTATIONS = {
     "reflection_sign": ("pmace_step", _step_wrong_reflection),
     "mann_sign": ("pmace_step", _step_wrong_sign),
     "nrmse_theta_conj": ("nrmse", _nrmse_conj_theta),
+    "sharp_init_conj_probe": ("sharp_plus_init", _sharp_init_conj_probe),
+    "sharp_init_transposed_probe": ("sharp_plus_init", _sharp_init_transposed_probe),
+    "sharp_init_probe_magnitude": ("sharp_plus_init", _sharp_init_magnitude),
 }
 
 

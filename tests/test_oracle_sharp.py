@@ -61,3 +61,30 @@ def test_overlap_of_next_state_is_overlap_of_magnitude_step():
     lhs = O.sharp_overlap_projection(s1, d, pos, x.shape)
     rhs = O.sharp_overlap_projection(O.sharp_magnitude_projection(s, y), d, pos, x.shape)
     assert np.allclose(lhs, rhs, atol=1e-10)
+
+
+def test_init_golden_hand_example():
+    """Alg. 2 initialisation s_j = D P_j x0 against the hand-worked example."""
+    from conftest import load_golden, cplx
+    g = load_golden("sharp_plus_init_worked.json")
+    s = O.sharp_plus_init(cplx(g["x0"]), cplx(g["probe"]), np.array(g["pos"]))
+    assert s.shape == (2, 2, 2)
+    assert np.allclose(s, cplx(g["s"]), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_reconstruct_inverts_init_on_covered_pixels(seed):
+    """(sum_k P_k^t |D|^2)^{-1} sum_j P_j^t D^* (D P_j x) = x wherever some
+    probe pixel with d != 0 covers the object pixel, and 0 elsewhere."""
+    rng = np.random.default_rng(seed)
+    n, np_ = 40, 12
+    x = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    d = (rng.standard_normal((np_, np_)) + 1j * rng.standard_normal((np_, np_)))
+    d[0, :3] = 0.0                     # exact zeros do not cover their pixels
+    pos = np.array([[0, 0], [5, 17], [20, 3], [28, 28], [13, 11]])
+    s = O.sharp_plus_init(x, d, pos)
+    xr = O.sharp_plus_reconstruct(s, d, pos, x.shape)
+    cover = O.back_project(np.broadcast_to(np.abs(d) ** 2, (len(pos), np_, np_)), pos, x.shape).real > 0
+    assert cover.sum() > 0 and (~cover).sum() > 0
+    assert np.allclose(xr[cover], x[cover], rtol=0, atol=1e-12)
+    assert np.all(xr[~cover] == 0)
