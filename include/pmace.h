@@ -238,6 +238,25 @@ pmace_status pmace_simulate(int32_t n1, int32_t n2, int32_t np, int32_t num_pos,
                             const void* probe_d, const int32_t* pos_d, const void* x_d,
                             double peak_photons, uint64_t seed, float* z_d, void* workspace_d,
                             size_t ws_bytes, double* scale_out, void* hip_stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * simulation as pmace_simulate, with the same arguments minus the workspace,
+ * and the same results bit for bit.  Its scratch memory (the maximum, a
+ * position flag and, for np > 128, the row transforms of the frames) is one
+ * static device array per GPU, held from the first call on that GPU until the
+ * process ends; nothing is allocated per call.  Limit: np > 128 needs
+ * num_pos*np*np*8 <= pmace_simulate_static_max_bytes() (64 MiB - 256 B, e.g.
+ * 127 positions of 256 x 256), else ENOMEM; np <= 128 has no such limit.
+ * Positions are validated on the device (EINVAL if a patch leaves the
+ * object).  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (other streams, other threads) race; serialise them.
+ * Synchronises hip_stream (the position check; and scale_out as in
+ * pmace_simulate). */
+size_t pmace_simulate_static_max_bytes(void);
+pmace_status pmace_simulate_static(int32_t n1, int32_t n2, int32_t np, int32_t num_pos,
+                                   const void* probe_d, const int32_t* pos_d, const void* x_d,
+                                   double peak_photons, uint64_t seed, float* z_d, double* scale_out,
+                                   void* hip_stream);
 /* Exposes the generator behind pmace_simulate for known-answer checks: io_d
  * holds n records of 6 uint32 (counter[4], key[2]); the counter words are
  * replaced by Philox4x32-10(counter, key). */

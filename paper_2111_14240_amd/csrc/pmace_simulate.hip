@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "pmace.h"
@@ -271,11 +272,89 @@ __global__ void poisson_test_k(const double* __restrict__ lam, float* __restrict
   out[i] = (float)poisson_draw(lam[i], u);
 }
 
+// Clears the maximum and the position flag (a kernel, not a memset, so the
+// call stays capturable).
+__global__ void sim_clear_k(unsigned* __restrict__ ctl) {
+  if (threadIdx.x < 2) ctl[threadIdx.x] = 0u;
+}
+
+// Flags (ctl[1] = 1) any position whose patch leaves the object.
+__global__ void sim_check_pos_k(const int2* __restrict__ pos, int J, int n1, int n2, int np,
+                                unsigned* __restrict__ ctl) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= J) return;
+  const int2 p = pos[j];
+  if (p.x < 0 || p.y < 0 || p.x > n1 - np || p.y > n2 - np) atomicOr(ctl + 1, 1u);
+}
+
+// Scratch of the allocation-free entry point: the maximum and the position
+// flag in the first 256 bytes, then (Np > 128) the frames' row transforms.
+// One copy per device, held until the process ends.
+constexpr size_t kSimScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kSimScratchBytes];
+
 }  // namespace pmace
 
 namespace {
 inline unsigned nblocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 inline size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Intensities, optional Poisson draws and the scale, into z_d; `fr` holds the
+// row transforms (Np > 128), `maxbits` the cleared maximum.  Stream-ordered;
+// synchronises only to return the scale.
+pmace_status run_simulation(int32_t n2, int32_t np, int32_t num_pos, const void* probe_d,
+                            const int32_t* pos_d, const void* x_d, double peak_photons, uint64_t seed,
+                            float* z_d, float2* fr, unsigned* maxbits, double* scale_out,
+                            hipStream_t st) {
+  const long long total = (long long)num_pos * np * np;
+  const float2* dd = reinterpret_cast<const float2*>(probe_d);
+  const int2* pp = reinterpret_cast<const int2*>(pos_d);
+  const float2* xx = reinterpret_cast<const float2*>(x_d);
+  hipError_t e = hipErrorInvalidValue;
+  switch (np) {
+    case 32: e = pmace::launch_sim_intensities<32>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 48: e = pmace::launch_sim_intensities<48>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 64: e = pmace::launch_sim_intensities<64>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 96: e = pmace::launch_sim_intensities<96>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 128: e = pmace::launch_sim_intensities<128>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 160: e = pmace::launch_sim_intensities<160>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 192: e = pmace::launch_sim_intensities<192>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    case 256: e = pmace::launch_sim_intensities<256>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
+    default: break;
+  }
+  if (e != hipSuccess) return PMACE_EDEVICE;
+  if (peak_photons > 0.0)
+    hipLaunchKernelGGL(pmace::poisson_k, dim3(nblocks(total, 256)), dim3(256), 0, st, z_d, maxbits,
+                       peak_photons, seed, total);
+  if (hipGetLastError() != hipSuccess) return PMACE_EDEVICE;
+  if (scale_out) {
+    unsigned mb = 0;
+    if (hipMemcpyAsync(&mb, maxbits, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return PMACE_EDEVICE;
+    float mx;
+    std::memcpy(&mx, &mb, 4);
+    *scale_out = (peak_photons > 0.0 && mx > 0.f) ? peak_photons / (double)mx : 1.0;
+  }
+  return PMACE_OK;
+}
+
+
+// Device address of `scratch` on each device, looked up once per device.
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+unsigned char* scratch_of_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(pmace::scratch)) != hipSuccess || !p) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return static_cast<unsigned char*>(g_scratch_ptr[dev]);
+}
 }  // namespace
 
 extern "C" {
@@ -314,38 +393,43 @@ pmace_status pmace_simulate(int32_t n1, int32_t n2, int32_t np, int32_t num_pos,
   char* base = reinterpret_cast<char*>(up256(reinterpret_cast<size_t>(workspace_d)));
   float2* fr = reinterpret_cast<float2*>(base);
   unsigned* maxbits = reinterpret_cast<unsigned*>(base + up256(J * np * np * 8));
-  const long long total = (long long)J * np * np;
   if (hipMemsetAsync(maxbits, 0, 4, st) != hipSuccess) return PMACE_EDEVICE;
-  const float2* dd = reinterpret_cast<const float2*>(probe_d);
-  const int2* pp = reinterpret_cast<const int2*>(pos_d);
-  const float2* xx = reinterpret_cast<const float2*>(x_d);
-  hipError_t e = hipErrorInvalidValue;
-  switch (np) {
-    case 32: e = pmace::launch_sim_intensities<32>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
-    case 48: e = pmace::launch_sim_intensities<48>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
-    case 64: e = pmace::launch_sim_intensities<64>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
-    case 96: e = pmace::launch_sim_intensities<96>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
-    case 128: e = pmace::launch_sim_intensities<128>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
-    case 160: e = pmace::launch_sim_intensities<160>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
-    case 192: e = pmace::launch_sim_intensities<192>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
-    case 256: e = pmace::launch_sim_intensities<256>(num_pos, dd, pp, xx, n2, fr, z_d, maxbits, st); break;
-    default: break;
-  }
-  if (e != hipSuccess) return PMACE_EDEVICE;
-  if (peak_photons > 0.0)
-    hipLaunchKernelGGL(pmace::poisson_k, dim3(nblocks(total, 256)), dim3(256), 0, st, z_d, maxbits,
-                       peak_photons, seed, total);
-  if (hipGetLastError() != hipSuccess) return PMACE_EDEVICE;
-  if (scale_out) {
-    unsigned mb = 0;
-    if (hipMemcpyAsync(&mb, maxbits, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      return PMACE_EDEVICE;
-    float mx;
-    std::memcpy(&mx, &mb, 4);
-    *scale_out = (peak_photons > 0.0 && mx > 0.f) ? peak_photons / (double)mx : 1.0;
-  }
-  return PMACE_OK;
+  return run_simulation(n2, np, num_pos, probe_d, pos_d, x_d, peak_photons, seed, z_d, fr, maxbits,
+                        scale_out, st);
+}
+
+size_t pmace_simulate_static_max_bytes(void) { return pmace::kSimScratchBytes - 256; }
+
+pmace_status pmace_simulate_static(int32_t n1, int32_t n2, int32_t np, int32_t num_pos,
+                                   const void* probe_d, const int32_t* pos_d, const void* x_d,
+                                   double peak_photons, uint64_t seed, float* z_d, double* scale_out,
+                                   void* hip_stream) {
+  if (np < 1 || num_pos < 1 || n1 < np || n2 < np || !probe_d || !pos_d || !x_d || !z_d ||
+      !std::isfinite(peak_photons))
+    return PMACE_EINVAL;
+  if (np != 32 && np != 48 && np != 64 && np != 96 && np != 128 && np != 160 && np != 192 && np != 256)
+    return PMACE_EUNSUPPORTED;
+  // Np > 128 keeps every frame's row transform in the scratch array
+  const size_t frames = np > 128 ? (size_t)num_pos * np * np * 8 : 0;
+  if (frames > pmace_simulate_static_max_bytes()) return PMACE_ENOMEM;
+  unsigned char* sp = scratch_of_current_device();
+  if (!sp) return PMACE_EDEVICE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  unsigned* ctl = reinterpret_cast<unsigned*>(sp);  // [0] maximum bits, [1] position flag
+  float2* fr = reinterpret_cast<float2*>(sp + 256);
+  // positions are checked on the device (no host buffer): the frame gather
+  // reads the object there, so nothing is launched until they are known good
+  hipLaunchKernelGGL(pmace::sim_clear_k, dim3(1), dim3(64), 0, st, ctl);
+  hipLaunchKernelGGL(pmace::sim_check_pos_k, dim3(nblocks(num_pos, 256)), dim3(256), 0, st,
+                     reinterpret_cast<const int2*>(pos_d), num_pos, n1, n2, np, ctl);
+  unsigned bad = 0;
+  if (hipGetLastError() != hipSuccess ||
+      hipMemcpyAsync(&bad, ctl + 1, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return PMACE_EDEVICE;
+  if (bad) return PMACE_EINVAL;
+  return run_simulation(n2, np, num_pos, probe_d, pos_d, x_d, peak_photons, seed, z_d, fr, ctl,
+                        scale_out, st);
 }
 
 pmace_status pmace_philox4x32_10(uint32_t* io_d, int32_t n, void* hip_stream) {

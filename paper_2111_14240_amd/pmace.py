@@ -119,6 +119,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pmace_simulate.argtypes = [i32, i32, i32, i32, vp, vp, vp, ctypes.c_double, ctypes.c_uint64, vp,
                                  vp, sz, ctypes.POINTER(ctypes.c_double), vp]
     L.pmace_simulate.restype = ctypes.c_int
+    L.pmace_simulate_static_max_bytes.argtypes = []
+    L.pmace_simulate_static_max_bytes.restype = sz
+    L.pmace_simulate_static.argtypes = [i32, i32, i32, i32, vp, vp, vp, ctypes.c_double, ctypes.c_uint64,
+                                        vp, ctypes.POINTER(ctypes.c_double), vp]
+    L.pmace_simulate_static.restype = ctypes.c_int
     L.pmace_philox4x32_10.argtypes = [vp, i32, vp]
     L.pmace_philox4x32_10.restype = ctypes.c_int
     L.pmace_poisson.argtypes = [vp, vp, i32, ctypes.c_uint64, vp]
@@ -326,6 +331,41 @@ def simulate(x, probe, pos, peak, seed: int, device="cuda", stream=None, out=Non
                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.byref(scale),
                                          _stream_ptr(stream)), "pmace_simulate")
     return z, scale.value
+
+
+def simulate_static(x, probe, pos, peak, seed: int, device="cuda", stream=None, out=None):
+    """As simulate(), through the allocation-free entry point: the library
+    uses its per-device static scratch instead of a workspace (Np > 128 then
+    needs J*Np*Np*8 <= simulate_static_max_bytes()).  Returns (z, scale)."""
+    torch = _torch()
+    dev = torch.device(device)
+    x_t = to_device_c64(x, dev)
+    d_t = to_device_c64(probe, dev)
+    pos_t = (pos if isinstance(pos, torch.Tensor) and pos.dtype == torch.int32
+             else torch.as_tensor(np.asarray(pos, dtype=np.int32))).to(dev).contiguous()
+    n1, n2 = x_t.shape
+    np_ = d_t.shape[-1]
+    J = pos_t.shape[0]
+    if out is None:
+        z = torch.empty((J, np_, np_), dtype=torch.float32, device=dev)
+    else:
+        if (out.dtype != torch.float32 or tuple(out.shape) != (J, np_, np_) or not out.is_contiguous()
+                or out.device != x_t.device):
+            raise ValueError(f"out must be a contiguous float32 ({J},{np_},{np_}) tensor on {x_t.device}")
+        z = out
+    scale = ctypes.c_double()
+    _check(load_library().pmace_simulate_static(n1, n2, np_, J, ctypes.c_void_p(d_t.data_ptr()),
+                                                ctypes.c_void_p(pos_t.data_ptr()),
+                                                ctypes.c_void_p(x_t.data_ptr()), float(peak or 0.0),
+                                                int(seed), ctypes.c_void_p(z.data_ptr()),
+                                                ctypes.byref(scale), _stream_ptr(stream)),
+           "pmace_simulate_static")
+    return z, scale.value
+
+
+def simulate_static_max_bytes() -> int:
+    """Largest Np > 128 frame buffer (J*Np*Np*8 bytes) simulate_static accepts."""
+    return int(load_library().pmace_simulate_static_max_bytes())
 
 
 def simulated_problem(n, np_, scan, step, peak, seed, device="cuda"):

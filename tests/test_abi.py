@@ -134,3 +134,20 @@ def test_binding_shares_pytorch_hip_runtime():
                          timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_simulate_static_checks_before_device(lib):
+    """The allocation-free simulate entry point rejects bad arguments and
+    sizes beyond its static scratch before touching a device."""
+    L = lib
+    mx = int(L.pmace_simulate_static_max_bytes())
+    assert mx == (64 << 20) - 256
+    big_j = mx // (256 * 256 * 8) + 1                        # one position too many for Np = 256
+    one = ctypes.c_void_p(1)
+    assert L.pmace_simulate_static(1024, 1024, 256, big_j, one, one, one, 0.0, 1, one, None,
+                                   None) == P.PMACE_ENOMEM
+    assert L.pmace_simulate_static(128, 128, 32, 4, None, one, one, 0.0, 1, one, None, None) == P.PMACE_EINVAL
+    assert L.pmace_simulate_static(128, 128, 33, 4, one, one, one, 0.0, 1, one, None,
+                                   None) == P.PMACE_EUNSUPPORTED
+    assert L.pmace_simulate_static(128, 128, 32, 4, one, one, one, float("nan"), 1, one, None,
+                                   None) == P.PMACE_EINVAL
