@@ -57,9 +57,14 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def iteration_kernels(np_, J, method="pmace"):
-    """The kernels one timed iteration (the roofline's unit) launches."""
+def iteration_kernels(np_, J, method="pmace", agent="three-pass"):
+    """The kernels one timed iteration (the roofline's unit) launches, for the
+    agent the reconstruction runs ('whole patch', 'three-pass', 'split')."""
     name = "PMACE" if method == "pmace" else "SHARP+"
+    if agent == "split":
+        return (f"one {name} iteration: agent_split_pair<{np_ // 2}> ({2 * J} workgroups, two "
+                f"{np_ // 2}x{np_ // 2} coset blocks each) + consensus_split<{np_ // 2}> (four partial sums "
+                f"per pixel) + image_update_split")
     if np_ <= 128:
         return (f"one {name} iteration: agent_fused<{np_}> ({J} workgroups) + "
                 f"consensus_gather<{np_}> (a9 fused)")
@@ -74,14 +79,16 @@ def raster_overhang(n, np_, scan, step):
     return f"; the raster overhangs the object by {ov} px, edge rows and columns clamped" if ov > 0 else ""
 
 
-def workload_key(config, method, np_override):
+def workload_key(config, method, np_override, agent="default"):
     """Row name of a workload in the traffic table: the config, then the
-    variant ('c3', 'c3-sharp', 'c3-np192')."""
+    variant ('c3', 'c3-sharp', 'c3-np192', 'c3-staged')."""
     key = config
     if method != "pmace":
         key += "-" + method
     if np_override:
         key += f"-np{np_override}"
+    if agent != "default":
+        key += "-" + agent
     return key
 
 
@@ -118,6 +125,38 @@ def calibration_copy(mib):
     torch.cuda.synchronize()
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline_all_cores(prob, alpha, kappa, rho, min_seconds=10.0, max_iters=6, method="pmace", beta=0.0):
+    """The same oracle with its FFT primitive (numpy's, one thread) served by
+    scipy.fft on every host core: the oracle's own arithmetic is unchanged,
+    only the library transform runs multi-threaded."""
+    import scipy.fft as sf
+    from oracle import pmace_oracle as O
+    cores = os.cpu_count() or 1
+    saved = (O.dft2, O.idft2)
+    O.dft2 = lambda a: sf.fft2(np.asarray(a, dtype=np.complex128), norm="ortho", workers=cores)
+    O.idft2 = lambda a: sf.ifft2(np.asarray(a, dtype=np.complex128), norm="ortho", workers=cores)
+    try:
+        out = cpu_baseline(prob, alpha, kappa, rho, min_seconds, max_iters, method, beta)
+    finally:
+        O.dft2, O.idft2 = saved
+    out["cores"] = cores
+    out["sample"] = out["sample"].replace("numpy FFT (single thread)",
+                                          f"scipy.fft on {cores} threads for the transforms")
+    return out
+
+
 def cpu_baseline(prob, alpha, kappa, rho, min_seconds=12.0, max_iters=6, method="pmace", beta=0.0):
     """The FP64 oracle, as it stands, timed on whole iterations of the same
     workload until at least min_seconds have passed (at most max_iters)."""
@@ -141,16 +180,23 @@ def cpu_baseline(prob, alpha, kappa, rho, min_seconds=12.0, max_iters=6, method=
             break
     return {"value": k * prob.num_pos / dt, "unit": "patch-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{k} iterations of the full workload ({prob.num_pos} positions each), "
-                      f"{dt:.2f} s, numpy FFT (single thread)"}
+                      f"{dt:.2f} s, numpy FFT (single thread)",
+            "cpu_model": cpu_model(), "host_cpu_count": os.cpu_count()}
+
+
+_MIX_CACHE = {}
 
 
 def _mix_problems(count, seed=4, device="cuda"):
     """The mixed-size workload: sizes from the seeded draw, intensities
-    simulated on the device (Poisson peak 1e5)."""
+    simulated on the device (Poisson peak 1e5); made once per process."""
     from paper_2111_14240_amd import pmace, synth
-    specs = synth.draw_mix_specs(count, seed=seed)
-    return [pmace.simulated_problem(s["n"], s["np_"], s["scan"], s["step"], s["peak"], s["seed"],
-                                    device=device) for s in specs]
+    key = (count, seed, str(device))
+    if key not in _MIX_CACHE:
+        specs = synth.draw_mix_specs(count, seed=seed)
+        _MIX_CACHE[key] = [pmace.simulated_problem(s["n"], s["np_"], s["scan"], s["step"], s["peak"], s["seed"],
+                                                   device=device) for s in specs]
+    return _MIX_CACHE[key]
 
 
 def _stop_rule(args):
@@ -165,6 +211,10 @@ def _stop_rule(args):
 
 
 def bench_batch(args):
+    print(json.dumps(batch_comparison(args)), flush=True)
+
+
+def batch_comparison(args):
     """All reconstructions advanced together (one graph launch per iteration)
     versus the plain solver (one at a time, in order), both to the same
     on-device stop rule; alone and in the batch each member takes the same
@@ -243,7 +293,7 @@ def bench_batch(args):
         "generation_s": gen_s,
         "total_patch_pixels": int(sum(p.patch_pixels for p in probs)),
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def simulate_cpu_baseline(x, d, pos, peak, seed, min_seconds=10.0):
@@ -329,6 +379,10 @@ def bench_simulate(args):
 
 
 def bench_serve(args):
+    print(json.dumps(serve_comparison(args)), flush=True)
+
+
+def serve_comparison(args):
     """Poisson arrivals of requests drawn from the mixed-size pool: the
     continuous-batching server against the plain FIFO solver."""
     import torch
@@ -386,7 +440,7 @@ def bench_serve(args):
         "served": results[names[0]], "plain": results["plain"],
         "served_variants": {n: results[n] for n in names},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -401,7 +455,18 @@ def main():
     ap.add_argument("--np", type=int, default=0,
                     help="plain mode: probe side other than the config's (same object, raster and step)")
     ap.add_argument("--chunk", type=int, default=0, help="Np > 128: at most this many positions per staging chunk (0 = tuned default)")
+    ap.add_argument("--n2", type=int, default=0,
+                    help="plain mode: a rectangular object with this many columns (the raster widened "
+                         "at the same step)")
+    ap.add_argument("--agent", default="default", choices=["default", "staged", "split"],
+                    help="plain mode: the library's choice, the three-pass agent (Np 192/256), or the "
+                         "coset-block agent (Np 128 too)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--systems", action=argparse.BooleanOptionalAction, default=True,
+                    help="plain mode: also run the 64-item batch and a short served run against the plain "
+                         "solver and add them to the line (--no-systems to skip)")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="plain mode with --systems: requests in the short served run")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB three times (counter calibration)")
     ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "simulate"])
@@ -441,6 +506,14 @@ def main():
     cfg = dict(synth.CONFIGS[args.config])
     if args.np:
         cfg["np_"] = args.np
+    cfg["scan2"] = cfg["scan"]
+    if args.n2:
+        # a rectangular object: the config's rows, N2 columns covered by the
+        # same step (scan x scan2 raster)
+        cfg["scan2"] = (args.n2 - cfg["np_"]) // cfg["step"] + 1
+        prob = synth.make_problem(cfg["n"], cfg["np_"], cfg["scan"], cfg["step"], cfg["peak"], cfg["seed"],
+                                  name=f"{args.config}-n2{args.n2}", n2=args.n2, scan2=cfg["scan2"])
+    elif args.np:
         prob = synth.make_problem(cfg["n"], cfg["np_"], cfg["scan"], cfg["step"], cfg["peak"], cfg["seed"],
                                   name=f"{args.config}-np{args.np}")
     else:
@@ -448,7 +521,8 @@ def main():
     alpha, kappa, rho = ALPHA[args.config], synth.KAPPA, synth.RHO
     sharp = args.method == "sharp"
     mkw = dict(method=pmace.PMACE_METHOD_SHARP_PLUS, beta=args.beta) if sharp else {}
-    key = workload_key(args.config, args.method, args.np)
+    mkw["flags"] = {"default": 0, "staged": pmace.PMACE_STAGED_AGENT, "split": pmace.PMACE_SPLIT_AGENT}[args.agent]
+    key = workload_key(args.config, args.method, args.np, args.agent) + (f"-n2{args.n2}" if args.n2 else "")
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):
@@ -468,6 +542,7 @@ def main():
         wall = time.perf_counter() - t0
         gpu_ms = ev0.elapsed_time(ev1)
         xh = R.reconstruct().cpu().numpy()
+        agent = R.agent
     ms_per_step = gpu_ms / args.steps
     J, np_ = prob.num_pos, prob.np_
     value = J * args.steps / (gpu_ms / 1e3)
@@ -494,14 +569,15 @@ def main():
         "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": f"{key}: object {prob.n1}x{prob.n2}, probe {np_}x{np_}, "
-                               f"{J} positions ({cfg['scan']}x{cfg['scan']} raster, step {cfg['step']} px"
+                               f"{J} positions ({cfg['scan']}x{cfg['scan2']} raster, step {cfg['step']} px"
                                f"{raster_overhang(prob.n1, np_, cfg['scan'], cfg['step'])}), "
                                f"Poisson peak {cfg['peak']}",
                    "method": "SHARP+ (Alg. 2)" if sharp else "PMACE (Alg. 1)",
                    **({"beta": args.beta} if sharp else {"alpha": alpha, "kappa": kappa, "rho": rho}),
                    "chunk": args.chunk,
+                   "agent": agent,
                    "iteration_graph": "HIP graphs of 32 iterations (single-iteration graph for the rest)"},
-        "roofline": {"bound": "hbm", "kernel": iteration_kernels(np_, J, args.method),
+        "roofline": {"bound": "hbm", "kernel": iteration_kernels(np_, J, args.method, agent),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(key),
                      "algorithmic_bytes_per_step": B},
@@ -513,8 +589,27 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, alpha, kappa, rho, method=args.method, beta=args.beta)
+        out["cpu_baseline_all_cores"] = cpu_baseline_all_cores(prob, alpha, kappa, rho, method=args.method,
+                                                               beta=args.beta)
     if args.copy_mib:
         calibration_copy(args.copy_mib)
+    if args.systems:
+        # the metric's second half: the mixed-size batch (64 reconstructions)
+        # and a short served run, each against the plain one-at-a-time solver
+        # on this GPU, to the same on-device stop rule
+        del R
+        torch.cuda.empty_cache()
+        b = batch_comparison(args)
+        out["batched_vs_plain"] = {k: b[k] for k in ("batched", "plain", "speedup", "same_iterations",
+                                                     "same_nrmse", "iterations", "nrmse")}
+        out["batched_vs_plain"]["workload"] = b["config"]["workload"]
+        sargs = argparse.Namespace(**vars(args))
+        sargs.requests = args.serve_requests
+        sv = serve_comparison(sargs)
+        keep = ("solves_per_s", "p50", "p99", "mean_latency", "completed", "max_active")
+        out["served_vs_plain"] = {"workload": sv["config"]["workload"], "policy": sv["config"]["policy"],
+                                  "served": {k: sv["served"].get(k) for k in keep},
+                                  "plain": {k: sv["plain"].get(k) for k in keep}}
     print(json.dumps(out), flush=True)
 
 

@@ -45,16 +45,20 @@ typedef enum {
 /* Intensities are stored with the zero frequency at the array centre
  * (fftshift layout); they are reordered once at init. */
 #define PMACE_CENTERED_DC 0x1u
-/* Agent variant for large patches (results agree to rounding; both are
- * exact algebra of eq. (9) and Alg. 1).  By default PMACE with np = 192 or
- * 256 and a probe without exact zeros keeps each state as the four coset
- * blocks of the top radix-2 step of its 2-D DFT, so every agent runs on
- * (np/2)^2 blocks held on chip and no spectrum is staged through memory;
+/* Agent variant (results agree to rounding; both are exact algebra of
+ * eq. (9) and Alg. 1).  PMACE with np = 128, 192 or 256 and a probe without
+ * exact zeros can keep each state as the four coset blocks of the top radix-2
+ * step of its 2-D DFT ("split" agent): every agent then runs on (np/2)^2
+ * blocks held on chip and no spectrum is staged through memory (about half
+ * the memory traffic), at the price of reading the probe and the consensus
+ * window once per block.  Otherwise np = 160, 192, 256 run the three-pass
+ * agent that stages each chunk's spectra, and np <= 128 the whole-patch one.
  * SHARP+, and probes with zeros (where eq. (9)'s d = 0 rule acts per pixel),
- * run the three-pass agent that stages each chunk's spectra.
- *   PMACE_STAGED_AGENT: use the three-pass agent for np = 192, 256 as well.
- *   PMACE_SPLIT_AGENT:  use the coset-block agent for np = 128 too (64^2
- *                       blocks) instead of the one-workgroup-per-patch one. */
+ * never use the split agent.  Which sides use it by default is a build
+ * choice (timed by the tuner; this build: np = 192).
+ *   PMACE_STAGED_AGENT: never the split agent.
+ *   PMACE_SPLIT_AGENT:  the split agent wherever it applies (np 128/192/256).
+ * Setting both is EINVAL. */
 #define PMACE_STAGED_AGENT 0x2u
 #define PMACE_SPLIT_AGENT 0x4u
 
@@ -142,6 +146,12 @@ pmace_status pmace_sync(pmace_ctx* ctx);
  * to the batch's stream.  Not for a context that a live batch holds (the
  * batch keeps launching on the stream it was created with). */
 pmace_status pmace_set_stream(pmace_ctx* ctx, void* hip_stream);
+
+/* Which agent a context runs (see the agent flags above): a host query. */
+#define PMACE_AGENT_WHOLE_PATCH 0  /* np <= 128: one workgroup per patch */
+#define PMACE_AGENT_THREE_PASS 1   /* np > 128: rows, columns, inverse rows, spectra staged */
+#define PMACE_AGENT_SPLIT 2        /* coset blocks of (np/2)^2, states in the split layout */
+int32_t pmace_agent_kind(const pmace_ctx* ctx);  /* -1 for NULL */
 
 /* Release the host context (not the caller's workspace).  NULL is a no-op. */
 void pmace_destroy(pmace_ctx* ctx);

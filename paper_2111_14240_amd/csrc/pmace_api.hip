@@ -142,7 +142,8 @@ pmace_status check_params(const pmace_params* p) {
   if (!(std::isfinite(p->alpha) && p->alpha >= 0.f)) return PMACE_EINVAL;
   if (!(std::isfinite(p->kappa) && p->kappa >= 0.f)) return PMACE_EINVAL;
   if (!(std::isfinite(p->rho) && p->rho > 0.f && p->rho < 1.f)) return PMACE_EINVAL;
-  if (p->flags & ~PMACE_CENTERED_DC) return PMACE_EINVAL;
+  if (p->flags & ~(PMACE_CENTERED_DC | PMACE_STAGED_AGENT | PMACE_SPLIT_AGENT)) return PMACE_EINVAL;
+  if ((p->flags & PMACE_STAGED_AGENT) && (p->flags & PMACE_SPLIT_AGENT)) return PMACE_EINVAL;
   if (p->chunk < 0) return PMACE_EINVAL;
   if (p->method != PMACE_METHOD_PMACE && p->method != PMACE_METHOD_SHARP_PLUS) return PMACE_EINVAL;
   if (p->method == PMACE_METHOD_SHARP_PLUS && !(std::isfinite(p->beta) && p->beta >= 0.f && p->beta <= 1.f))
@@ -155,8 +156,45 @@ pmace_status check_params(const pmace_params* p) {
 // Section offsets inside the workspace (relative to the aligned base).
 struct Layout {
   size_t t, ys, pos, d, pc, dinv, gw, omega64, laminv, num, sold, xbar, xhat, stage, tiles, list, status, desc,
-      items, gitems, ritems, red, tw, fit, total;
+      items, gitems, ritems, red, tw, fit, dr, qtiles, qlist, total;
 };
+
+// Patch sides whose default agent is the split (coset-block) one: a build
+// choice measured by the tuner (bit 0: Np = 128, bit 1: 192, bit 2: 256).
+#ifndef PMACE_SPLIT_SIDES
+#define PMACE_SPLIT_SIDES 2
+#endif
+bool split_default(int np) {
+  const int bit = np == 128 ? 1 : np == 192 ? 2 : np == 256 ? 4 : 0;
+  return (PMACE_SPLIT_SIDES & bit) != 0;
+}
+// The split agent may run: PMACE with Np in {128, 192, 256} when asked for,
+// or by default where the build chose it, unless the other agent is asked
+// for.  Whether it does also needs a probe without exact zeros (known at init).
+bool split_allowed(const pmace_params& p) {
+  if (p.method != PMACE_METHOD_PMACE) return false;
+  if (p.np != 128 && p.np != 192 && p.np != 256) return false;
+  if (p.flags & PMACE_SPLIT_AGENT) return true;
+  if (p.flags & PMACE_STAGED_AGENT) return false;
+  return split_default(p.np);
+}
+// Base tiles of the split consensus: rows [0, qrows), columns [0, qcols), the
+// quadrant-0 blocks of all positions lie in [0, n1 - M) x [0, n2 - M).
+int split_rows(const pmace_params& p) {
+  const int M = p.np / 2;
+  return (p.n1 - M + pmace::QT_R - 1) / pmace::QT_R * pmace::QT_R;
+}
+int split_cols(const pmace_params& p) {
+  const int M = p.np / 2;
+  return (p.n2 - M + pmace::QT_C - 1) / pmace::QT_C * pmace::QT_C;
+}
+size_t split_tiles(const pmace_params& p) {
+  return (size_t)(split_rows(p) / pmace::QT_R) * (split_cols(p) / pmace::QT_C);
+}
+size_t split_list(const pmace_params& p) {
+  const int M = p.np / 2;
+  return (size_t)p.num_pos * ((M - 1) / pmace::QT_R + 2) * ((M - 1) / pmace::QT_C + 2);
+}
 
 // Stage buffer: Np > 128 keeps a chunk's spectra between its passes; SHARP+
 // keeps its overlap numerators there; PMACE with Np <= 128 needs none.
@@ -187,7 +225,9 @@ Layout layout_of(const pmace_params& p) {
   L.sold = o;    o = align_up(o + npx * 8);
   L.xbar = o;    o = align_up(o + npx * 8);
   L.xhat = o;    o = align_up(o + npx * 8);
-  L.stage = o;   o = align_up(o + stage_patches(p) * np2 * 8);
+  // the staged spectra and the split layout's partial sums never coexist
+  const bool sp = split_allowed(p);
+  L.stage = o;   o = align_up(o + std::max(stage_patches(p) * np2 * 8, sp ? 4 * npx * 8 : (size_t)0));
   L.tiles = o;   o = align_up(o + max_tiles(p) * 16);
   L.list = o;    o = align_up(o + max_list(p) * 4);
   L.status = o;  o = align_up(o + 128);  // status word, stop flag, finish item, track[8] at +32
@@ -197,7 +237,10 @@ Layout layout_of(const pmace_params& p) {
   L.ritems = o;  o = align_up(o + (size_t)num_red(p) * 8);
   L.red = o;     o = align_up(o + (size_t)num_red(p) * 32);
   L.tw = o;      o = align_up(o + 256 * 8);
-  L.fit = o;     o = align_up(o + (size_t)p.num_pos * fit_bpp(p) * 8);
+  L.fit = o;     o = align_up(o + (size_t)p.num_pos * std::max(fit_bpp(p), sp ? 4 : 0) * 8);
+  L.dr = o;      o = align_up(o + (sp ? np2 * 8 : 0));
+  L.qtiles = o;  o = align_up(o + (sp ? split_tiles(p) * 16 : 0));
+  L.qlist = o;   o = align_up(o + (sp ? split_list(p) * 4 : 0));
   L.total = o;
   return L;
 }
@@ -213,8 +256,13 @@ pmace_status record(pmace_ctx* c, pmace_status s) {
   return s;
 }
 
+// A member that runs as its own chain of kernels (three-pass or split agent).
+bool own_chain(const pmace_ctx* c) { return np_large(c->prm.np) || c->h.split; }
+
 pmace_status enqueue_iteration(pmace_ctx* c, hipStream_t st) {
-  if (np_large(c->prm.np))
+  if (c->h.split)
+    PM_HIP(pmace::launch_split_iteration(c->h, 0, st));
+  else if (np_large(c->prm.np))
     PM_HIP(pmace::launch_large_iteration(c->h, nullptr, c->chunk_tiles.data(), st));
   else
     PM_HIP(pmace::launch_small_iteration(c->prm.np, c->h, c->ngitems, st));
@@ -353,6 +401,36 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   // Lambda = sum_j P_j^t omega and its inverse are formed on the device from
   // the FP64 weights and the consensus tile lists (see launch_init).
 
+  // Split layout: the window weights 2 rho d (FP64, rounded once) and the
+  // base tiles of its consensus.
+  const bool split = split_allowed(p) && !has_zero;
+  const int M = np / 2;
+  std::vector<float> dr;
+  std::vector<int4> qtiles;
+  std::vector<int> qlist;
+  if (split) {
+    dr.assign(2 * np2, 0.f);
+    for (size_t i = 0; i < np2; ++i) {
+      dr[2 * i] = (float)(2.0 * (double)p.rho * (double)probe[i].real());
+      dr[2 * i + 1] = (float)(2.0 * (double)p.rho * (double)probe[i].imag());
+    }
+    const int qr = split_rows(p) / pmace::QT_R, qc = split_cols(p) / pmace::QT_C;
+    std::vector<std::vector<int>> per_tile((size_t)qr * qc);
+    for (int j = 0; j < J; ++j) {
+      const int r = pos[2 * j], cc = pos[2 * j + 1];
+      for (int tr = r / pmace::QT_R; tr <= (r + M - 1) / pmace::QT_R && tr < qr; ++tr)
+        for (int tc = cc / pmace::QT_C; tc <= (cc + M - 1) / pmace::QT_C && tc < qc; ++tc)
+          per_tile[(size_t)tr * qc + tc].push_back(j);
+    }
+    for (int tr = 0; tr < qr; ++tr)
+      for (int tc = 0; tc < qc; ++tc) {
+        const auto& l = per_tile[(size_t)tr * qc + tc];
+        qtiles.push_back(make_int4((int)qlist.size(), (int)l.size(), tr * pmace::QT_R, tc * pmace::QT_C));
+        qlist.insert(qlist.end(), l.begin(), l.end());
+      }
+    if (qtiles.size() > split_tiles(p) || qlist.size() > split_list(p)) return PMACE_EDEVICE;
+  }
+
   // Gather tables: per chunk, GT_R x GT_C tiles over the rows its patches
   // cover, each with the chunk's positions overlapping it in ascending order.
   const int chunk = chunk_of(p);
@@ -433,7 +511,15 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   h.red = reinterpret_cast<double*>(base + L.red);
   h.twn = reinterpret_cast<float2*>(base + L.tw);
   h.fit = reinterpret_cast<double*>(base + L.fit);
-  h.fit_bpp = fit_bpp(p);
+  h.fit_bpp = split ? 4 : fit_bpp(p);
+  h.split = split ? 1 : 0;
+  h.dr = reinterpret_cast<float2*>(base + L.dr);
+  h.part = h.stage;   // the split layout keeps its partial sums where the stage would be
+  h.qtiles = reinterpret_cast<int4*>(base + L.qtiles);
+  h.qlist = reinterpret_cast<int*>(base + L.qlist);
+  h.qrows = split_rows(p);
+  h.qcols = split_cols(p);
+  h.nqt = (int)qtiles.size();
   h.xref = nullptr;
   h.mask = nullptr;
   h.n1 = n1;
@@ -499,6 +585,11 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
       hipMemcpyAsync(c->ritems, ritems.data(), ritems.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(c->fitem, &zero, 4, hipMemcpyHostToDevice, st) != hipSuccess ||
       hipMemcpyAsync(h.twn, tw.data(), (size_t)np * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+      (split &&
+       (hipMemcpyAsync(h.dr, dr.data(), dr.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h.qtiles, qtiles.data(), qtiles.size() * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
+        (!qlist.empty() &&
+         hipMemcpyAsync(h.qlist, qlist.data(), qlist.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess))) ||
       hipMemsetAsync(h.status, 0, 4, st) != hipSuccess ||
       hipMemcpyAsync(c->dev, &c->h, sizeof(Recon), hipMemcpyHostToDevice, st) != hipSuccess)
     return fail(PMACE_EDEVICE);
@@ -640,6 +731,12 @@ pmace_status pmace_sync(pmace_ctx* c) {
   return PMACE_OK;
 }
 
+int32_t pmace_agent_kind(const pmace_ctx* c) {
+  if (!c) return -1;
+  if (c->h.split) return PMACE_AGENT_SPLIT;
+  return np_large(c->prm.np) ? PMACE_AGENT_THREE_PASS : PMACE_AGENT_WHOLE_PATCH;
+}
+
 void pmace_destroy(pmace_ctx* c) {
   if (!c) return;
   // a batch still holding this context (a caller error) must not reach it
@@ -682,7 +779,7 @@ struct BatchLayout {
 BatchLayout batch_layout(pmace_ctx* const* ctxs, int n) {
   BatchLayout L{};
   for (int i = 0; i < n; ++i) {
-    const int k = class_of(ctxs[i]->prm.np);
+    const int k = own_chain(ctxs[i]) ? -1 : class_of(ctxs[i]->prm.np);
     if (k >= 0) {
       L.nitems[k] += ctxs[i]->prm.num_pos;
       L.ngitems[k] += ctxs[i]->ngitems;
@@ -718,7 +815,7 @@ pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes,
   // they fork before the merged launches of the smaller members, so both run
   // at once (the small ones are latency-bound and leave most CUs free)
   bool any_large = false;
-  for (int i = 0; i < b->n; ++i) any_large = any_large || (np_large(b->ctxs[i]->prm.np) && !b->pruned[i]);
+  for (int i = 0; i < b->n; ++i) any_large = any_large || (own_chain(b->ctxs[i]) && !b->pruned[i]);
   const bool forked = lanes && any_large;
   if (forked) {
     PM_HIP(hipEventRecord(b->fork, st));
@@ -731,13 +828,16 @@ pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes,
   int lane = 0;
   for (int i = 0; i < b->n; ++i) {
     pmace_ctx* c = b->ctxs[i];
-    if (!np_large(c->prm.np) || b->pruned[i]) continue;
+    if (!own_chain(c) || b->pruned[i]) continue;
     hipStream_t ls = st;
     if (forked) {
       ls = b->lanes[lane];
       lane = (lane + 1) % 4;
     }
-    PM_HIP(pmace::launch_large_iteration(c->h, b->recs + i, c->chunk_tiles.data(), ls));
+    if (c->h.split)
+      PM_HIP(pmace::launch_split_iteration(c->h, 1, ls));
+    else
+      PM_HIP(pmace::launch_large_iteration(c->h, b->recs + i, c->chunk_tiles.data(), ls));
   }
   if (forked)
     for (int l = 0; l < 4; ++l) {
@@ -752,7 +852,7 @@ pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes,
     for (int k = 0; k < kClasses; ++k)
       PM_HIP(pmace::launch_fit_batch(kSmallNp[k], b->recs, b->items[k], b->nitems[k], st));
     for (int i = 0; i < b->n; ++i)
-      if (np_large(b->ctxs[i]->prm.np) && !b->pruned[i])
+      if (own_chain(b->ctxs[i]) && !b->pruned[i])
         PM_HIP(pmace::launch_fit_member(b->ctxs[i]->h, b->recs + i, 1, st));
     PM_HIP(pmace::launch_fit_finish(b->recs, b->fitems, b->n, 1, b->rule.tol, b->rule.min_iter, st));
   }
@@ -838,7 +938,7 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
     recs[i] = c->h;
     fitems[i] = i;
     for (int r = 0; r < c->h.n_red; ++r) ritems.push_back(make_int2(i, r));
-    const int k = class_of(c->prm.np);
+    const int k = own_chain(c) ? -1 : class_of(c->prm.np);
     if (k < 0) continue;
     for (int j = 0; j < c->prm.num_pos; ++j) items[k].push_back(make_int2(i, j));
     for (int t = 0; t < c->ngitems; ++t) gitems[k].push_back(make_int2(i, t));
@@ -939,7 +1039,7 @@ pmace_status pmace_batch_poll_fit(pmace_batch* b, int32_t* done, double* nrmse, 
   if (hipStreamSynchronize(b->stream) != hipSuccess) return PMACE_EDEVICE;
   bool changed = false;
   for (int i = 0; i < b->n; ++i)
-    if (dn[i] && np_large(b->ctxs[i]->prm.np) && !b->pruned[i]) {
+    if (dn[i] && own_chain(b->ctxs[i]) && !b->pruned[i]) {
       b->pruned[i] = 1;
       b->pruned_at[i] = b->ctxs[i]->resets;
       changed = true;

@@ -99,8 +99,7 @@ struct Recon {
   // whose M x M DFT is the patch spectrum at the frequencies (2 k1 + a, 2 k2 + b);
   // the amplitudes are stored in the same coset order.
   int split;            // 1: t, ys and the data-fit partials in the split layout
-  float2* etab;         // 16 M^2: window coefficients 2 rho (-1)^{a q1 + b q2} W_Np^{a m1 + b m2} d[m + M q],
-                        //   table (2a + b) * 4 + (2 q1 + q2)
+  float2* dr;           // Np^2: 2 rho d (FP64, rounded once), the window weights of the split agent
   float2* part;         // 4 N1 N2: partial consensus sums, one image per quadrant q = 2 q1 + q2
   int4* qtiles;         // per base tile: (list start, count, first row, first col)
   int* qlist;           // positions whose quadrant-0 block meets each base tile, ascending
@@ -121,9 +120,9 @@ hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_
 hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int nitems,
                               const int2* gitems, int ngitems, hipStream_t st);
 // Np > 128, one reconstruction, chunk by chunk; chunk_tiles[g] = (first tile,
-// tile count) of chunk g (host array).  batch_rec: the member's device
-// descriptor when run inside a batch (its kernels honour the stop flag), else
-// null (descriptor passed by value).
+// tile count) of chunk g (host array); the descriptor h passed by value.
+// batch_rec non-null: run as a batch member (its kernels honour the stop
+// flag).
 hipError_t launch_large_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
                                   hipStream_t st);
 hipError_t launch_get_state(const Recon& h, const Recon* rec, float2* v, hipStream_t st);
@@ -151,9 +150,9 @@ hipError_t launch_tick(const Recon* recs, const int* fitems, int nf, int max_ite
                        hipStream_t st);
 hipError_t launch_fft2(int np, int count, const float2* in, float2* out, int inverse, hipStream_t st);
 // Split layout (h.split): one iteration (agent on every (position, coset),
-// consensus over the base tiles, image update); rec = the device descriptor,
-// check_done: skip if the stop flag is set (batch members).
-hipError_t launch_split_iteration(const Recon& h, const Recon* rec, int check_done, hipStream_t st);
+// consensus over the base tiles, image update), the descriptor h passed by
+// value; check_done: skip if the stop flag is set (batch members).
+hipError_t launch_split_iteration(const Recon& h, int check_done, hipStream_t st);
 // Split layout: the consensus sum of the current states into part, then
 // mode 0: sold = S (after init), mode 1: xhat = Lambda^{-1} S and sold = S
 // (after set_state).

@@ -130,7 +130,7 @@ __device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2*
 // see Recon::split).  The top radix-2 step of the Np-point transform, taken
 // outside, turns the patch into four independent NP x NP problems: the block
 // Z_ab of the frame d v = s + 2 rho d P_j xbar is the stored block of s plus
-//     sum_q e_{ab,q}[m] xbar[p_j + m + NP q]   (e = etab: 2 rho, sign, twiddle, d),
+// the split step of the window term (split_frame_row),
 // its NP x NP DFT is the patch spectrum at the frequencies (2 k1 + a, 2 k2 + b),
 // the state spectrum is formed there with the amplitudes stored in the same
 // order, and 4 x its unnormalised inverse is the block Z_ab of the new state
@@ -139,6 +139,54 @@ __device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2*
 // -------------------------------------------------------------------------
 __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 acc) {
   return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
+}
+// acc - a * b
+__device__ __forceinline__ float2 cfms(float2 a, float2 b, float2 acc) {
+  return make_float2(fmaf(-a.x, b.x, fmaf(a.y, b.y, acc.x)), fmaf(-a.x, b.y, fmaf(-a.y, b.x, acc.y)));
+}
+
+// Split-agent frame, elements [NB0, NB1) of row rr of block ab of position j
+// (columns c = p + A nb):
+//   Z_ab[rr][c] + W_Np^{a rr + b c} sum_q (-1)^{a q1 + b q2} (2 rho d)[(rr, c) + M q] xbar[p_j + (rr, c) + M q].
+// The quadrant loop is kept rolled, so one quadrant's loads are in flight at a
+// time (they are L2 hits: the probe table and the consensus image); the state
+// block, read from HBM, is loaded last.  twnp: W_Np^m, m < Np, in LDS.
+template <int M, int NB0, int NB1>
+__device__ __forceinline__ void split_frame_row(const Recon& g, const int j, const int ab, const int rr,
+                                                const int p, const float2* twnp, float2 (&x)[Geo<M>::B]) {
+  constexpr int A = Geo<M>::A, NP = 2 * M;
+  const int a = ab >> 1, b = ab & 1;
+  const int2 pj = g.pos[j];
+#pragma unroll
+  for (int nb = NB0; nb < NB1; ++nb) x[nb] = make_float2(0.f, 0.f);
+#pragma unroll 1
+  for (int q = 0; q < 4; ++q) {
+    const int q1 = q >> 1, q2 = q & 1;
+    const float2* dq = g.dr + (size_t)(rr + M * q1) * NP + M * q2;
+    const float2* xq = g.xbar + (size_t)(pj.x + rr + M * q1) * g.n2 + pj.y + M * q2;
+    if ((a * q1 + b * q2) & 1) {   // uniform across the workgroup
+#pragma unroll
+      for (int nb = NB0; nb < NB1; ++nb) x[nb] = cfms(dq[p + A * nb], xq[p + A * nb], x[nb]);
+    } else {
+#pragma unroll
+      for (int nb = NB0; nb < NB1; ++nb) x[nb] = cfma(dq[p + A * nb], xq[p + A * nb], x[nb]);
+    }
+  }
+  // an empty asm "writes" the row index, so the state and twiddle loads
+  // below cannot be hoisted above the quadrant loop (their registers would
+  // be held across it)
+  int ri = rr;
+  asm volatile("" : "+v"(ri));
+  const float2* z = g.t + ((size_t)j * 4 + ab) * M * M + (size_t)ri * M;
+#pragma unroll
+  for (int nb = NB0; nb < NB1; ++nb) {
+    const int c = p + A * nb;
+    x[nb] = cfma(twnp[a * ri + b * c], x[nb], z[c]);
+  }
+  // and the frame is formed here, not sunk to its first use (the loads it
+  // consumes would otherwise stay live across the next call's loop)
+#pragma unroll
+  for (int nb = NB0; nb < NB1; ++nb) asm volatile("" : "+v"(x[nb].x), "+v"(x[nb].y));
 }
 
 template <int NP, int METHOD, bool SPLIT = false>
@@ -158,19 +206,11 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, co
 
   float2 x[B];
   if constexpr (SPLIT) {
-    const float2* e = g.etab + (size_t)ab * 4 * NP * NP + (size_t)r * NP;
-    const size_t down = (size_t)NP * g.n2;   // NP object rows further
-#pragma unroll
-    for (int nb = 0; nb < B; ++nb) {
-      const int c = p + A * nb;
-      float2 f = trow[c];
-      f = cfma(e[c], xrow[c], f);
-      f = cfma(e[NP * NP + c], xrow[c + NP], f);
-      f = cfma(e[2 * NP * NP + c], xrow[down + c], f);
-      f = cfma(e[3 * NP * NP + c], xrow[down + c + NP], f);
-      x[nb] = f;
-    }
-    for (int m = tid; m < NP; m += NT) tw[m] = g.twn[2 * m];
+    __shared__ float2 twnp[2 * NP];
+    for (int m = tid; m < 2 * NP; m += NT) twnp[m] = g.twn[m];
+    __syncthreads();
+    for (int m = tid; m < NP; m += NT) tw[m] = twnp[2 * m];
+    split_frame_row<NP, 0, B>(g, j, ab, r, p, twnp, x);
   } else {
 #pragma unroll
     for (int nb = 0; nb < B; ++nb) {
@@ -254,16 +294,268 @@ __global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused_batch(const Recon
   agent_fused_body<NP, kPMACE>(g, it.y);
 }
 
+// The window term of two coset blocks, (a, 0) and (a, 1), of position j at
+// once: each product (2 rho d) xbar is loaded once and added to both blocks
+// with the signs (-1)^{a q1 + b q2}, so a workgroup doing both blocks reads
+// the probe and the consensus window half as often per block.  Each block's
+// sums are formed exactly as split_frame_row forms them.
+template <int M, int NB0, int NB1>
+__device__ __forceinline__ void split_frame_pair(const Recon& g, const int j, const int a, const int rr,
+                                                 const int p, const float2* twnp, float2 (&x0)[Geo<M>::B],
+                                                 float2 (&x1)[Geo<M>::B]) {
+  constexpr int A = Geo<M>::A, NP = 2 * M, NB = NB1 - NB0;
+  const int2 pj = g.pos[j];
+#pragma unroll
+  for (int nb = NB0; nb < NB1; ++nb) x0[nb] = x1[nb] = make_float2(0.f, 0.f);
+#pragma unroll 1
+  for (int q = 0; q < 4; ++q) {
+    const int q1 = q >> 1, q2 = q & 1;
+    const float2* dq = g.dr + (size_t)(rr + M * q1) * NP + M * q2;
+    const float2* xq = g.xbar + (size_t)(pj.x + rr + M * q1) * g.n2 + pj.y + M * q2;
+    float2 dv[NB], xv[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k) {
+      dv[k] = dq[p + A * (NB0 + k)];
+      xv[k] = xq[p + A * (NB0 + k)];
+    }
+    if ((a * q1) & 1) {            // block (a, 0); uniform across the workgroup
+#pragma unroll
+      for (int k = 0; k < NB; ++k) x0[NB0 + k] = cfms(dv[k], xv[k], x0[NB0 + k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NB; ++k) x0[NB0 + k] = cfma(dv[k], xv[k], x0[NB0 + k]);
+    }
+    if ((a * q1 + q2) & 1) {       // block (a, 1)
+#pragma unroll
+      for (int k = 0; k < NB; ++k) x1[NB0 + k] = cfms(dv[k], xv[k], x1[NB0 + k]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < NB; ++k) x1[NB0 + k] = cfma(dv[k], xv[k], x1[NB0 + k]);
+    }
+  }
+  int ri = rr;
+  asm volatile("" : "+v"(ri));
+  const float2* z0 = g.t + ((size_t)j * 4 + 2 * a) * M * M + (size_t)ri * M;
+  const float2* z1 = z0 + (size_t)M * M;
+#pragma unroll
+  for (int nb = NB0; nb < NB1; ++nb) {
+    const int c = p + A * nb;
+    x0[nb] = cfma(twnp[a * ri], x0[nb], z0[c]);
+    x1[nb] = cfma(twnp[a * ri + c], x1[nb], z1[c]);
+  }
+#pragma unroll
+  for (int nb = NB0; nb < NB1; ++nb) {
+    asm volatile("" : "+v"(x0[nb].x), "+v"(x0[nb].y));
+    asm volatile("" : "+v"(x1[nb].x), "+v"(x1[nb].y));
+  }
+}
+
+// One split block from its frame x (row layout) to its new state: forward
+// transforms, state spectrum with the block's amplitudes, inverse transforms,
+// store.  The same steps, in the same order, as agent_fused_body's split path.
+template <int M>
+__device__ __forceinline__ void split_block_pass(const Recon& g, const size_t pb, float2 (&x)[Geo<M>::B],
+                                                 float2* tile, const float2* tw) {
+  constexpr int A = Geo<M>::A, B = Geo<M>::B, S = M + A, MB = B / A;
+  const int tid = threadIdx.x;
+  const int r = tid / A, p = tid % A, c = tid % M, q = tid / M;
+  const float* yc = g.ys + pb + c;
+  float yv[B];
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) yv[m * A + ka] = yc[(size_t)(q + A * m + B * ka) * M];
+  __syncthreads();
+  float2* row = tile + r * S;
+  row_fwd<M>(x, row, p, tw);
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) row[p + A * m + B * ka] = x[m * A + ka];
+  __syncthreads();
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) x[nb] = tile[(q + A * nb) * S + c];
+  col_fwd<M>(x, tile, S, c, q, tw);
+  {
+    const float sb = 4.f * g.sb, s2r = 4.f * g.s2r;   // exact: powers of two
+#pragma unroll
+    for (int k = 0; k < B; ++k) x[k] = state_spectrum(x[k], yv[k], sb, s2r);
+  }
+  col_inv<M>(x, tile, S, c, q, tw);
+  __syncthreads();
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) tile[(q + A * nb) * S + c] = x[nb];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) x[m * A + ka] = row[p + A * m + B * ka];
+  row_inv<M>(x, row, p, tw);
+  float2* z = g.t + pb + (size_t)r * M;
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) z[p + A * nb] = x[nb];
+}
+
+// Split layout, two coset blocks per workgroup: blocks (a, 0) and (a, 1) of
+// one position share their window loads (split_frame_pair), then run one
+// after the other through the block transforms.
+template <int M>
+__device__ __forceinline__ void agent_split_pair_body(const Recon& g, const int j, const int a) {
+  constexpr int A = Geo<M>::A, B = Geo<M>::B, S = M + A, NT = M * A;
+  __shared__ float2 tile[M * S];
+  __shared__ float2 tw[M];
+  __shared__ float2 twnp[2 * M];
+  const int tid = threadIdx.x;
+  for (int m = tid; m < 2 * M; m += NT) twnp[m] = g.twn[m];
+  __syncthreads();
+  for (int m = tid; m < M; m += NT) tw[m] = twnp[2 * m];
+  const int r = tid / A, p = tid % A;
+  float2 x0[B], x1[B];
+  split_frame_pair<M, 0, B / 2>(g, j, a, r, p, twnp, x0, x1);
+  split_frame_pair<M, B / 2, B>(g, j, a, r, p, twnp, x0, x1);
+  split_block_pass<M>(g, ((size_t)j * 4 + 2 * a) * M * M, x0, tile, tw);
+  split_block_pass<M>(g, ((size_t)j * 4 + 2 * a + 1) * M * M, x1, tile, tw);
+}
+
+// Block b: position xcd * jper + (b / 8) / 2, row of cosets a = (b / 8) mod 2
+// (the two workgroups of a position on one XCD, back to back).
+template <int M>
+__global__ void __launch_bounds__(M * Geo<M>::A) agent_split_pair(const Recon g, int check_done, int jper) {
+  if (check_done && *g.done) return;
+  const int b = blockIdx.x, slot = b >> 3;
+  const int j = (b & 7) * jper + (slot >> 1);
+  if (j >= g.J) return;
+  agent_split_pair_body<M>(g, j, slot & 1);
+}
+
+// The split-layout agent for 128 x 128 blocks (Np = 256) with half the
+// threads and half the LDS of the whole-block version, so that two workgroups
+// share a CU and one's loads overlap the other's transforms: 512 threads;
+// each thread owns two rows (r and r + 64) in the row phase and two slots
+// (q and q + 4) of a column in the column phase.  The block passes between
+// the phases through a 64-row tile in two halves, and the column exchanges
+// run in two rounds.  Same arithmetic, in the same order, as
+// agent_fused_body<128, kPMACE, true>: the results are bitwise equal.
+template <int M>
+__device__ __forceinline__ void agent_split_half_body(const Recon& g, const int j, const int ab) {
+  constexpr int A = Geo<M>::A, B = Geo<M>::B, S = M + A, MB = B / A, HR = M / 2, NT = HR * A;
+  constexpr int MM = M * M;
+  static_assert(A % 2 == 0 && (B / 2) * A == HR, "two rows per thread, half the column slots");
+  __shared__ float2 tile[HR * S];
+  __shared__ float2 tw[M];
+  const int tid = threadIdx.x;
+  const size_t pb = ((size_t)j * 4 + ab) * MM;
+  const int r = tid / A, p = tid % A;
+  __shared__ float2 twnp[2 * M];
+  for (int m = tid; m < 2 * M; m += NT) twnp[m] = g.twn[m];
+  __syncthreads();
+  for (int m = tid; m < M; m += NT) tw[m] = twnp[2 * m];
+  float2 x0[B], x1[B];
+  split_frame_row<M, 0, B / 2>(g, j, ab, r, p, twnp, x0);
+  split_frame_row<M, B / 2, B>(g, j, ab, r, p, twnp, x0);
+  split_frame_row<M, 0, B / 2>(g, j, ab, r + HR, p, twnp, x1);
+  split_frame_row<M, B / 2, B>(g, j, ab, r + HR, p, twnp, x1);
+  __syncthreads();
+  float2* row = tile + r * S;
+  row_fwd<M>(x0, row, p, tw);
+  row_fwd<M>(x1, row, p, tw);
+
+  // rows -> columns: rows [0, HR) then [HR, M) through the tile
+  const int c = tid % M, q = tid / M, q2 = q + A / 2;
+  float2 xa[B], xb[B];
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) row[p + A * m + B * ka] = x0[m * A + ka];
+  __syncthreads();
+#pragma unroll
+  for (int nb = 0; nb < B / 2; ++nb) {
+    xa[nb] = tile[(q + A * nb) * S + c];
+    xb[nb] = tile[(q2 + A * nb) * S + c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) row[p + A * m + B * ka] = x1[m * A + ka];
+  __syncthreads();
+#pragma unroll
+  for (int nb = B / 2; nb < B; ++nb) {
+    xa[nb] = tile[(q + A * nb - HR) * S + c];
+    xb[nb] = tile[(q2 + A * nb - HR) * S + c];
+  }
+  col_fwd2<M, 2>(xa, xb, tile, M, c, q, tw);
+  {
+    const float* yc = g.ys + pb + c;
+    const float sb = 4.f * g.sb, s2r = 4.f * g.s2r;   // exact: powers of two
+#pragma unroll
+    for (int m = 0; m < MB; ++m)
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) {
+        const float ya = yc[(size_t)(q + A * m + B * ka) * M], yb = yc[(size_t)(q2 + A * m + B * ka) * M];
+        xa[m * A + ka] = state_spectrum(xa[m * A + ka], ya, sb, s2r);
+        xb[m * A + ka] = state_spectrum(xb[m * A + ka], yb, sb, s2r);
+      }
+  }
+  col_inv2<M, 2>(xa, xb, tile, M, c, q, tw);
+
+  // columns -> rows, in the same two halves
+  __syncthreads();
+#pragma unroll
+  for (int nb = 0; nb < B / 2; ++nb) {
+    tile[(q + A * nb) * S + c] = xa[nb];
+    tile[(q2 + A * nb) * S + c] = xb[nb];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) x0[m * A + ka] = row[p + A * m + B * ka];
+  __syncthreads();
+#pragma unroll
+  for (int nb = B / 2; nb < B; ++nb) {
+    tile[(q + A * nb - HR) * S + c] = xa[nb];
+    tile[(q2 + A * nb - HR) * S + c] = xb[nb];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int ka = 0; ka < A; ++ka) x1[m * A + ka] = row[p + A * m + B * ka];
+  row_inv<M>(x0, row, p, tw);
+  row_inv<M>(x1, row, p, tw);
+  float2* z0 = g.t + pb + (size_t)r * M;
+  float2* z1 = z0 + (size_t)HR * M;
+#pragma unroll
+  for (int nb = 0; nb < B; ++nb) {
+    z0[p + A * nb] = x0[nb];
+    z1[p + A * nb] = x1[nb];
+  }
+}
+
+template <int M>
+__global__ void __launch_bounds__(M / 2 * Geo<M>::A, 4) agent_split_half(const Recon g, int check_done,
+                                                                         int jper) {
+  if (check_done && *g.done) return;
+  const int b = blockIdx.x, slot = b >> 3;
+  const int j = (b & 7) * jper + (slot >> 2);
+  if (j >= g.J) return;
+  agent_split_half_body<M>(g, j, slot & 3);
+}
+
 // Split layout, Np = 2 M: one workgroup per (position, coset).  Workgroups
 // are dealt to the XCDs in turn (block b runs on XCD b mod 8), so block b
 // takes position xcd * jper + (b / 8) / 4 and coset (b / 8) mod 4: the four
 // cosets of a position, which read the same consensus window, share an XCD's
 // L2, and each XCD works through a contiguous run of positions (a band of
 // the object).
+// The descriptor is passed by value (a batch member's too: the kernels read
+// its stop flag through it), so the compiler knows its arrays are global
+// memory and issues global, not flat, loads.
 template <int M>
-__global__ void __launch_bounds__(M * Geo<M>::A) agent_split(const Recon* __restrict__ rec, int check_done,
-                                                             int jper) {
-  const Recon& g = *rec;
+__global__ void __launch_bounds__(M * Geo<M>::A) agent_split(const Recon g, int check_done, int jper) {
   if (check_done && *g.done) return;
   const int b = blockIdx.x, slot = b >> 3;
   const int j = (b & 7) * jper + (slot >> 2);
@@ -330,10 +622,12 @@ __global__ void __launch_bounds__(row_threads<NP>()) agent_rows(const Recon g, i
   agent_rows_body<NP, METHOD>(g, j0);
 }
 
+// Batch members: the member's descriptor by value (global, not flat, loads),
+// its stop flag read through it.
 template <int NP>
-__global__ void __launch_bounds__(row_threads<NP>()) agent_rows_batch(const Recon* __restrict__ rec, int j0) {
-  if (*rec->done) return;
-  agent_rows_body<NP, kPMACE>(*rec, j0);
+__global__ void __launch_bounds__(row_threads<NP>()) agent_rows_batch(const Recon g, int j0) {
+  if (*g.done) return;
+  agent_rows_body<NP, kPMACE>(g, j0);
 }
 
 template <int NP, int METHOD>
@@ -378,9 +672,9 @@ __global__ void __launch_bounds__(col_threads<NP>()) agent_cols(const Recon g, i
 }
 
 template <int NP>
-__global__ void __launch_bounds__(col_threads<NP>()) agent_cols_batch(const Recon* __restrict__ rec, int j0) {
-  if (*rec->done) return;
-  agent_cols_body<NP, kPMACE>(*rec, j0);
+__global__ void __launch_bounds__(col_threads<NP>()) agent_cols_batch(const Recon g, int j0) {
+  if (*g.done) return;
+  agent_cols_body<NP, kPMACE>(g, j0);
 }
 
 template <int NP, int METHOD>
@@ -432,10 +726,9 @@ __global__ void __launch_bounds__(row_threads<NP>()) agent_rowsinv(const Recon g
 }
 
 template <int NP>
-__global__ void __launch_bounds__(row_threads<NP>()) agent_rowsinv_batch(const Recon* __restrict__ rec,
-                                                                         int j0) {
-  if (*rec->done) return;
-  agent_rowsinv_body<NP, kPMACE>(*rec, j0);
+__global__ void __launch_bounds__(row_threads<NP>()) agent_rowsinv_batch(const Recon g, int j0) {
+  if (*g.done) return;
+  agent_rowsinv_body<NP, kPMACE>(g, j0);
 }
 
 // -------------------------------------------------------------------------
@@ -570,10 +863,10 @@ __global__ void __launch_bounds__(GT_THREADS) consensus_gather(const Recon g, in
 
 // One batch member (descriptor in device memory): block b handles tile first_tile + b.
 template <int NP, bool FUSE>
-__global__ void __launch_bounds__(GT_THREADS) consensus_gather_member(const Recon* __restrict__ rec,
-                                                                       int first_tile, int jbase) {
-  if (*rec->done) return;
-  consensus_gather_body<NP, FUSE, kPMACE>(*rec, first_tile + blockIdx.x, jbase);
+__global__ void __launch_bounds__(GT_THREADS) consensus_gather_member(const Recon g, int first_tile,
+                                                                       int jbase) {
+  if (*g.done) return;
+  consensus_gather_body<NP, FUSE, kPMACE>(g, first_tile + blockIdx.x, jbase);
 }
 
 // Batched: block b handles work item (reconstruction, tile) b.
@@ -599,9 +892,9 @@ __device__ __forceinline__ void image_update_body(const Recon& g) {
 
 __global__ void image_update(const Recon g) { image_update_body(g); }
 
-__global__ void image_update_batch(const Recon* __restrict__ rec) {
-  if (*rec->done) return;
-  image_update_body(*rec);
+__global__ void image_update_batch(const Recon g) {
+  if (*g.done) return;
+  image_update_body(g);
 }
 
 // After the states were set from outside (xbar = 0, t = v): xhat = the
@@ -1241,8 +1534,7 @@ __device__ __forceinline__ void consensus_split_body(const Recon& g, const int t
 }
 
 template <int M>
-__global__ void __launch_bounds__(QT_THREADS) consensus_split(const Recon* __restrict__ rec, int check_done) {
-  const Recon& g = *rec;
+__global__ void __launch_bounds__(QT_THREADS) consensus_split(const Recon g, int check_done) {
   if (check_done && *g.done) return;
   consensus_split_body<M>(g, blockIdx.x);
 }
@@ -1262,8 +1554,7 @@ __device__ __forceinline__ float2 split_sum(const Recon& g, int R, int C) {
 }
 
 // a9 for the split layout.
-__global__ void image_update_split(const Recon* __restrict__ rec, int check_done) {
-  const Recon& g = *rec;
+__global__ void image_update_split(const Recon g, int check_done) {
   if (check_done && *g.done) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n1 * g.n2) return;
@@ -1360,9 +1651,7 @@ __global__ void get_state_split_k(const Recon* __restrict__ rec, float2* v) {
 // per workgroup (frame split as above, M x M forward DFT), against the
 // amplitudes of the same coset.
 template <int M>
-__global__ void __launch_bounds__(M * Geo<M>::A) fit_split(const Recon* __restrict__ rec, int check_done,
-                                                           int jper) {
-  const Recon& g = *rec;
+__global__ void __launch_bounds__(M * Geo<M>::A) fit_split(const Recon g, int check_done, int jper) {
   if (check_done && *g.done) return;
   constexpr int A = Geo<M>::A, B = Geo<M>::B, S = M + A, NT = M * A, MB = B / A;
   const int bi = blockIdx.x, slot = bi >> 3;
@@ -1465,9 +1754,9 @@ static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* 
     const dim3 rgrid(cnt * (NP / rb_of<NP>())), cgrid(cnt * (NP / CB));
     const int2 ct = chunk_tiles[g];
     if (batch_rec) {
-      hipLaunchKernelGGL(agent_rows_batch<NP>, rgrid, dim3(RT), 0, st, batch_rec, j0);
-      hipLaunchKernelGGL(agent_cols_batch<NP>, cgrid, dim3(CT), 0, st, batch_rec, j0);
-      hipLaunchKernelGGL(agent_rowsinv_batch<NP>, rgrid, dim3(RT), 0, st, batch_rec, j0);
+      hipLaunchKernelGGL(agent_rows_batch<NP>, rgrid, dim3(RT), 0, st, h, j0);
+      hipLaunchKernelGGL(agent_cols_batch<NP>, cgrid, dim3(CT), 0, st, h, j0);
+      hipLaunchKernelGGL(agent_rowsinv_batch<NP>, rgrid, dim3(RT), 0, st, h, j0);
     } else if (h.method == kSharpPlus) {
       hipLaunchKernelGGL((agent_rows<NP, kSharpPlus>), rgrid, dim3(RT), 0, st, h, j0);
       hipLaunchKernelGGL((agent_cols<NP, kSharpPlus>), cgrid, dim3(CT), 0, st, h, j0);
@@ -1480,7 +1769,7 @@ static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* 
     if (ct.y > 0) {
       if (batch_rec)
         hipLaunchKernelGGL((consensus_gather_member<NP, false>), dim3(ct.y), dim3(GT_THREADS), 0,
-                           st, batch_rec, ct.x, j0);
+                           st, h, ct.x, j0);
       else if (h.method == kSharpPlus)
         hipLaunchKernelGGL((consensus_gather<NP, false, kSharpPlus>), dim3(ct.y), dim3(GT_THREADS),
                            0, st, h, ct.x, j0);
@@ -1491,7 +1780,7 @@ static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* 
   }
   const unsigned nb = blocks_for((long long)h.n1 * h.n2, 256);
   if (batch_rec)
-    hipLaunchKernelGGL(image_update_batch, dim3(nb), dim3(256), 0, st, batch_rec);
+    hipLaunchKernelGGL(image_update_batch, dim3(nb), dim3(256), 0, st, h);
   else
     hipLaunchKernelGGL(image_update, dim3(nb), dim3(256), 0, st, h);
 }
@@ -1535,20 +1824,35 @@ static hipError_t gather_into_num(const Recon& h, int2 ct, int j0, hipStream_t s
   return hipGetLastError();
 }
 
+#ifndef PMACE_SPLIT_HALF
+#define PMACE_SPLIT_HALF 0   // Np = 256: the 512-thread block agent (two workgroups per CU)
+#endif
+
+#ifndef PMACE_SPLIT_PAIR
+#define PMACE_SPLIT_PAIR 1   // two coset blocks per workgroup, sharing their window loads
+#endif
+
 template <int M>
-static void split_iteration(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
+static void split_iteration(const Recon& h, int check_done, hipStream_t st) {
   const int jper = (h.J + 7) / 8;
-  hipLaunchKernelGGL(agent_split<M>, dim3(8 * jper * 4), dim3(M * Geo<M>::A), 0, st, rec, check_done, jper);
-  hipLaunchKernelGGL(consensus_split<M>, dim3(h.nqt), dim3(QT_THREADS), 0, st, rec, check_done);
+  if constexpr (PMACE_SPLIT_PAIR)
+    hipLaunchKernelGGL(agent_split_pair<M>, dim3(8 * jper * 2), dim3(M * Geo<M>::A), 0, st, h, check_done,
+                       jper);
+  else if constexpr (M == 128 && PMACE_SPLIT_HALF)
+    hipLaunchKernelGGL(agent_split_half<M>, dim3(8 * jper * 4), dim3(M / 2 * Geo<M>::A), 0, st, h,
+                       check_done, jper);
+  else
+    hipLaunchKernelGGL(agent_split<M>, dim3(8 * jper * 4), dim3(M * Geo<M>::A), 0, st, h, check_done, jper);
+  hipLaunchKernelGGL(consensus_split<M>, dim3(h.nqt), dim3(QT_THREADS), 0, st, h, check_done);
   hipLaunchKernelGGL(image_update_split, dim3(blocks_for((long long)h.n1 * h.n2, 256)), dim3(256), 0, st,
-                     rec, check_done);
+                     h, check_done);
 }
 
-hipError_t launch_split_iteration(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
+hipError_t launch_split_iteration(const Recon& h, int check_done, hipStream_t st) {
   switch (h.np) {
-    case 128: split_iteration<64>(h, rec, check_done, st); break;
-    case 192: split_iteration<96>(h, rec, check_done, st); break;
-    case 256: split_iteration<128>(h, rec, check_done, st); break;
+    case 128: split_iteration<64>(h, check_done, st); break;
+    case 192: split_iteration<96>(h, check_done, st); break;
+    case 256: split_iteration<128>(h, check_done, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1556,9 +1860,9 @@ hipError_t launch_split_iteration(const Recon& h, const Recon* rec, int check_do
 
 hipError_t launch_split_consensus(const Recon& h, const Recon* rec, int mode, hipStream_t st) {
   switch (h.np) {
-    case 128: hipLaunchKernelGGL(consensus_split<64>, dim3(h.nqt), dim3(QT_THREADS), 0, st, rec, 0); break;
-    case 192: hipLaunchKernelGGL(consensus_split<96>, dim3(h.nqt), dim3(QT_THREADS), 0, st, rec, 0); break;
-    case 256: hipLaunchKernelGGL(consensus_split<128>, dim3(h.nqt), dim3(QT_THREADS), 0, st, rec, 0); break;
+    case 128: hipLaunchKernelGGL(consensus_split<64>, dim3(h.nqt), dim3(QT_THREADS), 0, st, h, 0); break;
+    case 192: hipLaunchKernelGGL(consensus_split<96>, dim3(h.nqt), dim3(QT_THREADS), 0, st, h, 0); break;
+    case 256: hipLaunchKernelGGL(consensus_split<128>, dim3(h.nqt), dim3(QT_THREADS), 0, st, h, 0); break;
     default: return hipErrorInvalidValue;
   }
   hipLaunchKernelGGL(image_from_split, dim3(blocks_for((long long)h.n1 * h.n2, 256)), dim3(256), 0, st, rec,
@@ -1566,13 +1870,13 @@ hipError_t launch_split_consensus(const Recon& h, const Recon* rec, int mode, hi
   return hipGetLastError();
 }
 
-static hipError_t launch_fit_split(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
+static hipError_t launch_fit_split(const Recon& h, int check_done, hipStream_t st) {
   const int jper = (h.J + 7) / 8;
   const dim3 grid(8 * jper * 4);
   switch (h.np) {
-    case 128: hipLaunchKernelGGL(fit_split<64>, grid, dim3(64 * Geo<64>::A), 0, st, rec, check_done, jper); break;
-    case 192: hipLaunchKernelGGL(fit_split<96>, grid, dim3(96 * Geo<96>::A), 0, st, rec, check_done, jper); break;
-    case 256: hipLaunchKernelGGL(fit_split<128>, grid, dim3(128 * Geo<128>::A), 0, st, rec, check_done, jper); break;
+    case 128: hipLaunchKernelGGL(fit_split<64>, grid, dim3(64 * Geo<64>::A), 0, st, h, check_done, jper); break;
+    case 192: hipLaunchKernelGGL(fit_split<96>, grid, dim3(96 * Geo<96>::A), 0, st, h, check_done, jper); break;
+    case 256: hipLaunchKernelGGL(fit_split<128>, grid, dim3(128 * Geo<128>::A), 0, st, h, check_done, jper); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1663,7 +1967,7 @@ static void fit_large(const Recon& h, const Recon* rec, int check_done, hipStrea
 }
 
 hipError_t launch_fit_member(const Recon& h, const Recon* rec, int check_done, hipStream_t st) {
-  if (h.split) return launch_fit_split(h, rec, check_done, st);
+  if (h.split) return launch_fit_split(h, check_done, st);
   switch (h.np) {
 #define PMACE_FIT(N)                                                                               \
   case N:                                                                                          \

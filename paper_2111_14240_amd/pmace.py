@@ -124,6 +124,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     L.pmace_simulate_static.argtypes = [i32, i32, i32, i32, vp, vp, vp, ctypes.c_double, ctypes.c_uint64,
                                         vp, ctypes.POINTER(ctypes.c_double), vp]
     L.pmace_simulate_static.restype = ctypes.c_int
+    L.pmace_agent_kind.argtypes = [vp]
+    L.pmace_agent_kind.restype = i32
     L.pmace_philox4x32_10.argtypes = [vp, i32, vp]
     L.pmace_philox4x32_10.restype = ctypes.c_int
     L.pmace_poisson.argtypes = [vp, vp, i32, ctypes.c_uint64, vp]
@@ -444,6 +446,13 @@ class Reconstruction:
 
     def iterate(self, n: int = 1):
         _check(pmace_iterate(self.ctx, n), "pmace_iterate")
+
+    @property
+    def agent(self) -> str:
+        """'whole patch', 'three-pass' or 'split' (coset blocks): the agent this
+        reconstruction runs."""
+        k = load_library().pmace_agent_kind(self.ctx)
+        return {0: "whole patch", 1: "three-pass", 2: "split"}[k]
 
     def reconstruct(self, out=None):
         torch = _torch()

@@ -166,13 +166,17 @@ def simulate_intensities(x: np.ndarray, d: np.ndarray, pos: np.ndarray,
 
 
 def make_problem(n: int, np_: int, scan: int, step: int, peak: Optional[float],
-                 seed: int, name: str = "", n2: Optional[int] = None) -> Problem:
-    """Build one seeded problem.  RNG draw order: object, jitter, Poisson."""
+                 seed: int, name: str = "", n2: Optional[int] = None,
+                 scan2: Optional[int] = None) -> Problem:
+    """Build one seeded problem.  RNG draw order: object, jitter, Poisson.
+    With scan2 the raster is scan x scan2 (rows x columns) on an n x n2 object."""
     n2 = n if n2 is None else n2
     rng = np.random.default_rng(seed)
     x = make_object(n, n2, rng)
     d = make_probe(np_)
-    if n2 != n:
+    if scan2 is not None:
+        pos = make_positions_rect(n, n2, np_, scan, scan2, step, rng)
+    elif n2 != n:
         pr = make_positions(n, np_, scan, step, rng)
         pc = make_positions(n2, np_, scan, step, rng)
         pos = np.stack([pr[:, 0], pc[:, 1]], axis=1).astype(np.int32)

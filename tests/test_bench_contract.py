@@ -28,8 +28,9 @@ def test_bench_line_has_the_contract_fields():
     torch = pytest.importorskip("torch")
     if not torch.cuda.is_available():
         pytest.skip("no HIP device")
-    print("[bench-contract] c1, 5 steps", flush=True)
-    r = _run(["--config", "c1", "--steps", "5", "--warmup", "1"])
+    print("[bench-contract] c1, 5 steps, small systems legs", flush=True)
+    r = _run(["--config", "c1", "--steps", "5", "--warmup", "1", "--items", "6", "--pool", "6",
+              "--serve-requests", "12"])
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
     assert len(lines) == 1
@@ -45,12 +46,21 @@ def test_bench_line_has_the_contract_fields():
     assert "traffic" in rl
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["cores"] >= 1 and cb["value"] > 0 and cb["sample"]
+    assert cb["cpu_model"] and cb["host_cpu_count"] >= 1
+    ca = d["cpu_baseline_all_cores"]
+    assert ca["kind"] == "oracle" and ca["cores"] >= 1 and ca["value"] > 0
+    bp = d["batched_vs_plain"]
+    assert bp["batched"]["solves_per_s"] > 0 and bp["plain"]["solves_per_s"] > 0 and bp["same_iterations"]
+    sp = d["served_vs_plain"]
+    assert sp["served"]["completed"] == 12 and sp["plain"]["completed"] == 12
+    assert sp["served"]["p99"] >= sp["served"]["p50"] > 0
 
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("args,metric", [
-    (["--config", "c1", "--method", "sharp", "--steps", "4", "--warmup", "1"], "SHARP+ patch-updates/s"),
-    (["--config", "c1", "--np", "48", "--steps", "4", "--warmup", "1"], "PMACE patch-updates/s"),
+    (["--config", "c1", "--method", "sharp", "--steps", "4", "--warmup", "1", "--no-systems"],
+     "SHARP+ patch-updates/s"),
+    (["--config", "c1", "--np", "48", "--steps", "4", "--warmup", "1", "--no-systems"], "PMACE patch-updates/s"),
     (["--mode", "simulate", "--config", "c1", "--steps", "3", "--warmup", "1"], "simulated frames/s"),
 ])
 def test_variant_lines(args, metric):
