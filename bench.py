@@ -29,6 +29,10 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmace_hbm_traffic.md")
 KERNEL_SOURCES = ["csrc/pmace_kernels.hip", "csrc/pmace_dft.hpp", "csrc/pmace_internal.hpp",
                   "csrc/pmace_api.hip", "tuned.json"]
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+# What `traffic` counts: requests leaving the L2 for the memory fabric
+# (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a plain copy).
+# The Infinity Cache sits behind those requests, so its hits are included.
+TRAFFIC_LEVEL = "L2-to-fabric bytes per iteration (Infinity Cache hits included)"
 ALPHA = {"c1": 0.1, "c2": 0.5, "c3": 0.5}
 
 
@@ -46,12 +50,19 @@ def algorithmic_flops(J, np_):
 
 
 def kernel_source_hash():
-    """Hash of the sources (and tuned launch shapes) the iteration kernels are built from."""
+    """Hash of the sources and the tuned build defines the iteration kernels are
+    built from (of tuned.json only its "defines": the timings it records do not
+    change the build)."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         path = os.path.join(ROOT, "paper_2111_14240_amd", f)
-        if os.path.exists(path):
+        if not os.path.exists(path):
+            continue
+        if f == "tuned.json":
+            with open(path) as fh:
+                h.update(json.dumps(json.load(fh).get("defines", {}), sort_keys=True).encode())
+        else:
             with open(path, "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
@@ -455,6 +466,8 @@ def main():
     ap.add_argument("--np", type=int, default=0,
                     help="plain mode: probe side other than the config's (same object, raster and step)")
     ap.add_argument("--chunk", type=int, default=0, help="Np > 128: at most this many positions per staging chunk (0 = tuned default)")
+    ap.add_argument("--ppw", type=int, default=0,
+                    help="plain mode, Np <= 64: patches per workgroup of the whole-patch agent (0 = tuned default)")
     ap.add_argument("--n2", type=int, default=0,
                     help="plain mode: a rectangular object with this many columns (the raster widened "
                          "at the same step)")
@@ -465,8 +478,10 @@ def main():
     ap.add_argument("--systems", action=argparse.BooleanOptionalAction, default=True,
                     help="plain mode: also run the 64-item batch and a short served run against the plain "
                          "solver and add them to the line (--no-systems to skip)")
-    ap.add_argument("--serve-requests", type=int, default=300,
+    ap.add_argument("--serve-requests", type=int, default=600,
                     help="plain mode with --systems: requests in the short served run")
+    ap.add_argument("--serve-rate", type=float, default=26.0,
+                    help="plain mode with --systems: arrivals per second in the short served run")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="after the run, copy this many MiB three times (counter calibration)")
     ap.add_argument("--mode", default="plain", choices=["plain", "batch", "serve", "simulate"])
@@ -522,6 +537,7 @@ def main():
     sharp = args.method == "sharp"
     mkw = dict(method=pmace.PMACE_METHOD_SHARP_PLUS, beta=args.beta) if sharp else {}
     mkw["flags"] = {"default": 0, "staged": pmace.PMACE_STAGED_AGENT, "split": pmace.PMACE_SPLIT_AGENT}[args.agent]
+    mkw["ppw"] = args.ppw
     key = workload_key(args.config, args.method, args.np, args.agent) + (f"-n2{args.n2}" if args.n2 else "")
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
@@ -575,12 +591,13 @@ def main():
                    "method": "SHARP+ (Alg. 2)" if sharp else "PMACE (Alg. 1)",
                    **({"beta": args.beta} if sharp else {"alpha": alpha, "kappa": kappa, "rho": rho}),
                    "chunk": args.chunk,
+                   **({"ppw": args.ppw} if args.ppw else {}),
                    "agent": agent,
                    "iteration_graph": "HIP graphs of 32 iterations (single-iteration graph for the rest)"},
         "roofline": {"bound": "hbm", "kernel": iteration_kernels(np_, J, args.method, agent),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(key),
-                     "algorithmic_bytes_per_step": B},
+                     "traffic_level": TRAFFIC_LEVEL, "algorithmic_bytes_per_step": B},
         "alu": {"algorithmic_flops_per_step": Fl,
                 "achieved_tflops": Fl / (ms_per_step / 1e3) / 1e12,
                 "peak_tflops": FP32_VECTOR_PEAK_TFLOPS},
@@ -605,6 +622,7 @@ def main():
         out["batched_vs_plain"]["workload"] = b["config"]["workload"]
         sargs = argparse.Namespace(**vars(args))
         sargs.requests = args.serve_requests
+        sargs.rate = args.serve_rate
         sv = serve_comparison(sargs)
         keep = ("solves_per_s", "p50", "p99", "mean_latency", "completed", "max_active")
         out["served_vs_plain"] = {"workload": sv["config"]["workload"], "policy": sv["config"]["policy"],

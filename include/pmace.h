@@ -81,6 +81,12 @@ typedef struct {
                          256^2/Np^2 so that every side stages about as many bytes */
   int32_t method;     /* PMACE_METHOD_PMACE (alpha, kappa, rho used) or PMACE_METHOD_SHARP_PLUS */
   float beta;         /* SHARP+ relaxation, 0 <= beta <= 1 (Alg. 2); ignored by PMACE */
+  int32_t ppw;        /* patches per workgroup of the whole-patch agent (Np <= 128): a power
+                         of two up to 8 within 1024 threads per workgroup (np 32: up to 8,
+                         48: 4, 64: 2 with this build's line splits; 96 and 128: 1), or 0 =
+                         the build's tuned default.  Other sides: 0 or 1.  A batch's merged
+                         launch for one patch side takes its first such member's value.
+                         Anything else is EINVAL.  Results do not depend on it. */
 } pmace_params;
 
 typedef struct pmace_ctx pmace_ctx;      /* one reconstruction */

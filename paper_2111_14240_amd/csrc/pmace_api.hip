@@ -77,6 +77,7 @@ struct pmace_batch {
   Recon* recs;                 // device: member descriptors
   int2* items[kClasses];       // device: agent items per fused patch size (kSmallNp)
   int nitems[kClasses];
+  int ppw[kClasses];           // patches per workgroup of each class's merged agent launch
   int2* gitems[kClasses];      // device: gather items per class
   int ngitems[kClasses];
   int2* ritems;                // device: (member, block) NRMSE items
@@ -150,6 +151,8 @@ pmace_status check_params(const pmace_params* p) {
     return PMACE_EINVAL;
   if ((long long)p->n1 * p->n2 > (1LL << 30)) return PMACE_EINVAL;
   if (!np_supported(p->np)) return PMACE_EUNSUPPORTED;
+  if (p->ppw < 0 || (p->ppw > 0 && ((p->ppw & (p->ppw - 1)) != 0 || p->ppw > pmace::max_ppw(p->np))))
+    return PMACE_EINVAL;
   return PMACE_OK;
 }
 
@@ -552,6 +555,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   }
   h.chunk = chunk;
   h.n_red = nred;
+  h.ppw = p.ppw > 0 ? p.ppw : pmace::default_ppw(p.np);
   c->dev = reinterpret_cast<Recon*>(base + L.desc);
   c->items = reinterpret_cast<int2*>(base + L.items);
   c->gitems = reinterpret_cast<int2*>(base + L.gitems);
@@ -824,7 +828,7 @@ pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes,
   for (int k = 0; k < kClasses; ++k)
     if (b->nitems[k] > 0)
       PM_HIP(pmace::launch_small_batch(kSmallNp[k], b->recs, b->items[k], b->nitems[k], b->gitems[k],
-                                       b->ngitems[k], st));
+                                       b->ngitems[k], b->ppw[k], st));
   int lane = 0;
   for (int i = 0; i < b->n; ++i) {
     pmace_ctx* c = b->ctxs[i];
@@ -940,6 +944,7 @@ pmace_status pmace_batch_create(pmace_ctx* const* ctxs, int32_t n, const pmace_s
     for (int r = 0; r < c->h.n_red; ++r) ritems.push_back(make_int2(i, r));
     const int k = own_chain(c) ? -1 : class_of(c->prm.np);
     if (k < 0) continue;
+    if (items[k].empty()) b->ppw[k] = c->h.ppw;   // the class takes its first member's choice
     for (int j = 0; j < c->prm.num_pos; ++j) items[k].push_back(make_int2(i, j));
     for (int t = 0; t < c->ngitems; ++t) gitems[k].push_back(make_int2(i, t));
   }

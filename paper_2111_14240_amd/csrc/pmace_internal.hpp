@@ -30,6 +30,15 @@ namespace pmace {
 #ifndef PMACE_CHUNK256
 #define PMACE_CHUNK256 128  // Np > 128: default positions per chunk
 #endif
+#ifndef PMACE_PPW32
+#define PMACE_PPW32 1     // Np = 32: patches per workgroup of the whole-patch agent
+#endif
+#ifndef PMACE_PPW48
+#define PMACE_PPW48 1     // Np = 48
+#endif
+#ifndef PMACE_PPW64
+#define PMACE_PPW64 1     // Np = 64
+#endif
 
 // Gather tile of the consensus: GT_R x GT_C object pixels, GT_K threads each
 // (GT_R * GT_C * GT_K = 16 GT_C threads per workgroup).  A narrower tile lists
@@ -38,6 +47,14 @@ constexpr int GT_K = PMACE_GT_K, GT_C = PMACE_GT_C, GT_R = 16 / GT_K;
 static_assert(GT_K == 1 || GT_K == 2 || GT_K == 4, "gather split must be 1, 2 or 4");
 static_assert(GT_C == 32 || GT_C == 64, "gather tile width must be 32 or 64");
 constexpr int GT_THREADS = GT_R * GT_C * GT_K;
+static_assert(PMACE_PPW32 >= 1 && PMACE_PPW48 >= 1 && PMACE_PPW64 >= 1, "patches per workgroup");
+// Patches per workgroup of the whole-patch agent: the largest the side can
+// take (a power of two up to 8 within 1024 threads; 1 for Np = 96, 128; 0 for
+// a side without the whole-patch agent), and the build's default (the tuned
+// PMACE_PPW<np>, 1 where that exceeds the maximum).  Each patch of a
+// workgroup has its own LDS tile and Np * (threads per line) threads.
+int max_ppw(int np);
+int default_ppw(int np);
 // NRMSE reduction: RED_PX object pixels per block of RED_T threads.
 constexpr int RED_T = 256, RED_PX = 4096;
 // Base tile of the split-layout consensus: QT_R x QT_C pixels, one thread each.
@@ -105,6 +122,7 @@ struct Recon {
   int* qlist;           // positions whose quadrant-0 block meets each base tile, ascending
   int qrows, qcols;     // base tiles cover rows [0, qrows) and columns [0, qcols)
   int nqt;              // number of base tiles
+  int ppw;              // Np <= 128: patches per workgroup of the whole-patch agent
 };
 
 // Kernel launchers (stream-ordered; return the hipError_t of the launches).
@@ -115,10 +133,11 @@ hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float s
 // Np <= 128, one reconstruction: fused agent over its J positions, then the
 // fused gather + image update over its ntiles tiles.
 hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_t st);
-// Np <= 128, batched: agent over `items` (recon index, position) and the fused
-// gather + image update over `gitems` (recon index, tile).
+// Np <= 128, batched: agent over `items` (recon index, position), ppw of them
+// per workgroup, and the fused gather + image update over `gitems` (recon
+// index, tile).
 hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int nitems,
-                              const int2* gitems, int ngitems, hipStream_t st);
+                              const int2* gitems, int ngitems, int ppw, hipStream_t st);
 // Np > 128, one reconstruction, chunk by chunk; chunk_tiles[g] = (first tile,
 // tile count) of chunk g (host array); the descriptor h passed by value.
 // batch_rec non-null: run as a batch member (its kernels honour the stop

@@ -189,14 +189,23 @@ __device__ __forceinline__ void split_frame_row(const Recon& g, const int j, con
   for (int nb = NB0; nb < NB1; ++nb) asm volatile("" : "+v"(x[nb].x), "+v"(x[nb].y));
 }
 
-template <int NP, int METHOD, bool SPLIT = false>
-__device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, const int ab = 0) {
+// PPW patches per workgroup: sub-group threadIdx.x / NT works on patch j with
+// its own tile; the twiddle table is shared.  A sub-group with live == false
+// (past the last position, or a stopped batch member) runs every step and
+// barrier on a valid patch j but stores nothing.
+template <int NP, int METHOD, bool SPLIT = false, int PPW = 1>
+__device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, const int ab = 0,
+                                                 const bool live = true) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, S = NP + A, NT = NP * A, M = B / A;
   static_assert(exch_phases<NP>() == 1, "the whole-patch tile exchanges in one round");
   static_assert(!SPLIT || METHOD == kPMACE, "the split layout is PMACE's");
-  __shared__ float2 tile[NP * S];
+  static_assert(!SPLIT || PPW == 1, "one coset block per workgroup");
+  static_assert(PPW * NT <= 1024, "patches per workgroup: at most 1024 threads");
+  __shared__ float2 tile_all[PPW * NP * S];
   __shared__ float2 tw[NP];
-  const int tid = threadIdx.x;
+  const int sub = PPW > 1 ? (int)threadIdx.x / NT : 0;
+  const int tid = PPW > 1 ? (int)threadIdx.x - sub * NT : (int)threadIdx.x;
+  float2* tile = tile_all + sub * (NP * S);
   const int2 pj = g.pos[j];
   const size_t pb = SPLIT ? ((size_t)j * 4 + ab) * NP * NP : (size_t)j * NP * NP;
   const int r = tid / A, p = tid % A;
@@ -219,7 +228,7 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, co
     }
     // the twiddle table after the frame's loads, so the two are in flight
     // together (the row transforms wait for both anyway)
-    load_twiddles<NP>(tw, g.twn, tid, NT);
+    if (sub == 0) load_twiddles<NP>(tw, g.twn, tid, NT);
   }
   // amplitudes of the column phase, fetched now so their latency hides
   // behind the row transforms
@@ -264,6 +273,7 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, co
 #pragma unroll
     for (int ka = 0; ka < A; ++ka) x[m * A + ka] = row[p + A * m + B * ka];
   row_inv<NP>(x, row, p, tw);
+  if (!live) return;   // no barrier follows
 
   if constexpr (SPLIT) {
 #pragma unroll
@@ -278,20 +288,42 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, co
   }
 }
 
-// One reconstruction (descriptor passed by value): block b handles position b.
-template <int NP, int METHOD>
-__global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused(const Recon g) {
-  agent_fused_body<NP, METHOD>(g, blockIdx.x);
+// One reconstruction (descriptor passed by value): block b handles positions
+// b PPW ... b PPW + PPW - 1.
+template <int NP, int METHOD, int PPW>
+__global__ void __launch_bounds__(PPW * NP * Geo<NP>::A) agent_fused(const Recon g) {
+  constexpr int NT = NP * Geo<NP>::A;
+  if constexpr (PPW == 1) {
+    agent_fused_body<NP, METHOD>(g, blockIdx.x);
+  } else {
+    const int j = (int)blockIdx.x * PPW + (int)threadIdx.x / NT;
+    const bool live = j < g.J;
+    agent_fused_body<NP, METHOD, false, PPW>(g, live ? j : g.J - 1, 0, live);
+  }
 }
 
-// Batched: block b handles work item (reconstruction, position) b.
-template <int NP>
-__global__ void __launch_bounds__(NP * Geo<NP>::A) agent_fused_batch(const Recon* __restrict__ recs,
-                                                                     const int2* __restrict__ items) {
-  const int2 it = items[blockIdx.x];
-  const Recon& g = recs[it.x];
-  if (*g.done) return;
-  agent_fused_body<NP, kPMACE>(g, it.y);
+// Batched: block b handles work items (reconstruction, position) b PPW ...
+// b PPW + PPW - 1 of the nitems; a block all of whose items belong to stopped
+// members returns at once (the test is the same in every thread).
+template <int NP, int PPW>
+__global__ void __launch_bounds__(PPW * NP * Geo<NP>::A) agent_fused_batch(
+    const Recon* __restrict__ recs, const int2* __restrict__ items, int nitems) {
+  constexpr int NT = NP * Geo<NP>::A;
+  if constexpr (PPW == 1) {
+    const int2 it = items[blockIdx.x];
+    const Recon& g = recs[it.x];
+    if (*g.done) return;
+    agent_fused_body<NP, kPMACE>(g, it.y);
+  } else {
+    const int i0 = (int)blockIdx.x * PPW;
+    bool any = false;
+    for (int s = 0; s < PPW && i0 + s < nitems; ++s) any |= *recs[items[i0 + s].x].done == 0;
+    if (!any) return;
+    const int i = i0 + (int)threadIdx.x / NT;
+    const int2 it = items[i < nitems ? i : nitems - 1];
+    const Recon& g = recs[it.x];
+    agent_fused_body<NP, kPMACE, false, PPW>(g, it.y, 0, i < nitems && *g.done == 0);
+  }
 }
 
 // The window term of two coset blocks, (a, 0) and (a, 1), of position j at
@@ -1694,55 +1726,109 @@ __global__ void __launch_bounds__(M * Geo<M>::A) fit_split(const Recon g, int ch
 // -------------------------------------------------------------------------
 static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_t st) {
+// Patches per workgroup the whole-patch agent can take for side np: powers
+// of two up to 8 within 1024 threads, 1 above Np = 64 (0 for other sides).
+int max_ppw(int np) {
+  int a = 0;
   switch (np) {
-#define PMACE_SMALL(N)                                                                            \
-  case N:                                                                                         \
-    if (h.method == kSharpPlus) {                                                                  \
-      hipLaunchKernelGGL((agent_fused<N, kSharpPlus>), dim3(h.J), dim3(N * Geo<N>::A), 0, st, h);  \
-      if (ntiles > 0)                                                                              \
-        hipLaunchKernelGGL((consensus_gather<N, true, kSharpPlus>), dim3(ntiles), dim3(GT_THREADS), \
-                           0, st, h, 0, 0);                                                        \
-    } else {                                                                                       \
-      hipLaunchKernelGGL((agent_fused<N, kPMACE>), dim3(h.J), dim3(N * Geo<N>::A), 0, st, h);      \
-      if (ntiles > 0)                                                                              \
-        hipLaunchKernelGGL((consensus_gather<N, true, kPMACE>), dim3(ntiles), dim3(GT_THREADS), 0, \
-                           st, h, 0, 0);                                                           \
-    }                                                                                              \
-    break;
-    PMACE_SMALL(32)
-    PMACE_SMALL(48)
-    PMACE_SMALL(64)
-    PMACE_SMALL(96)
-    PMACE_SMALL(128)
-#undef PMACE_SMALL
-    default:
-      return hipErrorInvalidValue;
+    case 32: a = Geo<32>::A; break;
+    case 48: a = Geo<48>::A; break;
+    case 64: a = Geo<64>::A; break;
+    case 96: case 128: case 160: case 192: case 256: return 1;
+    default: return 0;
+  }
+  int k = 1;
+  while (k < 8 && 2 * k * np * a <= 1024) k *= 2;
+  return k;
+}
+
+int default_ppw(int np) {
+  const int k = np == 32 ? PMACE_PPW32 : np == 48 ? PMACE_PPW48 : np == 64 ? PMACE_PPW64 : 1;
+  return k <= max_ppw(np) ? k : 1;
+}
+
+template <int N, int PPW>
+static void small_agent(const Recon& h, hipStream_t st) {
+  if constexpr (PPW * N * Geo<N>::A <= 1024) {
+    const dim3 grid((h.J + PPW - 1) / PPW), block(PPW * N * Geo<N>::A);
+    if (h.method == kSharpPlus)
+      hipLaunchKernelGGL((agent_fused<N, kSharpPlus, PPW>), grid, block, 0, st, h);
+    else
+      hipLaunchKernelGGL((agent_fused<N, kPMACE, PPW>), grid, block, 0, st, h);
+  }
+}
+
+template <int N>
+static hipError_t small_iteration(const Recon& h, int ntiles, hipStream_t st) {
+  if constexpr (N <= 64) {
+    switch (h.ppw) {
+      case 1: small_agent<N, 1>(h, st); break;
+      case 2: small_agent<N, 2>(h, st); break;
+      case 4: small_agent<N, 4>(h, st); break;
+      case 8: small_agent<N, 8>(h, st); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    if (h.ppw != 1) return hipErrorInvalidValue;
+    small_agent<N, 1>(h, st);
+  }
+  if (ntiles > 0) {
+    if (h.method == kSharpPlus)
+      hipLaunchKernelGGL((consensus_gather<N, true, kSharpPlus>), dim3(ntiles), dim3(GT_THREADS), 0, st, h,
+                         0, 0);
+    else
+      hipLaunchKernelGGL((consensus_gather<N, true, kPMACE>), dim3(ntiles), dim3(GT_THREADS), 0, st, h, 0,
+                         0);
   }
   return hipGetLastError();
 }
 
-hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int nitems,
-                              const int2* gitems, int ngitems, hipStream_t st) {
-  if (nitems <= 0) return hipSuccess;
+hipError_t launch_small_iteration(int np, const Recon& h, int ntiles, hipStream_t st) {
   switch (np) {
-#define PMACE_SMALL(N)                                                                              \
-  case N:                                                                                           \
-    hipLaunchKernelGGL(agent_fused_batch<N>, dim3(nitems), dim3(N * Geo<N>::A), 0, st, recs, items); \
-    if (ngitems > 0)                                                                                \
-      hipLaunchKernelGGL((consensus_gather_batch<N, true>), dim3(ngitems), dim3(GT_THREADS), 0,    \
-                         st, recs, gitems, 0);                                                      \
-    break;
-    PMACE_SMALL(32)
-    PMACE_SMALL(48)
-    PMACE_SMALL(64)
-    PMACE_SMALL(96)
-    PMACE_SMALL(128)
-#undef PMACE_SMALL
-    default:
-      return hipErrorInvalidValue;
+    case 32: return small_iteration<32>(h, ntiles, st);
+    case 48: return small_iteration<48>(h, ntiles, st);
+    case 64: return small_iteration<64>(h, ntiles, st);
+    case 96: return small_iteration<96>(h, ntiles, st);
+    case 128: return small_iteration<128>(h, ntiles, st);
+    default: return hipErrorInvalidValue;
   }
+}
+
+template <int N, int PPW>
+static void small_batch_agent(const Recon* recs, const int2* items, int nitems, hipStream_t st) {
+  if constexpr (PPW * N * Geo<N>::A <= 1024)
+    hipLaunchKernelGGL((agent_fused_batch<N, PPW>), dim3((nitems + PPW - 1) / PPW),
+                       dim3(PPW * N * Geo<N>::A), 0, st, recs, items, nitems);
+}
+
+template <int N>
+static hipError_t small_batch(const Recon* recs, const int2* items, int nitems, const int2* gitems,
+                              int ngitems, int ppw, hipStream_t st) {
+  switch (N <= 64 ? ppw : 1) {
+    case 1: small_batch_agent<N, 1>(recs, items, nitems, st); break;
+    case 2: small_batch_agent<N, 2>(recs, items, nitems, st); break;
+    case 4: small_batch_agent<N, 4>(recs, items, nitems, st); break;
+    case 8: small_batch_agent<N, 8>(recs, items, nitems, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (ngitems > 0)
+    hipLaunchKernelGGL((consensus_gather_batch<N, true>), dim3(ngitems), dim3(GT_THREADS), 0, st, recs, gitems,
+                       0);
   return hipGetLastError();
+}
+
+hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int nitems,
+                              const int2* gitems, int ngitems, int ppw, hipStream_t st) {
+  if (nitems <= 0) return hipSuccess;
+  if (ppw < 1 || ppw > max_ppw(np)) return hipErrorInvalidValue;
+  switch (np) {
+    case 32: return small_batch<32>(recs, items, nitems, gitems, ngitems, ppw, st);
+    case 48: return small_batch<48>(recs, items, nitems, gitems, ngitems, ppw, st);
+    case 64: return small_batch<64>(recs, items, nitems, gitems, ngitems, ppw, st);
+    case 96: return small_batch<96>(recs, items, nitems, gitems, ngitems, ppw, st);
+    case 128: return small_batch<128>(recs, items, nitems, gitems, ngitems, ppw, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int NP>

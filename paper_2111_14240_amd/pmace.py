@@ -42,7 +42,7 @@ class pmace_params(ctypes.Structure):
         ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("np", ctypes.c_int32),
         ("num_pos", ctypes.c_int32), ("alpha", ctypes.c_float), ("kappa", ctypes.c_float),
         ("rho", ctypes.c_float), ("flags", ctypes.c_uint32), ("chunk", ctypes.c_int32),
-        ("method", ctypes.c_int32), ("beta", ctypes.c_float),
+        ("method", ctypes.c_int32), ("beta", ctypes.c_float), ("ppw", ctypes.c_int32),
     ]
 
 
@@ -147,9 +147,9 @@ def _check(status: int, where: str):
 
 
 def make_params(n1, n2, np_, num_pos, alpha, kappa=1.25, rho=0.5, flags=0, chunk=0,
-                method=PMACE_METHOD_PMACE, beta=0.0) -> pmace_params:
+                method=PMACE_METHOD_PMACE, beta=0.0, ppw=0) -> pmace_params:
     return pmace_params(int(n1), int(n2), int(np_), int(num_pos), float(alpha), float(kappa),
-                        float(rho), int(flags), int(chunk), int(method), float(beta))
+                        float(rho), int(flags), int(chunk), int(method), float(beta), int(ppw))
 
 
 # Thin wrappers with the C names -------------------------------------------
@@ -413,7 +413,7 @@ class Reconstruction:
 
     def __init__(self, n1, n2, probe, pos, z, alpha, kappa=1.25, rho=0.5, x0=None,
                  flags=0, chunk=0, device="cuda", stream=None, workspace=None,
-                 method=PMACE_METHOD_PMACE, beta=0.0):
+                 method=PMACE_METHOD_PMACE, beta=0.0, ppw=0):
         torch = _torch()
         self.device = torch.device(device)
         self.stream = stream
@@ -427,7 +427,7 @@ class Reconstruction:
         if z_t.shape != (J, np_, np_):
             raise ValueError(f"intensities must be ({J},{np_},{np_}), got {tuple(z_t.shape)}")
         x0_t = None if x0 is None else to_device_c64(x0, self.device)
-        self.params = make_params(n1, n2, np_, J, alpha, kappa, rho, flags, chunk, method, beta)
+        self.params = make_params(n1, n2, np_, J, alpha, kappa, rho, flags, chunk, method, beta, ppw)
         fp = pmace_footprint(self.params)
         if fp == 0:
             raise PMACEError(PMACE_EINVAL, "pmace_footprint")

@@ -12,6 +12,10 @@ csrc/pmace_internal.hpp) plus one run-time default:
     PMACE_CHUNK256       Np > 128: positions per chunk (stage buffer size)
     PMACE_GEO32_A        32-point line split over threads: 4 x 8 or 2 x 16 registers
     PMACE_GEO64_A        64-point line split: 8 x 8 or 4 x 16
+    PMACE_PPW32/48/64    (run-time choice, recorded as the build's default) patches per
+                         workgroup of the whole-patch agent for Np = 32, 48, 64
+    PMACE_SPLIT_SIDES    (run-time choice, recorded for the build) which of Np = 128, 192, 256
+                         default to the split (coset-block) agent: bit 0, 1, 2
 
 Search (coordinate-wise, every candidate measured on the device):
   1. gather shape (GT_K x unroll x tile width) with the default row/column blocks, scored by
@@ -19,7 +23,11 @@ Search (coordinate-wise, every candidate measured on the device):
   2. row/column blocks with the default gather, scored on the Np = 256 workload
      (the row block found applies to 256-point lines; 160 and 192 keep PMACE_RB);
   3. the line-FFT split (radix) of Np = 32 and 64, each on a workload of its size;
-  4. the chunk size, at run time, with the combined choice.
+  4. the chunk size, at run time, with the combined choice;
+  5. patches per workgroup of the whole-patch agent (Np = 32, 48, 64), at run
+     time, each on a workload of its size, with the built library;
+  6. the agent of each side that has two (Np = 128: whole patch or split;
+     192 and 256: three-pass or split), at run time, with the built library.
 Each candidate library is built into a scratch directory and timed in a
 process of its own.  The choice is written to tuned.json beside this file;
 build.py passes it to hipcc as -D flags.
@@ -28,6 +36,8 @@ build.py passes it to hipcc as -D flags.
     python -m paper_2111_14240_amd.tune time DIR       # time them (GPU), write DIR/times.json
     python -m paper_2111_14240_amd.tune pick DIR       # write tuned.json from the times
     python -m paper_2111_14240_amd.tune chunk          # time chunk sizes with the built library
+    python -m paper_2111_14240_amd.tune ppw            # time patches per workgroup (built library)
+    python -m paper_2111_14240_amd.tune agent          # time the two agents per side (built library)
 """
 from __future__ import annotations
 
@@ -42,15 +52,19 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned.json")
 DEFAULTS = {"PMACE_GT_K": 1, "PMACE_GATHER_UNROLL": 8, "PMACE_GT_C": 64, "PMACE_RB": 32, "PMACE_RB256": 16,
-            "PMACE_CB": 16, "PMACE_GEO32_A": 4, "PMACE_GEO64_A": 8}
+            "PMACE_CB": 16, "PMACE_GEO32_A": 4, "PMACE_GEO64_A": 8,
+            "PMACE_PPW32": 1, "PMACE_PPW48": 1, "PMACE_PPW64": 1}
 GATHER_SPACE = [(k, u, c) for k in (1, 2, 4) for u in (8, 16) for c in (64, 32)]
 BLOCK_SPACE = [(rb, cb) for rb in (8, 16, 32) for cb in (16, 32)]
 GEO_SPACE = [(32, 2), (64, 4)]          # the non-default splits
+PPW_SPACE = {32: (1, 2, 4, 8), 48: (1, 2, 4), 64: (1, 2)}   # patches per workgroup per side
+AGENT_SIDES = {128: "np128", 192: "np192", 256: "np256"}
 CHUNKS = (64, 128, 192, 256, 400)
 
 # Tuning workloads: (object side, probe side, scan side, step, peak photons).
 WORKLOADS = {"np128": (512, 128, 15, 24, 1e5), "np256": (1024, 256, 40, 20, 1e6),
-             "np32": (256, 32, 14, 16, 1e5), "np64": (512, 64, 20, 22, 1e5)}
+             "np32": (256, 32, 14, 16, 1e5), "np64": (512, 64, 20, 22, 1e5),
+             "np48": (384, 48, 20, 16, 1e5), "np192": (1024, 192, 40, 20, 1e6)}
 
 
 def candidates():
@@ -79,6 +93,8 @@ def cmd_build(args):
     from . import build as B
     os.makedirs(args.dir, exist_ok=True)
     cands = candidates()
+    if args.family:
+        cands = {n: d for n, d in cands.items() if n.startswith(args.family) or n == "g1u8"}
     with open(os.path.join(args.dir, "candidates.json"), "w") as f:
         json.dump(cands, f, indent=1)
 
@@ -93,7 +109,7 @@ def cmd_build(args):
             print("built", name, flush=True)
 
 
-def _time_library(lib, workloads, iters, chunks=(0,)):
+def _time_library(lib, workloads, iters, chunks=(0,), flags=0, ppw=0):
     """Run in a fresh process: load `lib`, time `iters` iterations (one graph
     replay each) per workload, return ms per iteration."""
     import torch
@@ -107,7 +123,7 @@ def _time_library(lib, workloads, iters, chunks=(0,)):
             stream = torch.cuda.Stream()
             with torch.cuda.stream(stream):
                 R = pmace.Reconstruction(n, n, prob.probe, prob.pos, prob.z, 0.5, chunk=ch,
-                                         stream=stream)
+                                         stream=stream, flags=flags, ppw=ppw)
                 R.iterate(3)
                 R.sync()
                 best = float("inf")
@@ -130,11 +146,12 @@ def cmd_time(args):
     for name in sorted(cands):
         lib = os.path.join(args.dir, f"libpmace_{name}.so")
         if name == "g1u8":       # the default build is also timed on the small sizes
-            wl_extra = ["np32", "np64"]
+            wl_extra = ["np32", "np48", "np64"]
         else:
             wl_extra = []
         if name.startswith("geo"):
             wl = ["np32", "np64"]
+
         elif name.startswith("g"):
             wl = ["np128", "np256"]
         else:
@@ -186,10 +203,10 @@ def _pick(cands, times):
 def cmd_pick(args):
     cands = json.load(open(os.path.join(args.dir, "candidates.json")))
     times = json.load(open(os.path.join(args.dir, "times.json")))
-    d, score, b = _pick(cands, times)
     rec = {}
     if os.path.exists(TUNED):
         rec = json.load(open(TUNED))
+    d, score, b = _pick(cands, times)
     rec["defines"] = dict(rec.get("defines", {}), **d)
     rec["gather_scores"] = score
     rec["block_ms_np256"] = b
@@ -213,12 +230,77 @@ def cmd_chunk(args):
     print(json.dumps({"best_chunk": best, **res}))
 
 
+def _pick_ppw(res):
+    """Per side, the patches per workgroup with the least time (ties keep the
+    smaller value)."""
+    out = {}
+    for n, ks in sorted(PPW_SPACE.items()):
+        t = {k: res[f"np{n}_ppw{k}"] for k in ks if f"np{n}_ppw{k}" in res}
+        if t:
+            out[f"PMACE_PPW{n}"] = min(sorted(t), key=t.get)
+    return out
+
+
+def cmd_ppw(args):
+    """Time each patches-per-workgroup choice of the whole-patch agent on a
+    workload of each side (alternating, best of `rounds`) with the built
+    library, and record the fastest as the build's default for that side."""
+    from . import build as B
+    res = {}
+    for n, ks in sorted(PPW_SPACE.items()):
+        wl = f"np{n}"
+        for _ in range(args.rounds):
+            for k in ks:
+                t = _time_library(B.LIB, [wl], args.iters, ppw=k)[wl]
+                res[f"{wl}_ppw{k}"] = min(res.get(f"{wl}_ppw{k}", float("inf")), t)
+    d = _pick_ppw(res)
+    rec = json.load(open(TUNED)) if os.path.exists(TUNED) else {"defines": dict(DEFAULTS)}
+    rec["ppw_ms"] = res
+    if args.write:
+        rec["defines"].update(d)
+        with open(TUNED, "w") as f:
+            json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps({**d, **res}))
+
+
+def _split_sides(res):
+    """PMACE_SPLIT_SIDES from the agent times: bit i set where side i (128, 192,
+    256) ran faster with the split agent than with its other agent."""
+    bits = 0
+    for i, (np_, wl) in enumerate(sorted(AGENT_SIDES.items())):
+        if res[f"{wl}_split"] < res[f"{wl}_other"]:
+            bits |= 1 << i
+    return bits
+
+
+def cmd_agent(args):
+    """Per side with two agents, time each (alternating, best of `rounds`) with
+    the built library and record the faster as that side's default."""
+    from . import build as B
+    from . import pmace
+    res = {}
+    for np_, wl in sorted(AGENT_SIDES.items()):
+        for _ in range(args.rounds):
+            for name, fl in (("other", pmace.PMACE_STAGED_AGENT), ("split", pmace.PMACE_SPLIT_AGENT)):
+                t = _time_library(B.LIB, [wl], args.iters, flags=fl)[wl]
+                res[f"{wl}_{name}"] = min(res.get(f"{wl}_{name}", float("inf")), t)
+    bits = _split_sides(res)
+    rec = json.load(open(TUNED)) if os.path.exists(TUNED) else {"defines": dict(DEFAULTS)}
+    rec["agent_ms"] = res
+    if args.write:
+        rec["defines"]["PMACE_SPLIT_SIDES"] = bits
+        with open(TUNED, "w") as f:
+            json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps({"PMACE_SPLIT_SIDES": bits, **res}))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     sub = ap.add_subparsers(dest="cmd", required=True)
     p = sub.add_parser("build")
     p.add_argument("dir")
     p.add_argument("--jobs", type=int, default=4)
+    p.add_argument("--family", default="", help="only candidates whose name starts with this (and g1u8)")
     p.set_defaults(fn=cmd_build)
     p = sub.add_parser("time")
     p.add_argument("dir")
@@ -236,6 +318,16 @@ def main(argv=None):
     p.add_argument("--iters", type=int, default=20)
     p.add_argument("--write", action="store_true")
     p.set_defaults(fn=cmd_chunk)
+    p = sub.add_parser("ppw")
+    p.add_argument("--iters", type=int, default=50)
+    p.add_argument("--rounds", type=int, default=3)
+    p.add_argument("--write", action="store_true")
+    p.set_defaults(fn=cmd_ppw)
+    p = sub.add_parser("agent")
+    p.add_argument("--iters", type=int, default=20)
+    p.add_argument("--rounds", type=int, default=2)
+    p.add_argument("--write", action="store_true")
+    p.set_defaults(fn=cmd_agent)
     args = ap.parse_args(argv)
     args.fn(args)
 

@@ -151,3 +151,18 @@ def test_simulate_static_checks_before_device(lib):
                                    None) == P.PMACE_EUNSUPPORTED
     assert L.pmace_simulate_static(128, 128, 32, 4, one, one, one, float("nan"), 1, one, None,
                                    None) == P.PMACE_EINVAL
+
+
+def test_patches_per_workgroup_range(lib):
+    """pmace_params.ppw: 0 (the build's default) or a power of two within the
+    side's maximum (1024 threads per workgroup); anything else is EINVAL, so the
+    footprint query returns 0."""
+    fp = lambda np_, ppw, n=256: P.pmace_footprint(P.make_params(n, n, np_, 9, 0.5, ppw=ppw))
+    for np_, top in ((32, 8), (48, 4), (64, 2), (96, 1), (128, 1), (256, 1)):
+        assert fp(np_, 0) > 0
+        k = 1
+        while k <= top:
+            assert fp(np_, k) == fp(np_, 0), (np_, k)
+            k *= 2
+        assert fp(np_, 2 * top) == 0, (np_, 2 * top)
+    assert fp(32, 3) == 0 and fp(32, -1) == 0 and fp(48, 6) == 0

@@ -103,10 +103,19 @@ def make_recon(P, prob, alpha, kappa=1.25, rho=0.5, chunk=0, flags=0):
 # precision evaluation.  It is held to 1.5x the error of a plain complex64
 # evaluation of the same pass (single_precision_step_error), and reported.
 # The coset-block (split) agent's first flat-start pass lands further from the
-# FP64 oracle (its butterfly of four probe-weighted pixels adds rounding at
-# the noise floor that sets those phases): measured 7.9e-5 (Np 192), 2.1e-4
-# and 3.0e-4 (Np 256), 7.2e-4 (Np 128); it is held to max(1e-3, 2x the
-# complex64 evaluation) and reported, not counted towards the 1e-4 bar.
+# FP64 oracle, for one identified reason: the probe stand-in is symmetric
+# about its half-pixel centre, so the flat-start patch spectrum F(d 1) is
+# exactly zero on its Nyquist row and column (255 bins at Np 128, 511 at 256),
+# and the oracle's FP64 transform returns those zeros exactly, as the
+# row-column transforms of the other agents do in FP32.  The split agent's
+# coset transforms leave FP32 rounding noise there instead, so the eq. (9)
+# rule "0 where W = 0" does not fire, and a bin holding a photon gets
+# |U| = y/(1+alpha) instead of 0 (Np 128: 3 of 16 positions, an error of 0.67
+# in one bin of unit amplitude).  Measured whole-state errors: 7.9e-5 (Np 192),
+# 2.1e-4 and 3.0e-4 (Np 256), 7.2e-4 (Np 128).  The whole state is held to
+# max(1e-3, 2x the complex64 evaluation) and reported, not counted towards
+# the 1e-4 bar; the agent's state spectrum on every other bin is held to the
+# whole-patch agents' bound (agent_error_off_exact_zeros).
 FLAT_FACTOR = 1.5
 FLAT_FACTOR_SPLIT, FLAT_FLOOR_SPLIT = 2.0, 1e-3
 
@@ -116,6 +125,23 @@ def flat_start_bound(prob, v0, alpha, kappa, rho, split=False):
     if split:
         return max(FLAT_FLOOR_SPLIT, FLAT_FACTOR_SPLIT * e)
     return max(TOL, FLAT_FACTOR * e)
+
+
+def agent_error_off_exact_zeros(prob, v0, alpha, kappa, rho, v_dev, xh0, xh1):
+    """Relative error of the device agent's new state spectrum F(d t) against
+    the oracle's, over the bins where the FP64 spectrum F(d v0) of the start
+    is not exactly zero.  t is recovered from the device's outputs:
+    xbar = (xhat1 - (1 - rho) xhat0) / rho, t = v - 2 rho P_j xbar."""
+    d, z = as_f32_inputs(prob)
+    y = O.amplitudes(z)
+    shape = (prob.n1, prob.n2)
+    _, w, _ = O.pmace_step(v0, d, y, prob.pos, shape, alpha, kappa, rho)
+    t_or = v0 - 2 * rho * w
+    xb = (np.asarray(xh1, np.complex128) - (1 - rho) * np.asarray(xh0, np.complex128)) / rho
+    t = np.asarray(v_dev, np.complex128) - 2 * rho * O.extract(xb, prob.pos, prob.np_)
+    keep = O.dft2(d * v0) != 0
+    diff = (O.dft2(d * t) - O.dft2(d * t_or))[keep]
+    return float(np.linalg.norm(diff) / np.linalg.norm(O.dft2(d * t_or)[keep])), int((~keep).sum())
 
 
 def teacher_forced(P, R, vs, xs, ks, tol0=None, say=""):
@@ -238,12 +264,21 @@ def test_flat_start(P, case):
     alpha = 0.5
     vs, xs = oracle_trajectory(prob, alpha, 1.25, 0.5, 3)
     R = make_recon(P, prob, alpha, chunk=chunk, flags=flags)
-    tol0 = flat_start_bound(prob, vs[0], alpha, 1.25, 0.5, split=R.agent == "split")
+    split = R.agent == "split"
+    tol0 = flat_start_bound(prob, vs[0], alpha, 1.25, 0.5, split=split)
     _say("flat start", case, R.agent, f"tol0={tol0:.2e}")
+    xh0 = R.reconstruct().cpu().numpy()
     R.iterate(1)
-    e0 = rel(R.get_state().cpu().numpy(), vs[1])
+    v1 = R.get_state().cpu().numpy()
+    e0 = rel(v1, vs[1])
     _say(f"  k=0 rel(v)={e0:.2e}")
     assert e0 < tol0
+    if split:
+        ea, nz = agent_error_off_exact_zeros(prob, vs[0], alpha, 1.25, 0.5, v1, xh0,
+                                             R.reconstruct().cpu().numpy())
+        tol_a = flat_start_bound(prob, vs[0], alpha, 1.25, 0.5)
+        _say(f"  k=0 agent state spectrum off the {nz} exact zeros: {ea:.2e} (bound {tol_a:.2e})")
+        assert ea < tol_a
     for k in (1, 2):
         R.set_state(vs[k])
         R.iterate(1)

@@ -5,7 +5,7 @@ from paper_2111_14240_amd import tune
 
 
 def _times(cands, **override):
-    t = {n: {"np128": 1.0, "np256": 1.0, "np32": 1.0, "np64": 1.0} for n in cands}
+    t = {n: {"np128": 1.0, "np256": 1.0, "np32": 1.0, "np48": 1.0, "np64": 1.0} for n in cands}
     for name, (wl, v) in override.items():
         t[name][wl] = v
     return t
@@ -32,3 +32,30 @@ def test_gather_and_split_choices():
     d, score, _ = tune._pick(cands, t)
     assert (d["PMACE_GT_K"], d["PMACE_GATHER_UNROLL"], d["PMACE_GT_C"]) == (2, 8, 32)
     assert d["PMACE_GEO32_A"] == 2 and d["PMACE_GEO64_A"] == tune.DEFAULTS["PMACE_GEO64_A"]
+
+
+def test_patches_per_workgroup_per_side():
+    res = {"np32_ppw1": 1.0, "np32_ppw2": 0.95, "np32_ppw4": 0.9, "np32_ppw8": 0.9,
+           "np48_ppw1": 1.0, "np48_ppw2": 1.0, "np48_ppw4": 1.1, "np64_ppw1": 0.8, "np64_ppw2": 0.9}
+    # ties keep the smaller value
+    assert tune._pick_ppw(res) == {"PMACE_PPW32": 4, "PMACE_PPW48": 1, "PMACE_PPW64": 1}
+
+
+def test_ppw_choices_fit_a_workgroup():
+    # every value timed keeps ppw x Np x (threads per line) <= 1024 with the tuned line splits
+    d = dict(tune.DEFAULTS)
+    import json, os
+    if os.path.exists(tune.TUNED):
+        d.update(json.load(open(tune.TUNED))["defines"])
+    for n, ks in tune.PPW_SPACE.items():
+        a = {32: d["PMACE_GEO32_A"], 48: 4, 64: d["PMACE_GEO64_A"]}[n]
+        assert max(ks) * n * a <= 1024, n
+
+
+def test_split_sides_bitmask():
+    res = {"np128_other": 1.0, "np128_split": 1.2, "np192_other": 1.0, "np192_split": 0.9,
+           "np256_other": 1.0, "np256_split": 1.1}
+    assert tune._split_sides(res) == 2
+    res["np128_split"] = 0.5
+    res["np256_split"] = 0.5
+    assert tune._split_sides(res) == 7
