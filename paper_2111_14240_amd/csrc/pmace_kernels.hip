@@ -1804,12 +1804,17 @@ static void small_batch_agent(const Recon* recs, const int2* items, int nitems, 
 template <int N>
 static hipError_t small_batch(const Recon* recs, const int2* items, int nitems, const int2* gitems,
                               int ngitems, int ppw, hipStream_t st) {
-  switch (N <= 64 ? ppw : 1) {
-    case 1: small_batch_agent<N, 1>(recs, items, nitems, st); break;
-    case 2: small_batch_agent<N, 2>(recs, items, nitems, st); break;
-    case 4: small_batch_agent<N, 4>(recs, items, nitems, st); break;
-    case 8: small_batch_agent<N, 8>(recs, items, nitems, st); break;
-    default: return hipErrorInvalidValue;
+  if constexpr (N <= 64) {
+    switch (ppw) {
+      case 1: small_batch_agent<N, 1>(recs, items, nitems, st); break;
+      case 2: small_batch_agent<N, 2>(recs, items, nitems, st); break;
+      case 4: small_batch_agent<N, 4>(recs, items, nitems, st); break;
+      case 8: small_batch_agent<N, 8>(recs, items, nitems, st); break;
+      default: return hipErrorInvalidValue;
+    }
+  } else {
+    if (ppw != 1) return hipErrorInvalidValue;
+    small_batch_agent<N, 1>(recs, items, nitems, st);
   }
   if (ngitems > 0)
     hipLaunchKernelGGL((consensus_gather_batch<N, true>), dim3(ngitems), dim3(GT_THREADS), 0, st, recs, gitems,
