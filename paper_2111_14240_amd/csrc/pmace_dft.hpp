@@ -408,93 +408,4 @@ template <int N> __device__ __forceinline__ void col_inv(float2 (&x)[Geo<N>::B],
   dft<B, true>(x);
 }
 
-// ---------------------------------------------------------------------------
-// Column-direction line FFTs with two lines per thread and the exchange in H
-// rounds: thread (c, q) owns slots q and q + A/2 of column c (xa, xb), so
-// A/2 threads per column do the work of A, and each round moves B/H of a
-// slot's values (the tile needs (B/H) * A rows of stride S).  Used where half
-// the threads and half the LDS of the one-slot transforms let two workgroups
-// share a CU.
-// ---------------------------------------------------------------------------
-template <int N, int H>
-__device__ __forceinline__ void col_fwd2(float2 (&xa)[Geo<N>::B], float2 (&xb)[Geo<N>::B], float2* tile,
-                                         int S, int c, int q, const float2* tw) {
-  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A, BH = B / H, MH = M / H;
-  static_assert(M % H == 0 && A % 2 == 0, "rounds must split the groups evenly");
-  const int qb = q + A / 2;
-  dft<B, false>(xa);
-  dft<B, false>(xb);
-#pragma unroll
-  for (int kb = 1; kb < B; ++kb) {
-    xa[kb] = cmul(xa[kb], tw[q * kb]);
-    xb[kb] = cmul(xb[kb], tw[qb * kb]);
-  }
-#pragma unroll
-  for (int h = 0; h < H; ++h) {
-    __syncthreads();
-#pragma unroll
-    for (int kb = 0; kb < BH; ++kb) {
-      tile[(kb * A + q) * S + c] = xa[h * BH + kb];
-      tile[(kb * A + qb) * S + c] = xb[h * BH + kb];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int m = h * MH; m < (h + 1) * MH; ++m) {
-      const int ka0 = q + A * m - h * BH, kb0 = qb + A * m - h * BH;
-      float2 ga[A], gb[A];
-#pragma unroll
-      for (int na = 0; na < A; ++na) {
-        ga[na] = tile[(ka0 * A + na) * S + c];
-        gb[na] = tile[(kb0 * A + na) * S + c];
-      }
-      dft<A, false>(ga);
-      dft<A, false>(gb);
-#pragma unroll
-      for (int ka = 0; ka < A; ++ka) {
-        xa[m * A + ka] = ga[ka];
-        xb[m * A + ka] = gb[ka];
-      }
-    }
-  }
-}
-
-template <int N, int H>
-__device__ __forceinline__ void col_inv2(float2 (&xa)[Geo<N>::B], float2 (&xb)[Geo<N>::B], float2* tile,
-                                         int S, int c, int q, const float2* tw) {
-  constexpr int A = Geo<N>::A, B = Geo<N>::B, M = B / A, BH = B / H, MH = M / H;
-  const int qb = q + A / 2;
-#pragma unroll
-  for (int m = 0; m < M; ++m) {
-    const int ka0 = q + A * m, kb0 = qb + A * m;
-    dft<A, true>(&xa[m * A]);
-    dft<A, true>(&xb[m * A]);
-#pragma unroll
-    for (int na = 1; na < A; ++na) {
-      xa[m * A + na] = cmulc(xa[m * A + na], tw[na * ka0]);
-      xb[m * A + na] = cmulc(xb[m * A + na], tw[na * kb0]);
-    }
-  }
-#pragma unroll
-  for (int h = 0; h < H; ++h) {
-    __syncthreads();
-#pragma unroll
-    for (int m = h * MH; m < (h + 1) * MH; ++m) {
-      const int ka0 = q + A * m - h * BH, kb0 = qb + A * m - h * BH;
-#pragma unroll
-      for (int na = 0; na < A; ++na) {
-        tile[(ka0 * A + na) * S + c] = xa[m * A + na];
-        tile[(kb0 * A + na) * S + c] = xb[m * A + na];
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kb = 0; kb < BH; ++kb) {
-      xa[h * BH + kb] = tile[(kb * A + q) * S + c];
-      xb[h * BH + kb] = tile[(kb * A + qb) * S + c];
-    }
-  }
-  dft<B, true>(xa);
-  dft<B, true>(xb);
-}
-
 }  // namespace pmace

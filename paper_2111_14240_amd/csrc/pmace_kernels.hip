@@ -125,17 +125,6 @@ __device__ __forceinline__ void agent_output(float2 z, float2* tp, const float2*
 // Np <= 128: the whole patch lives in LDS; one workgroup per work item
 // (reconstruction, position) does a2-a7 in one pass (rows, columns, state
 // spectrum, columns, rows, new state).
-//
-// SPLIT: the same pass on one coset block of a split-layout state (Np = 2 NP,
-// see Recon::split).  The top radix-2 step of the Np-point transform, taken
-// outside, turns the patch into four independent NP x NP problems: the block
-// Z_ab of the frame d v = s + 2 rho d P_j xbar is the stored block of s plus
-// the split step of the window term (split_frame_row),
-// its NP x NP DFT is the patch spectrum at the frequencies (2 k1 + a, 2 k2 + b),
-// the state spectrum is formed there with the amplitudes stored in the same
-// order, and 4 x its unnormalised inverse is the block Z_ab of the new state
-// (the inverse of the split step gives 4 s' per block).  The NP-point
-// transforms use W_NP^m = W_Np^{2m}.
 // -------------------------------------------------------------------------
 __device__ __forceinline__ float2 cfma(float2 a, float2 b, float2 acc) {
   return make_float2(fmaf(a.x, b.x, fmaf(-a.y, b.y, acc.x)), fmaf(a.x, b.y, fmaf(a.y, b.x, acc.y)));
@@ -145,61 +134,14 @@ __device__ __forceinline__ float2 cfms(float2 a, float2 b, float2 acc) {
   return make_float2(fmaf(-a.x, b.x, fmaf(a.y, b.y, acc.x)), fmaf(-a.x, b.y, fmaf(-a.y, b.x, acc.y)));
 }
 
-// Split-agent frame, elements [NB0, NB1) of row rr of block ab of position j
-// (columns c = p + A nb):
-//   Z_ab[rr][c] + W_Np^{a rr + b c} sum_q (-1)^{a q1 + b q2} (2 rho d)[(rr, c) + M q] xbar[p_j + (rr, c) + M q].
-// The quadrant loop is kept rolled, so one quadrant's loads are in flight at a
-// time (they are L2 hits: the probe table and the consensus image); the state
-// block, read from HBM, is loaded last.  twnp: W_Np^m, m < Np, in LDS.
-template <int M, int NB0, int NB1>
-__device__ __forceinline__ void split_frame_row(const Recon& g, const int j, const int ab, const int rr,
-                                                const int p, const float2* twnp, float2 (&x)[Geo<M>::B]) {
-  constexpr int A = Geo<M>::A, NP = 2 * M;
-  const int a = ab >> 1, b = ab & 1;
-  const int2 pj = g.pos[j];
-#pragma unroll
-  for (int nb = NB0; nb < NB1; ++nb) x[nb] = make_float2(0.f, 0.f);
-#pragma unroll 1
-  for (int q = 0; q < 4; ++q) {
-    const int q1 = q >> 1, q2 = q & 1;
-    const float2* dq = g.dr + (size_t)(rr + M * q1) * NP + M * q2;
-    const float2* xq = g.xbar + (size_t)(pj.x + rr + M * q1) * g.n2 + pj.y + M * q2;
-    if ((a * q1 + b * q2) & 1) {   // uniform across the workgroup
-#pragma unroll
-      for (int nb = NB0; nb < NB1; ++nb) x[nb] = cfms(dq[p + A * nb], xq[p + A * nb], x[nb]);
-    } else {
-#pragma unroll
-      for (int nb = NB0; nb < NB1; ++nb) x[nb] = cfma(dq[p + A * nb], xq[p + A * nb], x[nb]);
-    }
-  }
-  // an empty asm "writes" the row index, so the state and twiddle loads
-  // below cannot be hoisted above the quadrant loop (their registers would
-  // be held across it)
-  int ri = rr;
-  asm volatile("" : "+v"(ri));
-  const float2* z = g.t + ((size_t)j * 4 + ab) * M * M + (size_t)ri * M;
-#pragma unroll
-  for (int nb = NB0; nb < NB1; ++nb) {
-    const int c = p + A * nb;
-    x[nb] = cfma(twnp[a * ri + b * c], x[nb], z[c]);
-  }
-  // and the frame is formed here, not sunk to its first use (the loads it
-  // consumes would otherwise stay live across the next call's loop)
-#pragma unroll
-  for (int nb = NB0; nb < NB1; ++nb) asm volatile("" : "+v"(x[nb].x), "+v"(x[nb].y));
-}
-
 // PPW patches per workgroup: sub-group threadIdx.x / NT works on patch j with
 // its own tile; the twiddle table is shared.  A sub-group with live == false
 // (past the last position, or a stopped batch member) runs every step and
 // barrier on a valid patch j but stores nothing.
-template <int NP, int METHOD, bool SPLIT = false, int PPW = 1>
-__device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, const int ab = 0,
-                                                 const bool live = true) {
+template <int NP, int METHOD, int PPW = 1>
+__device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, const bool live = true) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, S = NP + A, NT = NP * A, M = B / A;
   static_assert(exch_phases<NP>() == 1, "the whole-patch tile exchanges in one round");
-  static_assert(!SPLIT || METHOD == kPMACE, "the split layout is PMACE's");
-  static_assert(!SPLIT || PPW == 1, "one coset block per workgroup");
   static_assert(PPW * NT <= 1024, "patches per workgroup: at most 1024 threads");
   __shared__ float2 tile_all[PPW * NP * S];
   __shared__ float2 tw[NP];
@@ -207,29 +149,21 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, co
   const int tid = PPW > 1 ? (int)threadIdx.x - sub * NT : (int)threadIdx.x;
   float2* tile = tile_all + sub * (NP * S);
   const int2 pj = g.pos[j];
-  const size_t pb = SPLIT ? ((size_t)j * 4 + ab) * NP * NP : (size_t)j * NP * NP;
+  const size_t pb = (size_t)j * NP * NP;
   const int r = tid / A, p = tid % A;
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   float2* trow = g.t + pb + (size_t)r * NP;
   const float two_rho = g.two_rho;
 
   float2 x[B];
-  if constexpr (SPLIT) {
-    __shared__ float2 twnp[2 * NP];
-    for (int m = tid; m < 2 * NP; m += NT) twnp[m] = g.twn[m];
-    __syncthreads();
-    for (int m = tid; m < NP; m += NT) tw[m] = twnp[2 * m];
-    split_frame_row<NP, 0, B>(g, j, ab, r, p, twnp, x);
-  } else {
 #pragma unroll
-    for (int nb = 0; nb < B; ++nb) {
-      const int c = p + A * nb;
-      x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], two_rho);
-    }
-    // the twiddle table after the frame's loads, so the two are in flight
-    // together (the row transforms wait for both anyway)
-    if (sub == 0) load_twiddles<NP>(tw, g.twn, tid, NT);
+  for (int nb = 0; nb < B; ++nb) {
+    const int c = p + A * nb;
+    x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], two_rho);
   }
+  // the twiddle table after the frame's loads, so the two are in flight
+  // together (the row transforms wait for both anyway)
+  if (sub == 0) load_twiddles<NP>(tw, g.twn, tid, NT);
   // amplitudes of the column phase, fetched now so their latency hides
   // behind the row transforms
   const int c = tid % NP, q = tid / NP;
@@ -252,16 +186,10 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, co
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) x[nb] = tile[(q + A * nb) * S + c];
   col_fwd<NP>(x, tile, S, c, q, tw);
-  if constexpr (SPLIT) {
-    const float sb = 4.f * g.sb, s2r = 4.f * g.s2r;   // exact: powers of two
 #pragma unroll
-    for (int k = 0; k < B; ++k) x[k] = state_spectrum(x[k], yv[k], sb, s2r);
-  } else {
+  for (int m = 0; m < M; ++m)
 #pragma unroll
-    for (int m = 0; m < M; ++m)
-#pragma unroll
-      for (int ka = 0; ka < A; ++ka) x[m * A + ka] = spectrum_step<METHOD>(x[m * A + ka], yv[m * A + ka], g);
-  }
+    for (int ka = 0; ka < A; ++ka) x[m * A + ka] = spectrum_step<METHOD>(x[m * A + ka], yv[m * A + ka], g);
   col_inv<NP>(x, tile, S, c, q, tw);
   __syncthreads();
 #pragma unroll
@@ -275,16 +203,11 @@ __device__ __forceinline__ void agent_fused_body(const Recon& g, const int j, co
   row_inv<NP>(x, row, p, tw);
   if (!live) return;   // no barrier follows
 
-  if constexpr (SPLIT) {
+  float2* urow = g.stage + pb + (size_t)r * NP;  // SHARP+ only
 #pragma unroll
-    for (int nb = 0; nb < B; ++nb) trow[p + A * nb] = x[nb];
-  } else {
-    float2* urow = g.stage + pb + (size_t)r * NP;  // SHARP+ only
-#pragma unroll
-    for (int nb = 0; nb < B; ++nb) {
-      const int cc = p + A * nb;
-      agent_output<METHOD>(x[nb], &trow[cc], &xrow[cc], r * NP + cc, g, &urow[cc]);
-    }
+  for (int nb = 0; nb < B; ++nb) {
+    const int cc = p + A * nb;
+    agent_output<METHOD>(x[nb], &trow[cc], &xrow[cc], r * NP + cc, g, &urow[cc]);
   }
 }
 
@@ -298,7 +221,7 @@ __global__ void __launch_bounds__(PPW * NP * Geo<NP>::A) agent_fused(const Recon
   } else {
     const int j = (int)blockIdx.x * PPW + (int)threadIdx.x / NT;
     const bool live = j < g.J;
-    agent_fused_body<NP, METHOD, false, PPW>(g, live ? j : g.J - 1, 0, live);
+    agent_fused_body<NP, METHOD, PPW>(g, live ? j : g.J - 1, live);
   }
 }
 
@@ -322,15 +245,19 @@ __global__ void __launch_bounds__(PPW * NP * Geo<NP>::A) agent_fused_batch(
     const int i = i0 + (int)threadIdx.x / NT;
     const int2 it = items[i < nitems ? i : nitems - 1];
     const Recon& g = recs[it.x];
-    agent_fused_body<NP, kPMACE, false, PPW>(g, it.y, 0, i < nitems && *g.done == 0);
+    agent_fused_body<NP, kPMACE, PPW>(g, it.y, i < nitems && *g.done == 0);
   }
 }
 
 // The window term of two coset blocks, (a, 0) and (a, 1), of position j at
 // once: each product (2 rho d) xbar is loaded once and added to both blocks
 // with the signs (-1)^{a q1 + b q2}, so a workgroup doing both blocks reads
-// the probe and the consensus window half as often per block.  Each block's
-// sums are formed exactly as split_frame_row forms them.
+// the probe and the consensus window half as often per block.  Block (a, b)
+// at (rr, c) is
+//   Z_ab[rr][c] + W_Np^{a rr + b c} sum_q (-1)^{a q1 + b q2} (2 rho d)[(rr, c) + M q] xbar[p_j + (rr, c) + M q].
+// The quadrant loop is kept rolled, so one quadrant's loads are in flight at a
+// time (they are L2 hits: the probe table and the consensus image); the state
+// blocks, read from HBM, are loaded last.  twnp: W_Np^m, m < Np, in LDS.
 template <int M, int NB0, int NB1>
 __device__ __forceinline__ void split_frame_pair(const Recon& g, const int j, const int a, const int rr,
                                                  const int p, const float2* twnp, float2 (&x0)[Geo<M>::B],
@@ -382,9 +309,12 @@ __device__ __forceinline__ void split_frame_pair(const Recon& g, const int j, co
   }
 }
 
-// One split block from its frame x (row layout) to its new state: forward
-// transforms, state spectrum with the block's amplitudes, inverse transforms,
-// store.  The same steps, in the same order, as agent_fused_body's split path.
+// One split block from its frame x (row layout) to its new state: the M x M
+// DFT of the block is the patch spectrum at the frequencies (2 k1 + a,
+// 2 k2 + b); the state spectrum is formed there with the amplitudes stored
+// in the same order, and 4 x its unnormalised inverse is the block of the new
+// state (the inverse of the split step gives 4 s' per block).  The M-point
+// transforms use W_M^m = W_Np^{2m}.
 template <int M>
 __device__ __forceinline__ void split_block_pass(const Recon& g, const size_t pb, float2 (&x)[Geo<M>::B],
                                                  float2* tile, const float2* tw) {
@@ -461,139 +391,6 @@ __global__ void __launch_bounds__(M * Geo<M>::A) agent_split_pair(const Recon g,
   agent_split_pair_body<M>(g, j, slot & 1);
 }
 
-// The split-layout agent for 128 x 128 blocks (Np = 256) with half the
-// threads and half the LDS of the whole-block version, so that two workgroups
-// share a CU and one's loads overlap the other's transforms: 512 threads;
-// each thread owns two rows (r and r + 64) in the row phase and two slots
-// (q and q + 4) of a column in the column phase.  The block passes between
-// the phases through a 64-row tile in two halves, and the column exchanges
-// run in two rounds.  Same arithmetic, in the same order, as
-// agent_fused_body<128, kPMACE, true>: the results are bitwise equal.
-template <int M>
-__device__ __forceinline__ void agent_split_half_body(const Recon& g, const int j, const int ab) {
-  constexpr int A = Geo<M>::A, B = Geo<M>::B, S = M + A, MB = B / A, HR = M / 2, NT = HR * A;
-  constexpr int MM = M * M;
-  static_assert(A % 2 == 0 && (B / 2) * A == HR, "two rows per thread, half the column slots");
-  __shared__ float2 tile[HR * S];
-  __shared__ float2 tw[M];
-  const int tid = threadIdx.x;
-  const size_t pb = ((size_t)j * 4 + ab) * MM;
-  const int r = tid / A, p = tid % A;
-  __shared__ float2 twnp[2 * M];
-  for (int m = tid; m < 2 * M; m += NT) twnp[m] = g.twn[m];
-  __syncthreads();
-  for (int m = tid; m < M; m += NT) tw[m] = twnp[2 * m];
-  float2 x0[B], x1[B];
-  split_frame_row<M, 0, B / 2>(g, j, ab, r, p, twnp, x0);
-  split_frame_row<M, B / 2, B>(g, j, ab, r, p, twnp, x0);
-  split_frame_row<M, 0, B / 2>(g, j, ab, r + HR, p, twnp, x1);
-  split_frame_row<M, B / 2, B>(g, j, ab, r + HR, p, twnp, x1);
-  __syncthreads();
-  float2* row = tile + r * S;
-  row_fwd<M>(x0, row, p, tw);
-  row_fwd<M>(x1, row, p, tw);
-
-  // rows -> columns: rows [0, HR) then [HR, M) through the tile
-  const int c = tid % M, q = tid / M, q2 = q + A / 2;
-  float2 xa[B], xb[B];
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < MB; ++m)
-#pragma unroll
-    for (int ka = 0; ka < A; ++ka) row[p + A * m + B * ka] = x0[m * A + ka];
-  __syncthreads();
-#pragma unroll
-  for (int nb = 0; nb < B / 2; ++nb) {
-    xa[nb] = tile[(q + A * nb) * S + c];
-    xb[nb] = tile[(q2 + A * nb) * S + c];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < MB; ++m)
-#pragma unroll
-    for (int ka = 0; ka < A; ++ka) row[p + A * m + B * ka] = x1[m * A + ka];
-  __syncthreads();
-#pragma unroll
-  for (int nb = B / 2; nb < B; ++nb) {
-    xa[nb] = tile[(q + A * nb - HR) * S + c];
-    xb[nb] = tile[(q2 + A * nb - HR) * S + c];
-  }
-  col_fwd2<M, 2>(xa, xb, tile, M, c, q, tw);
-  {
-    const float* yc = g.ys + pb + c;
-    const float sb = 4.f * g.sb, s2r = 4.f * g.s2r;   // exact: powers of two
-#pragma unroll
-    for (int m = 0; m < MB; ++m)
-#pragma unroll
-      for (int ka = 0; ka < A; ++ka) {
-        const float ya = yc[(size_t)(q + A * m + B * ka) * M], yb = yc[(size_t)(q2 + A * m + B * ka) * M];
-        xa[m * A + ka] = state_spectrum(xa[m * A + ka], ya, sb, s2r);
-        xb[m * A + ka] = state_spectrum(xb[m * A + ka], yb, sb, s2r);
-      }
-  }
-  col_inv2<M, 2>(xa, xb, tile, M, c, q, tw);
-
-  // columns -> rows, in the same two halves
-  __syncthreads();
-#pragma unroll
-  for (int nb = 0; nb < B / 2; ++nb) {
-    tile[(q + A * nb) * S + c] = xa[nb];
-    tile[(q2 + A * nb) * S + c] = xb[nb];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < MB; ++m)
-#pragma unroll
-    for (int ka = 0; ka < A; ++ka) x0[m * A + ka] = row[p + A * m + B * ka];
-  __syncthreads();
-#pragma unroll
-  for (int nb = B / 2; nb < B; ++nb) {
-    tile[(q + A * nb - HR) * S + c] = xa[nb];
-    tile[(q2 + A * nb - HR) * S + c] = xb[nb];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int m = 0; m < MB; ++m)
-#pragma unroll
-    for (int ka = 0; ka < A; ++ka) x1[m * A + ka] = row[p + A * m + B * ka];
-  row_inv<M>(x0, row, p, tw);
-  row_inv<M>(x1, row, p, tw);
-  float2* z0 = g.t + pb + (size_t)r * M;
-  float2* z1 = z0 + (size_t)HR * M;
-#pragma unroll
-  for (int nb = 0; nb < B; ++nb) {
-    z0[p + A * nb] = x0[nb];
-    z1[p + A * nb] = x1[nb];
-  }
-}
-
-template <int M>
-__global__ void __launch_bounds__(M / 2 * Geo<M>::A, 4) agent_split_half(const Recon g, int check_done,
-                                                                         int jper) {
-  if (check_done && *g.done) return;
-  const int b = blockIdx.x, slot = b >> 3;
-  const int j = (b & 7) * jper + (slot >> 2);
-  if (j >= g.J) return;
-  agent_split_half_body<M>(g, j, slot & 3);
-}
-
-// Split layout, Np = 2 M: one workgroup per (position, coset).  Workgroups
-// are dealt to the XCDs in turn (block b runs on XCD b mod 8), so block b
-// takes position xcd * jper + (b / 8) / 4 and coset (b / 8) mod 4: the four
-// cosets of a position, which read the same consensus window, share an XCD's
-// L2, and each XCD works through a contiguous run of positions (a band of
-// the object).
-// The descriptor is passed by value (a batch member's too: the kernels read
-// its stop flag through it), so the compiler knows its arrays are global
-// memory and issues global, not flat, loads.
-template <int M>
-__global__ void __launch_bounds__(M * Geo<M>::A) agent_split(const Recon g, int check_done, int jper) {
-  if (check_done && *g.done) return;
-  const int b = blockIdx.x, slot = b >> 3;
-  const int j = (b & 7) * jper + (slot >> 2);
-  if (j >= g.J) return;
-  agent_fused_body<M, kPMACE, true>(g, j, slot & 3);
-}
 
 // -------------------------------------------------------------------------
 // Np in {160, 192, 256}: the patch (up to 512 KB) exceeds one CU's LDS, so
@@ -1915,25 +1712,11 @@ static hipError_t gather_into_num(const Recon& h, int2 ct, int j0, hipStream_t s
   return hipGetLastError();
 }
 
-#ifndef PMACE_SPLIT_HALF
-#define PMACE_SPLIT_HALF 0   // Np = 256: the 512-thread block agent (two workgroups per CU)
-#endif
-
-#ifndef PMACE_SPLIT_PAIR
-#define PMACE_SPLIT_PAIR 1   // two coset blocks per workgroup, sharing their window loads
-#endif
-
 template <int M>
 static void split_iteration(const Recon& h, int check_done, hipStream_t st) {
   const int jper = (h.J + 7) / 8;
-  if constexpr (PMACE_SPLIT_PAIR)
-    hipLaunchKernelGGL(agent_split_pair<M>, dim3(8 * jper * 2), dim3(M * Geo<M>::A), 0, st, h, check_done,
-                       jper);
-  else if constexpr (M == 128 && PMACE_SPLIT_HALF)
-    hipLaunchKernelGGL(agent_split_half<M>, dim3(8 * jper * 4), dim3(M / 2 * Geo<M>::A), 0, st, h,
-                       check_done, jper);
-  else
-    hipLaunchKernelGGL(agent_split<M>, dim3(8 * jper * 4), dim3(M * Geo<M>::A), 0, st, h, check_done, jper);
+  hipLaunchKernelGGL(agent_split_pair<M>, dim3(8 * jper * 2), dim3(M * Geo<M>::A), 0, st, h, check_done,
+                     jper);
   hipLaunchKernelGGL(consensus_split<M>, dim3(h.nqt), dim3(QT_THREADS), 0, st, h, check_done);
   hipLaunchKernelGGL(image_update_split, dim3(blocks_for((long long)h.n1 * h.n2, 256)), dim3(256), 0, st,
                      h, check_done);
