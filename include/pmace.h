@@ -45,8 +45,12 @@ typedef enum {
 /* Intensities are stored with the zero frequency at the array centre
  * (fftshift layout); they are reordered once at init. */
 #define PMACE_CENTERED_DC 0x1u
-/* Agent variant (results agree to rounding; both are exact algebra of
- * eq. (9) and Alg. 1).  PMACE with np = 128, 192 or 256 and a probe without
+/* Agent variant (both are exact algebra of eq. (9) and Alg. 1, and their
+ * results agree to rounding, except in spectral bins that are exactly zero in
+ * exact arithmetic, e.g. a probe symmetric about its half-pixel centre seen
+ * through the flat start: the whole-patch and three-pass transforms return
+ * those zeros exactly, the split agent's leave rounding noise there, and
+ * eq. (9)'s "0 where W = 0" then does not act).  PMACE with np = 128, 192 or 256 and a probe without
  * exact zeros can keep each state as the four coset blocks of the top radix-2
  * step of its 2-D DFT ("split" agent): every agent then runs on (np/2)^2
  * blocks held on chip and no spectrum is staged through memory (about half
