@@ -57,8 +57,13 @@ int max_ppw(int np);
 int default_ppw(int np);
 // NRMSE reduction: RED_PX object pixels per block of RED_T threads.
 constexpr int RED_T = 256, RED_PX = 4096;
-// Base tile of the split-layout consensus: QT_R x QT_C pixels, one thread each.
-constexpr int QT_R = 8, QT_C = 32, QT_THREADS = QT_R * QT_C;
+// Base tile of the split-layout consensus: QT_R x QT_C pixels, QT_K threads
+// each (every QT_K-th entry of the tile's list; partials added in a fixed order).
+#ifndef PMACE_QT_K
+#define PMACE_QT_K 2
+#endif
+constexpr int QT_R = 8, QT_C = 32, QT_K = PMACE_QT_K, QT_THREADS = QT_R * QT_C * QT_K;
+static_assert(QT_K >= 1 && QT_K <= 4, "split consensus: 1 to 4 threads per pixel");
 
 // Device-resident description of one reconstruction.  It lives in the
 // reconstruction's workspace; batched launches read an array of them.

@@ -1310,17 +1310,20 @@ __global__ void __launch_bounds__(col_threads<NP>()) fft_cols(const float2* in, 
 // of T at m = R - p_j undoes the split step from the four blocks at m,
 //     s[m + M q] = 1/4 sum_ab (-1)^{a q1 + b q2} W_Np^{-(a m1 + b m2)} Z_ab[m],
 // and adds the weighted values to the pixels T + M q: one partial sum per
-// quadrant q, written to part[q] (each block value is read once).  The image
-// update adds the four partials in the order q = 0..3.
+// quadrant q, written to part[q] (each block value is read once).  QT_K
+// threads share a pixel, thread k taking the entries k, k + QT_K, ...; their
+// sums are added in the order k = 0..QT_K-1.  The image update adds the four
+// partials in the order q = 0..3.
 template <int M>
 __device__ __forceinline__ void consensus_split_body(const Recon& g, const int tile) {
-  constexpr int NP = 2 * M, MM = M * M, LIST = 256;
+  constexpr int NP = 2 * M, MM = M * M, LIST = 256, TPX = QT_R * QT_C;
   __shared__ int3 sl[LIST];
   __shared__ float2 tw[NP];
-  const int tid = threadIdx.x;
+  __shared__ float2 red[QT_K > 1 ? (QT_K - 1) * 4 * TPX : 1];
+  const int tid = threadIdx.x, px = tid % TPX, k = tid / TPX;
   for (int m = tid; m < NP; m += QT_THREADS) tw[m] = g.twn[m];
   const int4 ti = g.qtiles[tile];
-  const int R = ti.z + tid / QT_C, C = ti.w + tid % QT_C;
+  const int R = ti.z + px / QT_C, C = ti.w + px % QT_C;
   float2 acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = make_float2(0.f, 0.f);
@@ -1334,7 +1337,7 @@ __device__ __forceinline__ void consensus_split_body(const Recon& g, const int t
     }
     __syncthreads();
 #pragma unroll 4
-    for (int i = 0; i < nb; ++i) {
+    for (int i = k; i < nb; i += QT_K) {
       const int3 e = sl[i];
       const unsigned rr = (unsigned)(R - e.y), cc = (unsigned)(C - e.z);
       const bool in = rr < (unsigned)M && cc < (unsigned)M;
@@ -1353,6 +1356,18 @@ __device__ __forceinline__ void consensus_split_body(const Recon& g, const int t
       acc[2] = cfma(c2, csub(u0, u2), acc[2]);
       acc[3] = cfma(c3, csub(u1, u3), acc[3]);
     }
+  }
+  if constexpr (QT_K > 1) {
+    if (k > 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[((k - 1) * 4 + q) * TPX + px] = acc[q];
+    }
+    __syncthreads();
+    if (k > 0) return;   // no barrier follows
+#pragma unroll
+    for (int kk = 1; kk < QT_K; ++kk)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = cadd(acc[q], red[((kk - 1) * 4 + q) * TPX + px]);
   }
   const size_t npx = (size_t)g.n1 * g.n2;
 #pragma unroll
