@@ -791,15 +791,27 @@ __global__ void __launch_bounds__(RED_T) nrmse_partial(const Recon* __restrict__
   if ((update_stop && *g.done) || !g.xref) return;
   const int npx = g.n1 * g.n2;
   const int base = it.y * RED_PX;
+  // every load of the thread's pixels is issued before the sums (one memory
+  // round trip, not one per pixel); the sums then run in the same order
+  constexpr int PER = RED_PX / RED_T;
+  float2 xr[PER], xh[PER];
+  bool on[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = base + (int)threadIdx.x + u * RED_T;
+    const int ic = i < npx ? i : 0;
+    on[u] = i < npx && (!g.mask || g.mask[ic]);
+    xr[u] = g.xref[ic];
+    xh[u] = g.xhat[ic];
+  }
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int k = threadIdx.x; k < RED_PX; k += RED_T) {
-    const int i = base + k;
-    if (i < npx && (!g.mask || g.mask[i])) {
-      const float2 xr = g.xref[i], xh = g.xhat[i];
-      acc[0] += (double)xr.x * xh.x + (double)xr.y * xh.y;   // Re conj(xref) xhat
-      acc[1] += (double)xr.x * xh.y - (double)xr.y * xh.x;   // Im conj(xref) xhat
-      acc[2] += (double)xh.x * xh.x + (double)xh.y * xh.y;   // |xhat|^2
-      acc[3] += (double)xr.x * xr.x + (double)xr.y * xr.y;   // |xref|^2
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    if (on[u]) {
+      acc[0] += (double)xr[u].x * xh[u].x + (double)xr[u].y * xh[u].y;   // Re conj(xref) xhat
+      acc[1] += (double)xr[u].x * xh[u].y - (double)xr[u].y * xh[u].x;   // Im conj(xref) xhat
+      acc[2] += (double)xh[u].x * xh[u].x + (double)xh[u].y * xh[u].y;   // |xhat|^2
+      acc[3] += (double)xr[u].x * xr[u].x + (double)xr[u].y * xr[u].y;   // |xref|^2
     }
   }
   block_sum<4>(acc);
