@@ -1,13 +1,13 @@
 // PMACE iteration kernels for gfx950 (MI355X).
 //
 // One iteration of Alg. 1 is carried as
-//     v_j   = t_j + 2 rho P_j xbar                      (finishes line 5 of the previous pass)
-//     w_j   = F_j(v_j)                                  (eq. (9), line 3)
-//     u_j   = 2 w_j - v_j                               (reflection, line 4)
-//     t_j  <- v_j - 2 rho w_j                           (first half of line 5)
+//     v_j   = t_j + 2 rho P_j xbar                      (finishes the previous pass's Mann update)
+//     w_j   = F_j(v_j)                                  (the data agent, eq. (9))
+//     u_j   = 2 w_j - v_j                               (the reflection)
+//     t_j  <- v_j - 2 rho w_j                           (first half of the Mann update)
 //     xbar  = Lambda^{-1} sum_j P_j^t |d|^kappa u_j     (eq. (11))
 //     xhat <- (1 - rho) xhat + rho xbar
-// Storing t instead of v is exact algebra of line 5 (v_new = t + 2 rho P_j xbar),
+// Storing t instead of v is exact algebra of the Mann update (v_new = t + 2 rho P_j xbar),
 // and the xhat recurrence is exact algebra of the returned weighted average
 // (the average of P_j xbar is xbar on covered pixels; the average of w is the
 // mean of the averages of u and v).
@@ -1446,7 +1446,7 @@ __device__ __forceinline__ float2 split_frame(const Recon& g, int2 pj, int ab, i
   return cmul(h, g.twn[a * m1 + b * m2]);
 }
 
-// Split-layout states from an object (Alg. 1 line 1, v_j = P_j x0, stored
+// Split-layout states from an object (Alg. 1's initialisation, v_j = P_j x0, stored
 // as d v in blocks): element i of block ab of position j.
 __global__ void init_split_k(const Recon* __restrict__ rec, const float2* x0) {
   const Recon& g = *rec;
