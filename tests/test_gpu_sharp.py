@@ -115,3 +115,43 @@ def test_sharp_plus_full_size(P, config):
         _say(f"  k={k} rel(s)={es:.2e} rel(xhat)={ex:.2e} elementwise {ms:.2e} {mx:.2e}")
         assert es < TOL and ex < TOL and ms < TOL and mx < TOL
     R.close()
+
+
+@pytest.mark.parametrize("case,iters", [("c1", 50), ("np256_ragged_chunks", 20)])
+def test_sharp_plus_every_iteration(P, case, iters):
+    """SHARP+ teacher-forced at every iteration of a longer run from a smooth
+    start (beta 0.8): the C1 workload to 50 iterations on the whole-patch agent,
+    and a three-pass case with ragged chunks to 20, each pass on every frame and
+    on the output, in L2 and element by element."""
+    beta = 0.8
+    if case == "c1":
+        prob = synth.make_config_problem("c1")
+        chunk = 0
+    else:
+        n, np_, scan, step, peak, seed, chunk = CASES[case]
+        prob = synth.make_problem(n, np_, scan, step, peak, seed)
+    n = prob.n1
+    d = prob.probe.astype(np.complex64).astype(np.complex128)
+    y = O.amplitudes(prob.z.astype(np.float32))
+    shape = (n, n)
+    x0 = synth.make_object(n, n, np.random.default_rng(98))
+    _say(case, "sharp+ oracle trajectory", iters)
+    ss = [O.sharp_plus_init(x0, d, prob.pos)]
+    for _ in range(iters):
+        ss.append(O.sharp_plus_step(ss[-1], d, y, prob.pos, shape, beta))
+    R = P.Reconstruction(n, n, prob.probe, prob.pos, prob.z, 0.0, x0=x0.astype(np.complex64),
+                         chunk=chunk, method=P.PMACE_METHOD_SHARP_PLUS, beta=beta)
+    worst = 0.0
+    for k in range(iters):
+        R.set_state(ss[k])
+        R.iterate(1)
+        s1 = R.get_state().cpu().numpy()
+        xr = O.sharp_plus_reconstruct(ss[k + 1], d, prob.pos, shape)
+        xh = R.reconstruct().cpu().numpy()
+        errs = (rel(s1, ss[k + 1]), rel(xh, xr), elem(s1, ss[k + 1]), elem(xh, xr))
+        if k % 10 == 0 or k == iters - 1:
+            _say(f"  k={k} rel(s)={errs[0]:.2e} rel(xhat)={errs[1]:.2e} elementwise {errs[2]:.2e} {errs[3]:.2e}")
+        assert max(errs) < TOL, (k, errs)
+        worst = max(worst, max(errs))
+    _say(f"  worst = {worst:.2e}")
+    R.close()
