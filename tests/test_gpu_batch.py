@@ -326,11 +326,12 @@ def test_batch_member_new_reference(P):
 
 
 def test_batched_members_match_oracle(P):
-    """Members advanced inside a mixed batch (fused sides, and a chunked
-    Np = 256 member), from smooth starts: every member's state and
+    """Members advanced inside a mixed batch (fused sides, a chunked Np = 256
+    member on the three-pass agent and an Np = 192 member on the split agent,
+    this side's default), from smooth starts: every member's state and
     reconstruction after K iterations equal the FP64 oracle's at 1e-4, in L2
     and element by element."""
-    cfgs = [MIX[1], MIX[3], MIX[4]]             # Np 64, 128, 256 (4 positions per chunk)
+    cfgs = [MIX[1], MIX[3], MIX[4], MIX[7]]     # Np 64, 128, 256 (4 positions per chunk), 192
     probs = [synth.make_problem(n, np_, sc, st, pk, sd) for (n, np_, sc, st, pk, sd, _) in cfgs]
     K = 3
     x0s = [synth.make_object(p.n1, p.n2, np.random.default_rng(200 + i)).astype(np.complex64)
@@ -350,7 +351,8 @@ def test_batched_members_match_oracle(P):
         ex = np.linalg.norm(xh - xr) / np.linalg.norm(xr)
         mv = np.max(np.abs(v - st.v)) / np.max(np.abs(st.v))
         mx = np.max(np.abs(xh - xr)) / np.max(np.abs(xr))
-        _say(f"batched member Np {p.np_}: rel(v)={ev:.2e} rel(xhat)={ex:.2e} elementwise {mv:.2e} {mx:.2e}")
+        _say(f"batched member Np {p.np_} ({R.agent}): rel(v)={ev:.2e} rel(xhat)={ex:.2e} "
+             f"elementwise {mv:.2e} {mx:.2e}")
         assert ev < 1e-4 and ex < 1e-4 and mv < 1e-4 and mx < 1e-4
     B.close()
     for R in Rs:
