@@ -66,6 +66,26 @@ template <bool INV> __device__ __forceinline__ float2 w16(int k, float2 a) {
   }
 }
 
+// multiply by W_32^k, k compile-time after unrolling (even k: W_16^{k/2})
+template <bool INV> __device__ __forceinline__ float2 w32(int k, float2 a) {
+  const float c1 = 0.98078528040323044913f;  // cos(pi/16)
+  const float s1 = 0.19509032201612826785f;  // sin(pi/16)
+  const float c3 = 0.83146961230254523708f;  // cos(3 pi/16)
+  const float s3 = 0.55557023301960222474f;  // sin(3 pi/16)
+  const float sg = INV ? 1.f : -1.f;
+  if (k % 2 == 0) return w16<INV>(k / 2, a);
+  switch (k) {
+    case 1: return cmul(a, make_float2(c1, sg * s1));
+    case 3: return cmul(a, make_float2(c3, sg * s3));
+    case 5: return cmul(a, make_float2(s3, sg * c3));
+    case 7: return cmul(a, make_float2(s1, sg * c1));
+    case 9: return cmul(a, make_float2(-s1, sg * c1));
+    case 11: return cmul(a, make_float2(-s3, sg * c3));
+    case 13: return cmul(a, make_float2(-c3, sg * s3));
+    default: return cmul(a, make_float2(-c1, sg * s1));
+  }
+}
+
 template <bool INV> __device__ __forceinline__ void dft2(float2* a) {
   float2 t = a[0];
   a[0] = cadd(t, a[1]);
@@ -107,6 +127,21 @@ template <bool INV> __device__ __forceinline__ void dft16(float2* a) {
     float2 t = w16<INV>(k, o[k]);
     a[k] = cadd(e[k], t);
     a[k + 8] = csub(e[k], t);
+  }
+}
+
+// 32 points: two 16-point DFTs on even/odd samples, then W_32 butterflies.
+template <bool INV> __device__ __forceinline__ void dft32(float2* a) {
+  float2 e[16], o[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) { e[i] = a[2 * i]; o[i] = a[2 * i + 1]; }
+  dft16<INV>(e);
+  dft16<INV>(o);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    float2 t = w32<INV>(k, o[k]);
+    a[k] = cadd(e[k], t);
+    a[k + 16] = csub(e[k], t);
   }
 }
 
@@ -189,28 +224,33 @@ template <int R, bool INV> __device__ __forceinline__ void dft(float2* a) {
   else if constexpr (R == 12) dft_pfa<3, 4, INV>(a);
   else if constexpr (R == 24) dft_pfa<3, 8, INV>(a);
   else if constexpr (R == 40) dft_pfa<5, 8, INV>(a);
+  else if constexpr (R == 32) dft32<INV>(a);
   else { static_assert(R == 16, "radix"); dft16<INV>(a); }
 }
 
 // Split N = A*B of a line over A threads with B registers each (B a multiple
 // of A).  Powers of two use radix 16/8/4; 48, 96, 192 add a factor 3 and 160
 // a factor 5 through the prime-factor DFTs above.
-// The splits of 32 and 64 points are build-time choices (tuned): 32 = 4x8 or
-// 2x16, 64 = 8x8 or 4x16.
+// The splits of 32, 64 and 128 points are build-time choices (tuned):
+// 32 = 4x8 or 2x16, 64 = 8x8 or 4x16, 128 = 8x16 or 4x32.
 #ifndef PMACE_GEO32_A
 #define PMACE_GEO32_A 4
 #endif
 #ifndef PMACE_GEO64_A
 #define PMACE_GEO64_A 8
 #endif
+#ifndef PMACE_GEO128_A
+#define PMACE_GEO128_A 8
+#endif
 static_assert(PMACE_GEO32_A == 2 || PMACE_GEO32_A == 4, "32-point split");
 static_assert(PMACE_GEO64_A == 4 || PMACE_GEO64_A == 8, "64-point split");
+static_assert(PMACE_GEO128_A == 4 || PMACE_GEO128_A == 8, "128-point split");
 template <int N> struct Geo;
 template <> struct Geo<32>  { static constexpr int A = PMACE_GEO32_A, B = 32 / PMACE_GEO32_A; };
 template <> struct Geo<48>  { static constexpr int A = 4,  B = 12; };
 template <> struct Geo<64>  { static constexpr int A = PMACE_GEO64_A, B = 64 / PMACE_GEO64_A; };
 template <> struct Geo<96>  { static constexpr int A = 4,  B = 24; };
-template <> struct Geo<128> { static constexpr int A = 8,  B = 16; };
+template <> struct Geo<128> { static constexpr int A = PMACE_GEO128_A, B = 128 / PMACE_GEO128_A; };
 template <> struct Geo<160> { static constexpr int A = 4,  B = 40; };
 template <> struct Geo<192> { static constexpr int A = 8,  B = 24; };
 template <> struct Geo<256> { static constexpr int A = 16, B = 16; };

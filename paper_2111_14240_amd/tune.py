@@ -12,6 +12,7 @@ csrc/pmace_internal.hpp) plus one run-time default:
     PMACE_CHUNK256       Np > 128: positions per chunk (stage buffer size)
     PMACE_GEO32_A        32-point line split over threads: 4 x 8 or 2 x 16 registers
     PMACE_GEO64_A        64-point line split: 8 x 8 or 4 x 16
+    PMACE_GEO128_A       128-point line split: 8 x 16 or 4 x 32
     PMACE_PPW32/48/64    (run-time choice, recorded as the build's default) patches per
                          workgroup of the whole-patch agent for Np = 32, 48, 64
     PMACE_SPLIT_SIDES    (run-time choice, recorded for the build) which of Np = 128, 192, 256
@@ -22,7 +23,7 @@ Search (coordinate-wise, every candidate measured on the device):
      the iteration time of a Np = 128 and a Np = 256 workload;
   2. row/column blocks with the default gather, scored on the Np = 256 workload
      (the row block found applies to 256-point lines; 160 and 192 keep PMACE_RB);
-  3. the line-FFT split (radix) of Np = 32 and 64, each on a workload of its size;
+  3. the line-FFT split (radix) of Np = 32, 64 and 128, each on a workload of its size;
   4. the chunk size, at run time, with the combined choice;
   5. patches per workgroup of the whole-patch agent (Np = 32, 48, 64), at run
      time, each on a workload of its size, with the built library;
@@ -52,11 +53,11 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned.json")
 DEFAULTS = {"PMACE_GT_K": 1, "PMACE_GATHER_UNROLL": 8, "PMACE_GT_C": 64, "PMACE_RB": 32, "PMACE_RB256": 16,
-            "PMACE_CB": 16, "PMACE_GEO32_A": 4, "PMACE_GEO64_A": 8,
+            "PMACE_CB": 16, "PMACE_GEO32_A": 4, "PMACE_GEO64_A": 8, "PMACE_GEO128_A": 8,
             "PMACE_PPW32": 1, "PMACE_PPW48": 1, "PMACE_PPW64": 1}
 GATHER_SPACE = [(k, u, c) for k in (1, 2, 4) for u in (8, 16) for c in (64, 32)]
 BLOCK_SPACE = [(rb, cb) for rb in (8, 16, 32) for cb in (16, 32)]
-GEO_SPACE = [(32, 2), (64, 4)]          # the non-default splits
+GEO_SPACE = [(32, 2), (64, 4), (128, 4)]   # the non-default splits
 PPW_SPACE = {32: (1, 2, 4, 8), 48: (1, 2, 4), 64: (1, 2)}   # patches per workgroup per side
 AGENT_SIDES = {128: "np128", 192: "np192", 256: "np256"}
 CHUNKS = (64, 128, 192, 256, 400)
@@ -149,7 +150,9 @@ def cmd_time(args):
             wl_extra = ["np32", "np48", "np64"]
         else:
             wl_extra = []
-        if name.startswith("geo"):
+        if name.startswith("geo128"):
+            wl = ["np128"]
+        elif name.startswith("geo"):
             wl = ["np32", "np64"]
 
         elif name.startswith("g"):
@@ -192,11 +195,10 @@ def _pick(cands, times):
     rb, cb = best_b[2:].split("cb")
     d["PMACE_RB256"], d["PMACE_CB"] = int(rb), int(cb)
     # line splits: the default build's time on each size against the variant's
-    if "np32" in base:
-        for n, a in GEO_SPACE:
-            key = f"geo{n}a{a}"
-            if key in times and times[key][f"np{n}"] < base[f"np{n}"]:
-                d[f"PMACE_GEO{n}_A"] = a
+    for n, a in GEO_SPACE:
+        key, wl = f"geo{n}a{a}", f"np{n}"
+        if key in times and wl in base and times[key][wl] < base[wl]:
+            d[f"PMACE_GEO{n}_A"] = a
     return d, score, b
 
 

@@ -59,3 +59,12 @@ def test_split_sides_bitmask():
     res["np128_split"] = 0.5
     res["np256_split"] = 0.5
     assert tune._split_sides(res) == 7
+
+
+def test_line_split_of_128_points():
+    cands = tune.candidates()
+    assert "geo128a4" in cands and cands["geo128a4"]["PMACE_GEO128_A"] == 4
+    d, _, _ = tune._pick(cands, _times(cands, geo128a4=("np128", 0.9)))
+    assert d["PMACE_GEO128_A"] == 4
+    d, _, _ = tune._pick(cands, _times(cands, geo128a4=("np128", 1.1)))
+    assert d["PMACE_GEO128_A"] == 8
