@@ -81,3 +81,26 @@ def test_variant_lines(args, metric):
     assert d["cpu_baseline"]["kind"] == "oracle" and d["cpu_baseline"]["value"] > 0
     if "--np" in args:
         assert "probe 48x48" in d["config"]["workload"]
+
+
+def test_traffic_table_lookup(tmp_path, monkeypatch):
+    """bench.py reports the counter-measured traffic only for the kernel
+    sources it was measured on: the table row's hash must equal the hash of
+    the current sources, otherwise `traffic` is null."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    h = bench.kernel_source_hash()
+    assert len(h) == 16 and int(h, 16) >= 0
+    assert bench.workload_key("c3", "pmace", 0) == "c3"
+    assert bench.workload_key("c3", "sharp", 0) == "c3-sharp"
+    assert bench.workload_key("c3", "pmace", 192, "staged") == "c3-np192-staged"
+    table = tmp_path / "traffic.md"
+    table.write_text("| workload | kernel sources | a | b | c | d | bytes |\n"
+                     f"| c3 | {h} | 1 | 2 | 3 | 4 | 6.5e+09 |\n"
+                     "| c2 | 0000000000000000 | 1 | 2 | 3 | 4 | 1.0e+08 |\n")
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(table))
+    assert bench.measured_traffic("c3") == 6.5e9
+    assert bench.measured_traffic("c2") is None          # measured on other sources
+    assert bench.measured_traffic("c1") is None          # not measured
