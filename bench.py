@@ -70,12 +70,17 @@ def kernel_source_hash():
 
 def iteration_kernels(np_, J, method="pmace", agent="three-pass"):
     """The kernels one timed iteration (the roofline's unit) launches, for the
-    agent the reconstruction runs ('whole patch', 'three-pass', 'split')."""
+    agent the reconstruction runs ('whole patch', 'three-pass', 'split',
+    'row-spectrum')."""
     name = "PMACE" if method == "pmace" else "SHARP+"
     if agent == "split":
         return (f"one {name} iteration: agent_split_pair<{np_ // 2}> ({2 * J} workgroups, two "
                 f"{np_ // 2}x{np_ // 2} coset blocks each) + consensus_split<{np_ // 2}> (four partial sums "
                 f"per pixel) + image_update_split")
+    if agent == "row-spectrum":
+        return (f"one {name} iteration: per chunk of positions agent_rows, agent_cols <{np_}> "
+                f"(states kept as row spectra) + consensus_rows<{np_}> (inverse row DFTs, one object "
+                f"row per workgroup), then image_update")
     if np_ <= 128:
         return (f"one {name} iteration: agent_fused<{np_}> ({J} workgroups) + "
                 f"consensus_gather<{np_}> (a9 fused)")
@@ -471,9 +476,9 @@ def main():
     ap.add_argument("--n2", type=int, default=0,
                     help="plain mode: a rectangular object with this many columns (the raster widened "
                          "at the same step)")
-    ap.add_argument("--agent", default="default", choices=["default", "staged", "split"],
-                    help="plain mode: the library's choice, the three-pass agent (Np 192/256), or the "
-                         "coset-block agent (Np 128 too)")
+    ap.add_argument("--agent", default="default", choices=["default", "staged", "split", "rowspec"],
+                    help="plain mode: the library's choice, the three-pass agent (Np > 128), the "
+                         "coset-block agent (Np 128/192/256) or the row-spectrum agent (Np > 128)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--systems", action=argparse.BooleanOptionalAction, default=True,
                     help="plain mode: also run the 64-item batch and a short served run against the plain "
@@ -536,7 +541,8 @@ def main():
     alpha, kappa, rho = ALPHA[args.config], synth.KAPPA, synth.RHO
     sharp = args.method == "sharp"
     mkw = dict(method=pmace.PMACE_METHOD_SHARP_PLUS, beta=args.beta) if sharp else {}
-    mkw["flags"] = {"default": 0, "staged": pmace.PMACE_STAGED_AGENT, "split": pmace.PMACE_SPLIT_AGENT}[args.agent]
+    mkw["flags"] = {"default": 0, "staged": pmace.PMACE_STAGED_AGENT, "split": pmace.PMACE_SPLIT_AGENT,
+                    "rowspec": pmace.PMACE_ROWSPEC_AGENT}[args.agent]
     mkw["ppw"] = args.ppw
     key = workload_key(args.config, args.method, args.np, args.agent) + (f"-n2{args.n2}" if args.n2 else "")
     dev = torch.device("cuda:0")

@@ -45,26 +45,34 @@ typedef enum {
 /* Intensities are stored with the zero frequency at the array centre
  * (fftshift layout); they are reordered once at init. */
 #define PMACE_CENTERED_DC 0x1u
-/* Agent variant (both are exact algebra of eq. (9) and Alg. 1, and their
+/* Agent variant (all are exact algebra of eq. (9) and Alg. 1, and their
  * results agree to rounding, except in spectral bins that are exactly zero in
  * exact arithmetic, e.g. a probe symmetric about its half-pixel centre seen
  * through the flat start: the whole-patch and three-pass transforms return
  * those zeros exactly, the split agent's leave rounding noise there, and
- * eq. (9)'s "0 where W = 0" then does not act).  PMACE with np = 128, 192 or 256 and a probe without
- * exact zeros can keep each state as the four coset blocks of the top radix-2
- * step of its 2-D DFT ("split" agent): every agent then runs on (np/2)^2
- * blocks held on chip and no spectrum is staged through memory (about half
- * the memory traffic), at the price of reading the probe and the consensus
- * window once per block.  Otherwise np = 160, 192, 256 run the three-pass
- * agent that stages each chunk's spectra, and np <= 128 the whole-patch one.
+ * eq. (9)'s "0 where W = 0" then does not act).  np <= 128 runs the
+ * whole-patch agent; np = 160, 192, 256 by default the three-pass agent, which
+ * stages each chunk's spectra through memory twice.  PMACE with a probe
+ * without exact zeros has two more:
+ *   - np = 128, 192 or 256: each state kept as the four coset blocks of the
+ *     top radix-2 step of its 2-D DFT ("split" agent): every agent then runs
+ *     on (np/2)^2 blocks held on chip and no spectrum is staged (about half
+ *     the memory traffic), at the price of reading the probe and the
+ *     consensus window once per block;
+ *   - np = 160, 192 or 256: each state kept as the DFTs of its rows
+ *     ("row-spectrum" agent): the column pass writes the new state itself,
+ *     and the consensus inverts the rows it sums, so each chunk's spectra are
+ *     staged once instead of twice.
  * SHARP+, and probes with zeros (where eq. (9)'s d = 0 rule acts per pixel),
- * never use the split agent.  Which sides use it by default is a build
- * choice (timed by the tuner; this build: np = 192).
- *   PMACE_STAGED_AGENT: never the split agent.
- *   PMACE_SPLIT_AGENT:  the split agent wherever it applies (np 128/192/256).
- * Setting both is EINVAL. */
+ * use neither.  Which sides use which by default is a build choice (timed by
+ * the tuner).
+ *   PMACE_STAGED_AGENT:  the three-pass agent (np > 128), never the split one.
+ *   PMACE_SPLIT_AGENT:   the split agent wherever it applies.
+ *   PMACE_ROWSPEC_AGENT: the row-spectrum agent wherever it applies.
+ * Setting more than one of them is EINVAL. */
 #define PMACE_STAGED_AGENT 0x2u
 #define PMACE_SPLIT_AGENT 0x4u
+#define PMACE_ROWSPEC_AGENT 0x8u
 
 /* Iteration run by a context (pmace_params.method). */
 #define PMACE_METHOD_PMACE 0      /* Alg. 1: Mann iteration of T = (2G - I)(2F - I) */
@@ -78,7 +86,8 @@ typedef struct {
   float alpha;        /* >= 0: noise-to-signal weight of the agent, eq. (9) */
   float kappa;        /* >= 0: probe exponent of the consensus weights, eq. (11) */
   float rho;          /* 0 < rho < 1: Mann averaging parameter, eq. (13) */
-  uint32_t flags;     /* PMACE_CENTERED_DC, PMACE_STAGED_AGENT, PMACE_SPLIT_AGENT or 0 */
+  uint32_t flags;     /* PMACE_CENTERED_DC and at most one of PMACE_STAGED_AGENT,
+                         PMACE_SPLIT_AGENT, PMACE_ROWSPEC_AGENT; or 0 */
   int32_t chunk;      /* Np > 128 only: at most this many positions per staging chunk
                          (>= 1, capped at J; the chunks are then evened out),
                          0 = the build's tuned default for Np = 256, scaled by
@@ -161,6 +170,7 @@ pmace_status pmace_set_stream(pmace_ctx* ctx, void* hip_stream);
 #define PMACE_AGENT_WHOLE_PATCH 0  /* np <= 128: one workgroup per patch */
 #define PMACE_AGENT_THREE_PASS 1   /* np > 128: rows, columns, inverse rows, spectra staged */
 #define PMACE_AGENT_SPLIT 2        /* coset blocks of (np/2)^2, states in the split layout */
+#define PMACE_AGENT_ROWSPEC 3      /* np > 128: rows, columns, states kept as row spectra */
 int32_t pmace_agent_kind(const pmace_ctx* ctx);  /* -1 for NULL */
 
 /* Release the host context (not the caller's workspace).  NULL is a no-op. */

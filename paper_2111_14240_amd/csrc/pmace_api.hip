@@ -60,6 +60,7 @@ struct pmace_ctx {
   int* fitem;                     // device: {0}
   int ngitems;
   std::vector<int2> chunk_tiles;  // host: per chunk (first gather item, count)
+  std::vector<int2> chunk_rows;   // host, row-spectrum states: per chunk (first row item, count)
   Graph graph;                    // one iteration
   Graph graph_k;                  // kGraphIters iterations back to back
   bool graph_tried;
@@ -143,8 +144,10 @@ pmace_status check_params(const pmace_params* p) {
   if (!(std::isfinite(p->alpha) && p->alpha >= 0.f)) return PMACE_EINVAL;
   if (!(std::isfinite(p->kappa) && p->kappa >= 0.f)) return PMACE_EINVAL;
   if (!(std::isfinite(p->rho) && p->rho > 0.f && p->rho < 1.f)) return PMACE_EINVAL;
-  if (p->flags & ~(PMACE_CENTERED_DC | PMACE_STAGED_AGENT | PMACE_SPLIT_AGENT)) return PMACE_EINVAL;
-  if ((p->flags & PMACE_STAGED_AGENT) && (p->flags & PMACE_SPLIT_AGENT)) return PMACE_EINVAL;
+  constexpr uint32_t kAgents = PMACE_STAGED_AGENT | PMACE_SPLIT_AGENT | PMACE_ROWSPEC_AGENT;
+  if (p->flags & ~(PMACE_CENTERED_DC | kAgents)) return PMACE_EINVAL;
+  const uint32_t ag = p->flags & kAgents;
+  if (ag & (ag - 1)) return PMACE_EINVAL;  // at most one agent asked for
   if (p->chunk < 0) return PMACE_EINVAL;
   if (p->method != PMACE_METHOD_PMACE && p->method != PMACE_METHOD_SHARP_PLUS) return PMACE_EINVAL;
   if (p->method == PMACE_METHOD_SHARP_PLUS && !(std::isfinite(p->beta) && p->beta >= 0.f && p->beta <= 1.f))
@@ -159,7 +162,7 @@ pmace_status check_params(const pmace_params* p) {
 // Section offsets inside the workspace (relative to the aligned base).
 struct Layout {
   size_t t, ys, pos, d, pc, dinv, gw, omega64, laminv, num, sold, xbar, xhat, stage, tiles, list, status, desc,
-      items, gitems, ritems, red, tw, fit, dr, qtiles, qlist, total;
+      items, gitems, ritems, red, tw, fit, dr, qtiles, qlist, citems, clist, total;
 };
 
 // Patch sides whose default agent is the split (coset-block) one: a build
@@ -178,9 +181,34 @@ bool split_allowed(const pmace_params& p) {
   if (p.method != PMACE_METHOD_PMACE) return false;
   if (p.np != 128 && p.np != 192 && p.np != 256) return false;
   if (p.flags & PMACE_SPLIT_AGENT) return true;
-  if (p.flags & PMACE_STAGED_AGENT) return false;
+  if (p.flags & (PMACE_STAGED_AGENT | PMACE_ROWSPEC_AGENT)) return false;
   return split_default(p.np);
 }
+// Patch sides whose default agent keeps row-spectrum states (bit 0: Np = 160,
+// bit 1: 192, bit 2: 256), where the split agent is not the default: a build
+// choice measured by the tuner.
+#ifndef PMACE_ROWSPEC_SIDES
+#define PMACE_ROWSPEC_SIDES 0
+#endif
+bool rowspec_default(int np) {
+  const int bit = np == 160 ? 1 : np == 192 ? 2 : np == 256 ? 4 : 0;
+  return (PMACE_ROWSPEC_SIDES & bit) != 0;
+}
+// The row-spectrum agent may run: PMACE with Np > 128 when asked for, or by
+// default where the build chose it and no other agent is asked for or chosen.
+// Whether it does also needs a probe without exact zeros (known at init).
+bool rowspec_allowed(const pmace_params& p) {
+  if (p.method != PMACE_METHOD_PMACE || !np_large(p.np)) return false;
+  if (p.flags & PMACE_ROWSPEC_AGENT) return true;
+  if (p.flags & (PMACE_STAGED_AGENT | PMACE_SPLIT_AGENT)) return false;
+  return !split_allowed(p) && rowspec_default(p.np);
+}
+// Bounds of its consensus tables (sizes only): every (chunk, object row,
+// segment) item, and an entry per patch row and segment it meets (at most two,
+// as a segment is at least 256 wide).
+int cr_segments(const pmace_params& p) { return (p.n2 + pmace::CR_W - 1) / pmace::CR_W; }
+size_t cr_items(const pmace_params& p) { return (size_t)num_chunks(p) * p.n1 * cr_segments(p); }
+size_t cr_list(const pmace_params& p) { return (size_t)p.num_pos * p.np * std::min(2, cr_segments(p)); }
 // Base tiles of the split consensus: rows [0, qrows), columns [0, qcols), the
 // quadrant-0 blocks of all positions lie in [0, n1 - M) x [0, n2 - M).
 int split_rows(const pmace_params& p) {
@@ -208,6 +236,20 @@ size_t stage_patches(const pmace_params& p) {
 
 // Data-fit partial sums per patch: one, or one per column block for Np > 128.
 int fit_bpp(const pmace_params& p) { return np_large(p.np) ? p.np / PMACE_CB : 1; }
+
+// Launch order of one row of tiles t[first, end), left to right. The
+// dispatcher sends workgroup b to XCD b mod 8, and each XCD has its own L2.
+// Side-by-side tiles read the same state lines at their common edge, so slot
+// b gets tile (b mod 8) * q + b / 8 of the row (q = n / 8; the last n mod 8
+// stay in place): each XCD runs q side-by-side tiles of every row, and the
+// second read of an edge line hits its L2. Only which workgroup sums which
+// pixel changes; every pixel's sum is the same.
+void xcd_runs(std::vector<int4>& t, size_t first, size_t end) {
+  const size_t q = (end - first) / 8;
+  if (q == 0) return;
+  const std::vector<int4> row(t.begin() + first, t.begin() + first + 8 * q);
+  for (size_t b = 0; b < 8 * q; ++b) t[first + b] = row[(b % 8) * q + b / 8];
+}
 
 Layout layout_of(const pmace_params& p) {
   Layout L;
@@ -244,6 +286,9 @@ Layout layout_of(const pmace_params& p) {
   L.dr = o;      o = align_up(o + (sp ? np2 * 8 : 0));
   L.qtiles = o;  o = align_up(o + (sp ? split_tiles(p) * 16 : 0));
   L.qlist = o;   o = align_up(o + (sp ? split_list(p) * 4 : 0));
+  const bool rs = rowspec_allowed(p);
+  L.citems = o;  o = align_up(o + (rs ? cr_items(p) * 16 : 0));
+  L.clist = o;   o = align_up(o + (rs ? cr_list(p) * 16 : 0));
   L.total = o;
   return L;
 }
@@ -266,7 +311,7 @@ pmace_status enqueue_iteration(pmace_ctx* c, hipStream_t st) {
   if (c->h.split)
     PM_HIP(pmace::launch_split_iteration(c->h, 0, st));
   else if (np_large(c->prm.np))
-    PM_HIP(pmace::launch_large_iteration(c->h, nullptr, c->chunk_tiles.data(), st));
+    PM_HIP(pmace::launch_large_iteration(c->h, nullptr, c->chunk_tiles.data(), c->chunk_rows.data(), st));
   else
     PM_HIP(pmace::launch_small_iteration(c->prm.np, c->h, c->ngitems, st));
   return PMACE_OK;
@@ -425,12 +470,15 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
         for (int tc = cc / pmace::QT_C; tc <= (cc + M - 1) / pmace::QT_C && tc < qc; ++tc)
           per_tile[(size_t)tr * qc + tc].push_back(j);
     }
-    for (int tr = 0; tr < qr; ++tr)
+    for (int tr = 0; tr < qr; ++tr) {
+      const size_t row0 = qtiles.size();
       for (int tc = 0; tc < qc; ++tc) {
         const auto& l = per_tile[(size_t)tr * qc + tc];
         qtiles.push_back(make_int4((int)qlist.size(), (int)l.size(), tr * pmace::QT_R, tc * pmace::QT_C));
         qlist.insert(qlist.end(), l.begin(), l.end());
       }
+      xcd_runs(qtiles, row0, qtiles.size());
+    }
     if (qtiles.size() > split_tiles(p) || qlist.size() > split_list(p)) return PMACE_EDEVICE;
   }
 
@@ -460,7 +508,12 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
             per_tile[(size_t)tr * tiles_c + tc].push_back(j);
       }
       chunk_tiles[g] = make_int2((int)gitems.size(), 0);
+      size_t row0 = tiles.size();
       for (size_t t = 0; t < per_tile.size(); ++t) {
+        if (t % tiles_c == 0) {
+          if (np_large(np)) xcd_runs(tiles, row0, tiles.size());
+          row0 = tiles.size();
+        }
         if (per_tile[t].empty()) continue;
         const int tr = (int)(t / tiles_c), tc = (int)(t % tiles_c);
         gitems.push_back(make_int2(0, (int)tiles.size()));
@@ -468,10 +521,50 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
                                   tc * pmace::GT_C));
         list.insert(list.end(), per_tile[t].begin(), per_tile[t].end());
       }
+      if (np_large(np)) xcd_runs(tiles, row0, tiles.size());
       chunk_tiles[g].y = (int)gitems.size() - chunk_tiles[g].x;
     }
   }
   if (tiles.size() > max_tiles(p) || list.size() > max_list(p)) return PMACE_EDEVICE;
+
+  // Row-spectrum states: per chunk, one item per object row its patches cover
+  // and CR_W-wide segment of that row, listing the chunk's positions whose
+  // patch covers the row and meets the segment, in ascending j.
+  const bool rowspec = rowspec_allowed(p) && !has_zero;
+  std::vector<int4> citems, clist;
+  std::vector<int2> chunk_rows(nch, make_int2(0, 0));
+  if (rowspec) {
+    const int nseg = cr_segments(p);
+    std::vector<std::vector<int4>> per_row;
+    for (int g = 0; g < nch; ++g) {
+      const int ja = g * chunk, jb = std::min(J, ja + chunk);
+      int lo = n1, hi = 0;
+      for (int j = ja; j < jb; ++j) {
+        lo = std::min(lo, pos[2 * j]);
+        hi = std::max(hi, pos[2 * j] + np);
+      }
+      per_row.assign((size_t)(hi - lo) * nseg, {});
+      for (int j = ja; j < jb; ++j) {
+        const int r = pos[2 * j], cc = pos[2 * j + 1];
+        for (int sg = cc / pmace::CR_W; sg <= (cc + np - 1) / pmace::CR_W; ++sg)
+          for (int rr = 0; rr < np; ++rr)
+            per_row[(size_t)(r + rr - lo) * nseg + sg].push_back(make_int4(j, rr, cc, 0));
+      }
+      chunk_rows[g] = make_int2((int)citems.size(), 0);
+      for (size_t t = 0; t < per_row.size(); ++t) {
+        if (per_row[t].empty()) continue;
+        // by patch column, then j: the entries covering a run of pixels are
+        // then consecutive (the consensus sums each pixel in this order)
+        std::stable_sort(per_row[t].begin(), per_row[t].end(),
+                         [](const int4& a, const int4& b) { return a.z < b.z; });
+        citems.push_back(make_int4((int)clist.size(), (int)per_row[t].size(), lo + (int)(t / nseg),
+                                   (int)(t % nseg) * pmace::CR_W));
+        clist.insert(clist.end(), per_row[t].begin(), per_row[t].end());
+      }
+      chunk_rows[g].y = (int)citems.size() - chunk_rows[g].x;
+    }
+    if (citems.size() > cr_items(p) || clist.size() > cr_list(p)) return PMACE_EDEVICE;
+  }
   std::vector<int2> items(J);
   for (int j = 0; j < J; ++j) items[j] = make_int2(0, j);
   const int nred = num_red(p);
@@ -523,6 +616,9 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   h.qrows = split_rows(p);
   h.qcols = split_cols(p);
   h.nqt = (int)qtiles.size();
+  h.rowspec = rowspec ? 1 : 0;
+  h.citems = reinterpret_cast<int4*>(base + L.citems);
+  h.clist = reinterpret_cast<int4*>(base + L.clist);
   h.xref = nullptr;
   h.mask = nullptr;
   h.n1 = n1;
@@ -562,6 +658,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   c->ritems = reinterpret_cast<int2*>(base + L.ritems);
   c->ngitems = (int)gitems.size();
   c->chunk_tiles = chunk_tiles;
+  c->chunk_rows = chunk_rows;
 
   const int zero = 0;
   std::vector<float> tw(512);
@@ -594,6 +691,9 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
         hipMemcpyAsync(h.qtiles, qtiles.data(), qtiles.size() * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
         (!qlist.empty() &&
          hipMemcpyAsync(h.qlist, qlist.data(), qlist.size() * 4, hipMemcpyHostToDevice, st) != hipSuccess))) ||
+      (rowspec && !citems.empty() &&
+       (hipMemcpyAsync(h.citems, citems.data(), citems.size() * 16, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(h.clist, clist.data(), clist.size() * 16, hipMemcpyHostToDevice, st) != hipSuccess)) ||
       hipMemsetAsync(h.status, 0, 4, st) != hipSuccess ||
       hipMemcpyAsync(c->dev, &c->h, sizeof(Recon), hipMemcpyHostToDevice, st) != hipSuccess)
     return fail(PMACE_EDEVICE);
@@ -738,6 +838,7 @@ pmace_status pmace_sync(pmace_ctx* c) {
 int32_t pmace_agent_kind(const pmace_ctx* c) {
   if (!c) return -1;
   if (c->h.split) return PMACE_AGENT_SPLIT;
+  if (c->h.rowspec) return PMACE_AGENT_ROWSPEC;
   return np_large(c->prm.np) ? PMACE_AGENT_THREE_PASS : PMACE_AGENT_WHOLE_PATCH;
 }
 
@@ -841,7 +942,7 @@ pmace_status enqueue_batch_iteration(pmace_batch* b, hipStream_t st, bool lanes,
     if (c->h.split)
       PM_HIP(pmace::launch_split_iteration(c->h, 1, ls));
     else
-      PM_HIP(pmace::launch_large_iteration(c->h, b->recs + i, c->chunk_tiles.data(), ls));
+      PM_HIP(pmace::launch_large_iteration(c->h, b->recs + i, c->chunk_tiles.data(), c->chunk_rows.data(), ls));
   }
   if (forked)
     for (int l = 0; l < 4; ++l) {

@@ -64,6 +64,17 @@ constexpr int RED_T = 256, RED_PX = 4096;
 #endif
 constexpr int QT_R = 8, QT_C = 32, QT_K = PMACE_QT_K, QT_THREADS = QT_R * QT_C * QT_K;
 static_assert(QT_K >= 1 && QT_K <= 4, "split consensus: 1 to 4 threads per pixel");
+// Consensus of row-spectrum states: CR_T threads per workgroup, one object
+// row segment of CR_W pixels each (CR_W >= 256, so a patch row meets at most
+// two segments).
+#ifndef PMACE_CR_T
+#define PMACE_CR_T 1024
+#endif
+#ifndef PMACE_CR_W
+#define PMACE_CR_W 1024
+#endif
+constexpr int CR_T = PMACE_CR_T, CR_W = PMACE_CR_W;
+static_assert(CR_T % 64 == 0 && CR_T <= 1024 && CR_W % CR_T == 0 && CR_W >= 256, "row consensus shape");
 
 // Device-resident description of one reconstruction.  It lives in the
 // reconstruction's workspace; batched launches read an array of them.
@@ -128,6 +139,13 @@ struct Recon {
   int qrows, qcols;     // base tiles cover rows [0, qrows) and columns [0, qcols)
   int nqt;              // number of base tiles
   int ppw;              // Np <= 128: patches per workgroup of the whole-patch agent
+  // Row-spectrum states (PMACE, Np > 128, a probe without exact zeros): t holds
+  // H_j = F_r(d t_j)/Np, the unnormalised DFT of every row of the probe-weighted
+  // state over Np, each row in natural frequency order.  The column pass then
+  // writes the new state directly, and the consensus inverts the rows.
+  int rowspec;
+  int4* citems;         // per (chunk, object row, segment): (list start, count, row, first column)
+  int4* clist;          // per entry: (j, row of P_j on that object row, patch column, 0), ascending j
 };
 
 // Kernel launchers (stream-ordered; return the hipError_t of the launches).
@@ -147,8 +165,9 @@ hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int 
 // tile count) of chunk g (host array); the descriptor h passed by value.
 // batch_rec non-null: run as a batch member (its kernels honour the stop
 // flag).
+// h.rowspec: chunk_rows[g] = (first row item, count) of chunk g (host array).
 hipError_t launch_large_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
-                                  hipStream_t st);
+                                  const int2* chunk_rows, hipStream_t st);
 hipError_t launch_get_state(const Recon& h, const Recon* rec, float2* v, hipStream_t st);
 hipError_t launch_set_state(const Recon& h, const Recon* rec, const float2* v,
                             const int2* chunk_tiles, hipStream_t st);

@@ -40,7 +40,9 @@
 
 namespace pmace {
 
-constexpr int kPMACE = 0, kSharpPlus = 1;
+// kRowSpec: PMACE on the Np > 128 passes with every state kept as the row
+// spectrum of its probe-weighted form (see agent_rows_body).
+constexpr int kPMACE = 0, kSharpPlus = 1, kRowSpec = 2;
 
 // Fourier-domain prox of eq. (9): U = W * (a + ys / |W|), 0 where W == 0.
 __device__ __forceinline__ float2 fourier_prox(float2 W, float ysv, float a) {
@@ -64,7 +66,7 @@ __device__ __forceinline__ float2 state_spectrum(float2 W, float ysv, float sb, 
 // SHARP+ the magnitude projection (a = 0).
 template <int METHOD>
 __device__ __forceinline__ float2 spectrum_step(float2 W, float ysv, const Recon& g) {
-  if constexpr (METHOD == kPMACE) return state_spectrum(W, ysv, g.sb, g.s2r);
+  if constexpr (METHOD != kSharpPlus) return state_spectrum(W, ysv, g.sb, g.s2r);
   else return fourier_prox(W, ysv, 0.f);
 }
 
@@ -422,7 +424,7 @@ __device__ __forceinline__ void agent_rows_body(const Recon& g, const int j0) {
   // PMACE: the table is written to LDS once the loads below are issued;
   // SHARP+ loads it first (each measured the faster for its method)
   TwiddleFetch<NP, RBn * A> twf;
-  if constexpr (METHOD == kPMACE) twf.fetch(g.twn, tid);
+  if constexpr (METHOD != kSharpPlus) twf.fetch(g.twn, tid);
   else load_twiddles<NP>(tw, g.twn, tid, RBn * A);
   const int jl = blockIdx.x / (NP / RBn), rb = blockIdx.x % (NP / RBn);
   const int j = j0 + jl;
@@ -431,14 +433,37 @@ __device__ __forceinline__ void agent_rows_body(const Recon& g, const int j0) {
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   const float2* trow = g.t + (size_t)j * NP * NP + (size_t)r * NP;
   float2 x[B];
+  if constexpr (METHOD == kRowSpec) {
+    // The state is kept as H = F_r(s)/Np (its row spectrum, natural order),
+    // so the frame's row spectrum is Np H + F_r(2 rho d P_j xbar): only the
+    // window term is transformed here.  H is fetched first, in the order the
+    // transform leaves its output, so its latency hides behind the transform.
+    float2 h[B];
 #pragma unroll
-  for (int nb = 0; nb < B; ++nb) {
-    const int c = p + A * nb;
-    x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], g.two_rho);
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) h[m * A + ka] = trow[p + A * m + B * ka];
+#pragma unroll
+    for (int nb = 0; nb < B; ++nb) {
+      const int c = p + A * nb;
+      x[nb] = cscale(cmul(g.d[r * NP + c], xrow[c]), g.two_rho);
+    }
+    twf.store(tw, tid);
+    __syncthreads();
+    row_fwd<NP>(x, tile + rl * S, p, tw);
+    constexpr float fnp = (float)NP;
+#pragma unroll
+    for (int k = 0; k < B; ++k) x[k] = make_float2(fmaf(fnp, h[k].x, x[k].x), fmaf(fnp, h[k].y, x[k].y));
+  } else {
+#pragma unroll
+    for (int nb = 0; nb < B; ++nb) {
+      const int c = p + A * nb;
+      x[nb] = agent_input<METHOD>(trow[c], xrow[c], g.d[r * NP + c], g.two_rho);
+    }
+    if constexpr (METHOD == kPMACE) twf.store(tw, tid);
+    __syncthreads();
+    row_fwd<NP>(x, tile + rl * S, p, tw);
   }
-  if constexpr (METHOD == kPMACE) twf.store(tw, tid);
-  __syncthreads();
-  row_fwd<NP>(x, tile + rl * S, p, tw);
   float2* out = g.stage + ((size_t)jl * NP + r) * NP;
 #pragma unroll
   for (int m = 0; m < M; ++m)
@@ -453,10 +478,10 @@ __global__ void __launch_bounds__(row_threads<NP>()) agent_rows(const Recon g, i
 
 // Batch members: the member's descriptor by value (global, not flat, loads),
 // its stop flag read through it.
-template <int NP>
+template <int NP, int METHOD>
 __global__ void __launch_bounds__(row_threads<NP>()) agent_rows_batch(const Recon g, int j0) {
   if (*g.done) return;
-  agent_rows_body<NP, kPMACE>(g, j0);
+  agent_rows_body<NP, METHOD>(g, j0);
 }
 
 template <int NP, int METHOD>
@@ -468,7 +493,7 @@ __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
   // PMACE: the table is written to LDS once the loads below are issued;
   // SHARP+ loads it first (each measured the faster for its method)
   TwiddleFetch<NP, CB * A> twf;
-  if constexpr (METHOD == kPMACE) twf.fetch(g.twn, tid);
+  if constexpr (METHOD != kSharpPlus) twf.fetch(g.twn, tid);
   else load_twiddles<NP>(tw, g.twn, tid, CB * A);
   const int jl = blockIdx.x / (NP / CB), cb = blockIdx.x % (NP / CB);
   const int j = j0 + jl;
@@ -485,14 +510,17 @@ __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
   for (int m = 0; m < M; ++m)
 #pragma unroll
     for (int ka = 0; ka < A; ++ka) yv[m * A + ka] = yc[(size_t)(q + A * m + B * ka) * NP];
-  if constexpr (METHOD == kPMACE) twf.store(tw, tid);
+  if constexpr (METHOD != kSharpPlus) twf.store(tw, tid);
   __syncthreads();
   col_fwd<NP>(x, tile, CB, c, q, tw);
 #pragma unroll
   for (int k = 0; k < B; ++k) x[k] = spectrum_step<METHOD>(x[k], yv[k], g);
   col_inv<NP>(x, tile, CB, c, q, tw);
+  // kRowSpec: the column inverse of the state spectrum is F_r(s_new)/Np, the
+  // new state itself; the inverse row pass is left to the consensus
+  float2* op = METHOD == kRowSpec ? g.t + (size_t)j * NP * NP + col : sp;
 #pragma unroll
-  for (int nb = 0; nb < B; ++nb) sp[(size_t)(q + A * nb) * NP] = x[nb];
+  for (int nb = 0; nb < B; ++nb) op[(size_t)(q + A * nb) * NP] = x[nb];
 }
 
 template <int NP, int METHOD>
@@ -500,10 +528,10 @@ __global__ void __launch_bounds__(col_threads<NP>()) agent_cols(const Recon g, i
   agent_cols_body<NP, METHOD>(g, j0);
 }
 
-template <int NP>
+template <int NP, int METHOD>
 __global__ void __launch_bounds__(col_threads<NP>()) agent_cols_batch(const Recon g, int j0) {
   if (*g.done) return;
-  agent_cols_body<NP, kPMACE>(g, j0);
+  agent_cols_body<NP, METHOD>(g, j0);
 }
 
 template <int NP, int METHOD>
@@ -707,6 +735,105 @@ __global__ void __launch_bounds__(GT_THREADS) consensus_gather_batch(const Recon
   const Recon& g = recs[it.x];
   if (*g.done) return;
   consensus_gather_body<NP, FUSE, kPMACE>(g, it.y, jbase);
+}
+
+// -------------------------------------------------------------------------
+// Consensus for states kept as row spectra (kRowSpec): S = sum_j P_j^t
+// (|d|^kappa / d) s_j with s_j = F_r^*(H_j) (the stored H_j = F_r(s_j)/Np), so
+// the inverse row transforms run here instead of in a pass of their own.  A
+// row of a patch lands on one object row: a workgroup owns one object row R
+// (a CR_W-pixel segment of it) and walks its list of the chunk's positions
+// whose patch covers R and meets the segment, with entries (j, row of P_j on
+// R, patch column), sorted by patch column and then j.  Each round
+// inverse-transforms cr_rows<NP>() such patch rows in LDS and weights them;
+// every thread then adds, in list order, the ones that cover its pixel of R.
+// Every pixel's sum thus runs in one fixed order (chunks in turn, then the
+// list), with no atomics: bitwise reproducible.  CHECK: batch member, skip
+// when stopped.
+// -------------------------------------------------------------------------
+// patch rows per round: CR_T threads' worth, at most 64 (LDS)
+template <int NP> constexpr int cr_rows() { return CR_T / Geo<NP>::A < 64 ? CR_T / Geo<NP>::A : 64; }
+template <int NP> constexpr int cr_threads() { return cr_rows<NP>() * Geo<NP>::A; }
+template <int NP> constexpr int cr_pitch() { return row_cap<NP>() > NP ? row_cap<NP>() : NP; }
+
+template <int NP, bool CHECK>
+__global__ void __launch_bounds__(cr_threads<NP>()) consensus_rows(const Recon g, int first_item) {
+  if constexpr (CHECK) {
+    if (*g.done) return;
+  }
+  constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = cr_pitch<NP>(), RN = cr_rows<NP>();
+  constexpr int NT = cr_threads<NP>(), PX = CR_W / NT;
+  static_assert(CR_W % NT == 0 && NT % 64 == 0, "row segment over the workgroup");
+  __shared__ float2 rows[RN * S];
+  __shared__ float2 tw[NP];
+  __shared__ int pcol[RN];
+  const int tid = threadIdx.x, rl = tid / A, p = tid % A;
+  const int4 it = g.citems[first_item + blockIdx.x];  // (list start, count, object row, first column)
+  TwiddleFetch<NP, NT> twf;
+  twf.fetch(g.twn, tid);
+  // this row group's entry of a round, its patch row (in the order the
+  // inverse transform takes it) and the weights of that row
+  int4 en;
+  float2 x[B], w[B];
+  auto fetch = [&](int e) {
+    en = e < it.y ? g.clist[it.x + e] : make_int4(0, 0, 0, 0);
+    const float2* hr = g.t + (size_t)en.x * NP * NP + (size_t)en.y * NP;
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+#pragma unroll
+      for (int ka = 0; ka < A; ++ka) x[m * A + ka] = hr[p + A * m + B * ka];
+#pragma unroll
+    for (int nb = 0; nb < B; ++nb) w[nb] = g.gw[en.y * NP + p + A * nb];
+  };
+  fetch(rl);
+  twf.store(tw, tid);
+  float ax[PX], ay[PX];
+#pragma unroll
+  for (int k = 0; k < PX; ++k) ax[k] = ay[k] = 0.f;
+  const int lane0 = __builtin_amdgcn_readfirstlane(tid & ~63);  // first pixel (relative) of this wave
+  const int w0 = __builtin_amdgcn_readfirstlane(it.w);
+  for (int e0 = 0; e0 < it.y; e0 += RN) {
+    const int ne = it.y - e0 < RN ? it.y - e0 : RN;
+    __syncthreads();  // the last round's sums are done with rows[]; tw is written
+    row_inv<NP>(x, rows + rl * S, p, tw);
+    wave_sync();
+    if (p == 0) pcol[rl] = en.z;
+#pragma unroll
+    for (int nb = 0; nb < B; ++nb) rows[rl * S + p + A * nb] = cmul(w[nb], x[nb]);
+    __syncthreads();
+    // Lane e of every wave holds entry e's patch column (past the round's
+    // entries: above any column).  The list is sorted by patch column, so the
+    // entries covering some of a wave's 64 pixels [cw, cw + 64) are the lanes
+    // [lo, hi) with cw - NP < pc <= cw + 63, counted by two ballots; each
+    // pixel adds the ones that cover it, in list order.
+    const int lane = tid & 63;
+    const int pv = lane < ne ? pcol[lane] : 0x7fffffff;
+#pragma unroll
+    for (int k = 0; k < PX; ++k) {
+      const int cw = w0 + lane0 + k * NT;
+      const int lo = __popcll(__ballot(pv <= cw - NP));
+      const int hi = __popcll(__ballot(pv <= cw + 63));
+      const int C = cw + lane;
+      for (int e = lo; e < hi; ++e) {
+        const unsigned cc = (unsigned)(C - __builtin_amdgcn_readlane(pv, e));
+        if (cc < (unsigned)NP) {
+          const float2 v = rows[e * S + cc];
+          ax[k] += v.x;
+          ay[k] += v.y;
+        }
+      }
+    }
+    if (e0 + RN < it.y) fetch(e0 + RN + rl);
+  }
+  float2* nrow = g.num + (size_t)it.z * g.n2;
+#pragma unroll
+  for (int k = 0; k < PX; ++k) {
+    const int C = it.w + tid + k * NT;
+    if (C < g.n2) {
+      const float2 o = nrow[C];
+      nrow[C] = make_float2(o.x + ax[k], o.y + ay[k]);
+    }
+  }
 }
 
 // a9 for Np > 128: consensus image, reconstruction recurrence, accumulator reset.
@@ -1118,7 +1245,9 @@ __global__ void init_images_k(const Recon* __restrict__ rec, const float2* x0) {
   g.num[i] = make_float2(0.f, 0.f);
 }
 
-__global__ void get_state_k(const Recon* __restrict__ rec, float2* v) {
+// src: the probe-weighted states (t itself, or their row-spectrum form
+// already transformed back into v, which is then rewritten in place).
+__global__ void get_state_k(const Recon* __restrict__ rec, const float2* src, float2* v) {
   const Recon& g = *rec;
   const long long per = (long long)g.np * g.np;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1131,9 +1260,9 @@ __global__ void get_state_k(const Recon* __restrict__ rec, float2* v) {
   // PMACE: v = t + 2 rho P_j xbar with t = d^{-1} s (dinv = d^{-1}/Np^2; s where
   // d == 0);  SHARP+: s = t + 2 beta d P_j xbar
   if (g.method == kSharpPlus) {
-    v[i] = mann_v(g.t[i], cmul(g.d[rem], xb), g.two_rho);
+    v[i] = mann_v(src[i], cmul(g.d[rem], xb), g.two_rho);
   } else {
-    const float2 di = g.dinv[rem], s = g.t[i];
+    const float2 di = g.dinv[rem], s = src[i];
     const float2 t = (di.x != 0.f || di.y != 0.f) ? cscale(cmul(di, s), g.np2f) : s;
     v[i] = mann_v(t, xb, g.two_rho);
   }
@@ -1662,15 +1791,32 @@ hipError_t launch_small_batch(int np, const Recon* recs, const int2* items, int 
 
 template <int NP>
 static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
-                            hipStream_t st) {
+                            const int2* chunk_rows, hipStream_t st) {
   constexpr int RT = row_threads<NP>(), CT = col_threads<NP>();
   for (int j0 = 0, g = 0; j0 < h.J; j0 += h.chunk, ++g) {
     const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
     const dim3 rgrid(cnt * (NP / rb_of<NP>())), cgrid(cnt * (NP / CB));
     const int2 ct = chunk_tiles[g];
+    if (h.rowspec) {
+      // row-spectrum states: rows (window term), columns (new state), then the
+      // consensus with the inverse row transforms
+      const int2 cr = chunk_rows[g];
+      if (batch_rec) {
+        hipLaunchKernelGGL((agent_rows_batch<NP, kRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
+        hipLaunchKernelGGL((agent_cols_batch<NP, kRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
+        if (cr.y > 0)
+          hipLaunchKernelGGL((consensus_rows<NP, true>), dim3(cr.y), dim3(cr_threads<NP>()), 0, st, h, cr.x);
+      } else {
+        hipLaunchKernelGGL((agent_rows<NP, kRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
+        hipLaunchKernelGGL((agent_cols<NP, kRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
+        if (cr.y > 0)
+          hipLaunchKernelGGL((consensus_rows<NP, false>), dim3(cr.y), dim3(cr_threads<NP>()), 0, st, h, cr.x);
+      }
+      continue;
+    }
     if (batch_rec) {
-      hipLaunchKernelGGL(agent_rows_batch<NP>, rgrid, dim3(RT), 0, st, h, j0);
-      hipLaunchKernelGGL(agent_cols_batch<NP>, cgrid, dim3(CT), 0, st, h, j0);
+      hipLaunchKernelGGL((agent_rows_batch<NP, kPMACE>), rgrid, dim3(RT), 0, st, h, j0);
+      hipLaunchKernelGGL((agent_cols_batch<NP, kPMACE>), cgrid, dim3(CT), 0, st, h, j0);
       hipLaunchKernelGGL(agent_rowsinv_batch<NP>, rgrid, dim3(RT), 0, st, h, j0);
     } else if (h.method == kSharpPlus) {
       hipLaunchKernelGGL((agent_rows<NP, kSharpPlus>), rgrid, dim3(RT), 0, st, h, j0);
@@ -1701,11 +1847,11 @@ static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* 
 }
 
 hipError_t launch_large_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
-                                  hipStream_t st) {
+                                  const int2* chunk_rows, hipStream_t st) {
   switch (h.np) {
-    case 160: large_iteration<160>(h, batch_rec, chunk_tiles, st); break;
-    case 192: large_iteration<192>(h, batch_rec, chunk_tiles, st); break;
-    case 256: large_iteration<256>(h, batch_rec, chunk_tiles, st); break;
+    case 160: large_iteration<160>(h, batch_rec, chunk_tiles, chunk_rows, st); break;
+    case 192: large_iteration<192>(h, batch_rec, chunk_tiles, chunk_rows, st); break;
+    case 256: large_iteration<256>(h, batch_rec, chunk_tiles, chunk_rows, st); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1783,6 +1929,34 @@ static hipError_t launch_fit_split(const Recon& h, int check_done, hipStream_t s
   return hipGetLastError();
 }
 
+// Row DFTs of `count` Np x Np patches (in may equal out: each row is read
+// whole before it is written): out = scale F_r(in), or scale F_r^*(in).
+template <int NP>
+static void row_transform(int count, const float2* in, float2* out, bool inverse, float scale,
+                          hipStream_t st) {
+  const dim3 rgrid(count * (NP / rb_of<NP>()));
+  if (inverse)
+    hipLaunchKernelGGL((fft_rows<NP, true>), rgrid, dim3(row_threads<NP>()), 0, st, in, out, scale);
+  else
+    hipLaunchKernelGGL((fft_rows<NP, false>), rgrid, dim3(row_threads<NP>()), 0, st, in, out, scale);
+}
+
+static hipError_t launch_row_transform(int np, int count, const float2* in, float2* out, bool inverse,
+                                       float scale, hipStream_t st) {
+  switch (np) {
+    case 160: row_transform<160>(count, in, out, inverse, scale, st); break;
+    case 192: row_transform<192>(count, in, out, inverse, scale, st); break;
+    case 256: row_transform<256>(count, in, out, inverse, scale, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Row-spectrum states from the probe-weighted ones in t: H = F_r(s)/Np.
+static hipError_t states_to_rowspec(const Recon& h, hipStream_t st) {
+  return launch_row_transform(h.np, h.J, h.t, h.t, false, 1.f / (float)h.np, st);
+}
+
 hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float scale,
                        int centered, const float2* x0, const int2* chunk_tiles, hipStream_t st) {
   const long long total = (long long)h.J * h.np * h.np;
@@ -1809,16 +1983,26 @@ hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float s
       if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(sold_from_num, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec);
+    // S above was summed from the probe-weighted states themselves
+    if (h.rowspec) return states_to_rowspec(h, st);
   }
   return hipGetLastError();
 }
 
 hipError_t launch_get_state(const Recon& h, const Recon* rec, float2* v, hipStream_t st) {
   const long long total = (long long)h.J * h.np * h.np;
-  if (h.split)
+  if (h.split) {
     hipLaunchKernelGGL(get_state_split_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, v);
-  else
-    hipLaunchKernelGGL(get_state_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec, v);
+  } else if (h.rowspec) {
+    // s = F_r^*(H) into v, then v from s in place
+    const hipError_t e = launch_row_transform(h.np, h.J, h.t, v, true, 1.f, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(get_state_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec,
+                       static_cast<const float2*>(v), v);
+  } else {
+    hipLaunchKernelGGL(get_state_k, dim3(blocks_for(total, 256)), dim3(256), 0, st, rec,
+                       static_cast<const float2*>(h.t), v);
+  }
   return hipGetLastError();
 }
 
@@ -1843,6 +2027,7 @@ hipError_t launch_set_state(const Recon& h, const Recon* rec, const float2* v,
     hipLaunchKernelGGL(sharp_image_k, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec);
     hipLaunchKernelGGL(sharp_state_k, dim3(blocks_for(per * h.J, 256)), dim3(256), 0, st, rec);
   }
+  if (h.rowspec) return states_to_rowspec(h, st);
   return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ PMACE_EDIVERGED = 6
 PMACE_CENTERED_DC = 0x1
 PMACE_STAGED_AGENT = 0x2
 PMACE_SPLIT_AGENT = 0x4
+PMACE_ROWSPEC_AGENT = 0x8
 PMACE_METHOD_PMACE = 0
 PMACE_METHOD_SHARP_PLUS = 1
 PMACE_STOP_NRMSE = 0
@@ -449,10 +450,10 @@ class Reconstruction:
 
     @property
     def agent(self) -> str:
-        """'whole patch', 'three-pass' or 'split' (coset blocks): the agent this
-        reconstruction runs."""
+        """'whole patch', 'three-pass', 'split' (coset blocks) or 'row-spectrum'
+        (states kept as row DFTs): the agent this reconstruction runs."""
         k = load_library().pmace_agent_kind(self.ctx)
-        return {0: "whole patch", 1: "three-pass", 2: "split"}[k]
+        return {0: "whole patch", 1: "three-pass", 2: "split", 3: "row-spectrum"}[k]
 
     def reconstruct(self, out=None):
         torch = _torch()

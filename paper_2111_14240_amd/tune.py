@@ -17,6 +17,8 @@ csrc/pmace_internal.hpp) plus one run-time default:
                          workgroup of the whole-patch agent for Np = 32, 48, 64
     PMACE_SPLIT_SIDES    (run-time choice, recorded for the build) which of Np = 128, 192, 256
                          default to the split (coset-block) agent: bit 0, 1, 2
+    PMACE_ROWSPEC_SIDES  (likewise) which of Np = 160, 192, 256 default to the row-spectrum
+                         agent: bit 0, 1, 2
 
 Search (coordinate-wise, every candidate measured on the device):
   1. gather shape (GT_K x unroll x tile width) with the default row/column blocks, scored by
@@ -27,8 +29,9 @@ Search (coordinate-wise, every candidate measured on the device):
   4. the chunk size, at run time, with the combined choice;
   5. patches per workgroup of the whole-patch agent (Np = 32, 48, 64), at run
      time, each on a workload of its size, with the built library;
-  6. the agent of each side that has two (Np = 128: whole patch or split;
-     192 and 256: three-pass or split), at run time, with the built library.
+  6. the agent of each side that has several (Np = 128: whole patch or split;
+     160: three-pass or row-spectrum; 192 and 256: three-pass, split or
+     row-spectrum), at run time, with the built library.
 Each candidate library is built into a scratch directory and timed in a
 process of its own.  The choice is written to tuned.json beside this file;
 build.py passes it to hipcc as -D flags.
@@ -38,7 +41,7 @@ build.py passes it to hipcc as -D flags.
     python -m paper_2111_14240_amd.tune pick DIR       # write tuned.json from the times
     python -m paper_2111_14240_amd.tune chunk          # time chunk sizes with the built library
     python -m paper_2111_14240_amd.tune ppw            # time patches per workgroup (built library)
-    python -m paper_2111_14240_amd.tune agent          # time the two agents per side (built library)
+    python -m paper_2111_14240_amd.tune agent          # time the agents of each side (built library)
 """
 from __future__ import annotations
 
@@ -59,13 +62,16 @@ GATHER_SPACE = [(k, u, c) for k in (1, 2, 4) for u in (8, 16) for c in (64, 32)]
 BLOCK_SPACE = [(rb, cb) for rb in (8, 16, 32) for cb in (16, 32)]
 GEO_SPACE = [(32, 2), (64, 4), (128, 4)]   # the non-default splits
 PPW_SPACE = {32: (1, 2, 4, 8), 48: (1, 2, 4), 64: (1, 2)}   # patches per workgroup per side
-AGENT_SIDES = {128: "np128", 192: "np192", 256: "np256"}
+# Agents timed per side ("other": the whole-patch agent for 128, three-pass above).
+AGENT_SIDES = {128: ("np128", ("other", "split")), 160: ("np160", ("other", "rowspec")),
+               192: ("np192", ("other", "split", "rowspec")), 256: ("np256", ("other", "split", "rowspec"))}
 CHUNKS = (64, 128, 192, 256, 400)
 
 # Tuning workloads: (object side, probe side, scan side, step, peak photons).
 WORKLOADS = {"np128": (512, 128, 15, 24, 1e5), "np256": (1024, 256, 40, 20, 1e6),
              "np32": (256, 32, 14, 16, 1e5), "np64": (512, 64, 20, 22, 1e5),
-             "np48": (384, 48, 20, 16, 1e5), "np192": (1024, 192, 40, 20, 1e6)}
+             "np48": (384, 48, 20, 16, 1e5), "np192": (1024, 192, 40, 20, 1e6),
+             "np160": (1024, 160, 40, 20, 1e6)}
 
 
 def candidates():
@@ -265,35 +271,45 @@ def cmd_ppw(args):
     print(json.dumps({**d, **res}))
 
 
-def _split_sides(res):
-    """PMACE_SPLIT_SIDES from the agent times: bit i set where side i (128, 192,
-    256) ran faster with the split agent than with its other agent."""
-    bits = 0
-    for i, (np_, wl) in enumerate(sorted(AGENT_SIDES.items())):
-        if res[f"{wl}_split"] < res[f"{wl}_other"]:
-            bits |= 1 << i
-    return bits
+SPLIT_BIT = {128: 0, 192: 1, 256: 2}     # PMACE_SPLIT_SIDES
+ROWSPEC_BIT = {160: 0, 192: 1, 256: 2}   # PMACE_ROWSPEC_SIDES
+
+
+def _agent_sides(res):
+    """(PMACE_SPLIT_SIDES, PMACE_ROWSPEC_SIDES) from the agent times: each side
+    defaults to its fastest agent (ties keep the earlier one in AGENT_SIDES)."""
+    split = rowspec = 0
+    for np_, (wl, names) in sorted(AGENT_SIDES.items()):
+        best = min(names, key=lambda n: res[f"{wl}_{n}"])
+        if best == "split":
+            split |= 1 << SPLIT_BIT[np_]
+        elif best == "rowspec":
+            rowspec |= 1 << ROWSPEC_BIT[np_]
+    return split, rowspec
 
 
 def cmd_agent(args):
-    """Per side with two agents, time each (alternating, best of `rounds`) with
-    the built library and record the faster as that side's default."""
+    """Per side with several agents, time each (alternating, best of `rounds`)
+    with the built library and record the fastest as that side's default."""
     from . import build as B
     from . import pmace
+    flag = {"other": pmace.PMACE_STAGED_AGENT, "split": pmace.PMACE_SPLIT_AGENT,
+            "rowspec": pmace.PMACE_ROWSPEC_AGENT}
     res = {}
-    for np_, wl in sorted(AGENT_SIDES.items()):
+    for np_, (wl, names) in sorted(AGENT_SIDES.items()):
         for _ in range(args.rounds):
-            for name, fl in (("other", pmace.PMACE_STAGED_AGENT), ("split", pmace.PMACE_SPLIT_AGENT)):
-                t = _time_library(B.LIB, [wl], args.iters, flags=fl)[wl]
+            for name in names:
+                t = _time_library(B.LIB, [wl], args.iters, flags=flag[name])[wl]
                 res[f"{wl}_{name}"] = min(res.get(f"{wl}_{name}", float("inf")), t)
-    bits = _split_sides(res)
+    split, rowspec = _agent_sides(res)
     rec = json.load(open(TUNED)) if os.path.exists(TUNED) else {"defines": dict(DEFAULTS)}
     rec["agent_ms"] = res
     if args.write:
-        rec["defines"]["PMACE_SPLIT_SIDES"] = bits
+        rec["defines"]["PMACE_SPLIT_SIDES"] = split
+        rec["defines"]["PMACE_ROWSPEC_SIDES"] = rowspec
         with open(TUNED, "w") as f:
             json.dump(rec, f, indent=1, sort_keys=True)
-    print(json.dumps({"PMACE_SPLIT_SIDES": bits, **res}))
+    print(json.dumps({"PMACE_SPLIT_SIDES": split, "PMACE_ROWSPEC_SIDES": rowspec, **res}))
 
 
 def main(argv=None):

@@ -67,12 +67,14 @@ def test_footprint_formula(lib):
     b = P.pmace_footprint(P.make_params(1024, 1024, 256, 1600, 0.5, chunk=128))
     stage = (124 - 64) * 256 * 256 * 8
     tile_tables = (25 - 13) * 256 * 32 * 24    # fewer chunks, fewer tile slots (at most)
-    assert stage - tile_tables - 4096 <= b - a <= stage + 4096
+    row_items = (25 - 13) * 1024 * 16          # and fewer row items of the row-spectrum consensus
+    assert stage - tile_tables - row_items - 4096 <= b - a <= stage + 4096
 
 
 @pytest.mark.parametrize("kw", [dict(np_=0), dict(num_pos=0), dict(n1=16), dict(alpha=-1.0),
                                 dict(alpha=float("nan")), dict(rho=0.0), dict(rho=1.0),
-                                dict(kappa=-0.5), dict(kappa=float("inf")), dict(flags=8),
+                                dict(kappa=-0.5), dict(kappa=float("inf")), dict(flags=0x10),
+                                dict(flags=0x2 | 0x8), dict(flags=0x4 | 0x8), dict(flags=0x2 | 0x4),
                                 dict(chunk=-1), dict(np_=40)])
 def test_invalid_params_rejected(lib, kw):
     assert _fp(**kw) == 0

@@ -4,7 +4,8 @@ FP64 oracle.
 * a zero start: every spectrum is exactly zero, the zero rule of eq. (9)
   applies everywhere and the state must stay exactly zero;
 * one patch covering the whole object (no overlap: G is the identity on it),
-  one position on the three-pass path, and every position at the same place;
+  one position of 192^2 on each large-side agent, and every position at the
+  same place;
 * a 2048 x 2048 object with 6400 positions of 256 x 256 (a 5.3 GB
   workspace): one iteration on the device, checked on sampled patches whose
   new states and reconstruction the oracle computes from the patches that
@@ -64,7 +65,7 @@ def test_zero_start_stays_zero(P, np_, chunk):
     R.close()
 
 
-def _teacher_forced(P, prob, chunk=0, kappa=1.25, rho=0.5, alpha=0.5, K=2):
+def _teacher_forced(P, prob, chunk=0, kappa=1.25, rho=0.5, alpha=0.5, K=2, flags=0):
     d, z = _f32(prob)
     y = O.amplitudes(z)
     shape = (prob.n1, prob.n2)
@@ -74,7 +75,8 @@ def _teacher_forced(P, prob, chunk=0, kappa=1.25, rho=0.5, alpha=0.5, K=2):
     for _ in range(K):
         st = O.pmace_iterate(st, d, y, prob.pos, shape, alpha, kappa, rho, 1)
         vs.append(st.v)
-    R = P.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, alpha, kappa, rho, chunk=chunk)
+    R = P.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, alpha, kappa, rho, chunk=chunk,
+                         flags=flags)
     worst = 0.0
     for k in range(K):
         R.set_state(vs[k])
@@ -96,10 +98,14 @@ def test_single_patch_covering_the_object(P):
     assert e < TOL
 
 
-def test_single_position_three_pass(P):
+@pytest.mark.parametrize("agent", ["staged", "split", "rowspec"])
+def test_single_position_large_side(P, agent):
+    """One position of 192^2 on each large-side agent (a one-position chunk
+    for the three-pass and row-spectrum agents)."""
     prob = synth.make_problem(300, 192, 1, 1, 1e5, 62)
-    e = _teacher_forced(P, prob, chunk=1)
-    _say("single position, Np 192", e)
+    flags = {"staged": P.PMACE_STAGED_AGENT, "split": P.PMACE_SPLIT_AGENT, "rowspec": P.PMACE_ROWSPEC_AGENT}[agent]
+    e = _teacher_forced(P, prob, chunk=1, flags=flags)
+    _say("single position, Np 192", agent, e)
     assert e < TOL
 
 
@@ -225,11 +231,14 @@ def _sampled_one_pass(P, n1, n2, np_, pos, z_dev, probe, x0, samples, alpha=0.5,
 
 @pytest.mark.slow
 @pytest.mark.parametrize("n1,n2,np_,step,peak,agent", [(1024, 2048, 256, 20, 1e6, "default"),
+                                                      (1024, 2048, 256, 20, 1e6, "staged"),
                                                       (768, 1280, 192, 16, 1e5, "staged"),
                                                       (768, 1280, 192, 16, 1e5, "default")])
 def test_rectangular_at_scale_sampled(P, n1, n2, np_, step, peak, agent):
     """Rectangular objects at full scale on the large-side agents: 1024 x 2048
-    with 39 x 90 positions of 256^2 (three-pass, default chunks), and 768 x 1280
+    with 39 x 90 positions of 256^2 (default chunks; the row-spectrum agent,
+    that side's default, whose consensus splits each object row into two
+    1024-pixel segments, and the three-pass agent), and 768 x 1280
     with 37 x 69 positions of 192^2 on the three-pass agent (chunked) and on
     the split agent (that side's default); intensities simulated on the
     device (eq. (1), eq. (16)), one pass from a smooth start, checked on
@@ -245,6 +254,6 @@ def test_rectangular_at_scale_sampled(P, n1, n2, np_, step, peak, agent):
     x0 = synth.make_object(n1, n2, np.random.default_rng(5)).astype(np.complex64)
     J = len(pos)
     samples = [0, s2 - 1, J // 2 + s2 // 2, J - s2, J - 1, s2 * (s1 // 3) + 1]
-    flags = P.PMACE_STAGED_AGENT if agent == "staged" else 0
+    flags = {"default": 0, "staged": P.PMACE_STAGED_AGENT, "rowspec": P.PMACE_ROWSPEC_AGENT}[agent]
     ev, em = _sampled_one_pass(P, n1, n2, np_, pos, z, probe, x0, samples, flags=flags)
     assert ev < TOL and em < TOL

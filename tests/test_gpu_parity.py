@@ -167,7 +167,7 @@ def teacher_forced(P, R, vs, xs, ks, tol0=None, say=""):
     return worst
 
 
-STAGED, SPLIT = 0x2, 0x4   # PMACE_STAGED_AGENT, PMACE_SPLIT_AGENT
+STAGED, SPLIT, ROWSPEC = 0x2, 0x4, 0x8   # PMACE_STAGED_AGENT, _SPLIT_AGENT, _ROWSPEC_AGENT
 
 SMALL_CASES = {
     # name: (n, np, scan, step, peak, seed, chunk[, flags])
@@ -183,6 +183,10 @@ SMALL_CASES = {
     "np160_ragged_chunks": (360, 160, 3, 80, 1e6, 53, 4),
     "np192_split": (400, 192, 3, 90, 1e5, 54, 0, SPLIT),
     "np192_staged": (400, 192, 3, 90, 1e5, 54, 0, STAGED),
+    # states kept as row spectra, with ragged chunks where the side allows
+    "np256_rowspec_chunks": (400, 256, 3, 60, 1e6, 23, 4, ROWSPEC),
+    "np192_rowspec": (400, 192, 3, 90, 1e5, 54, 0, ROWSPEC),
+    "np160_rowspec_chunks": (360, 160, 3, 80, 1e6, 53, 4, ROWSPEC),
 }
 
 
@@ -217,10 +221,11 @@ def test_init_state_is_patches_of_x0(P, case):
     # the states are held probe-weighted (d v); reading them out multiplies by
     # the FP64-rounded d^{-1}: exact up to a few single-precision roundings.
     # In the coset-block layout each stored value sums four probe-weighted
-    # pixels, so a pixel's error scales with its neighbours' magnitude times
-    # 1/|d| there: bounded against the largest value instead.
+    # pixels, and a row-spectrum value a whole row of them, so a pixel's error
+    # scales with its neighbours' magnitude times 1/|d| there: bounded
+    # against the largest value instead.
     ref = O.extract(x0.astype(np.complex128), prob.pos, np_).astype(np.complex64)
-    if R.agent == "split":
+    if R.agent in ("split", "row-spectrum"):
         assert np.max(np.abs(v - ref)) / np.max(np.abs(ref)) < 2e-5
     else:
         assert np.max(np.abs(v - ref) / np.maximum(np.abs(ref), 1e-30)) < 1e-6
@@ -339,12 +344,12 @@ def test_c2_teacher_forced_steps(P, np_):
     R.close()
 
 
-@pytest.mark.parametrize("flags", [SPLIT, STAGED])
+@pytest.mark.parametrize("flags", [SPLIT, STAGED, ROWSPEC])
 def test_large_side_every_iteration_to_50(P, flags):
     """Np = 256 on a 640^2 object, 144 positions in three chunks of 48:
     teacher-forced at every pass k = 0..49 (k = 0 from the flat start), so
     the near-converged regime of the kept consensus sums is covered; on the
-    coset-block agent and on the three-pass agent."""
+    coset-block, three-pass and row-spectrum agents."""
     prob = synth.make_problem(640, 256, 12, 32, 1e6, 57)
     alpha = 0.5
     K = 50
@@ -355,6 +360,34 @@ def test_large_side_every_iteration_to_50(P, flags):
     worst = teacher_forced(P, R, vs, xs, list(range(K)), tol0=tol0, say=f"np256 flags={flags}")
     _say(f"  worst (k >= 1) = {worst:.2e}")
     R.close()
+
+
+def test_rowspec_row_segments_and_chunks(P):
+    """Row-spectrum states on a 400 x 1280 object with 3 x 12 positions of
+    192^2 crossing column 1024, so the row consensus splits object rows into
+    two segments and patches straddle them; chunks of 8 positions (5 chunks,
+    the last ragged).  Teacher-forced at every pass k = 0..9 (k = 0 from the
+    flat start) and free-running for 10 passes from a smooth start."""
+    prob = synth.make_problem(400, 192, 3, 96, 1e5, 61, n2=1280, scan2=12)
+    assert prob.pos[:, 1].min() < 1024 - 192 and prob.pos[:, 1].max() > 1024
+    alpha = 0.5
+    K = 10
+    vs, xs = oracle_trajectory(prob, alpha, synth.KAPPA, synth.RHO, K)
+    R = make_recon(P, prob, alpha, chunk=8, flags=ROWSPEC)
+    assert R.agent == "row-spectrum"
+    tol0 = flat_start_bound(prob, vs[0], alpha, synth.KAPPA, synth.RHO)
+    teacher_forced(P, R, vs, xs, list(range(K)), tol0=tol0, say="rowspec segments")
+    R.close()
+    x0 = smooth_start(prob)
+    vs, xs = oracle_trajectory(prob, alpha, synth.KAPPA, synth.RHO, K, x0=x0)
+    R2 = P.Reconstruction(prob.n1, prob.n2, prob.probe, prob.pos, prob.z, alpha, synth.KAPPA, synth.RHO,
+                          chunk=8, flags=ROWSPEC, x0=x0.astype(np.complex64))
+    R2.iterate(K)
+    ev = rel(R2.get_state().cpu().numpy(), vs[K])
+    ex = rel(R2.reconstruct().cpu().numpy(), xs[K])
+    _say(f"  free-running {K} passes rel(v)={ev:.2e} rel(xhat)={ex:.2e}")
+    assert ev < TOL and ex < TOL
+    R2.close()
 
 
 def _support_probe(prob, frac=0.8):
@@ -459,7 +492,8 @@ def c3_geometry_problem(np_):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("np_,flags", [(256, 0), (256, SPLIT), (192, 0), (192, STAGED), (160, 0)])
+@pytest.mark.parametrize("np_,flags", [(256, 0), (256, SPLIT), (256, STAGED), (192, 0), (192, STAGED),
+                                       (192, ROWSPEC), (160, 0), (160, ROWSPEC)])
 def test_c3_full_size_steps(P, np_, flags):
     """The full 1024^2 / 1600-position workload (probe 256^2, and the 192^2 and
     160^2 sides bench.py times on the same geometry) in the launch

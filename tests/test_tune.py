@@ -52,13 +52,22 @@ def test_ppw_choices_fit_a_workgroup():
         assert max(ks) * n * a <= 1024, n
 
 
-def test_split_sides_bitmask():
-    res = {"np128_other": 1.0, "np128_split": 1.2, "np192_other": 1.0, "np192_split": 0.9,
-           "np256_other": 1.0, "np256_split": 1.1}
-    assert tune._split_sides(res) == 2
+def test_agent_sides_bitmasks():
+    res = {"np128_other": 1.0, "np128_split": 1.2, "np160_other": 1.0, "np160_rowspec": 1.1,
+           "np192_other": 1.0, "np192_split": 0.9, "np192_rowspec": 0.95,
+           "np256_other": 1.0, "np256_split": 1.1, "np256_rowspec": 1.2}
+    assert tune._agent_sides(res) == (2, 0)
     res["np128_split"] = 0.5
     res["np256_split"] = 0.5
-    assert tune._split_sides(res) == 7
+    assert tune._agent_sides(res) == (7, 0)
+    # the row-spectrum agent wins 160 and 256; 192 stays split
+    res.update({"np160_rowspec": 0.8, "np256_rowspec": 0.4})
+    assert tune._agent_sides(res) == (3, 5)
+    # every side's candidates are timed and map to a bit of their mask
+    for np_, (wl, names) in tune.AGENT_SIDES.items():
+        assert wl in tune.WORKLOADS and tune.WORKLOADS[wl][1] == np_
+        assert all(np_ in tune.SPLIT_BIT for n in names if n == "split")
+        assert all(np_ in tune.ROWSPEC_BIT for n in names if n == "rowspec")
 
 
 def test_line_split_of_128_points():
