@@ -109,14 +109,19 @@ bool np_supported(int np) {
 }
 bool np_large(int np) { return np > 128; }
 
+bool rowspec_allowed(const pmace_params& p);
+
 // Positions per chunk: Np <= 128 runs all positions in one fused launch;
-// Np > 128 stages chunk*Np^2 spectra between its three passes.
+// Np > 128 stages chunk*Np^2 spectra between its passes.
 int chunk_of(const pmace_params& p) {
   int c = p.num_pos;
-  // default: the tuned bound for 256-point patches, scaled so that every
-  // patch side stages about the same bytes per chunk
-  if (np_large(p.np))
-    c = p.chunk > 0 ? p.chunk : (int)((long long)PMACE_CHUNK256 * 256 * 256 / ((long long)p.np * p.np));
+  // default: the tuned bound for 256-point patches (one for the three-pass
+  // agent, one for the row-spectrum agent), scaled so that every patch side
+  // stages about the same bytes per chunk
+  if (np_large(p.np)) {
+    const long long c256 = rowspec_allowed(p) ? PMACE_CHUNK256_RS : PMACE_CHUNK256;
+    c = p.chunk > 0 ? p.chunk : (int)(c256 * 256 * 256 / ((long long)p.np * p.np));
+  }
   if (c > p.num_pos) c = p.num_pos;
   // the same number of chunks, evened out (no small last chunk)
   const int n = (p.num_pos + c - 1) / c;
@@ -535,6 +540,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   std::vector<int2> chunk_rows(nch, make_int2(0, 0));
   if (rowspec) {
     const int nseg = cr_segments(p);
+    const int rn = pmace::cr_round(np);
     std::vector<std::vector<int4>> per_row;
     for (int g = 0; g < nch; ++g) {
       const int ja = g * chunk, jb = std::min(J, ja + chunk);
@@ -553,10 +559,15 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
       chunk_rows[g] = make_int2((int)citems.size(), 0);
       for (size_t t = 0; t < per_row.size(); ++t) {
         if (per_row[t].empty()) continue;
-        // by patch column, then j: the entries covering a run of pixels are
-        // then consecutive (the consensus sums each pixel in this order)
-        std::stable_sort(per_row[t].begin(), per_row[t].end(),
-                         [](const int4& a, const int4& b) { return a.z < b.z; });
+        // By patch row, so that a round's rows share few weight rows (read
+        // once into the cache), then each round by patch column, so the
+        // entries covering a run of pixels are consecutive in it; ties in
+        // ascending j.  The consensus sums each pixel in this order.
+        auto& l = per_row[t];
+        std::stable_sort(l.begin(), l.end(), [](const int4& a, const int4& b) { return a.y < b.y; });
+        for (size_t r0 = 0; r0 < l.size(); r0 += (size_t)rn)
+          std::stable_sort(l.begin() + r0, l.begin() + std::min(l.size(), r0 + (size_t)rn),
+                           [](const int4& a, const int4& b) { return a.z < b.z; });
         citems.push_back(make_int4((int)clist.size(), (int)per_row[t].size(), lo + (int)(t / nseg),
                                    (int)(t % nseg) * pmace::CR_W));
         clist.insert(clist.end(), per_row[t].begin(), per_row[t].end());

@@ -28,7 +28,10 @@ namespace pmace {
 #define PMACE_CB 16       // Np > 128: patch columns per workgroup in the column pass
 #endif
 #ifndef PMACE_CHUNK256
-#define PMACE_CHUNK256 128  // Np > 128: default positions per chunk
+#define PMACE_CHUNK256 128  // Np > 128: default positions per chunk (at Np = 256)
+#endif
+#ifndef PMACE_CHUNK256_RS
+#define PMACE_CHUNK256_RS 4096  // ... for the row-spectrum agent
 #endif
 #ifndef PMACE_PPW32
 #define PMACE_PPW32 1     // Np = 32: patches per workgroup of the whole-patch agent
@@ -68,12 +71,14 @@ static_assert(QT_K >= 1 && QT_K <= 4, "split consensus: 1 to 4 threads per pixel
 // row segment of CR_W pixels each (CR_W >= 256, so a patch row meets at most
 // two segments).
 #ifndef PMACE_CR_T
-#define PMACE_CR_T 1024
+#define PMACE_CR_T 256
 #endif
 #ifndef PMACE_CR_W
 #define PMACE_CR_W 1024
 #endif
 constexpr int CR_T = PMACE_CR_T, CR_W = PMACE_CR_W;
+// Patch rows the row consensus transforms per round for side np (0 if none).
+int cr_round(int np);
 static_assert(CR_T % 64 == 0 && CR_T <= 1024 && CR_W % CR_T == 0 && CR_W >= 256, "row consensus shape");
 
 // Device-resident description of one reconstruction.  It lives in the

@@ -1846,6 +1846,15 @@ static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* 
     hipLaunchKernelGGL(image_update, dim3(nb), dim3(256), 0, st, h);
 }
 
+int cr_round(int np) {
+  switch (np) {
+    case 160: return cr_rows<160>();
+    case 192: return cr_rows<192>();
+    case 256: return cr_rows<256>();
+    default: return 0;
+  }
+}
+
 hipError_t launch_large_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
                                   const int2* chunk_rows, hipStream_t st) {
   switch (h.np) {

@@ -13,6 +13,7 @@ csrc/pmace_internal.hpp) plus one run-time default:
     PMACE_GEO32_A        32-point line split over threads: 4 x 8 or 2 x 16 registers
     PMACE_GEO64_A        64-point line split: 8 x 8 or 4 x 16
     PMACE_GEO128_A       128-point line split: 8 x 16 or 4 x 32
+    PMACE_CR_T           row-spectrum consensus: threads per workgroup (256, 512, 1024)
     PMACE_PPW32/48/64    (run-time choice, recorded as the build's default) patches per
                          workgroup of the whole-patch agent for Np = 32, 48, 64
     PMACE_SPLIT_SIDES    (run-time choice, recorded for the build) which of Np = 128, 192, 256
@@ -25,7 +26,9 @@ Search (coordinate-wise, every candidate measured on the device):
      the iteration time of a Np = 128 and a Np = 256 workload;
   2. row/column blocks with the default gather, scored on the Np = 256 workload
      (the row block found applies to 256-point lines; 160 and 192 keep PMACE_RB);
-  3. the line-FFT split (radix) of Np = 32, 64 and 128, each on a workload of its size;
+  3. the line-FFT split (radix) of Np = 32, 64 and 128, each on a workload of its size,
+     and the row-spectrum consensus width on the Np = 256 workload (that agent forced
+     for the side);
   4. the chunk size, at run time, with the combined choice;
   5. patches per workgroup of the whole-patch agent (Np = 32, 48, 64), at run
      time, each on a workload of its size, with the built library;
@@ -57,10 +60,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned.json")
 DEFAULTS = {"PMACE_GT_K": 1, "PMACE_GATHER_UNROLL": 8, "PMACE_GT_C": 64, "PMACE_RB": 32, "PMACE_RB256": 16,
             "PMACE_CB": 16, "PMACE_GEO32_A": 4, "PMACE_GEO64_A": 8, "PMACE_GEO128_A": 8,
-            "PMACE_PPW32": 1, "PMACE_PPW48": 1, "PMACE_PPW64": 1}
+            "PMACE_PPW32": 1, "PMACE_PPW48": 1, "PMACE_PPW64": 1, "PMACE_CR_T": 256}
 GATHER_SPACE = [(k, u, c) for k in (1, 2, 4) for u in (8, 16) for c in (64, 32)]
 BLOCK_SPACE = [(rb, cb) for rb in (8, 16, 32) for cb in (16, 32)]
 GEO_SPACE = [(32, 2), (64, 4), (128, 4)]   # the non-default splits
+CRT_SPACE = (256, 512, 1024)                # row-spectrum consensus threads per workgroup
 PPW_SPACE = {32: (1, 2, 4, 8), 48: (1, 2, 4), 64: (1, 2)}   # patches per workgroup per side
 # Agents timed per side ("other": the whole-patch agent for 128, three-pass above).
 AGENT_SIDES = {128: ("np128", ("other", "split")), 160: ("np160", ("other", "rowspec")),
@@ -86,6 +90,8 @@ def candidates():
     for n, a in GEO_SPACE:
         d = dict(DEFAULTS, **{f"PMACE_GEO{n}_A": a})
         out[f"geo{n}a{a}"] = d
+    for t in CRT_SPACE:     # Np = 256 on the row-spectrum agent in these builds
+        out[f"crt{t}"] = dict(DEFAULTS, PMACE_CR_T=t, PMACE_ROWSPEC_SIDES=4)
     # the default appears in both families: keep one copy
     uniq, seen = {}, set()
     for name, d in out.items():
@@ -205,6 +211,10 @@ def _pick(cands, times):
         key, wl = f"geo{n}a{a}", f"np{n}"
         if key in times and wl in base and times[key][wl] < base[wl]:
             d[f"PMACE_GEO{n}_A"] = a
+    # row-spectrum consensus width (ties keep the smaller)
+    crt = {t: times[f"crt{t}"]["np256"] for t in CRT_SPACE if f"crt{t}" in times}
+    if crt:
+        d["PMACE_CR_T"] = min(sorted(crt), key=crt.get)
     return d, score, b
 
 

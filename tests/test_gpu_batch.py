@@ -328,20 +328,20 @@ def test_batch_member_new_reference(P):
 def test_batched_members_match_oracle(P):
     """Members advanced inside a mixed batch (fused sides, a chunked Np = 256
     member on the three-pass agent, the same problem on the row-spectrum
-    agent, and an Np = 192 member on the split agent, this side's default),
-    from smooth starts: every member's state and reconstruction after K
-    iterations equal the FP64 oracle's at 1e-4, in L2 and element by element."""
+    agent, and an Np = 192 member on the split agent), from smooth starts:
+    every member's state and reconstruction after K iterations equal the FP64
+    oracle's at 1e-4, in L2 and element by element."""
     # Np 64, 128, 256 (4 positions per chunk) on the three-pass and the
     # row-spectrum agents, 192
     cfgs = [MIX[1], MIX[3], MIX[4], MIX[4], MIX[7]]
-    flags = [0, 0, P.PMACE_STAGED_AGENT, P.PMACE_ROWSPEC_AGENT, 0]
+    flags = [0, 0, P.PMACE_STAGED_AGENT, P.PMACE_ROWSPEC_AGENT, P.PMACE_SPLIT_AGENT]
     probs = [synth.make_problem(n, np_, sc, st, pk, sd) for (n, np_, sc, st, pk, sd, _) in cfgs]
     K = 3
     x0s = [synth.make_object(p.n1, p.n2, np.random.default_rng(200 + i)).astype(np.complex64)
            for i, p in enumerate(probs)]
     Rs = [P.Reconstruction(p.n1, p.n2, p.probe, p.pos, p.z, 0.5, chunk=cfg[-1], x0=x0, flags=fl)
           for p, cfg, x0, fl in zip(probs, cfgs, x0s, flags)]
-    assert [R.agent for R in Rs][2:4] == ["three-pass", "row-spectrum"]
+    assert [R.agent for R in Rs][2:] == ["three-pass", "row-spectrum", "split"]
     B = P.Batch(Rs, tol=0.0, min_iter=0, max_iter=K)
     B.step(K)
     for i, (R, p) in enumerate(zip(Rs, probs)):

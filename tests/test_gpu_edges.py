@@ -233,14 +233,14 @@ def _sampled_one_pass(P, n1, n2, np_, pos, z_dev, probe, x0, samples, alpha=0.5,
 @pytest.mark.parametrize("n1,n2,np_,step,peak,agent", [(1024, 2048, 256, 20, 1e6, "default"),
                                                       (1024, 2048, 256, 20, 1e6, "staged"),
                                                       (768, 1280, 192, 16, 1e5, "staged"),
-                                                      (768, 1280, 192, 16, 1e5, "default")])
+                                                      (768, 1280, 192, 16, 1e5, "split")])
 def test_rectangular_at_scale_sampled(P, n1, n2, np_, step, peak, agent):
     """Rectangular objects at full scale on the large-side agents: 1024 x 2048
     with 39 x 90 positions of 256^2 (default chunks; the row-spectrum agent,
     that side's default, whose consensus splits each object row into two
     1024-pixel segments, and the three-pass agent), and 768 x 1280
     with 37 x 69 positions of 192^2 on the three-pass agent (chunked) and on
-    the split agent (that side's default); intensities simulated on the
+    the split agent; intensities simulated on the
     device (eq. (1), eq. (16)), one pass from a smooth start, checked on
     sampled patches at the corners, the edges and the middle."""
     s1, s2 = (n1 - np_) // step + 1, (n2 - np_) // step + 1
@@ -254,6 +254,6 @@ def test_rectangular_at_scale_sampled(P, n1, n2, np_, step, peak, agent):
     x0 = synth.make_object(n1, n2, np.random.default_rng(5)).astype(np.complex64)
     J = len(pos)
     samples = [0, s2 - 1, J // 2 + s2 // 2, J - s2, J - 1, s2 * (s1 // 3) + 1]
-    flags = {"default": 0, "staged": P.PMACE_STAGED_AGENT, "rowspec": P.PMACE_ROWSPEC_AGENT}[agent]
+    flags = {"default": 0, "staged": P.PMACE_STAGED_AGENT, "split": P.PMACE_SPLIT_AGENT}[agent]
     ev, em = _sampled_one_pass(P, n1, n2, np_, pos, z, probe, x0, samples, flags=flags)
     assert ev < TOL and em < TOL

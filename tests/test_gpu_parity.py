@@ -493,7 +493,7 @@ def c3_geometry_problem(np_):
 
 @pytest.mark.slow
 @pytest.mark.parametrize("np_,flags", [(256, 0), (256, SPLIT), (256, STAGED), (192, 0), (192, STAGED),
-                                       (192, ROWSPEC), (160, 0), (160, ROWSPEC)])
+                                       (192, SPLIT), (160, 0), (160, ROWSPEC)])
 def test_c3_full_size_steps(P, np_, flags):
     """The full 1024^2 / 1600-position workload (probe 256^2, and the 192^2 and
     160^2 sides bench.py times on the same geometry) in the launch

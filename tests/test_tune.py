@@ -77,3 +77,15 @@ def test_line_split_of_128_points():
     assert d["PMACE_GEO128_A"] == 4
     d, _, _ = tune._pick(cands, _times(cands, geo128a4=("np128", 1.1)))
     assert d["PMACE_GEO128_A"] == 8
+
+
+def test_row_consensus_width():
+    cands = tune.candidates()
+    # every width is built with Np = 256 on the row-spectrum agent
+    for t in tune.CRT_SPACE:
+        assert cands[f"crt{t}"]["PMACE_CR_T"] == t and cands[f"crt{t}"]["PMACE_ROWSPEC_SIDES"] == 4
+    d, _, _ = tune._pick(cands, _times(cands, crt512=("np256", 0.9)))
+    assert d["PMACE_CR_T"] == 512
+    # a tie keeps the smaller width; the pick never sets the agent sides
+    d, _, _ = tune._pick(cands, _times(cands))
+    assert d["PMACE_CR_T"] == 256 and "PMACE_ROWSPEC_SIDES" not in d
