@@ -9,7 +9,8 @@ csrc/pmace_internal.hpp) plus one run-time default:
     PMACE_RB256          Np = 256 row passes: patch rows per workgroup (8, 16, 32)
     PMACE_RB             Np = 160, 192 row passes: patch rows per workgroup (fixed, 32)
     PMACE_CB             Np > 128 column pass: patch columns per workgroup (16, 32)
-    PMACE_CHUNK256       Np > 128: positions per chunk (stage buffer size)
+    PMACE_CHUNK256       Np > 128, three-pass agent: positions per chunk (stage buffer size)
+    PMACE_CHUNK256_RS    the same for the row-spectrum agent
     PMACE_GEO32_A        32-point line split over threads: 4 x 8 or 2 x 16 registers
     PMACE_GEO64_A        64-point line split: 8 x 8 or 4 x 16
     PMACE_GEO128_A       128-point line split: 8 x 16 or 4 x 32
@@ -29,7 +30,8 @@ Search (coordinate-wise, every candidate measured on the device):
   3. the line-FFT split (radix) of Np = 32, 64 and 128, each on a workload of its size,
      and the row-spectrum consensus width on the Np = 256 workload (that agent forced
      for the side);
-  4. the chunk size, at run time, with the combined choice;
+  4. the chunk size of each large-side agent (three-pass, row-spectrum), at run time,
+     with the combined choice;
   5. patches per workgroup of the whole-patch agent (Np = 32, 48, 64), at run
      time, each on a workload of its size, with the built library;
   6. the agent of each side that has several (Np = 128: whole patch or split;
@@ -69,7 +71,8 @@ PPW_SPACE = {32: (1, 2, 4, 8), 48: (1, 2, 4), 64: (1, 2)}   # patches per workgr
 # Agents timed per side ("other": the whole-patch agent for 128, three-pass above).
 AGENT_SIDES = {128: ("np128", ("other", "split")), 160: ("np160", ("other", "rowspec")),
                192: ("np192", ("other", "split", "rowspec")), 256: ("np256", ("other", "split", "rowspec"))}
-CHUNKS = (64, 128, 192, 256, 400)
+CHUNKS = (64, 128, 192, 256, 400)            # three-pass agent (PMACE_CHUNK256)
+CHUNKS_RS = (256, 400, 800, 1600, 4096)      # row-spectrum agent (PMACE_CHUNK256_RS)
 
 # Tuning workloads: (object side, probe side, scan side, step, peak photons).
 WORKLOADS = {"np128": (512, 128, 15, 24, 1e5), "np256": (1024, 256, 40, 20, 1e6),
@@ -235,17 +238,30 @@ def cmd_pick(args):
     print(json.dumps(rec["defines"]))
 
 
+def _best_chunk(res, chunks):
+    """The chunk bound with the least time (ties keep the smaller)."""
+    return min(chunks, key=lambda c: res[f"np256_chunk{c}"])
+
+
 def cmd_chunk(args):
+    """Chunk bounds at Np = 256 with the built library: the three-pass agent's
+    (PMACE_CHUNK256) and the row-spectrum agent's (PMACE_CHUNK256_RS), each
+    with that agent forced."""
     from . import build as B
-    res = _time_library(B.LIB, ["np256"], args.iters, chunks=CHUNKS)
-    best = min(CHUNKS, key=lambda c: res[f"np256_chunk{c}"])
+    from . import pmace
+    res = _time_library(B.LIB, ["np256"], args.iters, chunks=CHUNKS, flags=pmace.PMACE_STAGED_AGENT)
+    res_rs = _time_library(B.LIB, ["np256"], args.iters, chunks=CHUNKS_RS, flags=pmace.PMACE_ROWSPEC_AGENT)
+    best, best_rs = _best_chunk(res, CHUNKS), _best_chunk(res_rs, CHUNKS_RS)
     rec = json.load(open(TUNED)) if os.path.exists(TUNED) else {"defines": dict(DEFAULTS)}
     rec["chunk_ms_np256"] = res
+    rec["chunk_ms_np256_rowspec"] = res_rs
     if args.write:
         rec["defines"]["PMACE_CHUNK256"] = best
+        rec["defines"]["PMACE_CHUNK256_RS"] = best_rs
         with open(TUNED, "w") as f:
             json.dump(rec, f, indent=1, sort_keys=True)
-    print(json.dumps({"best_chunk": best, **res}))
+    print(json.dumps({"best_chunk": best, "best_chunk_rowspec": best_rs, **res,
+                      **{f"rowspec_{k}": v for k, v in res_rs.items()}}))
 
 
 def _pick_ppw(res):

@@ -89,3 +89,10 @@ def test_row_consensus_width():
     # a tie keeps the smaller width; the pick never sets the agent sides
     d, _, _ = tune._pick(cands, _times(cands))
     assert d["PMACE_CR_T"] == 256 and "PMACE_ROWSPEC_SIDES" not in d
+
+
+def test_chunk_bounds_per_agent():
+    res = {f"np256_chunk{c}": 1.0 for c in tune.CHUNKS_RS}
+    assert tune._best_chunk(res, tune.CHUNKS_RS) == min(tune.CHUNKS_RS)   # ties keep the smaller
+    res["np256_chunk1600"] = 0.9
+    assert tune._best_chunk(res, tune.CHUNKS_RS) == 1600
