@@ -51,21 +51,19 @@ typedef enum {
  * through the flat start: the whole-patch and three-pass transforms return
  * those zeros exactly, the split agent's leave rounding noise there, and
  * eq. (9)'s "0 where W = 0" then does not act).  np <= 128 runs the
- * whole-patch agent; np = 160, 192, 256 by default the three-pass agent, which
- * stages each chunk's spectra through memory twice.  PMACE with a probe
- * without exact zeros has two more:
- *   - np = 128, 192 or 256: each state kept as the four coset blocks of the
- *     top radix-2 step of its 2-D DFT ("split" agent): every agent then runs
- *     on (np/2)^2 blocks held on chip and no spectrum is staged (about half
- *     the memory traffic), at the price of reading the probe and the
- *     consensus window once per block;
+ * whole-patch agent; np = 160, 192, 256 the three-pass agent, which stages
+ * each chunk's spectra through memory twice, or:
  *   - np = 160, 192 or 256: each state kept as the DFTs of its rows
  *     ("row-spectrum" agent): the column pass writes the new state itself,
  *     and the consensus inverts the rows it sums, so each chunk's spectra are
- *     staged once instead of twice.
- * SHARP+, and probes with zeros (where eq. (9)'s d = 0 rule acts per pixel),
- * use neither.  Which sides use which by default is a build choice (timed by
- * the tuner).
+ *     staged once instead of twice (PMACE with a probe without exact zeros,
+ *     where eq. (9)'s d = 0 rule acts per pixel; SHARP+ with any probe);
+ *   - np = 128, 192 or 256, PMACE with a probe without exact zeros: each
+ *     state kept as the four coset blocks of the top radix-2 step of its 2-D
+ *     DFT ("split" agent): every agent then runs on (np/2)^2 blocks held on
+ *     chip and no spectrum is staged, at the price of reading the probe and
+ *     the consensus window once per block.
+ * Which sides use which by default is a build choice (timed by the tuner).
  *   PMACE_STAGED_AGENT:  the three-pass agent (np > 128), never the split one.
  *   PMACE_SPLIT_AGENT:   the split agent wherever it applies.
  *   PMACE_ROWSPEC_AGENT: the row-spectrum agent wherever it applies.

@@ -199,13 +199,20 @@ bool rowspec_default(int np) {
   const int bit = np == 160 ? 1 : np == 192 ? 2 : np == 256 ? 4 : 0;
   return (PMACE_ROWSPEC_SIDES & bit) != 0;
 }
-// The row-spectrum agent may run: PMACE with Np > 128 when asked for, or by
-// default where the build chose it and no other agent is asked for or chosen.
-// Whether it does also needs a probe without exact zeros (known at init).
+// SHARP+ on the row-spectrum agent by default where PMACE is (1), or only
+// when asked for (0): a build choice measured by the tuner.
+#ifndef PMACE_ROWSPEC_SHARP
+#define PMACE_ROWSPEC_SHARP 0
+#endif
+// The row-spectrum agent may run: Np > 128 when asked for, or by default
+// where the build chose it and no other agent is asked for or chosen.  PMACE
+// also needs a probe without exact zeros (known at init; its d = 0 rule acts
+// per pixel); SHARP+ has no such rule.
 bool rowspec_allowed(const pmace_params& p) {
-  if (p.method != PMACE_METHOD_PMACE || !np_large(p.np)) return false;
+  if (!np_large(p.np)) return false;
   if (p.flags & PMACE_ROWSPEC_AGENT) return true;
   if (p.flags & (PMACE_STAGED_AGENT | PMACE_SPLIT_AGENT)) return false;
+  if (p.method == PMACE_METHOD_SHARP_PLUS && !PMACE_ROWSPEC_SHARP) return false;
   return !split_allowed(p) && rowspec_default(p.np);
 }
 // Bounds of its consensus tables (sizes only): every (chunk, object row,
@@ -535,7 +542,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
   // Row-spectrum states: per chunk, one item per object row its patches cover
   // and CR_W-wide segment of that row, listing the chunk's positions whose
   // patch covers the row and meets the segment, in ascending j.
-  const bool rowspec = rowspec_allowed(p) && !has_zero;
+  const bool rowspec = rowspec_allowed(p) && (sharp || !has_zero);
   std::vector<int4> citems, clist;
   std::vector<int2> chunk_rows(nch, make_int2(0, 0));
   if (rowspec) {

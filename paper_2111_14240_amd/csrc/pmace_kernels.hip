@@ -40,9 +40,12 @@
 
 namespace pmace {
 
-// kRowSpec: PMACE on the Np > 128 passes with every state kept as the row
-// spectrum of its probe-weighted form (see agent_rows_body).
-constexpr int kPMACE = 0, kSharpPlus = 1, kRowSpec = 2;
+// kRowSpec / kSharpRowSpec: PMACE / SHARP+ on the Np > 128 passes with
+// every state kept as the row spectrum of the stored state (see
+// agent_rows_body).
+constexpr int kPMACE = 0, kSharpPlus = 1, kRowSpec = 2, kSharpRowSpec = 3;
+template <int METHOD> constexpr bool row_spec() { return METHOD == kRowSpec || METHOD == kSharpRowSpec; }
+template <int METHOD> constexpr bool sharp() { return METHOD == kSharpPlus || METHOD == kSharpRowSpec; }
 
 // Fourier-domain prox of eq. (9): U = W * (a + ys / |W|), 0 where W == 0.
 __device__ __forceinline__ float2 fourier_prox(float2 W, float ysv, float a) {
@@ -66,7 +69,7 @@ __device__ __forceinline__ float2 state_spectrum(float2 W, float ysv, float sb, 
 // SHARP+ the magnitude projection (a = 0).
 template <int METHOD>
 __device__ __forceinline__ float2 spectrum_step(float2 W, float ysv, const Recon& g) {
-  if constexpr (METHOD != kSharpPlus) return state_spectrum(W, ysv, g.sb, g.s2r);
+  if constexpr (!sharp<METHOD>()) return state_spectrum(W, ysv, g.sb, g.s2r);
   else return fourier_prox(W, ysv, 0.f);
 }
 
@@ -433,10 +436,10 @@ __device__ __forceinline__ void agent_rows_body(const Recon& g, const int j0) {
   const float2* xrow = g.xbar + (size_t)(pj.x + r) * g.n2 + pj.y;
   const float2* trow = g.t + (size_t)j * NP * NP + (size_t)r * NP;
   float2 x[B];
-  if constexpr (METHOD == kRowSpec) {
+  if constexpr (row_spec<METHOD>()) {
     // The state is kept as H = F_r(s)/Np (its row spectrum, natural order),
     // so the frame's row spectrum is Np H + F_r(2 rho d P_j xbar): only the
-    // window term is transformed here.  H is fetched first, in the order the
+    // window term is transformed here (SHARP+: 2 beta for 2 rho, and t for s).  H is fetched first, in the order the
     // transform leaves its output, so its latency hides behind the transform.
     float2 h[B];
 #pragma unroll
@@ -516,11 +519,30 @@ __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
 #pragma unroll
   for (int k = 0; k < B; ++k) x[k] = spectrum_step<METHOD>(x[k], yv[k], g);
   col_inv<NP>(x, tile, CB, c, q, tw);
-  // kRowSpec: the column inverse of the state spectrum is F_r(s_new)/Np, the
-  // new state itself; the inverse row pass is left to the consensus
-  float2* op = METHOD == kRowSpec ? g.t + (size_t)j * NP * NP + col : sp;
+  if constexpr (METHOD == kSharpRowSpec) {
+    // SHARP+ with row-spectrum states T = F_r(t)/Np: the column inverse C of
+    // the magnitude projection gives P_a s = F_r^*(C)/Np^2, and the next state
+    // t' = (1 - 2 beta) P_a s + beta (s - d P_j xbar) with s = t + 2 beta d P_j xbar
+    // is, in row spectra, T' = ka C + ((2 beta - 1)/(2 Np)) F_r(s) + T/2, where
+    // F_r(s) is this pass's input (read again: each thread's own elements).
+    // C goes back to the stage for the overlap projection.
+    float2* tp = g.t + (size_t)j * NP * NP + col;
+    const float c1 = (g.two_rho - 1.f) / (2.f * (float)NP);
 #pragma unroll
-  for (int nb = 0; nb < B; ++nb) op[(size_t)(q + A * nb) * NP] = x[nb];
+    for (int nb = 0; nb < B; ++nb) {
+      const size_t o = (size_t)(q + A * nb) * NP;
+      const float2 xs = sp[o], to = tp[o];
+      tp[o] = make_float2(fmaf(g.ka, x[nb].x, fmaf(c1, xs.x, 0.5f * to.x)),
+                          fmaf(g.ka, x[nb].y, fmaf(c1, xs.y, 0.5f * to.y)));
+      sp[o] = x[nb];
+    }
+  } else {
+    // kRowSpec: the column inverse of the state spectrum is F_r(s_new)/Np, the
+    // new state itself; the inverse row pass is left to the consensus
+    float2* op = METHOD == kRowSpec ? g.t + (size_t)j * NP * NP + col : sp;
+#pragma unroll
+    for (int nb = 0; nb < B; ++nb) op[(size_t)(q + A * nb) * NP] = x[nb];
+  }
 }
 
 template <int NP, int METHOD>
@@ -738,26 +760,31 @@ __global__ void __launch_bounds__(GT_THREADS) consensus_gather_batch(const Recon
 }
 
 // -------------------------------------------------------------------------
-// Consensus for states kept as row spectra (kRowSpec): S = sum_j P_j^t
-// (|d|^kappa / d) s_j with s_j = F_r^*(H_j) (the stored H_j = F_r(s_j)/Np), so
-// the inverse row transforms run here instead of in a pass of their own.  A
+// Consensus for states kept as row spectra: PMACE (kRowSpec) sums
+// S = sum_j P_j^t (|d|^kappa / d) s_j with s_j = F_r^*(H_j) (the stored
+// H_j = F_r(s_j)/Np); SHARP+ (kSharpRowSpec) sums the overlap numerators
+// sum_j P_j^t conj(d) P_a s_j with P_a s_j = F_r^*(C_j)/Np^2, C_j left in the
+// stage by the column pass (`jbase` = first position held there).  The
+// inverse row transforms thus run here instead of in a pass of their own.  A
 // row of a patch lands on one object row: a workgroup owns one object row R
 // (a CR_W-pixel segment of it) and walks its list of the chunk's positions
 // whose patch covers R and meets the segment, with entries (j, row of P_j on
-// R, patch column), sorted by patch column and then j.  Each round
-// inverse-transforms cr_rows<NP>() such patch rows in LDS and weights them;
-// every thread then adds, in list order, the ones that cover its pixel of R.
-// Every pixel's sum thus runs in one fixed order (chunks in turn, then the
-// list), with no atomics: bitwise reproducible.  CHECK: batch member, skip
-// when stopped.
+// R, patch column), in rounds of cr_rows<NP>() entries grouped by patch row,
+// each round sorted by patch column.  Each round inverse-transforms its patch
+// rows in LDS and weights them; every thread then adds, in list order, the
+// ones that cover its pixel of R.  Every pixel's sum thus runs in one fixed
+// order (chunks in turn, then the list), with no atomics: bitwise
+// reproducible.  CHECK: batch member, skip when stopped.
 // -------------------------------------------------------------------------
 // patch rows per round: CR_T threads' worth, at most 64 (LDS)
 template <int NP> constexpr int cr_rows() { return CR_T / Geo<NP>::A < 64 ? CR_T / Geo<NP>::A : 64; }
 template <int NP> constexpr int cr_threads() { return cr_rows<NP>() * Geo<NP>::A; }
 template <int NP> constexpr int cr_pitch() { return row_cap<NP>() > NP ? row_cap<NP>() : NP; }
 
-template <int NP, bool CHECK>
-__global__ void __launch_bounds__(cr_threads<NP>()) consensus_rows(const Recon g, int first_item) {
+template <int NP, bool CHECK, int METHOD>
+__global__ void __launch_bounds__(cr_threads<NP>()) consensus_rows(const Recon g, int first_item,
+                                                                    int jbase) {
+  static_assert(row_spec<METHOD>(), "row-spectrum states");
   if constexpr (CHECK) {
     if (*g.done) return;
   }
@@ -776,14 +803,23 @@ __global__ void __launch_bounds__(cr_threads<NP>()) consensus_rows(const Recon g
   int4 en;
   float2 x[B], w[B];
   auto fetch = [&](int e) {
-    en = e < it.y ? g.clist[it.x + e] : make_int4(0, 0, 0, 0);
-    const float2* hr = g.t + (size_t)en.x * NP * NP + (size_t)en.y * NP;
+    en = e < it.y ? g.clist[it.x + e] : make_int4(jbase, 0, 0, 0);
+    const float2* hr = METHOD == kSharpRowSpec
+                           ? g.stage + (size_t)(en.x - jbase) * NP * NP + (size_t)en.y * NP
+                           : g.t + (size_t)en.x * NP * NP + (size_t)en.y * NP;
 #pragma unroll
     for (int m = 0; m < M; ++m)
 #pragma unroll
       for (int ka = 0; ka < A; ++ka) x[m * A + ka] = hr[p + A * m + B * ka];
 #pragma unroll
-    for (int nb = 0; nb < B; ++nb) w[nb] = g.gw[en.y * NP + p + A * nb];
+    for (int nb = 0; nb < B; ++nb) {
+      if constexpr (METHOD == kSharpRowSpec) {
+        const float4 pcf = g.pc[en.y * NP + p + A * nb];  // {conj(d)/Np^2, conj(d)}
+        w[nb] = make_float2(pcf.x, pcf.y);
+      } else {
+        w[nb] = g.gw[en.y * NP + p + A * nb];
+      }
+    }
   };
   fetch(rl);
   twf.store(tw, tid);
@@ -1801,16 +1837,22 @@ static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* 
       // row-spectrum states: rows (window term), columns (new state), then the
       // consensus with the inverse row transforms
       const int2 cr = chunk_rows[g];
+      const dim3 crb(cr_threads<NP>());
       if (batch_rec) {
         hipLaunchKernelGGL((agent_rows_batch<NP, kRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
         hipLaunchKernelGGL((agent_cols_batch<NP, kRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
         if (cr.y > 0)
-          hipLaunchKernelGGL((consensus_rows<NP, true>), dim3(cr.y), dim3(cr_threads<NP>()), 0, st, h, cr.x);
+          hipLaunchKernelGGL((consensus_rows<NP, true, kRowSpec>), dim3(cr.y), crb, 0, st, h, cr.x, j0);
+      } else if (h.method == kSharpPlus) {
+        hipLaunchKernelGGL((agent_rows<NP, kSharpRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
+        hipLaunchKernelGGL((agent_cols<NP, kSharpRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
+        if (cr.y > 0)
+          hipLaunchKernelGGL((consensus_rows<NP, false, kSharpRowSpec>), dim3(cr.y), crb, 0, st, h, cr.x, j0);
       } else {
         hipLaunchKernelGGL((agent_rows<NP, kRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
         hipLaunchKernelGGL((agent_cols<NP, kRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
         if (cr.y > 0)
-          hipLaunchKernelGGL((consensus_rows<NP, false>), dim3(cr.y), dim3(cr_threads<NP>()), 0, st, h, cr.x);
+          hipLaunchKernelGGL((consensus_rows<NP, false, kRowSpec>), dim3(cr.y), crb, 0, st, h, cr.x, j0);
       }
       continue;
     }
@@ -1961,7 +2003,7 @@ static hipError_t launch_row_transform(int np, int count, const float2* in, floa
   return hipGetLastError();
 }
 
-// Row-spectrum states from the probe-weighted ones in t: H = F_r(s)/Np.
+// Row-spectrum states from the ones in t (PMACE: probe-weighted): F_r(t)/Np.
 static hipError_t states_to_rowspec(const Recon& h, hipStream_t st) {
   return launch_row_transform(h.np, h.J, h.t, h.t, false, 1.f / (float)h.np, st);
 }
@@ -1992,9 +2034,9 @@ hipError_t launch_init(const Recon& h, const Recon* rec, const float* z, float s
       if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(sold_from_num, dim3(blocks_for(npx, 256)), dim3(256), 0, st, rec);
-    // S above was summed from the probe-weighted states themselves
-    if (h.rowspec) return states_to_rowspec(h, st);
   }
+  // S above was summed from the stored states themselves
+  if (h.rowspec) return states_to_rowspec(h, st);
   return hipGetLastError();
 }
 

@@ -21,6 +21,7 @@ csrc/pmace_internal.hpp) plus one run-time default:
                          default to the split (coset-block) agent: bit 0, 1, 2
     PMACE_ROWSPEC_SIDES  (likewise) which of Np = 160, 192, 256 default to the row-spectrum
                          agent: bit 0, 1, 2
+    PMACE_ROWSPEC_SHARP  (likewise) 1: SHARP+ takes the row-spectrum agent on those sides too
 
 Search (coordinate-wise, every candidate measured on the device):
   1. gather shape (GT_K x unroll x tile width) with the default row/column blocks, scored by
@@ -125,9 +126,10 @@ def cmd_build(args):
             print("built", name, flush=True)
 
 
-def _time_library(lib, workloads, iters, chunks=(0,), flags=0, ppw=0):
+def _time_library(lib, workloads, iters, chunks=(0,), flags=0, ppw=0, method=0):
     """Run in a fresh process: load `lib`, time `iters` iterations (one graph
-    replay each) per workload, return ms per iteration."""
+    replay each) per workload, return ms per iteration (method 1: SHARP+,
+    beta 0.8)."""
     import torch
     from . import pmace
     pmace.load_library(lib)
@@ -139,7 +141,8 @@ def _time_library(lib, workloads, iters, chunks=(0,), flags=0, ppw=0):
             stream = torch.cuda.Stream()
             with torch.cuda.stream(stream):
                 R = pmace.Reconstruction(n, n, prob.probe, prob.pos, prob.z, 0.5, chunk=ch,
-                                         stream=stream, flags=flags, ppw=ppw)
+                                         stream=stream, flags=flags, ppw=ppw, method=method,
+                                         beta=0.8 if method else 0.5)
                 R.iterate(3)
                 R.sync()
                 best = float("inf")
@@ -301,6 +304,12 @@ SPLIT_BIT = {128: 0, 192: 1, 256: 2}     # PMACE_SPLIT_SIDES
 ROWSPEC_BIT = {160: 0, 192: 1, 256: 2}   # PMACE_ROWSPEC_SIDES
 
 
+def _sharp_rowspec(res):
+    """PMACE_ROWSPEC_SHARP: 1 where SHARP+ at Np = 256 ran faster on the
+    row-spectrum agent than on the three-pass one."""
+    return 1 if res["sharp_np256_rowspec"] < res["sharp_np256_other"] else 0
+
+
 def _agent_sides(res):
     """(PMACE_SPLIT_SIDES, PMACE_ROWSPEC_SIDES) from the agent times: each side
     defaults to its fastest agent (ties keep the earlier one in AGENT_SIDES)."""
@@ -327,15 +336,22 @@ def cmd_agent(args):
             for name in names:
                 t = _time_library(B.LIB, [wl], args.iters, flags=flag[name])[wl]
                 res[f"{wl}_{name}"] = min(res.get(f"{wl}_{name}", float("inf")), t)
+    for _ in range(args.rounds):       # SHARP+ (no split agent) at Np = 256
+        for name in ("other", "rowspec"):
+            t = _time_library(B.LIB, ["np256"], args.iters, flags=flag[name], method=1)["np256"]
+            res[f"sharp_np256_{name}"] = min(res.get(f"sharp_np256_{name}", float("inf")), t)
     split, rowspec = _agent_sides(res)
+    sharp_rs = _sharp_rowspec(res)
     rec = json.load(open(TUNED)) if os.path.exists(TUNED) else {"defines": dict(DEFAULTS)}
     rec["agent_ms"] = res
     if args.write:
         rec["defines"]["PMACE_SPLIT_SIDES"] = split
         rec["defines"]["PMACE_ROWSPEC_SIDES"] = rowspec
+        rec["defines"]["PMACE_ROWSPEC_SHARP"] = sharp_rs
         with open(TUNED, "w") as f:
             json.dump(rec, f, indent=1, sort_keys=True)
-    print(json.dumps({"PMACE_SPLIT_SIDES": split, "PMACE_ROWSPEC_SIDES": rowspec, **res}))
+    print(json.dumps({"PMACE_SPLIT_SIDES": split, "PMACE_ROWSPEC_SIDES": rowspec,
+                      "PMACE_ROWSPEC_SHARP": sharp_rs, **res}))
 
 
 def main(argv=None):

@@ -15,13 +15,20 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
 
+STAGED, ROWSPEC = 0x2, 0x8   # PMACE_STAGED_AGENT, PMACE_ROWSPEC_AGENT
+
 CASES = {
-    "np32": (128, 32, 6, 16, None, 1, 0),
-    "np64": (200, 64, 5, 30, 1e5, 21, 0),
-    "np128": (320, 128, 4, 56, 1e5, 22, 0),
-    "np256_ragged_chunks": (400, 256, 3, 60, 1e6, 23, 4),
-    "np96": (288, 96, 5, 40, 1e5, 52, 0),
-    "np192_chunks": (400, 192, 3, 90, 1e5, 54, 4),
+    # name: (n, np, scan, step, peak, seed, chunk, agent flags)
+    "np32": (128, 32, 6, 16, None, 1, 0, 0),
+    "np64": (200, 64, 5, 30, 1e5, 21, 0, 0),
+    "np128": (320, 128, 4, 56, 1e5, 22, 0, 0),
+    "np256_ragged_chunks": (400, 256, 3, 60, 1e6, 23, 4, STAGED),
+    "np96": (288, 96, 5, 40, 1e5, 52, 0, 0),
+    "np192_chunks": (400, 192, 3, 90, 1e5, 54, 4, STAGED),
+    # the states kept as row spectra (SHARP+ has no zero rule, so any probe)
+    "np256_rowspec_chunks": (400, 256, 3, 60, 1e6, 23, 4, ROWSPEC),
+    "np192_rowspec": (400, 192, 3, 90, 1e5, 54, 0, ROWSPEC),
+    "np160_rowspec_chunks": (360, 160, 3, 80, 1e6, 53, 4, ROWSPEC),
 }
 
 
@@ -46,7 +53,7 @@ def rel(a, b):
 @pytest.mark.parametrize("case", sorted(CASES))
 @pytest.mark.parametrize("beta", [0.5, 0.8])
 def test_sharp_plus_teacher_forced(P, case, beta):
-    n, np_, scan, step, peak, seed, chunk = CASES[case]
+    n, np_, scan, step, peak, seed, chunk, flags = CASES[case]
     prob = synth.make_problem(n, np_, scan, step, peak, seed)
     d = prob.probe.astype(np.complex64).astype(np.complex128)
     y = O.amplitudes(prob.z)
@@ -57,7 +64,9 @@ def test_sharp_plus_teacher_forced(P, case, beta):
         ss.append(O.sharp_plus_step(ss[-1], d, y, prob.pos, shape, beta))
     _say(case, "beta", beta)
     R = P.Reconstruction(n, n, prob.probe, prob.pos, prob.z, 0.0, x0=x0.astype(np.complex64),
-                         chunk=chunk, method=P.PMACE_METHOD_SHARP_PLUS, beta=beta)
+                         chunk=chunk, method=P.PMACE_METHOD_SHARP_PLUS, beta=beta, flags=flags)
+    if flags == ROWSPEC:
+        assert R.agent == "row-spectrum"
     s0 = R.get_state().cpu().numpy()
     assert rel(s0, ss[0]) < 1e-6
     for k in range(4):
@@ -70,7 +79,7 @@ def test_sharp_plus_teacher_forced(P, case, beta):
         assert es < TOL and ex < TOL
     # free-running from x0 follows the same trajectory for a few steps
     R2 = P.Reconstruction(n, n, prob.probe, prob.pos, prob.z, 0.0, x0=x0.astype(np.complex64),
-                          chunk=chunk, method=P.PMACE_METHOD_SHARP_PLUS, beta=beta)
+                          chunk=chunk, method=P.PMACE_METHOD_SHARP_PLUS, beta=beta, flags=flags)
     R2.iterate(4)
     assert rel(R2.get_state().cpu().numpy(), ss[4]) < 10 * TOL
     R.close()
@@ -84,12 +93,13 @@ def elem(a, b):
 
 
 @pytest.mark.slow
-@pytest.mark.parametrize("config", ["c3", "c2"])
-def test_sharp_plus_full_size(P, config):
-    """SHARP+ on the full C3 (1024^2 object, 1600 positions of 256^2) and C2
-    (512^2, 225 of 128^2) workloads in the launch configuration
-    bench.py --method sharp times (beta 0.8, tuned chunks): the first pass
-    from a smooth start and a teacher-forced second pass, on every frame."""
+@pytest.mark.parametrize("config,flags", [("c3", 0), ("c3", STAGED), ("c3", ROWSPEC), ("c2", 0)])
+def test_sharp_plus_full_size(P, config, flags):
+    """SHARP+ on the full C3 (1024^2 object, 1600 positions of 256^2; the
+    default agent, and the three-pass and row-spectrum agents) and C2 (512^2,
+    225 of 128^2) workloads in the launch configuration bench.py --method
+    sharp times (beta 0.8, tuned chunks): the first pass from a smooth start
+    and a teacher-forced second pass, on every frame."""
     beta = 0.8
     prob = synth.make_config_problem(config)
     n = prob.n1
@@ -102,7 +112,8 @@ def test_sharp_plus_full_size(P, config):
     for _ in range(2):
         ss.append(O.sharp_plus_step(ss[-1], d, y, prob.pos, shape, beta))
     R = P.Reconstruction(n, n, prob.probe, prob.pos, prob.z, 0.5, x0=x0.astype(np.complex64),
-                         method=P.PMACE_METHOD_SHARP_PLUS, beta=beta)
+                         method=P.PMACE_METHOD_SHARP_PLUS, beta=beta, flags=flags)
+    _say(f"  agent: {R.agent}")
     for k in range(2):
         if k:
             R.set_state(ss[k])
@@ -117,18 +128,19 @@ def test_sharp_plus_full_size(P, config):
     R.close()
 
 
-@pytest.mark.parametrize("case,iters", [("c1", 50), ("np256_ragged_chunks", 20)])
+@pytest.mark.parametrize("case,iters", [("c1", 50), ("np256_ragged_chunks", 20), ("np256_rowspec_chunks", 20)])
 def test_sharp_plus_every_iteration(P, case, iters):
     """SHARP+ teacher-forced at every iteration of a longer run from a smooth
     start (beta 0.8): the C1 workload to 50 iterations on the whole-patch agent,
-    and a three-pass case with ragged chunks to 20, each pass on every frame and
-    on the output, in L2 and element by element."""
+    and a case with ragged chunks to 20 on the three-pass and on the
+    row-spectrum agent, each pass on every frame and on the output, in L2 and
+    element by element."""
     beta = 0.8
     if case == "c1":
         prob = synth.make_config_problem("c1")
-        chunk = 0
+        chunk, flags = 0, 0
     else:
-        n, np_, scan, step, peak, seed, chunk = CASES[case]
+        n, np_, scan, step, peak, seed, chunk, flags = CASES[case]
         prob = synth.make_problem(n, np_, scan, step, peak, seed)
     n = prob.n1
     d = prob.probe.astype(np.complex64).astype(np.complex128)
@@ -140,7 +152,7 @@ def test_sharp_plus_every_iteration(P, case, iters):
     for _ in range(iters):
         ss.append(O.sharp_plus_step(ss[-1], d, y, prob.pos, shape, beta))
     R = P.Reconstruction(n, n, prob.probe, prob.pos, prob.z, 0.0, x0=x0.astype(np.complex64),
-                         chunk=chunk, method=P.PMACE_METHOD_SHARP_PLUS, beta=beta)
+                         chunk=chunk, method=P.PMACE_METHOD_SHARP_PLUS, beta=beta, flags=flags)
     worst = 0.0
     for k in range(iters):
         R.set_state(ss[k])

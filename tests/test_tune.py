@@ -96,3 +96,8 @@ def test_chunk_bounds_per_agent():
     assert tune._best_chunk(res, tune.CHUNKS_RS) == min(tune.CHUNKS_RS)   # ties keep the smaller
     res["np256_chunk1600"] = 0.9
     assert tune._best_chunk(res, tune.CHUNKS_RS) == 1600
+
+
+def test_sharp_plus_agent_choice():
+    assert tune._sharp_rowspec({"sharp_np256_other": 1.6, "sharp_np256_rowspec": 1.36}) == 1
+    assert tune._sharp_rowspec({"sharp_np256_other": 1.3, "sharp_np256_rowspec": 1.36}) == 0
