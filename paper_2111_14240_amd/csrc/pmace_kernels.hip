@@ -505,6 +505,20 @@ __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
   float2 x[B];
 #pragma unroll
   for (int nb = 0; nb < B; ++nb) x[nb] = sp[(size_t)(q + A * nb) * NP];
+  // SHARP+ on row-spectrum states: the part of the next state that does not
+  // depend on the projection, ((2 beta - 1)/(2 Np)) F_r(s) + T/2, formed from
+  // this pass's input and the old state now (both loads hide behind the
+  // transforms), so the input need not be read again at the end
+  float2 ysr[METHOD == kSharpRowSpec ? B : 1];
+  if constexpr (METHOD == kSharpRowSpec) {
+    const float2* tp = g.t + (size_t)j * NP * NP + col;
+    const float c1 = (g.two_rho - 1.f) / (2.f * (float)NP);
+#pragma unroll
+    for (int nb = 0; nb < B; ++nb) {
+      const float2 to = tp[(size_t)(q + A * nb) * NP];
+      ysr[nb] = make_float2(fmaf(c1, x[nb].x, 0.5f * to.x), fmaf(c1, x[nb].y, 0.5f * to.y));
+    }
+  }
   // amplitudes of the spectrum step, fetched now so their latency hides
   // behind the forward column transforms
   const float* yc = g.ys + (size_t)j * NP * NP + col;
@@ -524,16 +538,13 @@ __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
     // the magnitude projection gives P_a s = F_r^*(C)/Np^2, and the next state
     // t' = (1 - 2 beta) P_a s + beta (s - d P_j xbar) with s = t + 2 beta d P_j xbar
     // is, in row spectra, T' = ka C + ((2 beta - 1)/(2 Np)) F_r(s) + T/2, where
-    // F_r(s) is this pass's input (read again: each thread's own elements).
+    // F_r(s) is this pass's input (the last two terms are ysr, formed above).
     // C goes back to the stage for the overlap projection.
     float2* tp = g.t + (size_t)j * NP * NP + col;
-    const float c1 = (g.two_rho - 1.f) / (2.f * (float)NP);
 #pragma unroll
     for (int nb = 0; nb < B; ++nb) {
       const size_t o = (size_t)(q + A * nb) * NP;
-      const float2 xs = sp[o], to = tp[o];
-      tp[o] = make_float2(fmaf(g.ka, x[nb].x, fmaf(c1, xs.x, 0.5f * to.x)),
-                          fmaf(g.ka, x[nb].y, fmaf(c1, xs.y, 0.5f * to.y)));
+      tp[o] = make_float2(fmaf(g.ka, x[nb].x, ysr[nb].x), fmaf(g.ka, x[nb].y, ysr[nb].y));
       sp[o] = x[nb];
     }
   } else {
