@@ -167,3 +167,37 @@ def test_sharp_plus_every_iteration(P, case, iters):
         worst = max(worst, max(errs))
     _say(f"  worst = {worst:.2e}")
     R.close()
+
+
+def test_sharp_plus_rowspec_row_segments(P):
+    """SHARP+ on row-spectrum states over a 400 x 1280 object whose 3 x 12
+    positions of 192^2 cross column 1024 (object rows summed in two
+    segments, patches straddling them; consensus over the stage's projected
+    frames), chunks of 8 positions: teacher-forced at every iteration to 10
+    from a smooth start, beta 0.8, on every frame and on the output."""
+    beta = 0.8
+    prob = synth.make_problem(400, 192, 3, 96, 1e5, 61, n2=1280, scan2=12)
+    assert prob.pos[:, 1].min() < 1024 - 192 and prob.pos[:, 1].max() > 1024
+    n1, n2 = prob.n1, prob.n2
+    d = prob.probe.astype(np.complex64).astype(np.complex128)
+    y = O.amplitudes(prob.z.astype(np.float32))
+    shape = (n1, n2)
+    x0 = synth.make_object(n1, n2, np.random.default_rng(97))
+    ss = [O.sharp_plus_init(x0, d, prob.pos)]
+    for _ in range(10):
+        ss.append(O.sharp_plus_step(ss[-1], d, y, prob.pos, shape, beta))
+    R = P.Reconstruction(n1, n2, prob.probe, prob.pos, prob.z, 0.0, x0=x0.astype(np.complex64), chunk=8,
+                         method=P.PMACE_METHOD_SHARP_PLUS, beta=beta, flags=ROWSPEC)
+    assert R.agent == "row-spectrum"
+    worst = 0.0
+    for k in range(10):
+        R.set_state(ss[k])
+        R.iterate(1)
+        s1 = R.get_state().cpu().numpy()
+        xr = O.sharp_plus_reconstruct(ss[k + 1], d, prob.pos, shape)
+        xh = R.reconstruct().cpu().numpy()
+        errs = (rel(s1, ss[k + 1]), rel(xh, xr), elem(s1, ss[k + 1]), elem(xh, xr))
+        assert max(errs) < TOL, (k, errs)
+        worst = max(worst, max(errs))
+    _say(f"  row segments, sharp+ worst = {worst:.2e}")
+    R.close()
