@@ -80,7 +80,8 @@ def iteration_kernels(np_, J, method="pmace", agent="three-pass"):
     if agent == "row-spectrum":
         return (f"one {name} iteration: per chunk of positions agent_rows, agent_cols <{np_}> "
                 f"(states kept as row spectra) + consensus_rows<{np_}> (inverse row DFTs, one object "
-                f"row per workgroup), then image_update")
+                f"row per workgroup; a9 fused when one chunk holds every position, else image_update "
+                f"after the last chunk)")
     if np_ <= 128:
         return (f"one {name} iteration: agent_fused<{np_}> ({J} workgroups) + "
                 f"consensus_gather<{np_}> (a9 fused)")

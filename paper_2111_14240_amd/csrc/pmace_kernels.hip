@@ -785,14 +785,16 @@ __global__ void __launch_bounds__(GT_THREADS) consensus_gather_batch(const Recon
 // rows in LDS and weights them; every thread then adds, in list order, the
 // ones that cover its pixel of R.  Every pixel's sum thus runs in one fixed
 // order (chunks in turn, then the list), with no atomics: bitwise
-// reproducible.  CHECK: batch member, skip when stopped.
+// reproducible.  CHECK: batch member, skip when stopped.  FUSE (every
+// position in one chunk): each pixel's sum is complete, so a9 is finished
+// here instead of adding the sum to num.
 // -------------------------------------------------------------------------
 // patch rows per round: CR_T threads' worth, at most 64 (LDS)
 template <int NP> constexpr int cr_rows() { return CR_T / Geo<NP>::A < 64 ? CR_T / Geo<NP>::A : 64; }
 template <int NP> constexpr int cr_threads() { return cr_rows<NP>() * Geo<NP>::A; }
 template <int NP> constexpr int cr_pitch() { return row_cap<NP>() > NP ? row_cap<NP>() : NP; }
 
-template <int NP, bool CHECK, int METHOD>
+template <int NP, bool CHECK, int METHOD, bool FUSE>
 __global__ void __launch_bounds__(cr_threads<NP>()) consensus_rows(const Recon g, int first_item,
                                                                     int jbase) {
   static_assert(row_spec<METHOD>(), "row-spectrum states");
@@ -872,13 +874,17 @@ __global__ void __launch_bounds__(cr_threads<NP>()) consensus_rows(const Recon g
     }
     if (e0 + RN < it.y) fetch(e0 + RN + rl);
   }
-  float2* nrow = g.num + (size_t)it.z * g.n2;
+  const size_t row0 = (size_t)it.z * g.n2;
 #pragma unroll
   for (int k = 0; k < PX; ++k) {
     const int C = it.w + tid + k * NT;
     if (C < g.n2) {
-      const float2 o = nrow[C];
-      nrow[C] = make_float2(o.x + ax[k], o.y + ay[k]);
+      if constexpr (FUSE) {
+        finish_image<METHOD == kSharpRowSpec ? kSharpPlus : kPMACE>(g, row0 + C, make_float2(ax[k], ay[k]));
+      } else {
+        const float2 o = g.num[row0 + C];
+        g.num[row0 + C] = make_float2(o.x + ax[k], o.y + ay[k]);
+      }
     }
   }
 }
@@ -1840,6 +1846,8 @@ template <int NP>
 static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* chunk_tiles,
                             const int2* chunk_rows, hipStream_t st) {
   constexpr int RT = row_threads<NP>(), CT = col_threads<NP>();
+  // every position in one chunk: the row consensus finishes a9 itself
+  const bool one_chunk = h.chunk >= h.J;
   for (int j0 = 0, g = 0; j0 < h.J; j0 += h.chunk, ++g) {
     const int cnt = (h.J - j0 < h.chunk) ? (h.J - j0) : h.chunk;
     const dim3 rgrid(cnt * (NP / rb_of<NP>())), cgrid(cnt * (NP / CB));
@@ -1848,22 +1856,28 @@ static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* 
       // row-spectrum states: rows (window term), columns (new state), then the
       // consensus with the inverse row transforms
       const int2 cr = chunk_rows[g];
-      const dim3 crb(cr_threads<NP>());
+      const dim3 crb(cr_threads<NP>()), cg(cr.y);
       if (batch_rec) {
         hipLaunchKernelGGL((agent_rows_batch<NP, kRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
         hipLaunchKernelGGL((agent_cols_batch<NP, kRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
-        if (cr.y > 0)
-          hipLaunchKernelGGL((consensus_rows<NP, true, kRowSpec>), dim3(cr.y), crb, 0, st, h, cr.x, j0);
+        if (cr.y > 0 && one_chunk)
+          hipLaunchKernelGGL((consensus_rows<NP, true, kRowSpec, true>), cg, crb, 0, st, h, cr.x, j0);
+        else if (cr.y > 0)
+          hipLaunchKernelGGL((consensus_rows<NP, true, kRowSpec, false>), cg, crb, 0, st, h, cr.x, j0);
       } else if (h.method == kSharpPlus) {
         hipLaunchKernelGGL((agent_rows<NP, kSharpRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
         hipLaunchKernelGGL((agent_cols<NP, kSharpRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
-        if (cr.y > 0)
-          hipLaunchKernelGGL((consensus_rows<NP, false, kSharpRowSpec>), dim3(cr.y), crb, 0, st, h, cr.x, j0);
+        if (cr.y > 0 && one_chunk)
+          hipLaunchKernelGGL((consensus_rows<NP, false, kSharpRowSpec, true>), cg, crb, 0, st, h, cr.x, j0);
+        else if (cr.y > 0)
+          hipLaunchKernelGGL((consensus_rows<NP, false, kSharpRowSpec, false>), cg, crb, 0, st, h, cr.x, j0);
       } else {
         hipLaunchKernelGGL((agent_rows<NP, kRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
         hipLaunchKernelGGL((agent_cols<NP, kRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
-        if (cr.y > 0)
-          hipLaunchKernelGGL((consensus_rows<NP, false, kRowSpec>), dim3(cr.y), crb, 0, st, h, cr.x, j0);
+        if (cr.y > 0 && one_chunk)
+          hipLaunchKernelGGL((consensus_rows<NP, false, kRowSpec, true>), cg, crb, 0, st, h, cr.x, j0);
+        else if (cr.y > 0)
+          hipLaunchKernelGGL((consensus_rows<NP, false, kRowSpec, false>), cg, crb, 0, st, h, cr.x, j0);
       }
       continue;
     }
@@ -1892,6 +1906,7 @@ static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* 
                            st, h, ct.x, j0);
     }
   }
+  if (h.rowspec && one_chunk) return;
   const unsigned nb = blocks_for((long long)h.n1 * h.n2, 256);
   if (batch_rec)
     hipLaunchKernelGGL(image_update_batch, dim3(nb), dim3(256), 0, st, h);
