@@ -668,6 +668,7 @@ pmace_status pmace_init(const pmace_params* params, const void* probe_d, const i
     h.cn = (float)(1.0 / rho);
   }
   h.chunk = chunk;
+  h.nt_stage = rowspec && (double)std::min(chunk, p.num_pos) * np * np * 8.0 > 512.0 * (1 << 20) ? 1 : 0;
   h.n_red = nred;
   h.ppw = p.ppw > 0 ? p.ppw : pmace::default_ppw(p.np);
   c->dev = reinterpret_cast<Recon*>(base + L.desc);

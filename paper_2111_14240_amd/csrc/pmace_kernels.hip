@@ -417,7 +417,15 @@ static_assert(CB >= 8 && CB <= 32 && 160 % CB == 0 && 192 % CB == 0 && 256 % CB 
 template <int NP> constexpr int row_threads() { return rb_of<NP>() * Geo<NP>::A; }
 template <int NP> constexpr int col_threads() { return CB * Geo<NP>::A; }
 
-template <int NP, int METHOD>
+// A store that does not keep its line in the caches (data read back only
+// after far more than the caches hold has passed through them).
+typedef float pm_f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store_nt(float2* p, float2 v) {
+  const pm_f2v t = {v.x, v.y};
+  __builtin_nontemporal_store(t, reinterpret_cast<pm_f2v*>(p));
+}
+
+template <int NP, int METHOD, bool NT>
 __device__ __forceinline__ void agent_rows_body(const Recon& g, const int j0) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A, S = row_cap<NP>();
   constexpr int RBn = rb_of<NP>();
@@ -471,23 +479,28 @@ __device__ __forceinline__ void agent_rows_body(const Recon& g, const int j0) {
 #pragma unroll
   for (int m = 0; m < M; ++m)
 #pragma unroll
-    for (int ka = 0; ka < A; ++ka) out[p + A * m + B * ka] = x[m * A + ka];
+    for (int ka = 0; ka < A; ++ka) {
+      if constexpr (NT) store_nt(out + p + A * m + B * ka, x[m * A + ka]);
+      else out[p + A * m + B * ka] = x[m * A + ka];
+    }
 }
 
-template <int NP, int METHOD>
+// NT: the stage (and, in the column pass, the new row-spectrum states) written
+// past the caches, for stages far larger than the Infinity Cache
+template <int NP, int METHOD, bool NT = false>
 __global__ void __launch_bounds__(row_threads<NP>()) agent_rows(const Recon g, int j0) {
-  agent_rows_body<NP, METHOD>(g, j0);
+  agent_rows_body<NP, METHOD, NT>(g, j0);
 }
 
 // Batch members: the member's descriptor by value (global, not flat, loads),
 // its stop flag read through it.
-template <int NP, int METHOD>
+template <int NP, int METHOD, bool NT = false>
 __global__ void __launch_bounds__(row_threads<NP>()) agent_rows_batch(const Recon g, int j0) {
   if (*g.done) return;
-  agent_rows_body<NP, METHOD>(g, j0);
+  agent_rows_body<NP, METHOD, NT>(g, j0);
 }
 
-template <int NP, int METHOD>
+template <int NP, int METHOD, bool NT>
 __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
   constexpr int A = Geo<NP>::A, B = Geo<NP>::B, M = B / A;
   __shared__ float2 tile[col_rows<NP>() * CB];
@@ -552,19 +565,22 @@ __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
     // new state itself; the inverse row pass is left to the consensus
     float2* op = METHOD == kRowSpec ? g.t + (size_t)j * NP * NP + col : sp;
 #pragma unroll
-    for (int nb = 0; nb < B; ++nb) op[(size_t)(q + A * nb) * NP] = x[nb];
+    for (int nb = 0; nb < B; ++nb) {
+      if constexpr (NT && METHOD == kRowSpec) store_nt(op + (size_t)(q + A * nb) * NP, x[nb]);
+      else op[(size_t)(q + A * nb) * NP] = x[nb];
+    }
   }
 }
 
-template <int NP, int METHOD>
+template <int NP, int METHOD, bool NT = false>
 __global__ void __launch_bounds__(col_threads<NP>()) agent_cols(const Recon g, int j0) {
-  agent_cols_body<NP, METHOD>(g, j0);
+  agent_cols_body<NP, METHOD, NT>(g, j0);
 }
 
-template <int NP, int METHOD>
+template <int NP, int METHOD, bool NT = false>
 __global__ void __launch_bounds__(col_threads<NP>()) agent_cols_batch(const Recon g, int j0) {
   if (*g.done) return;
-  agent_cols_body<NP, METHOD>(g, j0);
+  agent_cols_body<NP, METHOD, NT>(g, j0);
 }
 
 template <int NP, int METHOD>
@@ -1858,22 +1874,35 @@ static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* 
       const int2 cr = chunk_rows[g];
       const dim3 crb(cr_threads<NP>()), cg(cr.y);
       if (batch_rec) {
-        hipLaunchKernelGGL((agent_rows_batch<NP, kRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
-        hipLaunchKernelGGL((agent_cols_batch<NP, kRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
+        if (h.nt_stage) {
+          hipLaunchKernelGGL((agent_rows_batch<NP, kRowSpec, true>), rgrid, dim3(RT), 0, st, h, j0);
+          hipLaunchKernelGGL((agent_cols_batch<NP, kRowSpec, true>), cgrid, dim3(CT), 0, st, h, j0);
+        } else {
+          hipLaunchKernelGGL((agent_rows_batch<NP, kRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
+          hipLaunchKernelGGL((agent_cols_batch<NP, kRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
+        }
         if (cr.y > 0 && one_chunk)
           hipLaunchKernelGGL((consensus_rows<NP, true, kRowSpec, true>), cg, crb, 0, st, h, cr.x, j0);
         else if (cr.y > 0)
           hipLaunchKernelGGL((consensus_rows<NP, true, kRowSpec, false>), cg, crb, 0, st, h, cr.x, j0);
       } else if (h.method == kSharpPlus) {
-        hipLaunchKernelGGL((agent_rows<NP, kSharpRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
+        if (h.nt_stage)
+          hipLaunchKernelGGL((agent_rows<NP, kSharpRowSpec, true>), rgrid, dim3(RT), 0, st, h, j0);
+        else
+          hipLaunchKernelGGL((agent_rows<NP, kSharpRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
         hipLaunchKernelGGL((agent_cols<NP, kSharpRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
         if (cr.y > 0 && one_chunk)
           hipLaunchKernelGGL((consensus_rows<NP, false, kSharpRowSpec, true>), cg, crb, 0, st, h, cr.x, j0);
         else if (cr.y > 0)
           hipLaunchKernelGGL((consensus_rows<NP, false, kSharpRowSpec, false>), cg, crb, 0, st, h, cr.x, j0);
       } else {
-        hipLaunchKernelGGL((agent_rows<NP, kRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
-        hipLaunchKernelGGL((agent_cols<NP, kRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
+        if (h.nt_stage) {
+          hipLaunchKernelGGL((agent_rows<NP, kRowSpec, true>), rgrid, dim3(RT), 0, st, h, j0);
+          hipLaunchKernelGGL((agent_cols<NP, kRowSpec, true>), cgrid, dim3(CT), 0, st, h, j0);
+        } else {
+          hipLaunchKernelGGL((agent_rows<NP, kRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
+          hipLaunchKernelGGL((agent_cols<NP, kRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
+        }
         if (cr.y > 0 && one_chunk)
           hipLaunchKernelGGL((consensus_rows<NP, false, kRowSpec, true>), cg, crb, 0, st, h, cr.x, j0);
         else if (cr.y > 0)
