@@ -151,8 +151,8 @@ struct Recon {
   int rowspec;
   // Row-spectrum agent: when a chunk's stage is over twice the 256 MB
   // Infinity Cache, the row pass writes it, and the column pass the new
-  // states, with non-temporal stores (smaller stages gain from the cache on
-  // their way to the column pass)
+  // states (PMACE and SHARP+), with non-temporal stores (smaller stages gain
+  // from the cache on their way to the column pass)
   int nt_stage;
   int4* citems;         // per (chunk, object row, segment): (list start, count, row, first column)
   int4* clist;          // per entry: (j, row of P_j on that object row, patch column, 0), ascending j

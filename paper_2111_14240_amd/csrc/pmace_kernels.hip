@@ -552,12 +552,15 @@ __device__ __forceinline__ void agent_cols_body(const Recon& g, const int j0) {
     // t' = (1 - 2 beta) P_a s + beta (s - d P_j xbar) with s = t + 2 beta d P_j xbar
     // is, in row spectra, T' = ka C + ((2 beta - 1)/(2 Np)) F_r(s) + T/2, where
     // F_r(s) is this pass's input (the last two terms are ysr, formed above).
-    // C goes back to the stage for the overlap projection.
+    // C goes back to the stage for the overlap projection (through the
+    // caches: the consensus reads it next; with NT the new state does not).
     float2* tp = g.t + (size_t)j * NP * NP + col;
 #pragma unroll
     for (int nb = 0; nb < B; ++nb) {
       const size_t o = (size_t)(q + A * nb) * NP;
-      tp[o] = make_float2(fmaf(g.ka, x[nb].x, ysr[nb].x), fmaf(g.ka, x[nb].y, ysr[nb].y));
+      const float2 tn = make_float2(fmaf(g.ka, x[nb].x, ysr[nb].x), fmaf(g.ka, x[nb].y, ysr[nb].y));
+      if constexpr (NT) store_nt(tp + o, tn);
+      else tp[o] = tn;
       sp[o] = x[nb];
     }
   } else {
@@ -1890,7 +1893,10 @@ static void large_iteration(const Recon& h, const Recon* batch_rec, const int2* 
           hipLaunchKernelGGL((agent_rows<NP, kSharpRowSpec, true>), rgrid, dim3(RT), 0, st, h, j0);
         else
           hipLaunchKernelGGL((agent_rows<NP, kSharpRowSpec>), rgrid, dim3(RT), 0, st, h, j0);
-        hipLaunchKernelGGL((agent_cols<NP, kSharpRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
+        if (h.nt_stage)
+          hipLaunchKernelGGL((agent_cols<NP, kSharpRowSpec, true>), cgrid, dim3(CT), 0, st, h, j0);
+        else
+          hipLaunchKernelGGL((agent_cols<NP, kSharpRowSpec>), cgrid, dim3(CT), 0, st, h, j0);
         if (cr.y > 0 && one_chunk)
           hipLaunchKernelGGL((consensus_rows<NP, false, kSharpRowSpec, true>), cg, crb, 0, st, h, cr.x, j0);
         else if (cr.y > 0)
