@@ -94,6 +94,37 @@ def test_batch_alone_equals_mix_bitwise(P):
         R.close()
 
 
+def test_batch_large_stage_member_bitwise(P):
+    """A row-spectrum member whose stage passes 512 MiB (1089 positions of
+    256x256: 558 MiB) takes the batch kernels that write the stage and the new
+    states past the caches; advanced in a batch it must equal the same
+    reconstruction advanced alone, bit for bit."""
+    big = synth.make_problem(768, 256, 33, 15, 1e5, 41)
+    small = synth.make_problem(128, 32, 6, 16, None, 1)
+    assert big.pos.shape[0] * 256 * 256 * 8 > 512 * 2**20
+    K = 3
+    alone = []
+    for prob in (big, small):
+        R = _recon(P, prob, 0)
+        if prob is big:
+            _say("large-stage member alone, agent", R.agent)
+            assert R.agent == "row-spectrum"
+        R.iterate(K)
+        alone.append((R.get_state().cpu().numpy(), R.reconstruct().cpu().numpy()))
+        R.close()
+    Rs = [_recon(P, prob, 0) for prob in (big, small)]
+    B = P.Batch(Rs, tol=0.0, min_iter=0, max_iter=K)
+    B.step(K)
+    done, _, iters = B.poll()
+    assert done.tolist() == [1, 1] and iters.tolist() == [K, K]
+    for i, R in enumerate(Rs):
+        v, xh = R.get_state().cpu().numpy(), R.reconstruct().cpu().numpy()
+        assert np.array_equal(v, alone[i][0]) and np.array_equal(xh, alone[i][1]), i
+    B.close()
+    for R in Rs:
+        R.close()
+
+
 def test_batch_stop_rule(P):
     probs = _problems()
     Rs = [_recon(P, prob, cfg[-1]) for prob, cfg in zip(probs, MIX)]
