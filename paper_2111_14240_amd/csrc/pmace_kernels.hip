@@ -811,7 +811,8 @@ __global__ void __launch_bounds__(GT_THREADS) consensus_gather_batch(const Recon
 // patch rows per round: CR_T threads' worth, at most 64 (LDS)
 template <int NP> constexpr int cr_rows() { return CR_T / Geo<NP>::A < 64 ? CR_T / Geo<NP>::A : 64; }
 template <int NP> constexpr int cr_threads() { return cr_rows<NP>() * Geo<NP>::A; }
-template <int NP> constexpr int cr_pitch() { return row_cap<NP>() > NP ? row_cap<NP>() : NP; }
+// (at least NP + 1: a row keeps a zero at index NP for the sums below)
+template <int NP> constexpr int cr_pitch() { return row_cap<NP>() > NP ? row_cap<NP>() : NP + 1; }
 
 template <int NP, bool CHECK, int METHOD, bool FUSE>
 __global__ void __launch_bounds__(cr_threads<NP>()) consensus_rows(const Recon g, int first_item,
@@ -865,7 +866,10 @@ __global__ void __launch_bounds__(cr_threads<NP>()) consensus_rows(const Recon g
     __syncthreads();  // the last round's sums are done with rows[]; tw is written
     row_inv<NP>(x, rows + rl * S, p, tw);
     wave_sync();
-    if (p == 0) pcol[rl] = en.z;
+    if (p == 0) {
+      pcol[rl] = en.z;
+      rows[rl * S + NP] = make_float2(0.f, 0.f);
+    }
 #pragma unroll
     for (int nb = 0; nb < B; ++nb) rows[rl * S + p + A * nb] = cmul(w[nb], x[nb]);
     __syncthreads();
@@ -873,7 +877,9 @@ __global__ void __launch_bounds__(cr_threads<NP>()) consensus_rows(const Recon g
     // entries: above any column).  The list is sorted by patch column, so the
     // entries covering some of a wave's 64 pixels [cw, cw + 64) are the lanes
     // [lo, hi) with cw - NP < pc <= cw + 63, counted by two ballots; each
-    // pixel adds the ones that cover it, in list order.
+    // pixel adds the ones that cover it, in list order.  An entry that does
+    // not cover the pixel adds the row's zero at index NP instead, so the
+    // loop has no branch and keeps several LDS reads in flight.
     const int lane = tid & 63;
     const int pv = lane < ne ? pcol[lane] : 0x7fffffff;
 #pragma unroll
@@ -882,13 +888,20 @@ __global__ void __launch_bounds__(cr_threads<NP>()) consensus_rows(const Recon g
       const int lo = __popcll(__ballot(pv <= cw - NP));
       const int hi = __popcll(__ballot(pv <= cw + 63));
       const int C = cw + lane;
-      for (int e = lo; e < hi; ++e) {
+      auto at = [&](int e) {
         const unsigned cc = (unsigned)(C - __builtin_amdgcn_readlane(pv, e));
-        if (cc < (unsigned)NP) {
-          const float2 v = rows[e * S + cc];
-          ax[k] += v.x;
-          ay[k] += v.y;
-        }
+        return rows[e * S + (cc < (unsigned)NP ? cc : (unsigned)NP)];
+      };
+      int e = lo;
+      for (; e + 4 <= hi; e += 4) {
+        const float2 v0 = at(e), v1 = at(e + 1), v2 = at(e + 2), v3 = at(e + 3);
+        ax[k] = ((ax[k] + v0.x) + v1.x + v2.x) + v3.x;
+        ay[k] = ((ay[k] + v0.y) + v1.y + v2.y) + v3.y;
+      }
+      for (; e < hi; ++e) {
+        const float2 v = at(e);
+        ax[k] += v.x;
+        ay[k] += v.y;
       }
     }
     if (e0 + RN < it.y) fetch(e0 + RN + rl);
