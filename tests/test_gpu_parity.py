@@ -180,7 +180,7 @@ SMALL_CASES = {
     # radix-3 and radix-5 patch sides (prime-factor DFTs)
     "np48": (160, 48, 5, 24, 1e5, 51, 0),
     "np96": (288, 96, 5, 40, 1e5, 52, 0),
-    "np160_ragged_chunks": (360, 160, 3, 80, 1e6, 53, 4),
+    "np160_ragged_chunks": (360, 160, 3, 80, 1e6, 53, 4, STAGED),
     "np192_split": (400, 192, 3, 90, 1e5, 54, 0, SPLIT),
     "np192_staged": (400, 192, 3, 90, 1e5, 54, 0, STAGED),
     # states kept as row spectra, with ragged chunks where the side allows
@@ -493,7 +493,7 @@ def c3_geometry_problem(np_):
 
 @pytest.mark.slow
 @pytest.mark.parametrize("np_,flags", [(256, 0), (256, SPLIT), (256, STAGED), (192, 0), (192, STAGED),
-                                       (192, SPLIT), (160, 0), (160, ROWSPEC)])
+                                       (192, SPLIT), (160, 0), (160, STAGED)])
 def test_c3_full_size_steps(P, np_, flags):
     """The full 1024^2 / 1600-position workload (probe 256^2, and the 192^2 and
     160^2 sides bench.py times on the same geometry) in the launch
