@@ -811,8 +811,10 @@ __global__ void __launch_bounds__(GT_THREADS) consensus_gather_batch(const Recon
 // patch rows per round: CR_T threads' worth, at most 64 (LDS)
 template <int NP> constexpr int cr_rows() { return CR_T / Geo<NP>::A < 64 ? CR_T / Geo<NP>::A : 64; }
 template <int NP> constexpr int cr_threads() { return cr_rows<NP>() * Geo<NP>::A; }
-// (at least NP + 1: a row keeps a zero at index NP for the sums below)
-template <int NP> constexpr int cr_pitch() { return row_cap<NP>() > NP ? row_cap<NP>() : NP + 1; }
+// (at least NP + 1: a row keeps a zero at index NP for the sums below; where
+// the transform's own span is shorter, NP + 4 sets consecutive rows 8 banks
+// apart, so the row groups of a wave do not collide in its LDS exchange)
+template <int NP> constexpr int cr_pitch() { return row_cap<NP>() > NP ? row_cap<NP>() : NP + 4; }
 
 template <int NP, bool CHECK, int METHOD, bool FUSE>
 __global__ void __launch_bounds__(cr_threads<NP>()) consensus_rows(const Recon g, int first_item,
